@@ -24,6 +24,26 @@ def nearest_pairs(A, B, sigma: float, k: int):
     return lam[order], X[:, order]
 
 
+def cluster_basis(A, B, sigma: float, k: int, rtol: float = 1e-9):
+    """B-orthonormal basis of the union of the eigenspaces of every
+    eigenvalue among the k nearest sigma.  When the k-th value is part of a
+    multiple eigenvalue, any k-dimensional subspace of that union made of
+    eigenvectors is a correct answer, so subspaces are compared with it."""
+    Ad = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    if B is None:
+        lam, X = np.linalg.eigh(Ad)
+    else:
+        Bd = B.toarray() if hasattr(B, "toarray") else np.asarray(B)
+        lam, X = sla.eigh(Ad, Bd)
+    order = np.lexsort((lam, np.abs(lam - sigma)))[:k]
+    sel = lam[order]
+    scale = max(np.abs(lam).max(), 1.0)
+    mask = np.zeros(len(lam), dtype=bool)
+    for v in sel:
+        mask |= np.abs(lam - v) <= rtol * scale
+    return lam[mask], X[:, mask]
+
+
 def all_eigenvalues(A, B=None):
     Ad = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
     if B is None:

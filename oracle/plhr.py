@@ -31,8 +31,9 @@ the design notes of the repository):
   quotient) are all converged; the extra column of the real variant is not
   required to converge;
 * B-orthonormalisation: classical Gram-Schmidt run twice per column in the
-  B-inner product; a W/S/P column whose norm falls below drop_tol times its
-  norm before projection is dropped; a dependent V column is an error;
+  B-inner product; a column whose norm falls below drop_tol times its norm
+  before projection adds nothing to span(Z) and is dropped (the start block
+  itself must have full rank);
 * sort key for xi: (|xi|, Re xi, -Im xi), so a conjugate pair is adjacent
   with the positive-imaginary member first.
 """
@@ -112,8 +113,6 @@ def b_orthonormalize(blocks, B, drop_tol: float = 1e-10):
             x = X[:, j].copy()
             n0 = np.sqrt(abs(np.vdot(x, _mul(B, x))))
             if n0 == 0.0:
-                if name == "V":
-                    raise Breakdown("zero column in V")
                 continue
             for _ in range(2):
                 if cols:
@@ -123,12 +122,14 @@ def b_orthonormalize(blocks, B, drop_tol: float = 1e-10):
             bx = _mul(B, x)
             nrm = np.sqrt(abs(np.vdot(x, bx)))
             if nrm <= drop_tol * n0:
-                if name == "V":
-                    raise Breakdown("V block is rank deficient")
+                # a numerically dependent column adds nothing to the span
+                # of Z, which is all the projection uses (Section 4)
                 continue
             cols.append(x / nrm)
             bcols.append(bx / nrm)
             labels.append((name, j))
+    if not any(lb[0] == "V" for lb in labels):
+        raise Breakdown("the V block vanished")
     return np.column_stack(cols), labels
 
 
@@ -263,6 +264,10 @@ class BPLHR:
         self.prob, self.k, self.real, self.lock = prob, k, real, lock
         self.drop_tol = drop_tol
         V = np.array(V0, dtype=np.float64 if real else np.complex128)
+        # the start block must have full rank
+        _, labels = b_orthonormalize([("V", V)], prob.B, drop_tol)
+        if len(labels) < V.shape[1]:
+            raise Breakdown("the start block is rank deficient")
         # step 1-2: B-normalise, Lambda = diag(V^* A V)
         V = b_normalize(prob.B, V)
         self.V = V
