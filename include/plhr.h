@@ -1,0 +1,257 @@
+/*
+ * plhr.h -- C ABI of the MI355X block PLHR eigensolver.
+ *
+ * Block PLHR (Vecharynski & Knyazev, "Preconditioned locally harmonic
+ * residual method for computing interior eigenpairs of certain classes of
+ * Hermitian matrices", arXiv:1408.0042) computes the k eigenpairs of
+ *
+ *     A v = lambda B v,   A = A^*,  B = B^* > 0            (eq. 1.1)
+ *
+ * whose eigenvalues are closest to a real shift sigma, using a Hermitian
+ * positive definite preconditioner T (Section 5) and the T-harmonic
+ * Rayleigh-Ritz extraction of eq. (3.5) on the trial subspace
+ * span{V, W, S, P} (Algorithm 2; Algorithm 3 in real arithmetic).
+ *
+ * Conventions for every entry point
+ *  - Block vectors are point-major: an n-by-c block is n rows of c
+ *    contiguous scalars (row-major, leading dimension c).
+ *  - Pointers documented as "device" must be HIP device memory on the
+ *    device that was current at plhr_create; pointers documented as "host"
+ *    are ordinary host memory.  All device buffers passed in are owned by
+ *    the caller and must outlive the context.
+ *  - Work is enqueued on the stream given to plhr_create.  Functions that
+ *    return host results synchronise that stream before returning.
+ *  - Every function returns a plhr_status; on failure a message describing
+ *    the first error is available from plhr_last_error() (thread-local).
+ *    No function throws or aborts on bad input.
+ *  - Nothing here is thread-safe for a single context; distinct contexts
+ *    may be used from distinct threads.
+ */
+#ifndef PLHR_H
+#define PLHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PLHR_OK = 0,
+  PLHR_ERR_ARG = 1,           /* invalid argument or descriptor                 */
+  PLHR_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement    */
+  PLHR_ERR_HIP = 3,           /* a HIP runtime call failed                      */
+  PLHR_ERR_NOT_HPD = 4,       /* Gram/projected matrix not positive definite    */
+  PLHR_ERR_BREAKDOWN = 5,     /* the V block became rank deficient              */
+  PLHR_ERR_NOT_CONVERGED = 6, /* max_iters reached; outputs hold best iterate   */
+  PLHR_ERR_STATE = 7          /* call out of order (e.g. backward before solve) */
+} plhr_status;
+
+/* Operator kinds (the model operators the paper uses, Section 6). */
+typedef enum {
+  PLHR_OP_IDENTITY = 0,
+  PLHR_OP_FD5_2D = 1, /* scale*(-Laplacian) 5-point, Dirichlet, + diag(V)   */
+  PLHR_OP_FD7_3D = 2  /* scale*(-Laplacian) 7-point, Dirichlet, + diag(V)   */
+} plhr_op_kind;
+
+typedef enum { PLHR_F64 = 0 } plhr_dtype;
+
+/* Operator descriptor.  Grid points are numbered x-fastest,
+ * p = i + nx*(j + ny*l); a 2-D grid has nz = 1.
+ *   kind       one of plhr_op_kind
+ *   dtype      PLHR_F64
+ *   nx, ny, nz interior points per direction (>= 1)
+ *   h          grid spacing (> 0)
+ *   scale      factor multiplying the negative discrete Laplacian (> 0)
+ *   potential  device, n doubles, or NULL for none: A += diag(potential)  */
+typedef struct {
+  int32_t kind;
+  int32_t dtype;
+  int32_t nx, ny, nz;
+  int32_t reserved0;
+  double h;
+  double scale;
+  const double* potential;
+} plhr_op_desc;
+
+/* Preconditioner kinds (Section 5: T must be Hermitian positive definite). */
+typedef enum {
+  PLHR_PREC_IDENTITY = 0,
+  PLHR_PREC_MG_VCYCLE = 1 /* one V-cycle on the Laplacian part of A */
+} plhr_prec_kind;
+
+/* Preconditioner descriptor.
+ *   kind     one of plhr_prec_kind
+ *   levels   number of grid levels including the finest (>= 1); each level
+ *            halves every grid dimension (which must stay even); the
+ *            coarsest level is solved with a dense inverse (at most 4096
+ *            points)
+ *   nu_pre, nu_post  weighted-Jacobi sweeps before / after the coarse
+ *            correction (must be equal so that T is Hermitian)
+ *   omega    Jacobi weight, 0 < omega <= 2/3 keeps T positive definite   */
+typedef struct {
+  int32_t kind;
+  int32_t levels;
+  int32_t nu_pre, nu_post;
+  double omega;
+} plhr_prec_desc;
+
+typedef enum { PLHR_PREC_FP64 = 0 } plhr_precision;
+
+/* Solver options (plhr_options_default fills the defaults shown).
+ *   tol          relative residual ||A v - lam B v|| /
+ *                ((||A||_1 + |lam| ||B||_1) ||v||) at which a pair counts
+ *                as converged                                 (1e-8)
+ *   max_iters    iteration limit                              (10000)
+ *   k_extra      extra block columns; 1 for real problems so that a
+ *                conjugate pair is not cut (Section 4.1)      (1)
+ *   precision    PLHR_PREC_FP64                               (FP64)
+ *   lock         soft locking of converged columns            (1)
+ *   check_every  iterations between host convergence checks   (1)
+ *   drop_tol     squared relative norm below which a W/S/P column is
+ *                dropped during B-orthonormalisation          (1e-12) */
+typedef struct {
+  double tol;
+  int32_t max_iters;
+  int32_t k_extra;
+  int32_t precision;
+  int32_t lock;
+  int32_t check_every;
+  int32_t reserved0;
+  double drop_tol;
+} plhr_options;
+
+typedef struct plhr_ctx_s* plhr_ctx;
+
+/* Per-call iteration report (host struct). */
+typedef struct {
+  int32_t iters;       /* iterations done since plhr_start                 */
+  int32_t converged;   /* 1 when the k wanted pairs meet tol               */
+  int32_t n_active;    /* columns still generating W/S/P                  */
+  int32_t status;      /* device status word (0 = ok)                      */
+  double max_rel_res;  /* largest relative residual among the k wanted     */
+} plhr_iter_info;
+
+/* Library version string. */
+const char* plhr_version(void);
+
+/* Message for the most recent failure on this thread ("" if none). */
+const char* plhr_last_error(void);
+
+/* Fill *opt with defaults.  Returns PLHR_ERR_ARG if opt is NULL. */
+plhr_status plhr_options_default(plhr_options* opt);
+
+/* Bytes of device workspace plhr_create needs for these arguments.
+ * Arguments as for plhr_create.  *ws_bytes (host) receives the size. */
+plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
+                                const plhr_prec_desc* T, double sigma, int32_t k,
+                                const plhr_options* opt, size_t* ws_bytes);
+
+/* Create a solver for the k eigenpairs of A v = lambda B v nearest sigma
+ * (Algorithm 3 for these real operators).
+ *   A          host descriptor of A (FD5_2D or FD7_3D)
+ *   B          host descriptor of B, or NULL for the identity
+ *   T          host descriptor of the HPD preconditioner, or NULL for I
+ *   sigma      finite real shift
+ *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n
+ *   opt        host options, or NULL for defaults
+ *   stream     HIP stream (hipStream_t) all work is enqueued on; NULL is
+ *              the null stream
+ *   workspace  device buffer of at least plhr_workspace_size bytes, or
+ *              NULL to let the library allocate (and free at destroy)
+ *   ws_bytes   size of workspace (ignored when workspace is NULL)
+ *   out        host; receives the context handle                        */
+plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B,
+                        const plhr_prec_desc* T, double sigma, int32_t k,
+                        const plhr_options* opt, void* stream, void* workspace,
+                        size_t ws_bytes, plhr_ctx* out);
+
+/* Algorithm 3, steps 1-2: load the start block and B-normalise it.
+ *   V0   device, n x (k + k_extra) doubles, point-major; copied.          */
+plhr_status plhr_start(plhr_ctx ctx, const double* V0);
+
+/* Run up to n_steps iterations of the while-loop of Algorithm 3, stopping
+ * early when the k wanted pairs converge.  info (host) may be NULL.
+ * Returns PLHR_OK (also when not yet converged), or an error.            */
+plhr_status plhr_iterate(plhr_ctx ctx, int32_t n_steps, plhr_iter_info* info);
+
+/* Final standard Rayleigh-Ritz on span(V) (Algorithm 2/3, last step).
+ *   eigvals  device, k doubles, ordered by |lambda - sigma| (ties: smaller)
+ *   V        device, n x k doubles, B-orthonormal Ritz vectors, or NULL
+ *   rel_res  host, k doubles (relative residuals recomputed from fresh
+ *            operator products), or NULL                                 */
+plhr_status plhr_finish(plhr_ctx ctx, double* eigvals, double* V, double* rel_res);
+
+/* plhr_start + plhr_iterate until convergence or max_iters + plhr_finish.
+ *   iters (host) receives the iteration count, may be NULL.
+ * Returns PLHR_ERR_NOT_CONVERGED (outputs still written) when max_iters
+ * is reached first.                                                      */
+plhr_status plhr_solve(plhr_ctx ctx, const double* V0, double* eigvals, double* V,
+                       double* rel_res, int32_t* iters);
+
+/* Hellmann-Feynman gradient of L(lambda) with respect to the diagonal
+ * potential of A: for B = I and A = L + diag(pot),
+ *     dL/dpot_x = sum_j dL/dlambda_j * |v_j(x)|^2 / (v_j^* B v_j)
+ * over the k pairs returned by the last plhr_finish.
+ *   dL_dlambda  device, k doubles
+ *   dL_dpot     device, n doubles; overwritten, or added to when
+ *               accumulate != 0
+ * PLHR_ERR_STATE if plhr_finish has not run.                              */
+plhr_status plhr_eigvals_backward(plhr_ctx ctx, const double* dL_dlambda, double* dL_dpot,
+                                  int32_t accumulate);
+
+/* Apply one operator of the context to a block (no iteration state used).
+ *   which  0: Y = A X;  1: Y = (A - sigma B) X;  2: Y = T X
+ *   X, Y   device, n x ncols doubles, point-major; must not overlap
+ *   ncols  1 <= ncols <= 2*(k + k_extra)                                  */
+plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, int32_t ncols);
+
+/* Read back iteration state for inspection (synchronises the stream).
+ *   lam      host, k + k_extra doubles (current Rayleigh quotients)
+ *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */
+plhr_status plhr_get_state(plhr_ctx ctx, double* lam, double* V);
+
+/* Kernel-category launch profile (HIP events around every launch).
+ * Categories: 0 operator block products, 1 V-cycle smoothing sweeps,
+ * 2 V-cycle transfers and coarse solve, 3 Gram products, 4 B-orthonormal
+ * transform and Ritz-vector update, 5 projected-problem kernels,
+ * 6 residual formation, reductions and copies.
+ * bytes/flops are algorithmic (what the operation must read, write and
+ * compute); total_ms sums the event-measured kernel durations.           */
+typedef struct {
+  int32_t launches[8];
+  double total_ms[8];
+  double bytes[8];
+  double flops[8];
+  int32_t truncated;  /* 1 if more launches happened than were recorded */
+  int32_t reserved0;
+} plhr_profile;
+
+/* Start recording launches of one category (-1: all) on this context, for
+ * at most max_launches launches (events are created here, host side).    */
+plhr_status plhr_profile_start(plhr_ctx ctx, int32_t category, int32_t max_launches);
+
+/* Stop recording; synchronises the stream and fills *out (host).         */
+plhr_status plhr_profile_stop(plhr_ctx ctx, plhr_profile* out);
+
+/* Diagnostic read-back of internal buffers (synchronises the stream).
+ *   which  0: Gram of Z (m x m); 1: orthonormalising transform M (m x m);
+ *          2: [G_L | G_R] (m x 2m); 3: coefficients Y' (m x kint);
+ *          4: sorted xi (2 x m: real parts, imaginary parts); 5: lambda
+ *          (kint); 6: relative residuals (kint); 7: Z (n x m); 8: QZ;
+ *          9: TQZ; 10: kept-slot mask (m, as doubles); 11: column kinds
+ *          and partners (2 x kint, as doubles); 12: clock stamps of the
+ *          phases of the last projected eigensolve (12, as doubles)
+ *   dst    host buffer of `count` doubles; count must not exceed the size
+ *          of the buffer named by `which` (m = 4*kint)                    */
+plhr_status plhr_debug_read(plhr_ctx ctx, int32_t which, double* dst, size_t count);
+
+/* Release the context and any workspace it allocated. NULL is ignored.   */
+void plhr_destroy(plhr_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLHR_H */

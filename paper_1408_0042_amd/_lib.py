@@ -1,0 +1,115 @@
+"""ctypes binding of libplhr.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only mirrors the
+C structs of include/plhr.h and loads the shared object.  Loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplhr.so")
+
+# status codes
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOT_HPD, ERR_BREAKDOWN, ERR_NOT_CONVERGED, ERR_STATE = range(8)
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_HPD",
+                5: "ERR_BREAKDOWN", 6: "ERR_NOT_CONVERGED", 7: "ERR_STATE"}
+
+OP_IDENTITY, OP_FD5_2D, OP_FD7_3D = 0, 1, 2
+F64 = 0
+PREC_IDENTITY, PREC_MG_VCYCLE = 0, 1
+PRECISION_FP64 = 0
+
+
+class OpDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("reserved0", C.c_int32), ("h", C.c_double),
+                ("scale", C.c_double), ("potential", C.c_void_p)]
+
+
+class PrecDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("levels", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("omega", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("k_extra", C.c_int32),
+                ("precision", C.c_int32), ("lock", C.c_int32), ("check_every", C.c_int32),
+                ("reserved0", C.c_int32), ("drop_tol", C.c_double)]
+
+
+class IterInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_active", C.c_int32),
+                ("status", C.c_int32), ("max_rel_res", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int32 * 8), ("total_ms", C.c_double * 8),
+                ("bytes", C.c_double * 8), ("flops", C.c_double * 8),
+                ("truncated", C.c_int32), ("reserved0", C.c_int32)]
+
+
+KCAT_NAMES = ["stencil", "vcycle_smooth", "vcycle_transfer", "gram", "rowmul", "small", "vec"]
+
+
+class PLHRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libplhr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libplhr.so not found at {LIB_PATH}; run "
+                           "`python -m paper_1408_0042_amd.build` first")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "plhr_version": (C.c_char_p, []),
+        "plhr_last_error": (C.c_char_p, []),
+        "plhr_options_default": (C.c_int, [C.POINTER(Options)]),
+        "plhr_workspace_size": (C.c_int, [C.POINTER(OpDesc), C.POINTER(OpDesc), C.POINTER(PrecDesc),
+                                          C.c_double, C.c_int32, C.POINTER(Options),
+                                          C.POINTER(C.c_size_t)]),
+        "plhr_create": (C.c_int, [C.POINTER(OpDesc), C.POINTER(OpDesc), C.POINTER(PrecDesc),
+                                  C.c_double, C.c_int32, C.POINTER(Options), P, P, C.c_size_t,
+                                  C.POINTER(P)]),
+        "plhr_start": (C.c_int, [P, P]),
+        "plhr_iterate": (C.c_int, [P, C.c_int32, C.POINTER(IterInfo)]),
+        "plhr_finish": (C.c_int, [P, P, P, C.POINTER(C.c_double)]),
+        "plhr_solve": (C.c_int, [P, P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "plhr_eigvals_backward": (C.c_int, [P, P, P, C.c_int32]),
+        "plhr_apply": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
+        "plhr_get_state": (C.c_int, [P, C.POINTER(C.c_double), P]),
+        "plhr_debug_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
+        "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),
+        "plhr_profile_stop": (C.c_int, [P, C.POINTER(Profile)]),
+        "plhr_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> None:
+    if code != OK:
+        msg = load().plhr_last_error().decode(errors="replace")
+        raise PLHRError(code, msg)
+
+
+def default_options() -> Options:
+    o = Options()
+    check(load().plhr_options_default(C.byref(o)))
+    return o

@@ -1,0 +1,793 @@
+// C ABI of libplhr and the host driver of the block PLHR iteration
+// (Algorithm 3 of the paper for real symmetric A, B = I and an SPD T).
+//
+// Device data layout (point-major, n rows):
+//   Z, QZ, TQZ  n x m, m = 4 kint columns in slots V | W | S | P
+//               Z = basis, QZ = (A - sigma B) Z, TQZ = T (A - sigma B) Z;
+//               keeping the three blocks lets one iteration use two block
+//               operator products and four block preconditioner
+//               applications (Section 4, storage/cost paragraph).
+//   R           n x 2 kint  preconditioner input staging
+//   Vfin, QVfin n x k       returned Ritz vectors and their products
+// All small matrices live in a separate region of the same workspace.
+//
+// One iteration, all on the caller's stream, no host round trip:
+//   R = QV - V(Lam - sigma), column norms       (k_resid_prep)
+//   relative residuals, soft locking, stop flag   (k_conv_check)
+//   W = T R                                        (V-cycle)
+//   QW = (A - sigma)W; [S | TQW] = T[QW - W(Lam - sigma) | QW]
+//   QS = (A - sigma)S; TQS = T QS
+//   G = Z^T Z, Cholesky with dropping, Z,QZ,TQZ <- (.)M   (B-orthonormalise)
+//   [G_L | G_R] = TQZ^T [QZ | Z]                    (eq. 3.5)
+//   T-harmonic eigensolve and real basis Y'         (Algorithm 3 steps 6-9)
+//   V = Zhat Y', P = [What Shat Phat] Y'_{WSP}, same for QZ, TQZ
+//   Rayleigh quotients, eq. (4.1) for pairs
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace plhr {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Per-launch event profiling (see KCat).  The driver points g_prof at the
+// active context's recorder for the duration of each entry point.
+struct Prof {
+  int cat = -2;  // -1: all categories; -2: off
+  std::vector<hipEvent_t> ev;
+  std::vector<int> evcat;
+  size_t used = 0;
+  double bytes[KC_COUNT] = {0}, flops[KC_COUNT] = {0};
+  long launches[KC_COUNT] = {0};
+  bool skip_end = false;
+};
+static thread_local Prof* g_prof = nullptr;
+
+void prof_begin(int cat, double bytes, double flops, hipStream_t s) {
+  Prof* p = g_prof;
+  if (!p || (p->cat != -1 && p->cat != cat)) return;
+  if (p->used + 2 > p->ev.size()) {
+    p->skip_end = true;
+    return;
+  }
+  p->skip_end = false;
+  (void)hipEventRecord(p->ev[p->used], s);
+  p->evcat[p->used / 2] = cat;
+  p->bytes[cat] += bytes;
+  p->flops[cat] += flops;
+  p->launches[cat] += 1;
+}
+
+void prof_end(int cat, hipStream_t s) {
+  Prof* p = g_prof;
+  if (!p || (p->cat != -1 && p->cat != cat)) return;
+  if (p->skip_end) return;
+  (void)hipEventRecord(p->ev[p->used + 1], s);
+  p->used += 2;
+}
+
+}  // namespace plhr
+
+using namespace plhr;
+
+struct plhr_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Grid grid;
+  const double* pot = nullptr;
+  int prec_kind = PLHR_PREC_IDENTITY;
+  MG mg;
+  double sigma = 0.0;
+  int k = 0, kint = 0, m = 0;
+  plhr_options opt{};
+  double normA1 = 1.0, normB1 = 1.0;
+  size_t n = 0;
+  bool own_ws = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double *Z = nullptr, *QZ = nullptr, *TQZ = nullptr, *R = nullptr;
+  double *Vfin = nullptr, *QVfin = nullptr;
+  double *part = nullptr, *gpart = nullptr, *HM = nullptr;
+  int gram_nblk = 1;
+  SmallBufs sb{};
+  SmallParams sp{};
+  DevStatus* st = nullptr;
+  DevStatus* st_host = nullptr;
+  bool started = false, finished = false;
+  Prof prof;
+};
+
+namespace {
+// Points the launch profiler at this context while an entry point runs.
+struct ProfScope {
+  explicit ProfScope(plhr_ctx_s* c) { g_prof = (c && c->prof.cat != -2) ? &c->prof : nullptr; }
+  ~ProfScope() { g_prof = nullptr; }
+};
+}  // namespace
+
+namespace {
+
+struct Layout {
+  size_t bytes = 0;
+  size_t take(size_t b) {
+    size_t off = bytes;
+    bytes += al(b);
+    return off;
+  }
+};
+
+plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
+                     double sigma, int32_t k, const plhr_options* opt) {
+  if (!A) {
+    set_error("A descriptor is NULL");
+    return PLHR_ERR_ARG;
+  }
+  if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D) {
+    set_error("A: only PLHR_OP_FD5_2D and PLHR_OP_FD7_3D are supported");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (A->dtype != PLHR_F64) {
+    set_error("A: only PLHR_F64 is supported");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (A->nx < 1 || A->ny < 1 || A->nz < 1 || (A->kind == PLHR_OP_FD5_2D && A->nz != 1)) {
+    set_error("A: grid dimensions must be >= 1 (nz = 1 in 2-D)");
+    return PLHR_ERR_ARG;
+  }
+  if (!(A->h > 0.0) || !std::isfinite(A->h) || !(A->scale > 0.0) || !std::isfinite(A->scale)) {
+    set_error("A: h and scale must be positive and finite");
+    return PLHR_ERR_ARG;
+  }
+  if (B && B->kind != PLHR_OP_IDENTITY) {
+    set_error("B: only the identity is supported by this build");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (!std::isfinite(sigma)) {
+    set_error("sigma must be finite");
+    return PLHR_ERR_ARG;
+  }
+  const int kextra = opt ? opt->k_extra : 1;
+  if (k < 1 || kextra < 0) {
+    set_error("k must be >= 1 and k_extra >= 0");
+    return PLHR_ERR_ARG;
+  }
+  const size_t n = (size_t)A->nx * A->ny * A->nz;
+  const int kint = k + kextra;
+  if ((size_t)4 * kint > n) {
+    set_error("4*(k + k_extra) must not exceed n");
+    return PLHR_ERR_ARG;
+  }
+  if (4 * kint > 100) {
+    set_error("4*(k + k_extra) > 100 exceeds the on-chip projected-problem limit");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (opt) {
+    if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
+        !(opt->drop_tol > 0.0) || opt->precision != PLHR_PREC_FP64) {
+      set_error("invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, FP64)");
+      return PLHR_ERR_ARG;
+    }
+  }
+  if (T && T->kind != PLHR_PREC_IDENTITY) {
+    if (T->kind != PLHR_PREC_MG_VCYCLE) {
+      set_error("T: unknown preconditioner kind");
+      return PLHR_ERR_ARG;
+    }
+    if (T->levels < 1 || T->nu_pre < 1 || T->nu_pre != T->nu_post || !(T->omega > 0.0) ||
+        T->omega > 1.0) {
+      set_error("T: need levels >= 1, nu_pre == nu_post >= 1, 0 < omega <= 1");
+      return PLHR_ERR_ARG;
+    }
+    const int f = 1 << (T->levels - 1);
+    const int dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
+    if (A->nx % f || A->ny % f || (dim == 3 && A->nz % f)) {
+      set_error("T: every grid dimension must be divisible by 2^(levels-1)");
+      return PLHR_ERR_ARG;
+    }
+    size_t nc = (size_t)(A->nx / f) * (A->ny / f) * (dim == 3 ? A->nz / f : 1);
+    if (nc > 1024) {
+      set_error("T: coarsest level has more than 1024 points; add levels");
+      return PLHR_ERR_ARG;
+    }
+  }
+  return PLHR_OK;
+}
+
+Grid make_grid(const plhr_op_desc* A) {
+  Grid g;
+  g.nx = A->nx;
+  g.ny = A->ny;
+  g.nz = A->nz;
+  g.dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
+  g.h = A->h;
+  g.scale = A->scale;
+  return g;
+}
+
+Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s* c) {
+  Layout L;
+  const size_t n = g.n();
+  const int m = 4 * kint;
+  const int gnb = gram_blocks(n);
+  size_t oZ = L.take(n * m * 8), oQZ = L.take(n * m * 8), oTQZ = L.take(n * m * 8);
+  size_t oR = L.take(n * 2 * kint * 8);
+  size_t oVf = L.take(n * k * 8), oQVf = L.take(n * k * 8);
+  size_t opart = L.take((size_t)512 * 2 * kint * 8);
+  size_t ogp = L.take((size_t)gnb * m * 2 * m * 8);
+  size_t oHM = L.take((size_t)kint * 2 * kint * 8);
+  size_t oG = L.take((size_t)m * m * 8), oM = L.take((size_t)m * m * 8);
+  size_t oGLR = L.take((size_t)m * 2 * m * 8), oY = L.take((size_t)m * kint * 8);
+  size_t olam = L.take(kint * 8), orel = L.take(kint * 8), oxi = L.take(2 * m * 8);
+  size_t okeep = L.take(m * 4), oact = L.take(kint * 4), okind = L.take(kint * 4),
+         opair = L.take(kint * 4);
+  size_t ofc = L.take((size_t)kint * kint * 8), oft = L.take(kint * 8), ovbv = L.take(kint * 8);
+  size_t ost = L.take(sizeof(DevStatus));
+  size_t omg = L.bytes;
+  if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint);
+  if (c) {
+    char* b = c->ws;
+    c->Z = (double*)(b + oZ);
+    c->QZ = (double*)(b + oQZ);
+    c->TQZ = (double*)(b + oTQZ);
+    c->R = (double*)(b + oR);
+    c->Vfin = (double*)(b + oVf);
+    c->QVfin = (double*)(b + oQVf);
+    c->part = (double*)(b + opart);
+    c->gpart = (double*)(b + ogp);
+    c->gram_nblk = gnb;
+    c->HM = (double*)(b + oHM);
+    c->sb.G = (double*)(b + oG);
+    c->sb.M = (double*)(b + oM);
+    c->sb.GLR = (double*)(b + oGLR);
+    c->sb.Y = (double*)(b + oY);
+    c->sb.lam = (double*)(b + olam);
+    c->sb.relres = (double*)(b + orel);
+    c->sb.xi = (double*)(b + oxi);
+    c->sb.keep = (int*)(b + okeep);
+    c->sb.active = (int*)(b + oact);
+    c->sb.kinds = (int*)(b + okind);
+    c->sb.pair = (int*)(b + opair);
+    c->sb.final_C = (double*)(b + ofc);
+    c->sb.final_theta = (double*)(b + oft);
+    c->sb.vbv = (double*)(b + ovbv);
+    c->sb.scratch = nullptr;
+    c->st = (DevStatus*)(b + ost);
+    (void)omg;
+  }
+  return L;
+}
+
+double exact_norm1(const Grid& g, const std::vector<double>& pot) {
+  // max over points of |diag + pot| + (#interior neighbours) * scale / h^2
+  const double d = g.diag(), o = -g.off();
+  double best = 0.0;
+  for (int l = 0; l < g.nz; ++l)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        int nb = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1);
+        if (g.dim == 3) nb += (l > 0) + (l < g.nz - 1);
+        const size_t p = (size_t)i + (size_t)g.nx * (j + (size_t)g.ny * l);
+        const double v = fabs(d + (pot.empty() ? 0.0 : pot[p])) + nb * o;
+        if (v > best) best = v;
+      }
+  return best;
+}
+
+void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
+             Blk outc, int ncols, double shift, const DevStatus* st) {
+  launch_fd_apply(c->grid, c->pot, shift, X, ldx, out, outr, colshift, c->sigma, outc, ncols, st,
+                  c->stream);
+}
+
+// T applied to ncols columns of R (ld ldr); output split at `split`.
+void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split, int ncols,
+             const DevStatus* st) {
+  if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
+    mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, st, c->stream);
+  } else {
+    if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream);
+    if (split < ncols) launch_copy(c->n, Rin + split, ldr, o1.ptr, o1.ld, ncols - split, c->stream);
+  }
+}
+
+void enqueue_iteration(plhr_ctx_s* c) {
+  const int kint = c->kint, m = c->m;
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  DevStatus* st = c->st;
+  double *Z = c->Z, *QZ = c->QZ, *TQZ = c->TQZ, *R = c->R;
+  const Blk none{nullptr, 0};
+  // residuals of the current block, convergence and locking
+  int nb = launch_resid_prep(n, Z, QZ, m, c->sb.lam, c->sigma, R, kint, kint, c->part, st, s);
+  launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
+  // W = T (A V - B V Lam)
+  precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st);
+  // QW = (A - sigma) W;  R = [QW - W (Lam - sigma) | QW]
+  stencil(c, Z + kint, m, Blk{QZ + kint, m}, Blk{R, 2 * kint}, c->sb.lam, Blk{R + kint, 2 * kint},
+          kint, c->sigma, st);
+  // S = T (A W - B W Lam), TQW = T (A - sigma) W
+  precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, Blk{TQZ + kint, m}, kint, 2 * kint, st);
+  // QS = (A - sigma) S ; TQS = T QS
+  stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st);
+  precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
+  // B-orthonormalise Z = [V W S P] (Cholesky-QR in slot order)
+  launch_gram(n, Z, m, m, Z, m, m, nullptr, 0, m, c->gpart, c->gram_nblk, c->sb.G, st, s);
+  launch_ortho_small(c->sp, c->sb, st, s);
+  double* arrs[3] = {Z, QZ, TQZ};
+  launch_transform(n, arrs, 3, m, m, c->sb.M, st, s);
+  // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | Zhat]
+  launch_gram(n, TQZ, m, m, QZ, m, m, Z, m, 2 * m, c->gpart, c->gram_nblk, c->sb.GLR, st, s);
+  launch_tharm_small(c->sp, c->sb, st, s);
+  // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
+  nb = launch_update(n, arrs, 3, m, m, kint, c->sb.Y, kint, 3 * kint, c->part, st, s);
+  launch_rq_small(c->sp, c->part, nb, c->sb, st, s);
+}
+
+plhr_status read_status(plhr_ctx_s* c) {
+  PLHR_HIP_CHECK(hipMemcpyAsync(c->st_host, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                                c->stream));
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return PLHR_OK;
+}
+
+plhr_status device_error(plhr_ctx_s* c) {
+  const int e = c->st_host->error;
+  if (e == 0) return PLHR_OK;
+  static const char* why[] = {"unspecified",
+                              "the start block is rank deficient",
+                              "the projected eigensolver did not converge",
+                              "a wanted residual is not finite",
+                              "V^T B V of the final Rayleigh-Ritz step is not positive definite",
+                              "every column of V became linearly dependent"};
+  const int r = c->st_host->reason;
+  set_error(std::string("device check failed: ") + why[(r >= 0 && r <= 5) ? r : 0] +
+            " (iteration " + std::to_string(c->st_host->iter) + ")");
+  return (plhr_status)e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* plhr_version(void) { return "plhr-mi355x 0.1 (gfx950, FP64)"; }
+
+const char* plhr_last_error(void) { return g_last_error.c_str(); }
+
+plhr_status plhr_options_default(plhr_options* opt) {
+  if (!opt) {
+    set_error("opt is NULL");
+    return PLHR_ERR_ARG;
+  }
+  std::memset(opt, 0, sizeof(*opt));
+  opt->tol = 1e-8;
+  opt->max_iters = 10000;
+  opt->k_extra = 1;
+  opt->precision = PLHR_PREC_FP64;
+  opt->lock = 1;
+  opt->check_every = 1;
+  opt->drop_tol = 1e-12;
+  return PLHR_OK;
+}
+
+plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
+                                const plhr_prec_desc* T, double sigma, int32_t k,
+                                const plhr_options* opt, size_t* ws_bytes) {
+  plhr_options o;
+  plhr_options_default(&o);
+  if (opt) o = *opt;
+  plhr_status s = validate(A, B, T, sigma, k, &o);
+  if (s != PLHR_OK) return s;
+  if (!ws_bytes) {
+    set_error("ws_bytes is NULL");
+    return PLHR_ERR_ARG;
+  }
+  const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
+  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, nullptr);
+  *ws_bytes = L.bytes;
+  return PLHR_OK;
+}
+
+plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
+                        double sigma, int32_t k, const plhr_options* opt, void* stream,
+                        void* workspace, size_t ws_bytes, plhr_ctx* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return PLHR_ERR_ARG;
+  }
+  *out = nullptr;
+  plhr_options o;
+  plhr_options_default(&o);
+  if (opt) o = *opt;
+  plhr_status s = validate(A, B, T, sigma, k, &o);
+  if (s != PLHR_OK) return s;
+  plhr_ctx_s* c = new plhr_ctx_s();
+  PLHR_HIP_CHECK(hipGetDevice(&c->device));
+  c->stream = (hipStream_t)stream;
+  c->grid = make_grid(A);
+  c->pot = A->potential;
+  c->sigma = sigma;
+  c->k = k;
+  c->kint = k + o.k_extra;
+  c->m = 4 * c->kint;
+  c->opt = o;
+  c->n = c->grid.n();
+  const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
+  c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
+  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, nullptr);
+  if (workspace) {
+    if (ws_bytes < L.bytes) {
+      set_error("workspace smaller than plhr_workspace_size");
+      delete c;
+      return PLHR_ERR_ARG;
+    }
+    if (((uintptr_t)workspace) & 255) {
+      set_error("workspace must be 256-byte aligned");
+      delete c;
+      return PLHR_ERR_ARG;
+    }
+    c->ws = (char*)workspace;
+    c->own_ws = false;
+  } else {
+    hipError_t e = hipMalloc((void**)&c->ws, L.bytes);
+    if (e != hipSuccess) {
+      set_error(std::string("workspace allocation failed: ") + hipGetErrorString(e));
+      delete c;
+      return PLHR_ERR_HIP;
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = L.bytes;
+  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, c);
+  // norms for the relative residual
+  std::vector<double> pot;
+  if (c->pot) {
+    pot.resize(c->n);
+    hipError_t e = hipMemcpy(pot.data(), c->pot, c->n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_error(std::string("reading the potential failed: ") + hipGetErrorString(e));
+      plhr_destroy(c);
+      return PLHR_ERR_HIP;
+    }
+  }
+  c->normA1 = exact_norm1(c->grid, pot);
+  c->normB1 = 1.0;
+  if (mgp) {
+    char* wp = c->ws + L.bytes - mg_workspace_bytes(c->grid, T->levels, 2 * c->kint);
+    s = mg_setup(c->mg, c->grid, T->levels, T->nu_pre, T->nu_post, T->omega, 2 * c->kint, wp,
+                 c->stream);
+    if (s != PLHR_OK) {
+      plhr_destroy(c);
+      return s;
+    }
+  }
+  c->sp.kint = c->kint;
+  c->sp.k = k;
+  c->sp.m = c->m;
+  c->sp.sigma = sigma;
+  c->sp.tol = o.tol;
+  c->sp.normA1 = c->normA1;
+  c->sp.normB1 = c->normB1;
+  c->sp.drop_tol = o.drop_tol;
+  c->sp.lock = o.lock;
+  hipError_t e = small_set_attributes(c->m, c->kint);
+  if (e != hipSuccess) {
+    set_error(std::string("LDS attribute: ") + hipGetErrorString(e));
+    plhr_destroy(c);
+    return PLHR_ERR_HIP;
+  }
+  e = hipHostMalloc((void**)&c->st_host, sizeof(DevStatus), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error(std::string("pinned status allocation failed: ") + hipGetErrorString(e));
+    plhr_destroy(c);
+    return PLHR_ERR_HIP;
+  }
+  std::memset(c->st_host, 0, sizeof(DevStatus));
+  *out = c;
+  return PLHR_OK;
+}
+
+plhr_status plhr_start(plhr_ctx c, const double* V0) {
+  ProfScope prof_scope(c);
+  if (!c || !V0) {
+    set_error("plhr_start: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  const int kint = c->kint, m = c->m;
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  // clear the basis blocks: unused slots must hold finite values
+  PLHR_HIP_CHECK(hipMemsetAsync(c->Z, 0, n * m * sizeof(double), s));
+  PLHR_HIP_CHECK(hipMemsetAsync(c->QZ, 0, n * m * sizeof(double), s));
+  PLHR_HIP_CHECK(hipMemsetAsync(c->TQZ, 0, n * m * sizeof(double), s));
+  PLHR_HIP_CHECK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
+  launch_copy(n, V0, kint, c->Z, m, kint, s);
+  const Blk none{nullptr, 0};
+  stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr);
+  precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
+  const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s);
+  launch_init_lam(c->sp, c->part, nb, c->sb, c->st, s);
+  launch_gram(n, c->Z, m, kint, c->Z, m, kint, nullptr, 0, kint, c->gpart, c->gram_nblk, c->sb.G,
+              nullptr, s);
+  launch_start_check(c->sp, c->sb, c->st, s);
+  PLHR_HIP_CHECK(hipGetLastError());
+  c->started = true;
+  c->finished = false;
+  plhr_status st = read_status(c);
+  if (st != PLHR_OK) return st;
+  return device_error(c);
+}
+
+plhr_status plhr_iterate(plhr_ctx c, int32_t n_steps, plhr_iter_info* info) {
+  ProfScope prof_scope(c);
+  if (!c) {
+    set_error("plhr_iterate: NULL context");
+    return PLHR_ERR_ARG;
+  }
+  if (!c->started) {
+    set_error("plhr_iterate before plhr_start");
+    return PLHR_ERR_STATE;
+  }
+  if (n_steps < 0) {
+    set_error("n_steps must be >= 0");
+    return PLHR_ERR_ARG;
+  }
+  int done_steps = 0;
+  while (done_steps < n_steps) {
+    const int chunk = std::min(c->opt.check_every, n_steps - done_steps);
+    for (int i = 0; i < chunk; ++i) enqueue_iteration(c);
+    PLHR_HIP_CHECK(hipGetLastError());
+    done_steps += chunk;
+    plhr_status s = read_status(c);
+    if (s != PLHR_OK) return s;
+    if (c->st_host->error || c->st_host->done) break;
+  }
+  if (info) {
+    info->iters = c->st_host->iter;
+    info->converged = c->st_host->done;
+    info->n_active = c->st_host->n_active;
+    info->status = c->st_host->error;
+    info->max_rel_res = c->st_host->max_rel_res;
+  }
+  return device_error(c);
+}
+
+plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res) {
+  ProfScope prof_scope(c);
+  if (!c) {
+    set_error("plhr_finish: NULL context");
+    return PLHR_ERR_ARG;
+  }
+  if (!c->started) {
+    set_error("plhr_finish before plhr_start");
+    return PLHR_ERR_STATE;
+  }
+  const int kint = c->kint, k = c->k, m = c->m;
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  // H = V^T (A - sigma) V, M = V^T V
+  const int gnb = c->gram_nblk;
+  launch_gram(n, c->Z, m, kint, c->QZ, m, kint, c->Z, m, 2 * kint, c->gpart, gnb, c->HM, nullptr,
+              s);
+  launch_final_rr(c->sp, c->HM, c->sb, c->st, s);
+  launch_small_gemm(n, c->Z, m, kint, c->sb.final_C, k, c->Vfin, k, s);
+  const Blk none{nullptr, 0};
+  stencil(c, c->Vfin, k, Blk{c->QVfin, k}, none, nullptr, none, k, c->sigma, nullptr);
+  const int nb = launch_coldots(n, c->Vfin, k, c->QVfin, k, k, c->sb.final_theta, c->sigma,
+                                c->part, s);
+  SmallParams fp = c->sp;
+  launch_final_res(fp, c->part, nb, c->sb, s);
+  if (eigvals)
+    PLHR_HIP_CHECK(hipMemcpyAsync(eigvals, c->sb.final_theta, k * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+  if (V)
+    PLHR_HIP_CHECK(hipMemcpyAsync(V, c->Vfin, n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> rr(k);
+  PLHR_HIP_CHECK(hipMemcpyAsync(rr.data(), c->sb.relres, k * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+  PLHR_HIP_CHECK(hipGetLastError());
+  plhr_status st = read_status(c);
+  if (st != PLHR_OK) return st;
+  if (rel_res) std::memcpy(rel_res, rr.data(), k * sizeof(double));
+  c->finished = true;
+  return device_error(c);
+}
+
+plhr_status plhr_solve(plhr_ctx c, const double* V0, double* eigvals, double* V, double* rel_res,
+                       int32_t* iters) {
+  plhr_status s = plhr_start(c, V0);
+  if (s != PLHR_OK) return s;
+  plhr_iter_info info{};
+  s = plhr_iterate(c, c->opt.max_iters, &info);
+  if (s != PLHR_OK) return s;
+  if (iters) *iters = info.iters;
+  s = plhr_finish(c, eigvals, V, rel_res);
+  if (s != PLHR_OK) return s;
+  if (!info.converged) {
+    set_error("max_iters reached before convergence");
+    return PLHR_ERR_NOT_CONVERGED;
+  }
+  return PLHR_OK;
+}
+
+plhr_status plhr_eigvals_backward(plhr_ctx c, const double* dL_dlambda, double* dL_dpot,
+                                  int32_t accumulate) {
+  if (!c || !dL_dlambda || !dL_dpot) {
+    set_error("plhr_eigvals_backward: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (!c->finished) {
+    set_error("plhr_eigvals_backward before plhr_finish");
+    return PLHR_ERR_STATE;
+  }
+  launch_hf(c->n, c->Vfin, c->k, c->k, dL_dlambda, c->sb.vbv, dL_dpot, accumulate, c->stream);
+  PLHR_HIP_CHECK(hipGetLastError());
+  return PLHR_OK;
+}
+
+plhr_status plhr_apply(plhr_ctx c, int32_t which, const double* X, double* Y, int32_t ncols) {
+  ProfScope prof_scope(c);
+  if (!c || !X || !Y) {
+    set_error("plhr_apply: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (ncols < 1 || ncols > 2 * c->kint) {
+    set_error("plhr_apply: need 1 <= ncols <= 2*(k + k_extra)");
+    return PLHR_ERR_ARG;
+  }
+  const Blk none{nullptr, 0};
+  if (which == 0 || which == 1) {
+    stencil(c, X, ncols, Blk{Y, ncols}, none, nullptr, none, ncols, which == 1 ? c->sigma : 0.0,
+            nullptr);
+  } else if (which == 2) {
+    precond(c, X, ncols, Blk{Y, ncols}, none, ncols, ncols, nullptr);
+  } else {
+    set_error("plhr_apply: which must be 0, 1 or 2");
+    return PLHR_ERR_ARG;
+  }
+  PLHR_HIP_CHECK(hipGetLastError());
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return PLHR_OK;
+}
+
+plhr_status plhr_get_state(plhr_ctx c, double* lam, double* V) {
+  if (!c || !lam) {
+    set_error("plhr_get_state: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (!c->started) {
+    set_error("plhr_get_state before plhr_start");
+    return PLHR_ERR_STATE;
+  }
+  PLHR_HIP_CHECK(hipMemcpyAsync(lam, c->sb.lam, c->kint * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  if (V) launch_copy(c->n, c->Z, c->m, V, c->kint, c->kint, c->stream);
+  PLHR_HIP_CHECK(hipGetLastError());
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return PLHR_OK;
+}
+
+plhr_status plhr_debug_read(plhr_ctx c, int32_t which, double* dst, size_t count) {
+  if (!c || !dst) {
+    set_error("plhr_debug_read: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  const size_t m = c->m, kint = c->kint, n = c->n;
+  const double* src = nullptr;
+  size_t cap = 0;
+  std::vector<double> tmp;
+  switch (which) {
+    case 0: src = c->sb.G; cap = m * m; break;
+    case 1: src = c->sb.M; cap = m * m; break;
+    case 2: src = c->sb.GLR; cap = 2 * m * m; break;
+    case 3: src = c->sb.Y; cap = m * kint; break;
+    case 4: src = c->sb.xi; cap = 2 * m; break;
+    case 5: src = c->sb.lam; cap = kint; break;
+    case 6: src = c->sb.relres; cap = kint; break;
+    case 7: src = c->Z; cap = n * m; break;
+    case 8: src = c->QZ; cap = n * m; break;
+    case 9: src = c->TQZ; cap = n * m; break;
+    case 10: case 11: break;
+    case 12: {
+      PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+      DevStatus hs;
+      PLHR_HIP_CHECK(hipMemcpy(&hs, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost));
+      if (count > 12) {
+        set_error("plhr_debug_read: count exceeds the buffer");
+        return PLHR_ERR_ARG;
+      }
+      for (size_t i = 0; i < count; ++i) dst[i] = (double)hs.tphase[i];
+      return PLHR_OK;
+    }
+    default:
+      set_error("plhr_debug_read: unknown buffer");
+      return PLHR_ERR_ARG;
+  }
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  if (which == 10 || which == 11) {
+    const size_t cnt = (which == 10) ? m : 2 * kint;
+    if (count > cnt) {
+      set_error("plhr_debug_read: count exceeds the buffer");
+      return PLHR_ERR_ARG;
+    }
+    std::vector<int> iv(cnt);
+    if (which == 10) {
+      PLHR_HIP_CHECK(hipMemcpy(iv.data(), c->sb.keep, m * sizeof(int), hipMemcpyDeviceToHost));
+    } else {
+      PLHR_HIP_CHECK(hipMemcpy(iv.data(), c->sb.kinds, kint * sizeof(int), hipMemcpyDeviceToHost));
+      PLHR_HIP_CHECK(hipMemcpy(iv.data() + kint, c->sb.pair, kint * sizeof(int),
+                               hipMemcpyDeviceToHost));
+    }
+    for (size_t i = 0; i < count; ++i) dst[i] = iv[i];
+    return PLHR_OK;
+  }
+  if (count > cap) {
+    set_error("plhr_debug_read: count exceeds the buffer");
+    return PLHR_ERR_ARG;
+  }
+  PLHR_HIP_CHECK(hipMemcpy(dst, src, count * sizeof(double), hipMemcpyDeviceToHost));
+  return PLHR_OK;
+}
+
+plhr_status plhr_profile_start(plhr_ctx c, int32_t category, int32_t max_launches) {
+  if (!c || category < -1 || category >= KC_COUNT || max_launches < 1) {
+    set_error("plhr_profile_start: bad argument");
+    return PLHR_ERR_ARG;
+  }
+  Prof& p = c->prof;
+  const size_t need = 2 * (size_t)max_launches;
+  while (p.ev.size() < need) {
+    hipEvent_t e;
+    PLHR_HIP_CHECK(hipEventCreate(&e));
+    p.ev.push_back(e);
+  }
+  p.evcat.assign(p.ev.size() / 2 + 1, 0);
+  p.used = 0;
+  for (int i = 0; i < KC_COUNT; ++i) p.bytes[i] = p.flops[i] = 0.0, p.launches[i] = 0;
+  p.cat = category;
+  return PLHR_OK;
+}
+
+plhr_status plhr_profile_stop(plhr_ctx c, plhr_profile* out) {
+  if (!c || !out) {
+    set_error("plhr_profile_stop: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  Prof& p = c->prof;
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (size_t i = 0; i + 1 < p.used + 1 && i < p.used; i += 2) {
+    float ms = 0.f;
+    PLHR_HIP_CHECK(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+    out->total_ms[p.evcat[i / 2]] += ms;
+  }
+  for (int i = 0; i < KC_COUNT; ++i) {
+    out->launches[i] = (int32_t)p.launches[i];
+    out->bytes[i] = p.bytes[i];
+    out->flops[i] = p.flops[i];
+  }
+  out->truncated = (p.used / 2 < (size_t)[&] {
+    long s = 0;
+    for (int i = 0; i < KC_COUNT; ++i) s += p.launches[i];
+    return s;
+  }()) ? 1 : 0;
+  p.cat = -2;
+  return PLHR_OK;
+}
+
+void plhr_destroy(plhr_ctx c) {
+  if (!c) return;
+  for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+}
+
+}  // extern "C"

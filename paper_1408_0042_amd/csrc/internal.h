@@ -1,0 +1,222 @@
+// Internal declarations shared by the HIP translation units of libplhr.
+// Kernels live next to their host-side launchers; the driver (api.hip)
+// only calls launchers, so no relocatable device code is needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+#include <vector>
+
+#include "../../include/plhr.h"
+
+namespace plhr {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+
+#define PLHR_HIP_CHECK(expr)                                                    \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess) {                                                     \
+      ::plhr::set_error(std::string("HIP error in ") + #expr + ": " +          \
+                        hipGetErrorString(_e));                                 \
+      return PLHR_ERR_HIP;                                                      \
+    }                                                                           \
+  } while (0)
+
+// ------------------------------------------------------------ device status
+// One word block in device memory; every iteration kernel reads `done` and
+// `error` first and returns at once when either is set, so that iterations
+// enqueued past convergence leave the state untouched.
+struct DevStatus {
+  int done;          // the k wanted pairs met tol
+  int error;         // nonzero plhr_status raised on the device
+  int iter;          // iterations completed since start
+  int n_active;      // columns generating W/S/P in the current iteration
+  int m_kept;        // columns kept by the last B-orthonormalisation
+  int have_p;        // the P block holds a conjugate direction
+  int n_dropped;     // columns dropped by the last orthonormalisation
+  int reason;        // which check raised `error` (kReason*)
+  double max_rel_res;  // largest relative residual among the k wanted
+  double reserved[3];
+  long long tphase[12];  // clock stamps of the projected-solver phases
+};
+
+enum : int {
+  kReasonNone = 0,
+  kReasonStartRank = 1,   // the start block is rank deficient
+  kReasonQR = 2,          // the projected eigensolver did not converge
+  kReasonNonFinite = 3,   // a wanted residual is not finite
+  kReasonFinalGram = 4,   // V^T B V of the final Rayleigh-Ritz is not HPD
+  kReasonVVanished = 5    // every column of V became dependent
+};
+
+// ---------------------------------------------------- launch profiling
+// Kernel categories for per-launch HIP-event timing.  When a context turns
+// profiling on for one category, every launch of that category is
+// bracketed by two events on its stream and its algorithmic bytes and
+// flops (what the operation must read, write and compute, not what the
+// hardware moves) are accumulated.
+enum KCat : int {
+  KC_STENCIL = 0,   // operator block products
+  KC_SMOOTH = 1,    // V-cycle Jacobi sweeps
+  KC_TRANSFER = 2,  // V-cycle residual, restriction, prolongation, coarse solve
+  KC_GRAM = 3,      // Gram products and their reduction
+  KC_ROWMUL = 4,    // orthonormalising transform and Ritz-vector update
+  KC_SMALL = 5,     // single-workgroup projected-problem kernels
+  KC_VEC = 6,       // residual formation, column reductions, copies
+  KC_COUNT = 7
+};
+void prof_begin(int cat, double bytes, double flops, hipStream_t s);
+void prof_end(int cat, hipStream_t s);
+
+// --------------------------------------------------------------- geometry
+struct Grid {
+  int nx = 1, ny = 1, nz = 1;
+  int dim = 2;
+  double h = 1.0;
+  double scale = 1.0;
+  size_t n() const { return (size_t)nx * ny * nz; }
+  double diag() const { return scale * 2.0 * dim / (h * h); }
+  double off() const { return -scale / (h * h); }
+};
+
+// A block descriptor: element (p, c) lives at ptr[p * ld + c].
+struct Blk {
+  double* ptr;
+  int ld;
+};
+
+// ------------------------------------------------------------- launchers
+// Stencil: out = scale*(-Lap)X + pot.*X - shift*X  (shift = sigma for
+// (A - sigma I)X, 0 for AX).  Optional extra outputs:
+//   out_r (if ptr != null): out_r[:, c] = out[:, c] - X[:, c] * (colshift[c] - csub)
+//   out_c (if ptr != null): out_c[:, c] = out[:, c]
+void launch_fd_apply(const Grid& g, const double* pot, double shift, const double* X, int ldx,
+                     Blk out, Blk out_r, const double* colshift, double csub, Blk out_c,
+                     int ncols, const DevStatus* st, hipStream_t s);
+
+// Multigrid V-cycle (k_mg.hip).
+struct MGLevel {
+  Grid g;
+  double* x = nullptr;   // n_l x cmax
+  double* t = nullptr;   // n_l x cmax
+  double* r = nullptr;   // n_l x cmax (levels > 0)
+};
+struct MG {
+  int levels = 0, nu_pre = 2, nu_post = 2;
+  double omega = 2.0 / 3.0;
+  int cmax = 0;
+  std::vector<MGLevel> lv;
+  double* coarse_inv = nullptr;  // nc x nc, row-major
+  int nc = 0;
+};
+size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax);
+plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_post, double omega,
+                     int cmax, char*& ws, hipStream_t s);
+// X_out = T R (ncols columns).  Output may be split over two blocks:
+// columns [0, split) go to out0, [split, ncols) to out1.
+void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, int ncols,
+              const DevStatus* st, hipStream_t s);
+
+// Dense level-0 helpers (k_blas.hip)
+// residual prep: R[:, c] = QV[:, c] - V[:, c] * (lam[c] - sigma); partial
+// sums of |R|^2 and |V|^2 per column per block written to part
+// (nblk x 2c).  Returns the number of blocks used.
+int launch_resid_prep(size_t n, const double* V, const double* QV, int ld, const double* lam,
+                      double sigma, double* R, int ldr, int ncols, double* part,
+                      const DevStatus* st, hipStream_t s);
+int resid_prep_blocks(size_t n);
+
+// Split-K Gram: out(i, j) = sum_p X[p, i] * Y[p, j] for i < mx, j < my,
+// where the Y columns come from up to two blocks: columns [0, my1) of Y1
+// followed by [0, my - my1) of Y2.  If qshift != 0 the first block is
+// formed on the fly as Y1 - qshift * Yq (Yq has the same ld as Y1).
+// Partials go to part (nblk x mx x my), then a second kernel reduces them
+// in a fixed order into out (mx x my, row-major).
+void launch_gram(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
+                 int my1, const double* Y2, int ldy2, int my, double* part, int nblk, double* out,
+                 const DevStatus* st, hipStream_t s);
+int gram_blocks(size_t n);
+
+// In-place right multiplication by an upper-triangular m x m matrix:
+// X[p, :m] <- X[p, :m] * M for each of the nx arrays (row-wise, so
+// in-place is safe).
+void launch_transform(size_t n, double* const* X, int nx, int ld, int m, const double* M,
+                      const DevStatus* st, hipStream_t s);
+
+// Block update from the coefficient matrix Y (m x kc, row-major):
+//   Vn = Zrow[:m] * Y ;  Pn = Zrow[kv:m] * Y[kv:m]
+// written in place to columns [0,kc) (V) and [pcol, pcol+kc) (P) of the
+// same arrays.  For array 0 also writes per-block partial column sums of
+// v*v and v*(Q v) (from array 1) into part (nblk x 2kc).
+int launch_update(size_t n, double* const* X, int nx, int ld, int m, int kv, const double* Y,
+                  int kc, int pcol, double* part, const DevStatus* st, hipStream_t s);
+int update_blocks(size_t n);
+
+// Y[p, c] = X[p, c] * M  for dense (kin x kout) M; X ld ldx, Y ld ldy.
+void launch_small_gemm(size_t n, const double* X, int ldx, int kin, const double* M, int kout,
+                       double* Y, int ldy, hipStream_t s);
+
+// copy n x c block with leading dimensions
+void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s);
+
+// column partial sums of |X|^2, X.*Y (nblk x 2c) for final residuals:
+int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
+                   const double* lam, double sigma, double* part, hipStream_t s);
+
+// partial column sums of x.x and x.y (nblk x 2c)
+int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, int ncols,
+                 double* part, hipStream_t s);
+
+// Hellmann-Feynman: g[x] (+)= sum_j dl[j] * V[x,j]^2 / vbv[j]
+void launch_hf(size_t n, const double* V, int ldv, int k, const double* dl, const double* vbv,
+               double* g, int accumulate, hipStream_t s);
+
+// Small single-workgroup kernels (k_small.hip)
+struct SmallBufs {
+  double* G;        // m x m
+  double* M;        // m x m
+  double* GLR;      // m x 2m : [G_L-ish | G_R] raw Gram output
+  double* Y;        // m x kint
+  double* lam;      // kint
+  double* relres;   // kint
+  double* xi;       // 2 x m (re, im) diagnostics
+  int* keep;        // m
+  int* active;      // kint
+  int* kinds;       // kint
+  int* pair;        // kint
+  double* final_C;  // kint x kint
+  double* final_theta;  // kint
+  double* vbv;      // kint
+  double* scratch;  // misc
+};
+
+struct SmallParams {
+  int kint, k, m;     // m = 4 * kint
+  double sigma;
+  double tol;
+  double normA1, normB1;
+  double drop_tol;
+  int lock;
+};
+
+void launch_init_lam(const SmallParams& p, const double* part, int nblk, SmallBufs b,
+                     DevStatus* st, hipStream_t s);
+void launch_start_check(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+void launch_conv_check(const SmallParams& p, const double* part, int nblk, SmallBufs b,
+                       DevStatus* st, int max_iters, hipStream_t s);
+void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,
+                     DevStatus* st, hipStream_t s);
+void launch_final_rr(const SmallParams& p, const double* HM, SmallBufs b, DevStatus* st,
+                     hipStream_t s);
+void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallBufs b,
+                      hipStream_t s);
+size_t small_max_lds(int m, int kint);
+hipError_t small_set_attributes(int m, int kint);
+
+}  // namespace plhr

@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every symbol include/plhr.h
+declares; host-side argument validation (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1408_0042_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "plhr.h")).read()
+    return sorted(set(re.findall(r"\b(plhr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared()
+    assert "plhr_create" in names and "plhr_eigvals_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_options_default_and_version():
+    o = L.default_options()
+    assert o.tol == 1e-8 and o.k_extra == 1 and o.lock == 1 and o.check_every == 1
+    assert b"gfx950" in L.load().plhr_version()
+
+
+def _ws(a, t=None, sigma=1.0, k=4, o=None):
+    sz = C.c_size_t()
+    code = L.load().plhr_workspace_size(C.byref(a), None, C.byref(t) if t else None, sigma, k,
+                                        C.byref(o) if o else None, C.byref(sz))
+    return code, sz.value
+
+
+def _fd3(N=64):
+    a = L.OpDesc()
+    a.kind, a.dtype, a.nx, a.ny, a.nz, a.h, a.scale = L.OP_FD7_3D, L.F64, N, N, N, 1 / (N + 1), 1.0
+    return a
+
+
+def test_workspace_size_and_validation():
+    a = _fd3()
+    t = L.PrecDesc()
+    t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = L.PREC_MG_VCYCLE, 5, 2, 2, 2 / 3
+    code, sz = _ws(a, t, 12667.6, 16)
+    assert code == L.OK
+    n, kint = 64**3, 17
+    assert sz >= 3 * n * 4 * kint * 8        # Z, QZ, TQZ
+    # invalid inputs are rejected on the host
+    assert _ws(a, t, float("nan"), 16)[0] == L.ERR_ARG
+    assert _ws(a, t, 1.0, 0)[0] == L.ERR_ARG
+    bad = _fd3()
+    bad.h = -1.0
+    assert _ws(bad, t, 1.0, 4)[0] == L.ERR_ARG
+    t2 = L.PrecDesc()
+    t2.kind, t2.levels, t2.nu_pre, t2.nu_post, t2.omega = L.PREC_MG_VCYCLE, 5, 2, 1, 2 / 3
+    assert _ws(a, t2, 1.0, 4)[0] == L.ERR_ARG          # asymmetric V-cycle
+    t3 = L.PrecDesc()
+    t3.kind, t3.levels, t3.nu_pre, t3.nu_post, t3.omega = L.PREC_MG_VCYCLE, 8, 2, 2, 2 / 3
+    assert _ws(a, t3, 1.0, 4)[0] == L.ERR_ARG          # 64 not divisible by 2^7
+    small = _fd3(2)
+    assert _ws(small, None, 1.0, 4)[0] == L.ERR_ARG     # 4 (k + k_extra) > n
+    assert _ws(a, None, 1.0, 30)[0] == L.ERR_UNSUPPORTED  # projected problem too large
+    assert b"4*(k + k_extra)" in L.load().plhr_last_error()

@@ -1,0 +1,83 @@
+"""Parity of the HIP block PLHR (Algorithm 3) with the oracle: per-step
+Rayleigh quotients, converged eigenpairs against brute force, closed forms
+and the oracle's own run; error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense, mg, operators as ops, plhr
+from tests import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(**kw):
+    from paper_1408_0042_amd.plhr import Solver
+    return Solver(**kw)
+
+
+def test_first_steps_match_oracle():
+    """Three iterations from the same start block: the Rayleigh quotients
+    of the GPU iterate equal the oracle's (span-level quantities, so the
+    different orthonormalisation methods do not matter)."""
+    from tests.gpu_util import dev
+    dims, h = (16, 16), 1 / 17
+    pot = np.random.default_rng(40).uniform(0, 200, 256)
+    A = ops.fd_dirichlet(dims, h, potential=pot)
+    sigma = 900.0
+    k, kx = 4, 2
+    V0 = wl.start_block(256, k + kx, (41, 0))
+    T = mg.VCycle("fd", dims, h, 1.0, 3)
+    prob = plhr.Problem(A=A, T=T.apply, sigma=sigma)
+    o = plhr.BPLHR(prob, V0, k, real=True, lock=False)
+    S = _solver(kind="fd5_2d", dims=dims, h=h, sigma=sigma, k=k, k_extra=kx, lock=False,
+                potential=dev(pot), precond={"levels": 3, "nu": 2, "omega": 2 / 3})
+    S.start(dev(V0))
+    lam_g, _ = S.state()
+    assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-12)
+    for it in range(3):
+        o.step()
+        S.iterate(1)
+        lam_g, Vg = S.state()
+        assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-8), (it, lam_g, o.lam)
+    S.close()
+
+
+def test_small_2d_identity_preconditioner_matches_closed_form_and_oracle():
+    from tests.gpu_util import dev, host
+    N, h = 12, 1 / 13
+    ev = cf.fd_dirichlet_eigs((N, N), h)
+    sigma = 0.4 * ev.max()
+    ref = ev[np.lexsort((ev, np.abs(ev - sigma)))][:4]
+    V0 = wl.start_block(N * N, 6, (1, 0))
+    S = _solver(kind="fd5_2d", dims=(N, N), h=h, sigma=sigma, k=4, k_extra=2, tol=1e-12,
+                max_iters=5000)
+    r = S.solve(dev(V0))
+    lam = host(r.eigvals)
+    assert r.converged
+    assert np.allclose(lam, ref, rtol=1e-10)
+    A = ops.fd_dirichlet((N, N), h)
+    lam_b, X_b = dense.nearest_pairs(A, None, sigma, 4)
+    assert dense.subspace_sine(X_b, host(r.V)) < 1e-7
+    assert np.all(r.rel_res <= 1e-11)   # fresh products after the final Rayleigh-Ritz
+    S.close()
+
+
+def test_3d_multigrid_small_matches_brute_force():
+    from tests.gpu_util import dev, host
+    w = wl.small_fd7(8, 4, 0.1, seed=(21, 0), levels=2)
+    w.k_extra = 3
+    A = ops.fd_dirichlet(w.dims, w.h)
+    lam_b, X_b = dense.nearest_pairs(A, None, w.sigma, w.k)
+    S = _solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=w.k, k_extra=w.k_extra,
+                tol=1e-12, max_iters=2000, precond={"levels": 2, "nu": 2, "omega": 2 / 3})
+    r = S.solve(dev(w.v0()))
+    assert r.converged
+    assert np.allclose(host(r.eigvals), lam_b, rtol=1e-10)
+    # the 4th value belongs to a 3-fold eigenvalue: compare with the union
+    _, U = dense.cluster_basis(A, None, w.sigma, w.k)
+    assert U.shape[1] == 6
+    assert dense.subspace_sine(U, host(r.V)) < 1e-7
+    S.close()
