@@ -24,6 +24,7 @@
 //   Rayleigh quotients, eq. (4.1) for pairs
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,6 +37,8 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static constexpr int kRefreshT = 10;  // iterations between T(A - sigma B)V refreshes
 
 // Per-launch event profiling (see KCat).  The driver points g_prof at the
 // active context's recorder for the duration of each entry point.
@@ -94,6 +97,7 @@ struct plhr_ctx_s {
   size_t ws_bytes = 0;
   double *Z = nullptr, *QZ = nullptr, *TQZ = nullptr, *R = nullptr;
   double *Vfin = nullptr, *QVfin = nullptr;
+  double* QVf = nullptr;  // fresh (A - sigma B)V for residuals and RQs
   double *part = nullptr, *gpart = nullptr, *HM = nullptr;
   int gram_nblk = 1;
   SmallBufs sb{};
@@ -101,6 +105,8 @@ struct plhr_ctx_s {
   DevStatus* st = nullptr;
   DevStatus* st_host = nullptr;
   bool started = false, finished = false;
+  long host_iter = 0;  // iterations enqueued since plhr_start
+  bool use_mfma = true;
   Prof prof;
 };
 
@@ -164,8 +170,8 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("4*(k + k_extra) must not exceed n");
     return PLHR_ERR_ARG;
   }
-  if (4 * kint > 100) {
-    set_error("4*(k + k_extra) > 100 exceeds the on-chip projected-problem limit");
+  if (4 * kint > 68) {
+    set_error("4*(k + k_extra) > 68 exceeds the on-chip projected-problem limit");
     return PLHR_ERR_UNSUPPORTED;
   }
   if (opt) {
@@ -219,6 +225,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
   size_t oZ = L.take(n * m * 8), oQZ = L.take(n * m * 8), oTQZ = L.take(n * m * 8);
   size_t oR = L.take(n * 2 * kint * 8);
   size_t oVf = L.take(n * k * 8), oQVf = L.take(n * k * 8);
+  size_t oQVr = L.take(n * kint * 8);
   size_t opart = L.take((size_t)512 * 2 * kint * 8);
   size_t ogp = L.take((size_t)gnb * m * 2 * m * 8);
   size_t oHM = L.take((size_t)kint * 2 * kint * 8);
@@ -228,6 +235,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
   size_t okeep = L.take(m * 4), oact = L.take(kint * 4), okind = L.take(kint * 4),
          opair = L.take(kint * 4);
   size_t ofc = L.take((size_t)kint * kint * 8), oft = L.take(kint * 8), ovbv = L.take(kint * 8);
+  size_t owork = L.take((size_t)4 * m * m * 8);
   size_t ost = L.take(sizeof(DevStatus));
   size_t omg = L.bytes;
   if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint);
@@ -239,6 +247,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
     c->R = (double*)(b + oR);
     c->Vfin = (double*)(b + oVf);
     c->QVfin = (double*)(b + oQVf);
+    c->QVf = (double*)(b + oQVr);
     c->part = (double*)(b + opart);
     c->gpart = (double*)(b + ogp);
     c->gram_nblk = gnb;
@@ -257,6 +266,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
     c->sb.final_C = (double*)(b + ofc);
     c->sb.final_theta = (double*)(b + oft);
     c->sb.vbv = (double*)(b + ovbv);
+    c->sb.work = (double*)(b + owork);
     c->sb.scratch = nullptr;
     c->st = (DevStatus*)(b + ost);
     (void)omg;
@@ -297,6 +307,40 @@ void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int spli
   }
 }
 
+// Gram product on the matrix cores when the shape fits.
+void gram(plhr_ctx_s* c, const double* X, int ldx, int mx, const double* Y1, int ldy1, int my1,
+          const double* Y2, int ldy2, int my, double* out, const DevStatus* st) {
+  if (c->use_mfma && gram_mfma_ok(mx, my))
+    launch_gram_mfma(c->n, X, ldx, mx, Y1, ldy1, my1, Y2, ldy2, my, c->gpart, c->gram_nblk, out,
+                     st, c->stream);
+  else
+    launch_gram(c->n, X, ldx, mx, Y1, ldy1, my1, Y2, ldy2, my, c->gpart, c->gram_nblk, out, st,
+                c->stream);
+}
+
+void transform(plhr_ctx_s* c, double* const* arrs, int narr, const DevStatus* st) {
+  const int m = c->m;
+  if (c->use_mfma && rowmul_mfma_ok(m, m)) {
+    const size_t ntiles = (c->n + 63) / 64;
+    const int nb = (int)(ntiles < 1024 ? ntiles : 1024);
+    launch_rowmul_mfma(c->n, arrs, narr, m, m, c->sb.M, m, 0, 0, 0, 0, nullptr, nb, st, c->stream);
+  } else {
+    launch_transform(c->n, arrs, narr, m, m, c->sb.M, st, c->stream);
+  }
+}
+
+int update(plhr_ctx_s* c, double* const* arrs, int narr, const DevStatus* st) {
+  const int m = c->m, kint = c->kint;
+  if (c->use_mfma && rowmul_mfma_ok(m, 2 * kint)) {
+    const int nb = update_blocks(c->n);
+    launch_rowmul_mfma(c->n, arrs, narr, m, m, c->sb.Y, 2 * kint, 1, kint, kint, 3 * kint, c->part,
+                       nb, st, c->stream);
+    return nb;
+  }
+  return launch_update(c->n, arrs, narr, m, m, kint, c->sb.Y, kint, 3 * kint, c->part, st,
+                       c->stream);
+}
+
 void enqueue_iteration(plhr_ctx_s* c) {
   const int kint = c->kint, m = c->m;
   const size_t n = c->n;
@@ -304,8 +348,26 @@ void enqueue_iteration(plhr_ctx_s* c) {
   DevStatus* st = c->st;
   double *Z = c->Z, *QZ = c->QZ, *TQZ = c->TQZ, *R = c->R;
   const Blk none{nullptr, 0};
+  // (A - sigma B)V afresh from V, and the Rayleigh quotients from it: the
+  // copy carried by the block updates drifts from the true product by
+  // rounding (about 1e-11 relative after a thousand iterations), which
+  // would let the convergence test and the soft locking act on residuals
+  // that are not the true ones.  T(A - sigma B)V is refreshed every
+  // kRefreshT iterations for the same reason.
+  // The fresh product goes to its own buffer: the V slots of QZ and TQZ
+  // must stay consistent with each other (the orthonormalising transform
+  // divides by small pivots and would amplify any mismatch into P), so
+  // they are refreshed together, every kRefreshT iterations.
+  if (c->host_iter % kRefreshT == kRefreshT - 1) {
+    stencil(c, Z, m, Blk{QZ, m}, none, nullptr, none, kint, c->sigma, st);
+    precond(c, QZ, m, Blk{TQZ, m}, none, kint, kint, st);
+  }
+  stencil(c, Z, m, Blk{c->QVf, kint}, none, nullptr, none, kint, c->sigma, st);
+  int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s);
+  launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
   // residuals of the current block, convergence and locking
-  int nb = launch_resid_prep(n, Z, QZ, m, c->sb.lam, c->sigma, R, kint, kint, c->part, st, s);
+  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, R, kint, kint, c->part, st,
+                         s);
   launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
   // W = T (A V - B V Lam)
   precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st);
@@ -318,16 +380,17 @@ void enqueue_iteration(plhr_ctx_s* c) {
   stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st);
   precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
   // B-orthonormalise Z = [V W S P] (Cholesky-QR in slot order)
-  launch_gram(n, Z, m, m, Z, m, m, nullptr, 0, m, c->gpart, c->gram_nblk, c->sb.G, st, s);
+  gram(c, Z, m, m, Z, m, m, nullptr, 0, m, c->sb.G, st);
   launch_ortho_small(c->sp, c->sb, st, s);
   double* arrs[3] = {Z, QZ, TQZ};
-  launch_transform(n, arrs, 3, m, m, c->sb.M, st, s);
+  transform(c, arrs, 3, st);
   // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | Zhat]
-  launch_gram(n, TQZ, m, m, QZ, m, m, Z, m, 2 * m, c->gpart, c->gram_nblk, c->sb.GLR, st, s);
+  gram(c, TQZ, m, m, QZ, m, m, Z, m, 2 * m, c->sb.GLR, st);
   launch_tharm_small(c->sp, c->sb, st, s);
   // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
-  nb = launch_update(n, arrs, 3, m, m, kint, c->sb.Y, kint, 3 * kint, c->part, st, s);
-  launch_rq_small(c->sp, c->part, nb, c->sb, st, s);
+  nb = update(c, arrs, 3, st);
+  launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
+  ++c->host_iter;
 }
 
 plhr_status read_status(plhr_ctx_s* c) {
@@ -476,7 +539,9 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->sp.normB1 = c->normB1;
   c->sp.drop_tol = o.drop_tol;
   c->sp.lock = o.lock;
+  c->use_mfma = (getenv("PLHR_NO_MFMA") == nullptr);
   hipError_t e = small_set_attributes(c->m, c->kint);
+  if (e == hipSuccess) e = mfma_set_attributes(c->m, c->kint);
   if (e != hipSuccess) {
     set_error(std::string("LDS attribute: ") + hipGetErrorString(e));
     plhr_destroy(c);
@@ -513,12 +578,12 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
   const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s);
   launch_init_lam(c->sp, c->part, nb, c->sb, c->st, s);
-  launch_gram(n, c->Z, m, kint, c->Z, m, kint, nullptr, 0, kint, c->gpart, c->gram_nblk, c->sb.G,
-              nullptr, s);
+  gram(c, c->Z, m, kint, c->Z, m, kint, nullptr, 0, kint, c->sb.G, nullptr);
   launch_start_check(c->sp, c->sb, c->st, s);
   PLHR_HIP_CHECK(hipGetLastError());
   c->started = true;
   c->finished = false;
+  c->host_iter = 0;
   plhr_status st = read_status(c);
   if (st != PLHR_OK) return st;
   return device_error(c);
@@ -571,10 +636,12 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
   const int kint = c->kint, k = c->k, m = c->m;
   const size_t n = c->n;
   hipStream_t s = c->stream;
-  // H = V^T (A - sigma) V, M = V^T V
+  // H = V^T (A - sigma) V, M = V^T V, from a fresh (A - sigma)V
+  const Blk none0{nullptr, 0};
+  stencil(c, c->Z, m, Blk{c->QZ, m}, none0, nullptr, none0, kint, c->sigma, nullptr);
   const int gnb = c->gram_nblk;
-  launch_gram(n, c->Z, m, kint, c->QZ, m, kint, c->Z, m, 2 * kint, c->gpart, gnb, c->HM, nullptr,
-              s);
+  gram(c, c->Z, m, kint, c->QZ, m, kint, c->Z, m, 2 * kint, c->HM, nullptr);
+  (void)gnb;
   launch_final_rr(c->sp, c->HM, c->sb, c->st, s);
   launch_small_gemm(n, c->Z, m, kint, c->sb.final_C, k, c->Vfin, k, s);
   const Blk none{nullptr, 0};

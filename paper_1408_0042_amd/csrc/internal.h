@@ -125,8 +125,8 @@ void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, i
 // residual prep: R[:, c] = QV[:, c] - V[:, c] * (lam[c] - sigma); partial
 // sums of |R|^2 and |V|^2 per column per block written to part
 // (nblk x 2c).  Returns the number of blocks used.
-int launch_resid_prep(size_t n, const double* V, const double* QV, int ld, const double* lam,
-                      double sigma, double* R, int ldr, int ncols, double* part,
+int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
+                      const double* lam, double sigma, double* R, int ldr, int ncols, double* part,
                       const DevStatus* st, hipStream_t s);
 int resid_prep_blocks(size_t n);
 
@@ -175,6 +175,22 @@ int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, i
 void launch_hf(size_t n, const double* V, int ldv, int k, const double* dl, const double* vbv,
                double* g, int accumulate, hipStream_t s);
 
+// Up to four arrays processed by one row-product launch.
+struct ArrPtrs {
+  double* a[4];
+};
+
+// Matrix-core versions (k_mfma.hip); *_ok tells whether the shape fits.
+int gram_mfma_ok(int mx, int my);
+void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
+                      int my1, const double* Y2, int ldy2, int my, double* part, int nblk,
+                      double* out, const DevStatus* st, hipStream_t s);
+int rowmul_mfma_ok(int m, int kout);
+void launch_rowmul_mfma(size_t n, double* const* X, int narr, int ld, int m, const double* M,
+                        int kout, int mode, int kv, int kc, int pcol, double* part, int nblk,
+                        const DevStatus* st, hipStream_t s);
+hipError_t mfma_set_attributes(int m, int kint);
+
 // Small single-workgroup kernels (k_small.hip)
 struct SmallBufs {
   double* G;        // m x m
@@ -191,6 +207,7 @@ struct SmallBufs {
   double* final_C;  // kint x kint
   double* final_theta;  // kint
   double* vbv;      // kint
+  double* work;     // 4 m^2: projected-solver matrices between its kernels
   double* scratch;  // misc
 };
 
@@ -210,13 +227,15 @@ void launch_conv_check(const SmallParams& p, const double* part, int nblk, Small
                        DevStatus* st, int max_iters, hipStream_t s);
 void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// Rayleigh quotients from per-block partial sums [v.v | v.(A - sigma B)v];
+// end_of_iteration also advances the iteration counter.
 void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,
-                     DevStatus* st, hipStream_t s);
+                     DevStatus* st, int end_of_iteration, hipStream_t s);
 void launch_final_rr(const SmallParams& p, const double* HM, SmallBufs b, DevStatus* st,
                      hipStream_t s);
 void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                       hipStream_t s);
-size_t small_max_lds(int m, int kint);
 hipError_t small_set_attributes(int m, int kint);
+hipError_t tharm_set_attributes(int m, int kint);
 
 }  // namespace plhr

@@ -37,7 +37,7 @@ __device__ __forceinline__ void block_colsum(double (&acc)[NV], int ncols, doubl
 
 // R = QV - V * (lam - sigma); partial |R|^2, |V|^2 per column.
 __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __restrict__ V,
-                                                    const double* __restrict__ QV, int ld,
+                                                    int ldv, const double* __restrict__ QV, int ldq,
                                                     const double* __restrict__ lam, double sigma,
                                                     double* __restrict__ R, int ldr, int ncols,
                                                     double* __restrict__ part,
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
     const size_t pe = (pb + chunk < n) ? pb + chunk : n;
     const double sh = lam[c] - sigma;
     for (size_t p = pb + r0; p < pe; p += rpi) {
-      const double v = V[p * ld + c];
-      const double r = QV[p * ld + c] - v * sh;
+      const double v = V[p * ldv + c];
+      const double r = QV[p * ldq + c] - v * sh;
       if (R) R[p * ldr + c] = r;
       acc[0] += r * r;
       acc[1] += v * v;
@@ -64,12 +64,12 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
   block_colsum<2>(acc, ncols, part);
 }
 
-int launch_resid_prep(size_t n, const double* V, const double* QV, int ld, const double* lam,
-                      double sigma, double* R, int ldr, int ncols, double* part,
+int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
+                      const double* lam, double sigma, double* R, int ldr, int ncols, double* part,
                       const DevStatus* st, hipStream_t s) {
   prof_begin(KC_VEC, (double)n * ncols * 8.0 * (R ? 3.0 : 2.0), 5.0 * n * ncols, s);
-  hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, V, QV, ld, lam, sigma, R,
-                     ldr, ncols, part, st);
+  hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, V, ldv, QV, ldq, lam,
+                     sigma, R, ldr, ncols, part, st);
   prof_end(KC_VEC, s);
   return kRedBlocks;
 }
@@ -105,11 +105,8 @@ int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, i
 // Column sums for the final residual check: |QX - X*(lam - sigma)|^2, |X|^2.
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
                    const double* lam, double sigma, double* part, hipStream_t s) {
-  // reuse k_resid_prep with separate leading dimensions is not possible
-  // (single ld); the callers pass equal ld.
-  hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, X, QX, ldx, lam, sigma,
-                     (double*)nullptr, 0, c, part, (const DevStatus*)nullptr);
-  (void)ldq;
+  hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, X, ldx, QX, ldq, lam,
+                     sigma, (double*)nullptr, 0, c, part, (const DevStatus*)nullptr);
   return kRedBlocks;
 }
 
@@ -228,10 +225,6 @@ void launch_gram(size_t n, const double* X, int ldx, int mx, const double* Y1, i
 // In mode 1, array 0's V rows are kept in LDS and array 1's V rows are
 // dotted with them: partial sums of v.v and v.(Qv) per column.
 static constexpr int kRB = 64;  // rows per workgroup tile
-
-struct ArrPtrs {
-  double* a[4];
-};
 
 __global__ void k_rowmul(size_t n, ArrPtrs arrs, int narr, int ld, int m, const double* __restrict__ M,
                          int kout, int mode, int kv, int kc, int pcol, double* __restrict__ part,

@@ -190,3 +190,28 @@ class Solver:
         V = torch.empty((self.n, self.kint), dtype=torch.float64, device="cuda")
         L.check(self.lib.plhr_get_state(self.ctx, lam, C.c_void_p(V.data_ptr())))
         return np.array(lam[:]), V
+
+
+def eigvals(potential: torch.Tensor, V0: torch.Tensor, **opts) -> torch.Tensor:
+    """Differentiable eigenvalues of scale*(-Laplacian) + diag(potential)
+    nearest sigma (opts as for Solver).  backward() returns dL/dpotential
+    from the library's Hellmann-Feynman kernel, d lambda_j / d pot_x =
+    v_j(x)^2 / (v_j^T v_j)."""
+    return _EigvalsWithStart.apply(potential, V0, opts)
+
+
+class _EigvalsWithStart(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, potential, V0, opts):
+        S = Solver(potential=potential.detach().contiguous(), **opts)
+        r = S.solve(V0.detach().contiguous())
+        ctx.solver = S
+        ctx.result = r
+        return r.eigvals.clone()
+
+    @staticmethod
+    def backward(ctx, grad_lam):
+        S = ctx.solver
+        g = S.backward(grad_lam.detach().contiguous().to(torch.float64))
+        S.close()
+        return g, None, None

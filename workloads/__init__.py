@@ -116,3 +116,59 @@ def small_fd5(N: int, k: int, frac: float, seed=(8, 0), precond="identity", leve
         sigma=frac * lmax, k=k, k_extra=1, precond=precond, v0_seed=seed,
         mg_levels=lv,
     )
+
+
+def fd7_closed_form(N: int, h: float) -> np.ndarray:
+    """Sorted eigenvalues of the 3-D 7-point Dirichlet Laplacian (N^3)."""
+    s = (4.0 / h**2) * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    return np.sort(np.add.outer(np.add.outer(s, s), s).ravel())
+
+
+def shift_between(ev: np.ndarray, nbelow: int, frac: float = 0.4) -> float:
+    """A shift with about `nbelow` eigenvalues below it, placed `frac` of the
+    way between two consecutive distinct eigenvalues (so that it is not an
+    eigenvalue and the two neighbouring clusters are not equidistant)."""
+    u = np.unique(np.round(ev, 8))
+    i = int(np.searchsorted(u, ev[nbelow]))
+    return float(u[i - 1] + frac * (u[i] - u[i - 1]))
+
+
+def bench_workload(N: int = 64, nbelow: int = 121) -> Workload:
+    """The benchmark workload: the 3-D Laplacian of the second configuration
+    (64^3, h = 1/65, k = 16, 5-level V-cycle) with the shift about 125
+    eigenvalues into the spectrum (sigma ~ 485.22 for N = 64), where the 16
+    nearest eigenvalues form whole clusters of the cube's degenerate
+    spectrum (1 + 6 + 6 + 3), so that the wanted set is unambiguous.  The
+    design notes explain why the quarter-of-lambda_max shift of the
+    configuration is not used for the throughput number."""
+    w = config2(N)
+    w.sigma = shift_between(fd7_closed_form(N, w.h), nbelow)
+    w.name = f"fd7_3d_{N}cubed_k16_below{nbelow}"
+    return w
+
+
+def gaussian_potential(N: int, ngauss: int, seed: Tuple[int, ...], d: int = 2) -> np.ndarray:
+    """Sum of negative Gaussians on an N^d grid (grid units, points at
+    1..N): depth U(1, 4), width U(0.5, 1.5), centres U(1, N)^d.  Returned
+    x-fastest, length N^d."""
+    g = rng(*seed)
+    depth = g.uniform(1.0, 4.0, ngauss)
+    width = g.uniform(0.5, 1.5, ngauss)
+    centres = g.uniform(1.0, float(N), (ngauss, d))
+    axes = [np.arange(1, N + 1, dtype=np.float64)] * d
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")[::-1]   # mesh[0] = x (fastest)
+    V = np.zeros((N,) * d)
+    for a in range(ngauss):
+        r2 = sum((mesh[i] - centres[a, i]) ** 2 for i in range(d))
+        V -= depth[a] * np.exp(-r2 / (2.0 * width[a] ** 2))
+    return V.ravel()
+
+
+def batched_problem(b: int, sizes=(64, 96, 128, 160)):
+    """Problem b of the batched set: grid size N_b, potential, targets."""
+    g = rng(5, 2)
+    Ns = g.choice(np.array(sizes), 256)
+    N = int(Ns[b])
+    pot = gaussian_potential(N, 16, (5, 1, b))
+    targets = np.sort(rng(5, 3, b).uniform(1.5, 2.5, 8))
+    return N, pot, targets
