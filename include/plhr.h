@@ -131,6 +131,10 @@ typedef struct {
   int32_t n_active;    /* columns still generating W/S/P                  */
   int32_t status;      /* device status word (0 = ok)                      */
   double max_rel_res;  /* largest relative residual among the k wanted     */
+  int32_t n_excluded;  /* basis slots left out of projected problems since
+                          plhr_start because G_L had a clearly negative
+                          pivot (inconsistent carried products)           */
+  int32_t reserved0;
 } plhr_iter_info;
 
 /* Library version string. */
@@ -154,7 +158,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
  *   B          host descriptor of B, or NULL for the identity
  *   T          host descriptor of the HPD preconditioner, or NULL for I
  *   sigma      finite real shift
- *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n
+ *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n; a trial
+ *              subspace wider than 84 (4*(k + k_extra) > 84) gives
+ *              PLHR_ERR_UNSUPPORTED
  *   opt        host options, or NULL for defaults
  *   stream     HIP stream (hipStream_t) all work is enqueued on; NULL is
  *              the null stream

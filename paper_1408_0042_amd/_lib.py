@@ -42,7 +42,8 @@ class Options(C.Structure):
 
 class IterInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_active", C.c_int32),
-                ("status", C.c_int32), ("max_rel_res", C.c_double)]
+                ("status", C.c_int32), ("max_rel_res", C.c_double),
+                ("n_excluded", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class Profile(C.Structure):

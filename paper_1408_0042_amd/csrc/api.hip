@@ -170,8 +170,8 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("4*(k + k_extra) must not exceed n");
     return PLHR_ERR_ARG;
   }
-  if (4 * kint > 68) {
-    set_error("4*(k + k_extra) > 68 exceeds the on-chip projected-problem limit");
+  if (4 * kint > kMaxM) {
+    set_error("4*(k + k_extra) > 84 exceeds the on-chip projected-problem limit");
     return PLHR_ERR_UNSUPPORTED;
   }
   if (opt) {
@@ -619,6 +619,8 @@ plhr_status plhr_iterate(plhr_ctx c, int32_t n_steps, plhr_iter_info* info) {
     info->n_active = c->st_host->n_active;
     info->status = c->st_host->error;
     info->max_rel_res = c->st_host->max_rel_res;
+    info->n_excluded = c->st_host->n_excluded;
+    info->reserved0 = 0;
   }
   return device_error(c);
 }

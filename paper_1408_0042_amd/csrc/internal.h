@@ -13,6 +13,11 @@
 
 namespace plhr {
 
+// Largest trial-subspace width m = 4 (k + k_extra) handled on chip: the
+// projected eigensolver keeps two m x m matrices and the selected vectors
+// of the m x m problem in one workgroup's LDS (160 KiB on gfx950).
+constexpr int kMaxM = 84;
+
 // ------------------------------------------------------------------ errors
 void set_error(const std::string& msg);
 
@@ -39,6 +44,8 @@ struct DevStatus {
   int have_p;        // the P block holds a conjugate direction
   int n_dropped;     // columns dropped by the last orthonormalisation
   int reason;        // which check raised `error` (kReason*)
+  int n_excluded;    // slots left out of projected problems so far (G_L pivot < 0)
+  int pad0;
   double max_rel_res;  // largest relative residual among the k wanted
   double reserved[3];
   long long tphase[12];  // clock stamps of the projected-solver phases

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce8(const double* __restrict__
   }
 }
 
-int gram_mfma_ok(int mx, int my) { return mx <= 128 && my <= 9 * 16; }
+int gram_mfma_ok(int mx, int my) { return mx <= 128 && my <= 11 * 16; }
 
 void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
                       int my1, const double* Y2, int ldy2, int my, double* part, int nblk,
@@ -126,7 +126,7 @@ void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* 
     break;
   switch (TJ) {
     GRAM_CASE(1) GRAM_CASE(2) GRAM_CASE(3) GRAM_CASE(4) GRAM_CASE(5) GRAM_CASE(6) GRAM_CASE(7)
-    GRAM_CASE(8) GRAM_CASE(9)
+    GRAM_CASE(8) GRAM_CASE(9) GRAM_CASE(10) GRAM_CASE(11)
     default: break;
   }
 #undef GRAM_CASE

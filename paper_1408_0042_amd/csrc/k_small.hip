@@ -76,6 +76,7 @@ __global__ void k_init_lam(SmallParams p, const double* __restrict__ part, int n
     st->n_active = p.kint;
     st->m_kept = 0;
     st->n_dropped = 0;
+    st->n_excluded = 0;
     st->max_rel_res = 0.0;
   }
 }

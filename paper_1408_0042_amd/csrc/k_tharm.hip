@@ -13,7 +13,7 @@
 // global work area (L2-resident):
 //   k_tharm_reduce  (256 threads) Cholesky of G_L, C, Householder
 //                   reduction of C to upper Hessenberg H = Q^T C Q
-//   k_tharm_qr      (one wavefront) Francis double-shift QR of H to real
+//   k_tharm_qr      (two wavefronts) Francis double-shift QR of H to real
 //                   Schur form T, accumulating Q; 2x2 blocks with real
 //                   eigenvalues are split by a rotation
 //   k_tharm_vectors (256 threads) eigenvalues and their ordering by
@@ -47,7 +47,7 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 __device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
 
 constexpr int kNT = 256;  // threads of the parallel phases
-constexpr int kQR = 64;   // the QR wavefront
+constexpr int kQR = 128;  // the QR workgroup (two wavefronts)
 
 // 1/d from the hardware reciprocal estimate and two Newton steps (the
 // Householder coefficients need a few-ulp reciprocal, not an IEEE
@@ -59,15 +59,23 @@ __device__ __forceinline__ double fast_rcp(double d) {
   return r;
 }
 
-// Ordering point inside the single-wavefront QR kernel.  A wavefront's LDS
-// instructions are executed in issue order, so a store issued before a
-// load by another lane of the same wavefront is seen by that load; only
-// the compiler must be kept from moving memory operations across this
-// point.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Frobenius norm of the n x n matrix X (row stride ld), by every thread
+// of the block in a fixed order; `red` is LDS scratch of blockDim/64
+// doubles.  Must be called by all threads.
+__device__ double block_fro(const double* X, int n, int ld, double* red) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  double a = 0.0;
+  for (int e = t; e < n * n; e += nt) {
+    const int i = e / n, j = e - i * n;
+    a += X[i * ld + j] * X[i * ld + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if ((t & 63) == 0) red[t >> 6] = a;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nt / 64; ++w) s += red[w];
+  __syncthreads();
+  return sqrt(s);
 }
 
 // Compact list of kept slots (shared by all three kernels).
@@ -86,7 +94,8 @@ __device__ int kept_slots(const int* keep, int m, int* idx) {
 }  // namespace
 
 // ------------------------------------------------------------ reduction
-// LDS: L n*n | H n*n | Q n*n | u n | w n | red 256
+// LDS: H n*n | L n*n (L is written out once C is formed and the region
+// then holds Q) | u n | w n | red 256
 __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   if (threadIdx.x == 0) st->tphase[0] = clock64();
@@ -103,10 +112,10 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
   }
   const int tx = t & 15, ty = t >> 4;
   const int ld = n | 1;  // odd row stride: column sweeps spread over the LDS banks
-  double* L = sm;
-  double* H = L + n * ld;
-  double* Q = H + n * ld;
-  double* u = Q + n * ld;
+  double* H = sm;
+  double* L = H + n * ld;
+  double* Q = L;  // after L has been written out
+  double* u = L + n * ld;
   double* w = u + n;
   double* red = w + n;
   const int ld2 = 2 * m;
@@ -115,18 +124,40 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
       const int ia = idx[i], ic = idx[c];
       L[i * ld + c] = 0.5 * (b.GLR[(size_t)ia * ld2 + ic] + b.GLR[(size_t)ic * ld2 + ia]);
       H[i * ld + c] = b.GLR[(size_t)ia * ld2 + m + ic];
-      Q[i * ld + c] = (i == c) ? 1.0 : 0.0;
     }
   __syncthreads();
-  // Cholesky G_L = L L^T (right-looking).  A pivot below 1e-15 max diag
-  // (sigma an eigenvalue whose vector lies in span Z) is raised to it.
+  // Cholesky G_L = L L^T (right-looking).  A pivot in [-1e-10, 1e-15] max
+  // diag (G_L singular to rounding: sigma an eigenvalue whose vector lies
+  // in span Z, xi = 0) is raised to 1e-15 max diag.  A pivot below
+  // -1e-10 max diag cannot come from an HPD G_L: the stored products of
+  // that slot no longer agree (T(A - sigma B)Z carried by linear
+  // combination has drifted from T applied to (A - sigma B)Z), and the
+  // slot is left out: its row and column of L become e_j and those of G_R
+  // zero, so that it contributes only tau = 0 (xi = infinity), never
+  // selected, and the remaining slots form the projected problem on
+  // their own span.
+  __shared__ int dead[256];
+  __shared__ int ndead;
   double maxd = 0.0;
   for (int j = 0; j < n; ++j) maxd = fmax(maxd, L[j * ld + j]);
   const double floor_ = fmax(1e-15 * maxd, 1e-300);
+  for (int j = t; j < n; j += kNT) dead[j] = 0;
+  if (t == 0) ndead = 0;
   for (int j = 0; j < n; ++j) {
-    const double piv = fmax(L[j * ld + j], floor_);
-    const double djj = sqrt(piv);
+    const double p0 = L[j * ld + j];
     __syncthreads();
+    if (p0 < -1e-10 * maxd) {  // uniform
+      for (int i = j + 1 + t; i < n; i += kNT) L[i * ld + j] = 0.0;
+      for (int c = t; c < j; c += kNT) L[j * ld + c] = 0.0;
+      if (t == 0) {
+        L[j * ld + j] = 1.0;
+        dead[j] = 1;
+        ++ndead;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double djj = sqrt(fmax(p0, floor_));
     for (int i = j + 1 + t; i < n; i += kNT) L[i * ld + j] /= djj;
     if (t == 0) L[j * ld + j] = djj;
     __syncthreads();
@@ -135,6 +166,20 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
       for (int c = j + 1 + tx; c <= i; c += 16) L[i * ld + c] -= lij * L[c * ld + j];
     }
     __syncthreads();
+  }
+  if (ndead) {  // uniform
+    for (int i = ty; i < n; i += 16)
+      for (int c = tx; c < n; c += 16)
+        if (dead[i] || dead[c]) H[i * ld + c] = 0.0;
+    if (t == 0) st->n_excluded += ndead;
+    __syncthreads();
+    if (n - ndead < p.kint) {
+      if (t == 0) {
+        st->error = PLHR_ERR_BREAKDOWN;
+        st->reason = kReasonVVanished;
+      }
+      return;
+    }
   }
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16)
@@ -163,6 +208,16 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
     }
     __syncthreads();
   }
+  // L (compact n x n) to the work area; its LDS region becomes Q = I
+  double* gw = b.work;
+  for (int e = t; e < n * n; e += kNT) {
+    const int i = e / n, j = e - i * n;
+    gw[e] = L[i * ld + j];
+  }
+  __syncthreads();
+  for (int i = ty; i < n; i += 16)
+    for (int c = tx; c < n; c += 16) Q[i * ld + c] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
   if (t == 0) st->tphase[2] = clock64();
   // Householder reduction to upper Hessenberg form, Q accumulated
   for (int k = 0; k + 2 < n; ++k) {
@@ -210,12 +265,11 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
     for (int i = k + 2 + t; i < n; i += kNT) H[i * ld + k] = 0.0;
     __syncthreads();
   }
-  // write L, H, Q (n x n each, compact) to the work area
-  double* gw = b.work;
-  for (int e = t; e < 3 * n * n; e += kNT) {
-    const int mat = e / (n * n), r = e - mat * n * n;
-    const int i = r / n, j = r - i * n;
-    gw[e] = sm[mat * n * ld + i * ld + j];
+  // H and Q (n x n each, compact) to the work area after L
+  for (int e = t; e < n * n; e += kNT) {
+    const int i = e / n, j = e - i * n;
+    gw[n * n + e] = H[i * ld + j];
+    gw[2 * n * n + e] = Q[i * ld + j];
   }
   if (t == 0) st->tphase[3] = clock64();
 }
@@ -228,21 +282,46 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
 // 1e8*ulp: degenerate eigenvalues of the pencil (symmetric grids) make
 // clusters of three or more equal tau, on which double-shift sweeps make
 // no progress, and the widened test accepts the tiny coupling inside such
-// a cluster, whose eigenvalues are equal to that accuracy.
-__device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, int* sweeps) {
-  const int t = threadIdx.x;
+// a cluster, whose eigenvalues are equal to that accuracy.  Exceptional
+// shifts every 10 sweeps without deflation.
+//
+// Layout: row stride ld >= n + 1 and n + 1 rows for each of H and Q
+// (Q = H + (n + 1) ld); row n and column n are padding.  A bulge step
+// k applies P = I - tau v v^T (v = (1, v1, v2) on indices k..k+2) as
+// H <- P H P, Q <- Q P in a single pass over disjoint groups of three
+// entries: the left update of each column outside the 3 x 3 block, the
+// right update of each row outside it, the right update of each row of
+// Q, and both updates of the block (one lane).  Every lane issues all of
+// its loads before the reflector is formed; groups that do not exist
+// (past n, or inside the block) point at the padding, so no lane
+// branches, and for the last step of a sweep (two rows) v2 = 0 makes the
+// third entry of each group a no-op.  One barrier per bulge step.
+__device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, int* sweeps,
+                           int* steps) {
+  constexpr int NT = kQR;
+  constexpr int U = (kMaxM + NT) / NT;  // groups of each kind per lane
+  const int t = threadIdx.x, lane = t & 63;
   const double ulp = 2.220446049250313e-16;
   const double small = 1e-300;
   int hi = n - 1;
-  int its = 0, total = 0;
+  int its = 0, total = 0, nsteps = 0;
   while (hi >= 0) {
     const double mult = (its >= 10) ? pow(10.0, (double)min(its / 10, 8)) : 1.0;
-    int l = hi;
-    for (; l > 0; --l) {
-      const double h = fabs(H[l * ld + l - 1]);
-      double tst = fabs(H[(l - 1) * ld + l - 1]) + fabs(H[l * ld + l]);
-      if (tst == 0.0) tst = hnorm;
-      if (h <= mult * ulp * tst || h <= ulp * hnorm || h <= small) break;
+    int l = 0;
+    for (int base = hi; base >= 1; base -= 64) {
+      const int lc = base - lane;
+      bool ok = false;
+      if (lc >= 1) {
+        const double h = fabs(H[lc * ld + lc - 1]);
+        double tst = fabs(H[(lc - 1) * ld + lc - 1]) + fabs(H[lc * ld + lc]);
+        if (tst == 0.0) tst = hnorm;
+        ok = (h <= mult * ulp * tst || h <= ulp * hnorm || h <= small);
+      }
+      const unsigned long long bal = __ballot64(ok);
+      if (bal) {
+        l = base - (__ffsll(bal) - 1);
+        break;
+      }
     }
     __syncthreads();
     if (l > 0) {
@@ -267,18 +346,18 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
         const double r = hypot(e1, e2);
         const double cs = e1 / r, sn = e2 / r;
         __syncthreads();
-        for (int j = q + t; j < n; j += kQR) {
+        for (int j = q + t; j < n; j += NT) {
           const double h0 = H[q * ld + j], h1 = H[(q + 1) * ld + j];
           H[q * ld + j] = cs * h0 + sn * h1;
           H[(q + 1) * ld + j] = -sn * h0 + cs * h1;
         }
         __syncthreads();
-        for (int i = t; i <= q + 1; i += kQR) {
+        for (int i = t; i <= q + 1; i += NT) {
           const double h0 = H[i * ld + q], h1 = H[i * ld + q + 1];
           H[i * ld + q] = cs * h0 + sn * h1;
           H[i * ld + q + 1] = -sn * h0 + cs * h1;
         }
-        for (int i = t; i < n; i += kQR) {
+        for (int i = t; i < n; i += NT) {
           const double z0 = Q[i * ld + q], z1 = Q[i * ld + q + 1];
           Q[i * ld + q] = cs * z0 + sn * z1;
           Q[i * ld + q + 1] = -sn * z0 + cs * z1;
@@ -294,6 +373,7 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
     if (total >= 60 * n) return false;
     ++its;
     ++total;
+    nsteps += hi - l;
     double h11, h12, h21, h22;
     if (its % 10 == 0) {
       const double s = fabs(H[hi * ld + hi - 1]) + fabs(H[(hi - 1) * ld + hi - 2]);
@@ -312,94 +392,139 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
                tr * H[l * ld + l] + det;
     double y = H[(l + 1) * ld + l] * (H[l * ld + l] + H[(l + 1) * ld + l + 1] - tr);
     double z = H[(l + 1) * ld + l] * H[(l + 2) * ld + l + 1];
+    const int dummyR = n * ld;  // row n: padding
     for (int k = l; k <= hi - 1; ++k) {
-      const int nr = (k < hi - 1) ? 3 : 2;
+      const bool three = (k < hi - 1);
+      const int nr = three ? 3 : 2;
+      const int jlo = (k > l) ? k - 1 : l;
+      const int ihi = (k + 3 < hi) ? k + 3 : hi;
       if (k > l) {
         x = H[k * ld + k - 1];
         y = H[(k + 1) * ld + k - 1];
-        z = (nr == 3) ? H[(k + 2) * ld + k - 1] : 0.0;
+        const double zz = H[(k + 2) * ld + k - 1];
+        z = three ? zz : 0.0;
       }
+      // groups: three entries each, at offset o, o + s, o + 2s; invalid
+      // groups point at padding
+      double aL[U][3], aR[U][3], aQ[U][3];
+      int oL[U], oR[U], oQ[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = jlo + t + NT * u;
+        const bool vl = (j < n) && (j < k || j >= k + nr);
+        oL[u] = k * ld + (vl ? j : n);
+        aL[u][0] = H[oL[u]];
+        aL[u][1] = H[oL[u] + ld];
+        aL[u][2] = H[oL[u] + 2 * ld];
+        const int i = t + NT * u;
+        const bool vr = (i <= ihi) && (i < k || i >= k + nr);
+        oR[u] = (vr ? i * ld : dummyR) + k;
+        aR[u][0] = H[oR[u]];
+        aR[u][1] = H[oR[u] + 1];
+        aR[u][2] = H[oR[u] + 2];
+        oQ[u] = ((i < n) ? i * ld : dummyR) + k;
+        aQ[u][0] = Q[oQ[u]];
+        aQ[u][1] = Q[oQ[u] + 1];
+        aQ[u][2] = Q[oQ[u] + 2];
+      }
+      double blk[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) blk[r][c] = H[(k + r) * ld + k + c];
       const double s = fabs(x) + fabs(y) + fabs(z);
-      __syncthreads();
-      if (s == 0.0) continue;
-      const double is = fast_rcp(s);
-      const double xs = x * is, ys = y * is, zs = z * is;
-      const double nrm = sqrt(xs * xs + ys * ys + zs * zs);
-      const double beta = (xs >= 0.0) ? -nrm : nrm;
-      const double tau = (beta - xs) * fast_rcp(beta);
-      const double iv = fast_rcp(xs - beta);
-      const double v1 = ys * iv, v2 = zs * iv;
-      const int jlo = (k > l) ? k - 1 : l;
-      for (int j = jlo + t; j < n; j += kQR) {
-        const double a0 = H[k * ld + j], a1 = H[(k + 1) * ld + j];
-        const double a2 = (nr == 3) ? H[(k + 2) * ld + j] : 0.0;
-        const double sm = tau * (a0 + v1 * a1 + v2 * a2);
-        H[k * ld + j] = a0 - sm;
-        H[(k + 1) * ld + j] = a1 - sm * v1;
-        if (nr == 3) H[(k + 2) * ld + j] = a2 - sm * v2;
+      if (s == 0.0) continue;  // uniform
+      const double ss = fma(z, z, fma(y, y, x * x));
+      double r = __builtin_amdgcn_rsq(ss);
+      double e = fma(-ss * r, r, 1.0);
+      r = fma(0.5 * r, e, r);
+      e = fma(-ss * r, r, 1.0);
+      r = fma(0.5 * r, e, r);
+      const double nrm = ss * r;
+      const double sg = (x >= 0.0) ? 1.0 : -1.0;
+      const double beta = -sg * nrm;
+      const double tau = (beta - x) * (-sg * r);
+      const double iv = fast_rcp(x - beta);
+      const double v1 = y * iv, v2 = three ? z * iv : 0.0;
+      const int sub = (k > l) ? k * ld + k - 1 : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double sl = tau * (aL[u][0] + v1 * aL[u][1] + v2 * aL[u][2]);
+        const bool zs = (oL[u] == sub);
+        H[oL[u]] = aL[u][0] - sl;
+        H[oL[u] + ld] = zs ? 0.0 : aL[u][1] - sl * v1;
+        H[oL[u] + 2 * ld] = zs ? 0.0 : aL[u][2] - sl * v2;
+        const double sr = tau * (aR[u][0] + v1 * aR[u][1] + v2 * aR[u][2]);
+        H[oR[u]] = aR[u][0] - sr;
+        H[oR[u] + 1] = aR[u][1] - sr * v1;
+        H[oR[u] + 2] = aR[u][2] - sr * v2;
+        const double sq = tau * (aQ[u][0] + v1 * aQ[u][1] + v2 * aQ[u][2]);
+        Q[oQ[u]] = aQ[u][0] - sq;
+        Q[oQ[u] + 1] = aQ[u][1] - sq * v1;
+        Q[oQ[u] + 2] = aQ[u][2] - sq * v2;
       }
-      __syncthreads();
-      const int ihi = (k + 3 < hi) ? k + 3 : hi;
-      for (int i = t; i < n; i += kQR) {
-        if (i <= ihi) {
-          const double a0 = H[i * ld + k], a1 = H[i * ld + k + 1];
-          const double a2 = (nr == 3) ? H[i * ld + k + 2] : 0.0;
-          const double sm = tau * (a0 + v1 * a1 + v2 * a2);
-          H[i * ld + k] = a0 - sm;
-          H[i * ld + k + 1] = a1 - sm * v1;
-          if (nr == 3) H[i * ld + k + 2] = a2 - sm * v2;
+      if (t == NT - 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double sm = tau * (blk[0][c] + v1 * blk[1][c] + v2 * blk[2][c]);
+          blk[0][c] -= sm;
+          blk[1][c] -= sm * v1;
+          blk[2][c] -= sm * v2;
         }
-        const double b0 = Q[i * ld + k], b1 = Q[i * ld + k + 1];
-        const double b2 = (nr == 3) ? Q[i * ld + k + 2] : 0.0;
-        const double sq = tau * (b0 + v1 * b1 + v2 * b2);
-        Q[i * ld + k] = b0 - sq;
-        Q[i * ld + k + 1] = b1 - sq * v1;
-        if (nr == 3) Q[i * ld + k + 2] = b2 - sq * v2;
-      }
-      __syncthreads();
-      if (k > l && t == 0) {
-        H[(k + 1) * ld + k - 1] = 0.0;
-        if (nr == 3) H[(k + 2) * ld + k - 1] = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr) {
+          const double sm = tau * (blk[rr][0] + v1 * blk[rr][1] + v2 * blk[rr][2]);
+          blk[rr][0] -= sm;
+          blk[rr][1] -= sm * v1;
+          blk[rr][2] -= sm * v2;
+        }
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (rr < nr && c < nr) H[(k + rr) * ld + k + c] = blk[rr][c];
       }
       __syncthreads();
     }
   }
   __syncthreads();
   *sweeps = total;
+  *steps = nsteps;
   return true;
 }
 
-// LDS: H n*n | Q n*n
+
+// LDS: H (n + 1) x ld | Q (n + 1) x ld, ld = (n + 1) | 1
 __global__ __launch_bounds__(kQR) void k_tharm_qr(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   extern __shared__ double sm[];
   __shared__ int idx[256];
-  __shared__ double hn;
   const int t = threadIdx.x;
   const int n = kept_slots(b.keep, p.m, idx);
-  // odd row stride (in doubles) so that column sweeps of the 64 lanes
-  // spread over the LDS banks
-  const int ld = n | 1;
+  // odd row stride (in doubles) so that column sweeps spread over the LDS
+  // banks, and at least n + 1 for the padding column
+  const int ld = (n + 1) | 1;
   double* H = sm;
-  double* Q = H + n * ld;
+  double* Q = H + (n + 1) * ld;
   const double* gH = b.work + n * n;
   const double* gQ = b.work + 2 * n * n;
+  for (int e = t; e < 2 * (n + 1) * ld; e += kQR) sm[e] = 0.0;
+  __syncthreads();
   for (int e = t; e < n * n; e += kQR) {
     const int i = e / n, j = e - i * n;
     H[i * ld + j] = gH[e];
     Q[i * ld + j] = gQ[e];
   }
   __syncthreads();
+  __shared__ double red[kQR / 64];
+  const double hn = block_fro(H, n, ld, red);
+  if (t == 0) st->tphase[4] = clock64();
+  int sweeps = 0, steps = 0;
+  const bool ok = francis_qr(H, Q, n, ld, hn > 0.0 ? hn : 1.0, &sweeps, &steps);
   if (t == 0) {
-    double s = 0.0;
-    for (int e = 0; e < n * n; ++e) s += gH[e] * gH[e];
-    hn = sqrt(s);
-    st->tphase[4] = clock64();
+    st->tphase[10] = steps;
+    st->tphase[11] = sweeps;
   }
-  __syncthreads();
-  int sweeps = 0;
-  const bool ok = francis_qr(H, Q, n, ld, hn > 0.0 ? hn : 1.0, &sweeps);
-  if (t == 0) st->tphase[11] = sweeps;
   if (!ok) {
     if (t == 0) {
       st->error = PLHR_ERR_BREAKDOWN;
@@ -418,19 +543,20 @@ __global__ __launch_bounds__(kQR) void k_tharm_qr(SmallParams p, SmallBufs b, De
 }
 
 // ---------------------------------------------------------- eigenvectors
-// LDS: L n*n | T n*n | Q n*n | Xre n*ks | Xim n*ks | 5n doubles | 5n ints
+// LDS: T n*n | Q n*n | Xre n*ks | Xim n*ks | 5n doubles | 5n ints.  L is
+// read from the work area; once the eigenvectors of T are known, the T
+// region holds the real parts of Y and the Xre region the imaginary parts.
 __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   extern __shared__ double sm[];
   __shared__ int idx[256];
-  __shared__ double hn;
   const int m = p.m, kint = p.kint, t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   const int n = kept_slots(b.keep, m, idx);
   const int ks = kint;
   const int ld = n | 1;  // odd row stride (LDS banks)
-  double* L = sm;
-  double* T = L + n * ld;
+  const double* L = b.work;  // compact, row stride n
+  double* T = sm;
   double* Q = T + n * ld;
   double* Xre = Q + n * ld;
   double* Xim = Xre + n * ks;
@@ -444,17 +570,15 @@ __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs 
   int* selcol = rnk + n;
   int* selkind = selcol + n;
   int* order = selkind + n;
-  for (int e = t; e < 3 * n * n; e += kNT) {
-    const int mat = e / (n * n), r = e - mat * n * n;
-    const int i = r / n, j = r - i * n;
-    sm[mat * n * ld + i * ld + j] = b.work[e];
+  for (int e = t; e < n * n; e += kNT) {
+    const int i = e / n, j = e - i * n;
+    T[i * ld + j] = b.work[n * n + e];
+    Q[i * ld + j] = b.work[2 * n * n + e];
   }
   __syncthreads();
+  __shared__ double red[kNT / 64];
+  const double hn = block_fro(T, n, ld, red);
   if (t == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) s += T[i * ld + j] * T[i * ld + j];
-    hn = sqrt(s);
     st->tphase[6] = clock64();
     // eigenvalues tau from the 1x1 and 2x2 blocks; a complex block's
     // leader is the member with Im tau < 0 (its xi has Im > 0)
@@ -591,11 +715,11 @@ __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs 
   const int nsel = nsel_s;
   // Q <- L^-T Q (solve L^T Y = Q, right-looking from the last row)
   for (int i = n - 1; i >= 0; --i) {
-    const double inv = 1.0 / L[i * ld + i];
+    const double inv = 1.0 / L[i * n + i];
     for (int c = t; c < n; c += kNT) Q[i * ld + c] *= inv;
     __syncthreads();
     for (int r = ty; r < i; r += 16) {
-      const double lir = L[i * ld + r];
+      const double lir = L[i * n + r];
       for (int c = tx; c < n; c += 16) Q[r * ld + c] -= lir * Q[i * ld + c];
     }
     __syncthreads();
@@ -710,19 +834,24 @@ __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs 
   }
   __syncthreads();
   if (t == 0) st->tphase[9] = clock64();
-  // y = (L^-T Q) x into the L (re) and T (im) regions
-  double* Yre = L;
-  double* Yim = T;
+  // y = (L^-T Q) x: real parts into the T region (free after the back
+  // substitution), then imaginary parts into the Xre region (free once the
+  // real parts are formed)
+  double* Yre = T;
+  double* Yim = Xre;
+  for (int e = t; e < n * nsel; e += kNT) {
+    const int i = e / nsel, si = e - i * nsel;
+    const int u = selcol[order[si]];
+    double sr = 0.0;
+    for (int q = 0; q < n; ++q) sr += Q[i * ld + q] * Xre[q * ks + u];
+    Yre[i * ks + u] = sr;
+  }
   __syncthreads();
   for (int e = t; e < n * nsel; e += kNT) {
     const int i = e / nsel, si = e - i * nsel;
     const int u = selcol[order[si]];
-    double sr = 0.0, sim = 0.0;
-    for (int q = 0; q < n; ++q) {
-      sr += Q[i * ld + q] * Xre[q * ks + u];
-      sim += Q[i * ld + q] * Xim[q * ks + u];
-    }
-    Yre[i * ks + u] = sr;
+    double sim = 0.0;
+    for (int q = 0; q < n; ++q) sim += Q[i * ld + q] * Xim[q * ks + u];
     Yim[i * ks + u] = sim;
   }
   for (int e = t; e < m * kint; e += kNT) b.Y[e] = 0.0;
@@ -756,10 +885,10 @@ __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs 
   }
 }
 
-static size_t reduce_lds(int m) { return ((size_t)3 * m * (m | 1) + 2 * m + kNT) * sizeof(double); }
-static size_t qr_lds(int m) { return (size_t)2 * m * (m | 1) * sizeof(double); }
+static size_t reduce_lds(int m) { return ((size_t)2 * m * (m | 1) + 2 * m + kNT) * sizeof(double); }
+static size_t qr_lds(int m) { return (size_t)2 * (m + 1) * ((m + 1) | 1) * sizeof(double); }
 static size_t vectors_lds(int m, int kint) {
-  return ((size_t)3 * m * (m | 1) + 2 * (size_t)m * kint + 5 * m) * sizeof(double) +
+  return ((size_t)2 * m * (m | 1) + 2 * (size_t)m * kint + 5 * m) * sizeof(double) +
          5 * m * sizeof(int);
 }
 

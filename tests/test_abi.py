@@ -65,5 +65,6 @@ def test_workspace_size_and_validation():
     assert _ws(a, t3, 1.0, 4)[0] == L.ERR_ARG          # 64 not divisible by 2^7
     small = _fd3(2)
     assert _ws(small, None, 1.0, 4)[0] == L.ERR_ARG     # 4 (k + k_extra) > n
-    assert _ws(a, None, 1.0, 17)[0] == L.ERR_UNSUPPORTED  # projected problem too large
+    assert _ws(a, None, 1.0, 20)[0] == 0                  # m = 84, the largest supported
+    assert _ws(a, None, 1.0, 21)[0] == L.ERR_UNSUPPORTED  # m = 88: projected problem too large
     assert b"4*(k + k_extra)" in L.load().plhr_last_error()

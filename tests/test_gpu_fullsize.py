@@ -48,7 +48,7 @@ def test_bench_workload_full_size():
     normA = 12.0 / w.h**2
     tol = 1e-8 * gap / (normA + abs(w.sigma))        # ||r|| <= 1e-8 * gap
     S = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=k, k_extra=w.k_extra,
-               tol=tol, max_iters=8000, check_every=20,
+               tol=tol, max_iters=8000, check_every=20, lock=w.lock,
                precond={"levels": w.mg_levels, "nu": 2, "omega": 2 / 3})
     V0 = torch.from_numpy(w.v0()).to("cuda")
     r = S.solve(V0)
