@@ -62,6 +62,32 @@ def pick_sigma(N, h, mode):
     return u[i - 1] + 0.4 * (u[i] - u[i - 1]), ev
 
 
+# categories whose work is a dense contraction (matrix cores)
+CONTRACTIONS = ("gram", "transform", "update")
+# single-workgroup kernels: plain ALU work on one compute unit
+SINGLE_WG = ("tharm_reduce", "tharm_qr", "tharm_vectors", "ortho", "small_other")
+
+
+def roofline_entry(cat, p):
+    """Roofline of one kernel category from its algorithmic bytes/flops and
+    its event-measured time.  Contractions take the binding one of the HBM
+    and FP64-MFMA roofs (the larger fraction); single-workgroup kernels are
+    plain FP64 ALU work against the chip's FP64 vector peak; the rest are
+    HBM-bound stencil/vector sweeps."""
+    sec = p["ms"] * 1e-3
+    gbs = p["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    tfs = p["flops"] / sec / 1e12 if sec > 0 else 0.0
+    if cat in SINGLE_WG:
+        return {"bound": "alu", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": tfs / FP64_PEAK_TFS, "traffic": None}
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+    if cat in CONTRACTIONS and tfs / FP64_PEAK_TFS > hbm["frac"]:
+        return {"bound": "mfma", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": tfs / FP64_PEAK_TFS, "traffic": None}
+    return hbm
+
+
 def cpu_baseline(w, sigma, k, kx, lock, gpu_iters, budget_s):
     """The oracle as it stands, on the host cores, for a bounded number of
     iterations of the same workload; extrapolated to the GPU's iteration
@@ -179,24 +205,17 @@ def main():
     value = (k * sum(1 for c, r in zip(conv, correct) if c and r) / el)
 
     p = prof[dom]
-    if dom in ("gram", "rowmul"):
-        ach = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
-        roof = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFS, "traffic": None}
-    elif dom == "small":
-        # latency-bound single-workgroup kernels: report their share of time
-        roof = {"bound": "alu", "achieved": p["ms"] / max(1, p["launches"]) * 1e3,
-                "peak": None, "unit": "us/launch", "frac": None, "traffic": None}
-    else:
-        ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None}
-    roof["kernel"] = dom
+    roof = roofline_entry(dom, p)
+    roof["kernel"] = L.KCAT_KERNELS[dom_id]
+    roof["launches"] = p["launches"]
     roof["avg_launch_us"] = 1e3 * p["ms"] / max(1, p["launches"])
-    roof["algorithmic_bytes_per_launch"] = p["bytes"] / max(1, p["launches"])
+    roof["algorithmic_per_launch"] = (p["bytes"] if roof["unit"] == "GB/s" else p["flops"]) / max(1, p["launches"])
     roof["share_of_step"] = p["ms"] / (1e3 * el)
-    breakdown = {c: round(prof_all[c]["ms"], 3) for c in cats}
-
+    kernels = {}
+    for c in cats:
+        e = roofline_entry(c, prof_all[c])
+        kernels[c] = {"ms_per_step": round(prof_all[c]["ms"], 3), "bound": e["bound"],
+                      "achieved": round(e["achieved"], 2), "unit": e["unit"], "frac": round(e["frac"], 5)}
     out = {
         "metric": "converged eigenpairs/s at rel. residual 1e-8 (FP64)",
         "value": value,
@@ -216,7 +235,7 @@ def main():
                    "n": w.n, "k": k, "k_extra": kx, "iterations": iters, "converged": conv,
                    "matches_closed_form": correct},
         "roofline": roof,
-        "kernel_ms_per_step": {c: v / 1.0 for c, v in breakdown.items()},
+        "kernels": kernels,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, sigma, k, kx, args.lock, int(np.median(iters)),

@@ -218,18 +218,23 @@ plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, 
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */
 plhr_status plhr_get_state(plhr_ctx ctx, double* lam, double* V);
 
-/* Kernel-category launch profile (HIP events around every launch).
- * Categories: 0 operator block products, 1 V-cycle smoothing sweeps,
- * 2 V-cycle transfers and coarse solve, 3 Gram products, 4 B-orthonormal
- * transform and Ritz-vector update, 5 projected-problem kernels,
- * 6 residual formation, reductions and copies.
+/* Per-kernel launch profile (HIP events around every launch).
+ * Categories (PLHR_KC_*): 0 operator block products, 1 V-cycle Jacobi
+ * sweeps, 2 V-cycle residual, 3 restriction, 4 prolongation,
+ * 5 coarsest-level solve, 6 Gram products, 7 Gram reduction,
+ * 8 orthonormalising transform, 9 block update, 10 Cholesky /
+ * C / Hessenberg of the projected problem, 11 Francis QR, 12 selection
+ * and eigenvectors, 13 Cholesky-QR factor, 14 other single-workgroup
+ * kernels, 15 residual formation, column reductions and copies.
  * bytes/flops are algorithmic (what the operation must read, write and
- * compute); total_ms sums the event-measured kernel durations.           */
+ * compute; model operation counts for the single-workgroup kernels);
+ * total_ms sums the event-measured kernel durations.                    */
+#define PLHR_KC_COUNT 16
 typedef struct {
-  int32_t launches[8];
-  double total_ms[8];
-  double bytes[8];
-  double flops[8];
+  int32_t launches[PLHR_KC_COUNT];
+  double total_ms[PLHR_KC_COUNT];
+  double bytes[PLHR_KC_COUNT];
+  double flops[PLHR_KC_COUNT];
   int32_t truncated;  /* 1 if more launches happened than were recorded */
   int32_t reserved0;
 } plhr_profile;

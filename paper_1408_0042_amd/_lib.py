@@ -46,13 +46,23 @@ class IterInfo(C.Structure):
                 ("n_excluded", C.c_int32), ("reserved0", C.c_int32)]
 
 
+KC_COUNT = 16
+
+
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int32 * 8), ("total_ms", C.c_double * 8),
-                ("bytes", C.c_double * 8), ("flops", C.c_double * 8),
+    _fields_ = [("launches", C.c_int32 * KC_COUNT), ("total_ms", C.c_double * KC_COUNT),
+                ("bytes", C.c_double * KC_COUNT), ("flops", C.c_double * KC_COUNT),
                 ("truncated", C.c_int32), ("reserved0", C.c_int32)]
 
 
-KCAT_NAMES = ["stencil", "vcycle_smooth", "vcycle_transfer", "gram", "rowmul", "small", "vec"]
+KCAT_NAMES = ["stencil", "jacobi", "mg_residual", "restrict", "prolong", "coarse_solve", "gram",
+              "gram_reduce", "transform", "update", "tharm_reduce", "tharm_qr", "tharm_vectors",
+              "ortho", "small_other", "vec"]
+# the HIP kernel each category times
+KCAT_KERNELS = ["k_fd_apply", "k_jacobi", "k_residual", "k_restrict", "k_prolong_add",
+                "k_dense_apply", "k_gram_mfma", "k_gram_reduce8", "k_rowmul_mfma (transform)",
+                "k_rowmul_mfma (update)", "k_tharm_reduce", "k_tharm_qr", "k_tharm_vectors",
+                "k_ortho_small", "k_rq_small, k_conv_check", "k_resid_prep, k_xdots, k_copy"]
 
 
 class PLHRError(RuntimeError):

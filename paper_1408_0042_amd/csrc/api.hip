@@ -38,6 +38,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static_assert(KC_COUNT == PLHR_KC_COUNT, "profile categories");
 static constexpr int kRefreshT = 10;  // iterations between T(A - sigma B)V refreshes
 
 // Per-launch event profiling (see KCat).  The driver points g_prof at the

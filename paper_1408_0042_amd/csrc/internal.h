@@ -67,14 +67,23 @@ enum : int {
 // flops (what the operation must read, write and compute, not what the
 // hardware moves) are accumulated.
 enum KCat : int {
-  KC_STENCIL = 0,   // operator block products
-  KC_SMOOTH = 1,    // V-cycle Jacobi sweeps
-  KC_TRANSFER = 2,  // V-cycle residual, restriction, prolongation, coarse solve
-  KC_GRAM = 3,      // Gram products and their reduction
-  KC_ROWMUL = 4,    // orthonormalising transform and Ritz-vector update
-  KC_SMALL = 5,     // single-workgroup projected-problem kernels
-  KC_VEC = 6,       // residual formation, column reductions, copies
-  KC_COUNT = 7
+  KC_STENCIL = 0,        // operator block products (k_fd_apply)
+  KC_JACOBI = 1,         // V-cycle weighted-Jacobi sweeps
+  KC_RESIDUAL = 2,       // V-cycle residual before restriction
+  KC_RESTRICT = 3,       // V-cycle restriction
+  KC_PROLONG = 4,        // V-cycle prolongation and correction
+  KC_COARSE = 5,         // V-cycle coarsest-level dense solve
+  KC_GRAM = 6,           // Gram products (per-workgroup partials)
+  KC_GRAM_REDUCE = 7,    // reduction of the Gram partials
+  KC_TRANSFORM = 8,      // orthonormalising transform Z <- Z M
+  KC_UPDATE = 9,         // block update V, P <- Zhat Y'
+  KC_THARM_REDUCE = 10,  // Cholesky of G_L, C, Hessenberg reduction
+  KC_THARM_QR = 11,      // Francis QR of the Hessenberg matrix
+  KC_THARM_VECTORS = 12, // selection and eigenvectors of the projected problem
+  KC_ORTHO = 13,         // Cholesky-QR factor of the Gram of Z
+  KC_SMALL = 14,         // other single-workgroup kernels (RQ, convergence)
+  KC_VEC = 15,           // residual formation, column reductions, copies
+  KC_COUNT = 16  // PLHR_KC_COUNT
 };
 void prof_begin(int cat, double bytes, double flops, hipStream_t s);
 void prof_end(int cat, hipStream_t s);

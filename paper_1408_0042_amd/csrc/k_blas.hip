@@ -207,10 +207,10 @@ void launch_gram(size_t n, const double* X, int ldx, int mx, const double* Y1, i
                      ldy2, my, part, st);
   prof_end(KC_GRAM, s);
   const int total = mx * my;
-  prof_begin(KC_VEC, (double)nblk * total * 8.0, (double)nblk * total, s);
+  prof_begin(KC_GRAM_REDUCE, (double)nblk * total * 8.0, (double)nblk * total, s);
   hipLaunchKernelGGL(k_gram_reduce, dim3((total + 255) / 256), dim3(256), 0, s, part, nblk, total,
                      out, st);
-  prof_end(KC_VEC, s);
+  prof_end(KC_GRAM_REDUCE, s);
 }
 
 // ----------------------------------------------- row-block right multiply
@@ -353,10 +353,10 @@ void launch_transform(size_t n, double* const* X, int nx, int ld, int m, const d
   const int threads = (kRB / 4) * ((m + 3) / 4);
   const size_t ntiles = (n + kRB - 1) / kRB;
   const int nb = (int)(ntiles < 2048 ? ntiles : 2048);
-  prof_begin(KC_ROWMUL, 2.0 * nx * n * m * 8.0, 2.0 * nx * n * (double)m * m, s);
+  prof_begin(KC_TRANSFORM, 2.0 * nx * n * m * 8.0, 2.0 * nx * n * (double)m * m, s);
   hipLaunchKernelGGL(k_rowmul, dim3(nb), dim3(threads), rowmul_shm(m, m, 0), s, n, a, nx, ld, m,
                      M, m, 0, 0, 0, 0, (double*)nullptr, st);
-  prof_end(KC_ROWMUL, s);
+  prof_end(KC_TRANSFORM, s);
 }
 
 int launch_update(size_t n, double* const* X, int nx, int ld, int m, int kv, const double* Y,
@@ -365,10 +365,10 @@ int launch_update(size_t n, double* const* X, int nx, int ld, int m, int kv, con
   for (int i = 0; i < nx; ++i) a.a[i] = X[i];
   const int kout = 2 * kc;
   const int threads = (kRB / 4) * ((kout + 3) / 4);
-  prof_begin(KC_ROWMUL, (double)nx * n * (m + kout) * 8.0, 2.0 * nx * n * (double)m * kout, s);
+  prof_begin(KC_UPDATE, (double)nx * n * (m + kout) * 8.0, 2.0 * nx * n * (double)m * kout, s);
   hipLaunchKernelGGL(k_rowmul, dim3(kRedBlocks), dim3(threads), rowmul_shm(m, kout, kc), s, n, a,
                      nx, ld, m, Y, kout, 1, kv, kc, pcol, part, st);
-  prof_end(KC_ROWMUL, s);
+  prof_end(KC_UPDATE, s);
   return kRedBlocks;
 }
 

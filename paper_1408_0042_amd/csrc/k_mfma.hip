@@ -132,10 +132,10 @@ void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* 
 #undef GRAM_CASE
   prof_end(KC_GRAM, s);
   const int total = mx * my;
-  prof_begin(KC_VEC, (double)nblk * total * 8.0, (double)nblk * total, s);
+  prof_begin(KC_GRAM_REDUCE, (double)nblk * total * 8.0, (double)nblk * total, s);
   hipLaunchKernelGGL(k_gram_reduce8, dim3((total + 31) / 32), dim3(256), 0, s, part, nblk, total,
                      out, st);
-  prof_end(KC_VEC, s);
+  prof_end(KC_GRAM_REDUCE, s);
 }
 
 // ------------------------------------------------------------ row product
@@ -271,7 +271,8 @@ void launch_rowmul_mfma(size_t n, double* const* X, int narr, int ld, int m, con
   const int TJ = (kout + 15) / 16;
   const size_t shm = rowmul_mfma_shm(m, kout, mode == 1 ? kc : 0);
   const double bytes = (mode == 0) ? 2.0 * narr * n * m * 8.0 : (double)narr * n * (m + kout) * 8.0;
-  prof_begin(KC_ROWMUL, bytes, 2.0 * narr * n * (double)m * kout, s);
+  const int cat = (mode == 0) ? KC_TRANSFORM : KC_UPDATE;
+  prof_begin(cat, bytes, 2.0 * narr * n * (double)m * kout, s);
 #define ROW_CASE(T)                                                                             \
   case T:                                                                                       \
     hipLaunchKernelGGL(k_rowmul_mfma<T>, dim3(nblk), dim3(256), shm, s, n, a, narr, ld, m, M,  \
@@ -283,7 +284,7 @@ void launch_rowmul_mfma(size_t n, double* const* X, int narr, int ld, int m, con
     default: break;
   }
 #undef ROW_CASE
-  prof_end(KC_ROWMUL, s);
+  prof_end(cat, s);
 }
 
 hipError_t mfma_set_attributes(int m, int kint) {

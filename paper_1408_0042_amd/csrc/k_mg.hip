@@ -345,14 +345,14 @@ static double* cycle(MG& mg, int lev, const double* r, int ldr, Blk out0, Blk ou
     if (lev == 0) {
       // single-level "cycle": dense solve on the finest grid
       launch_copy(g.n(), r, ldr, L.t, ncols, ncols, s);
-      PROF_LAUNCH(KC_TRANSFER, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
+      PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
                   k_dense_apply, dim3(nbk), blk, 0, s, mg.nc, mg.coarse_inv, L.t, L.x, ncols, st);
       if (split > 0) launch_copy(g.n(), L.x, ncols, out0.ptr, out0.ld, split, s);
       if (split < ncols)
         launch_copy(g.n(), L.x + split, ncols, out1.ptr, out1.ld, ncols - split, s);
       return nullptr;
     }
-    PROF_LAUNCH(KC_TRANSFER, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
+    PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
                 k_dense_apply, dim3(nbk), blk, 0, s, mg.nc, mg.coarse_inv, r, L.x, ncols, st);
     return L.x;
   }
@@ -361,32 +361,32 @@ static double* cycle(MG& mg, int lev, const double* r, int ldr, Blk out0, Blk ou
   double* oth = L.t;
   // pre-smoothing from a zero guess (nu_pre >= 1)
   for (int it = 0; it < mg.nu_pre; ++it) {
-    PROF_LAUNCH(KC_SMOOTH, (it == 0 ? 2.0 : 3.0) * nb, (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl,
+    PROF_LAUNCH(KC_JACOBI, (it == 0 ? 2.0 : 3.0) * nb, (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl,
                 k_jacobi<DIM>, dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
                 it == 0 ? (const double*)nullptr : (const double*)cur, r, ldr, oth, ncols, oth,
                 ncols, ncols, ncols, st);
     std::swap(cur, oth);
   }
   // residual -> oth, restrict -> coarse r, coarse cycle, prolongate into cur
-  PROF_LAUNCH(KC_TRANSFER, 3.0 * nb, (2.0 * DIM + 3.0) * fl, k_residual<DIM>, dim3(rows), blk, 0,
+  PROF_LAUNCH(KC_RESIDUAL, 3.0 * nb, (2.0 * DIM + 3.0) * fl, k_residual<DIM>, dim3(rows), blk, 0,
               s, g.nx, g.ny, g.nz, diag, off, cur, r, ldr, oth, ncols, st);
   MGLevel& C = mg.lv[lev + 1];
   const int crows = C.g.ny * C.g.nz;
-  PROF_LAUNCH(KC_TRANSFER, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+  PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
               k_restrict<DIM>, dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, C.r, ncols, st);
   double* ec = cycle<DIM>(mg, lev + 1, C.r, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
                           ncols, st, s);
-  PROF_LAUNCH(KC_TRANSFER, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+  PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
               k_prolong_add<DIM>, dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols, st);
   // post-smoothing (nu_post >= 1); at level 0 the last sweep writes the output
   for (int it = 0; it < mg.nu_post; ++it) {
     if (it == mg.nu_post - 1 && lev == 0) {
-      PROF_LAUNCH(KC_SMOOTH, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
+      PROF_LAUNCH(KC_JACOBI, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
                   g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, out0.ptr, out0.ld, out1.ptr,
                   out1.ld, split, ncols, st);
       return nullptr;
     }
-    PROF_LAUNCH(KC_SMOOTH, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
+    PROF_LAUNCH(KC_JACOBI, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
                 g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, oth, ncols, oth, ncols, ncols, ncols,
                 st);
     std::swap(cur, oth);

@@ -450,9 +450,11 @@ void launch_conv_check(const SmallParams& p, const double* part, int nblk, Small
 }
 void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
   const size_t lds = ((size_t)2 * p.m * p.m + p.m) * sizeof(double);
-  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  // model count: Cholesky m^3/3, inverse of the factor m^3/3, scaling
+  const double m3 = (double)p.m * p.m * p.m;
+  prof_begin(KC_ORTHO, 2.0 * p.m * p.m * 8.0, 2.0 * m3 / 3.0, s);
   hipLaunchKernelGGL(k_ortho_small, dim3(1), dim3(256), lds, s, p, b, st);
-  prof_end(KC_SMALL, s);
+  prof_end(KC_ORTHO, s);
 }
 void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                      DevStatus* st, int end_of_iteration, hipStream_t s) {

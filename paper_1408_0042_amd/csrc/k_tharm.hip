@@ -905,15 +905,21 @@ hipError_t tharm_set_attributes(int m, int kint) {
 }
 
 void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
-  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  // model operation counts at the full width m (the kept width is known
+  // only on the device): Cholesky m^3/3, C = L^-1 G_R L^-T 2m^3,
+  // Hessenberg reduction with Q 14m^3/3; Francis QR to the real Schur
+  // form with Schur vectors about 20m^3 (two double-shift sweeps per
+  // eigenvalue pair); L^-T Q m^3 and Y = (L^-T Q) X 2 m^2 kint
+  const double m3 = (double)p.m * p.m * p.m, mm = (double)p.m * p.m;
+  prof_begin(KC_THARM_REDUCE, 2.0 * mm * 8.0 + 3.0 * mm * 8.0, (1.0 / 3.0 + 2.0 + 14.0 / 3.0) * m3, s);
   hipLaunchKernelGGL(k_tharm_reduce, dim3(1), dim3(kNT), reduce_lds(p.m), s, p, b, st);
-  prof_end(KC_SMALL, s);
-  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  prof_end(KC_THARM_REDUCE, s);
+  prof_begin(KC_THARM_QR, 4.0 * mm * 8.0, 20.0 * m3, s);
   hipLaunchKernelGGL(k_tharm_qr, dim3(1), dim3(kQR), qr_lds(p.m), s, p, b, st);
-  prof_end(KC_SMALL, s);
-  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  prof_end(KC_THARM_QR, s);
+  prof_begin(KC_THARM_VECTORS, 3.0 * mm * 8.0 + mm * 8.0, m3 + 2.0 * mm * p.kint, s);
   hipLaunchKernelGGL(k_tharm_vectors, dim3(1), dim3(kNT), vectors_lds(p.m, p.kint), s, p, b, st);
-  prof_end(KC_SMALL, s);
+  prof_end(KC_THARM_VECTORS, s);
 }
 
 }  // namespace plhr
