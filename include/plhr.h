@@ -97,7 +97,16 @@ typedef struct {
   double omega;
 } plhr_prec_desc;
 
-typedef enum { PLHR_PREC_FP64 = 0 } plhr_precision;
+/* Arithmetic of the preconditioner.  PLHR_PREC_MIXED runs the multigrid
+ * V-cycles that produce search directions (W = T R and S) in FP32
+ * (storage and arithmetic on every level, FP64 input and output blocks).
+ * The products that enter the T-harmonic Grams, T(A - sigma B)Z, keep the
+ * FP64 V-cycle: G_L = Z^*(A - sigma B)T(A - sigma B)Z spans many orders of
+ * magnitude and loses definiteness with an FP32 T.  Every other step
+ * (operator products, residuals, Grams, Cholesky-QR, projected problem,
+ * block updates, convergence test) stays in FP64, so the converged pairs
+ * meet the same FP64 tolerance.  No effect when T is the identity.      */
+typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
 
 /* Solver options (plhr_options_default fills the defaults shown).
  *   tol          relative residual ||A v - lam B v|| /
@@ -106,7 +115,7 @@ typedef enum { PLHR_PREC_FP64 = 0 } plhr_precision;
  *   max_iters    iteration limit                              (10000)
  *   k_extra      extra block columns; 1 for real problems so that a
  *                conjugate pair is not cut (Section 4.1)      (1)
- *   precision    PLHR_PREC_FP64                               (FP64)
+ *   precision    PLHR_PREC_FP64 or PLHR_PREC_MIXED            (FP64)
  *   lock         soft locking of converged columns            (1)
  *   check_every  iterations between host convergence checks   (1)
  *   drop_tol     squared relative norm below which a W/S/P column is
@@ -208,7 +217,8 @@ plhr_status plhr_eigvals_backward(plhr_ctx ctx, const double* dL_dlambda, double
                                   int32_t accumulate);
 
 /* Apply one operator of the context to a block (no iteration state used).
- *   which  0: Y = A X;  1: Y = (A - sigma B) X;  2: Y = T X
+ *   which  0: Y = A X;  1: Y = (A - sigma B) X;  2: Y = T X (in the
+ *          precision used for search directions: FP32 V-cycle in mixed)
  *   X, Y   device, n x ncols doubles, point-major; must not overlap
  *   ncols  1 <= ncols <= 2*(k + k_extra)                                  */
 plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, int32_t ncols);

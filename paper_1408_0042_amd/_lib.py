@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 OP_IDENTITY, OP_FD5_2D, OP_FD7_3D = 0, 1, 2
 F64 = 0
 PREC_IDENTITY, PREC_MG_VCYCLE = 0, 1
-PRECISION_FP64 = 0
+PRECISION_FP64, PRECISION_MIXED = 0, 1
 
 
 class OpDesc(C.Structure):

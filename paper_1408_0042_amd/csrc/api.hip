@@ -177,8 +177,11 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
   }
   if (opt) {
     if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
-        !(opt->drop_tol > 0.0) || opt->precision != PLHR_PREC_FP64) {
-      set_error("invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, FP64)");
+        !(opt->drop_tol > 0.0) ||
+        (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED)) {
+      set_error(
+          "invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, "
+          "precision FP64 or MIXED)");
       return PLHR_ERR_ARG;
     }
   }
@@ -298,10 +301,14 @@ void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const d
 }
 
 // T applied to ncols columns of R (ld ldr); output split at `split`.
+// `direction`: the result only spans search directions (W, S), so the
+// mixed mode may compute it with the FP32 V-cycle; products that enter the
+// T-harmonic Grams (T(A - sigma B)Z) always use the FP64 V-cycle.
 void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split, int ncols,
-             const DevStatus* st) {
+             const DevStatus* st, bool direction = false) {
   if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
-    mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, st, c->stream);
+    const bool f32 = direction && c->opt.precision == PLHR_PREC_MIXED;
+    mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, f32, st, c->stream);
   } else {
     if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream);
     if (split < ncols) launch_copy(c->n, Rin + split, ldr, o1.ptr, o1.ld, ncols - split, c->stream);
@@ -371,12 +378,17 @@ void enqueue_iteration(plhr_ctx_s* c) {
                          s);
   launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
   // W = T (A V - B V Lam)
-  precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st);
+  precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st, true);
   // QW = (A - sigma) W;  R = [QW - W (Lam - sigma) | QW]
   stencil(c, Z + kint, m, Blk{QZ + kint, m}, Blk{R, 2 * kint}, c->sb.lam, Blk{R + kint, 2 * kint},
           kint, c->sigma, st);
   // S = T (A W - B W Lam), TQW = T (A - sigma) W
-  precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, Blk{TQZ + kint, m}, kint, 2 * kint, st);
+  if (c->opt.precision == PLHR_PREC_MIXED) {
+    precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
+    precond(c, R + kint, 2 * kint, Blk{TQZ + kint, m}, none, kint, kint, st);
+  } else {
+    precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, Blk{TQZ + kint, m}, kint, 2 * kint, st);
+  }
   // QS = (A - sigma) S ; TQS = T QS
   stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st);
   precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
@@ -716,7 +728,7 @@ plhr_status plhr_apply(plhr_ctx c, int32_t which, const double* X, double* Y, in
     stencil(c, X, ncols, Blk{Y, ncols}, none, nullptr, none, ncols, which == 1 ? c->sigma : 0.0,
             nullptr);
   } else if (which == 2) {
-    precond(c, X, ncols, Blk{Y, ncols}, none, ncols, ncols, nullptr);
+    precond(c, X, ncols, Blk{Y, ncols}, none, ncols, ncols, nullptr, true);
   } else {
     set_error("plhr_apply: which must be 0, 1 or 2");
     return PLHR_ERR_ARG;

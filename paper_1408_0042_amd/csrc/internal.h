@@ -127,15 +127,17 @@ struct MG {
   int cmax = 0;
   std::vector<MGLevel> lv;
   double* coarse_inv = nullptr;  // nc x nc, row-major
+  float* coarse_inv32 = nullptr;  // the same in FP32
   int nc = 0;
 };
 size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax);
 plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_post, double omega,
                      int cmax, char*& ws, hipStream_t s);
 // X_out = T R (ncols columns).  Output may be split over two blocks:
-// columns [0, split) go to out0, [split, ncols) to out1.
+// columns [0, split) go to out0, [split, ncols) to out1.  f32: level
+// storage and arithmetic in FP32 (FP64 input and output).
 void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, int ncols,
-              const DevStatus* st, hipStream_t s);
+              bool f32, const DevStatus* st, hipStream_t s);
 
 // Dense level-0 helpers (k_blas.hip)
 // residual prep: R[:, c] = QV[:, c] - V[:, c] * (lam[c] - sigma); partial

@@ -24,12 +24,29 @@
 
 namespace plhr {
 
-template <int DIM>
-__device__ __forceinline__ double nb_sum(const double* xp, int i, int j, int l, int nx, int ny,
-                                         int nz, int ld) {
+// Thread layout of the row kernels: `ncols` consecutive threads share one
+// grid point (thread t: column t % ncols, point t / ncols), P = blockDim /
+// ncols points per pass; the remaining blockDim % ncols threads idle.  No
+// division inside the loops.
+struct RowLanes {
+  int c, i0, P;
+  bool on;
+};
+__device__ __forceinline__ RowLanes row_lanes(int ncols) {
+  RowLanes r;
+  r.P = blockDim.x / ncols;
+  r.c = threadIdx.x % ncols;
+  r.i0 = threadIdx.x / ncols;
+  r.on = r.i0 < r.P;
+  return r;
+}
+
+template <int DIM, typename S>
+__device__ __forceinline__ S nb_sum(const S* xp, int i, int j, int l, int nx, int ny, int nz,
+                                    int ld) {
   const ptrdiff_t sy = (ptrdiff_t)nx * ld;
   const ptrdiff_t sz = (ptrdiff_t)nx * ny * ld;
-  double nb = 0.0;
+  S nb = 0;
   if (i > 0) nb += xp[-ld];
   if (i < nx - 1) nb += xp[ld];
   if (j > 0) nb += xp[-sy];
@@ -42,100 +59,110 @@ __device__ __forceinline__ double nb_sum(const double* xp, int i, int j, int l, 
 }
 
 // x_out = x_in + omega * (r - A x_in) / diag; x_in == nullptr means zero.
-// Output columns [0, split) go to o0, the rest to o1.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, double diag, double off,
-                                                double omega, const double* __restrict__ xin,
-                                                const double* __restrict__ r, int ldr,
-                                                double* __restrict__ o0, int ld0,
-                                                double* __restrict__ o1, int ld1, int split,
+// Level storage and arithmetic in S; r is read as RT (the FP64 input block
+// at level 0), the output written as OT; columns [0, split) go to o0, the
+// rest to o1.
+template <int DIM, typename S, typename RT, typename OT>
+__global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, S off, S omega,
+                                                const S* __restrict__ xin,
+                                                const RT* __restrict__ r, int ldr,
+                                                OT* __restrict__ o0, int ld0,
+                                                OT* __restrict__ o1, int ld1, int split,
                                                 int ncols, const DevStatus* st) {
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
-  const int nelem = nx * ncols;
+  const RowLanes ln = row_lanes(ncols);
+  if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
-  const double w = omega / diag;
-  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
-    const int i = e / ncols;
-    const int c = e - i * ncols;
+  const S w = omega / diag;
+  const int c = ln.c;
+  OT* const ob = (c < split) ? o0 + c : o1 + (c - split);
+  const int ldo = (c < split) ? ld0 : ld1;
+  for (int i = ln.i0; i < nx; i += ln.P) {
     const size_t p = rowp + i;
-    const double rv = r[p * ldr + c];
-    double v;
+    const S rv = (S)r[p * ldr + c];
+    S v;
     if (xin) {
-      const double* xp = xin + p * ncols + c;
-      const double xc = xp[0];
-      const double ax = diag * xc + off * nb_sum<DIM>(xp, i, j, l, nx, ny, nz, ncols);
+      const S* xp = xin + p * ncols + c;
+      const S xc = xp[0];
+      const S ax = diag * xc + off * nb_sum<DIM, S>(xp, i, j, l, nx, ny, nz, ncols);
       v = xc + w * (rv - ax);
     } else {
       v = w * rv;
     }
-    if (c < split)
-      o0[p * ld0 + c] = v;
-    else
-      o1[p * ld1 + (c - split)] = v;
+    ob[p * ldo] = (OT)v;
   }
 }
 
 // res = r - A x
-template <int DIM>
-__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, double diag, double off,
-                                                  const double* __restrict__ x,
-                                                  const double* __restrict__ r, int ldr,
-                                                  double* __restrict__ res, int ncols,
+template <int DIM, typename S, typename RT>
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, S diag, S off,
+                                                  const S* __restrict__ x,
+                                                  const RT* __restrict__ r, int ldr,
+                                                  S* __restrict__ res, int ncols,
                                                   const DevStatus* st) {
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
-  const int nelem = nx * ncols;
+  const RowLanes ln = row_lanes(ncols);
+  if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
-  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
-    const int i = e / ncols;
-    const int c = e - i * ncols;
+  const int c = ln.c;
+  for (int i = ln.i0; i < nx; i += ln.P) {
     const size_t p = rowp + i;
-    const double* xp = x + p * ncols + c;
-    const double ax = diag * xp[0] + off * nb_sum<DIM>(xp, i, j, l, nx, ny, nz, ncols);
-    res[p * ncols + c] = r[p * ldr + c] - ax;
+    const S* xp = x + p * ncols + c;
+    const S ax = diag * xp[0] + off * nb_sum<DIM, S>(xp, i, j, l, nx, ny, nz, ncols);
+    res[p * ncols + c] = (S)r[p * ldr + c] - ax;
   }
 }
 
 // Coarse r = P^T res / 2^d.  One workgroup per coarse row.
-template <int DIM>
+template <int DIM, typename S>
 __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
-                                                  const double* __restrict__ res,
-                                                  double* __restrict__ rc, int ncols,
+                                                  const S* __restrict__ res,
+                                                  S* __restrict__ rc, int ncols,
                                                   const DevStatus* st) {
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int cj = row % cny, cl = row / cny;
   const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
-  const int nelem = cnx * ncols;
-  const double wt[4] = {0.25, 0.75, 0.75, 0.25};
-  const double norm = (DIM == 3) ? 0.125 : 0.25;
-  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
-    const int ci = e / ncols;
-    const int c = e - ci * ncols;
-    double acc = 0.0;
-    const int zlo = (DIM == 3) ? 0 : 1, zhi = (DIM == 3) ? 4 : 2;
-    for (int dz = zlo; dz < zhi; ++dz) {
-      int fl = 0;
-      double wz = 1.0;
-      if (DIM == 3) {
-        fl = 2 * cl - 1 + dz;
-        if (fl < 0 || fl >= fnz) continue;
-        wz = wt[dz];
-      }
-      for (int dy = 0; dy < 4; ++dy) {
-        const int fj = 2 * cj - 1 + dy;
-        if (fj < 0 || fj >= fny) continue;
-        const double wy = wz * wt[dy];
-        const size_t base = ((size_t)fl * fny + fj) * fnx;
-        for (int dx = 0; dx < 4; ++dx) {
-          const int fi = 2 * ci - 1 + dx;
-          if (fi < 0 || fi >= fnx) continue;
-          acc += wy * wt[dx] * res[(base + fi) * ncols + c];
-        }
-      }
+  const RowLanes ln = row_lanes(ncols);
+  if (!ln.on) return;
+  const int c = ln.c;
+  const S norm = (DIM == 3) ? (S)0.125 : (S)0.25;
+  // the 4 fine rows (2-D) or 4 x 4 fine rows (3-D) under this coarse row,
+  // with their weights; rows outside the box get weight 0 and row 0
+  size_t rb[16];
+  S rw[16];
+  int nrows = 0;
+  for (int dz = 0; dz < ((DIM == 3) ? 4 : 1); ++dz) {
+    int fl = 0;
+    S wz = 1;
+    if (DIM == 3) {
+      fl = 2 * cl - 1 + dz;
+      wz = (dz == 0 || dz == 3) ? (S)0.25 : (S)0.75;
+      if (fl < 0 || fl >= fnz) wz = 0, fl = 0;
+    }
+    for (int dy = 0; dy < 4; ++dy) {
+      int fj = 2 * cj - 1 + dy;
+      S wy = wz * ((dy == 0 || dy == 3) ? (S)0.25 : (S)0.75);
+      if (fj < 0 || fj >= fny) wy = 0, fj = 0;
+      rb[nrows] = ((size_t)fl * fny + fj) * fnx;
+      rw[nrows] = wy;
+      ++nrows;
+    }
+  }
+  for (int ci = ln.i0; ci < cnx; ci += ln.P) {
+    const int f0 = 2 * ci - 1;
+    S acc = 0;
+#pragma unroll
+    for (int q = 0; q < ((DIM == 3) ? 16 : 4); ++q) {
+      const S* rp = res + rb[q] * ncols + c;
+      S a = (S)0.75 * (rp[(size_t)(f0 + 1) * ncols] + rp[(size_t)(f0 + 2) * ncols]);
+      if (f0 >= 0) a += (S)0.25 * rp[(size_t)f0 * ncols];
+      if (f0 + 3 < fnx) a += (S)0.25 * rp[(size_t)(f0 + 3) * ncols];
+      acc += rw[q] * a;
     }
     const size_t cp = ((size_t)cl * cny + cj) * cnx + ci;
     rc[cp * ncols + c] = acc * norm;
@@ -143,60 +170,63 @@ __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
 }
 
 // x += P e (fine grid dims nx, ny, nz; coarse dims half).
-template <int DIM>
+template <int DIM, typename S>
 __global__ __launch_bounds__(256) void k_prolong_add(int nx, int ny, int nz,
-                                                     const double* __restrict__ ec,
-                                                     double* __restrict__ x, int ncols,
+                                                     const S* __restrict__ ec,
+                                                     S* __restrict__ x, int ncols,
                                                      const DevStatus* st) {
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
   const int cnx = nx / 2, cny = ny / 2, cnz = (DIM == 3) ? nz / 2 : 1;
-  const int nelem = nx * ncols;
+  const RowLanes ln = row_lanes(ncols);
+  if (!ln.on) return;
+  const int c = ln.c;
   const size_t rowp = (size_t)row * nx;
-  // parent and neighbour-parent in y and z
+  // parent and neighbour-parent coarse rows in y and z, with weights
   const int pj = j >> 1, qj = (j & 1) ? pj + 1 : pj - 1;
   const int pl = (DIM == 3) ? (l >> 1) : 0;
   const int ql = (DIM == 3) ? ((l & 1) ? pl + 1 : pl - 1) : 0;
-  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
-    const int i = e / ncols;
-    const int c = e - i * ncols;
+  size_t cb[4];
+  S cw[4];
+  for (int az = 0; az < 2; ++az)
+    for (int ay = 0; ay < 2; ++ay) {
+      const int q = az * 2 + ay;
+      int cl = (DIM == 3) ? (az ? ql : pl) : 0;
+      int cj = ay ? qj : pj;
+      S w = (ay ? (S)0.25 : (S)0.75) * ((DIM == 3) ? (az ? (S)0.25 : (S)0.75) : (az ? (S)0 : (S)1));
+      if (cl < 0 || cl >= cnz || cj < 0 || cj >= cny) w = 0, cl = 0, cj = 0;
+      cb[q] = ((size_t)cl * cny + cj) * cnx;
+      cw[q] = w;
+    }
+  for (int i = ln.i0; i < nx; i += ln.P) {
     const int pi = i >> 1, qi = (i & 1) ? pi + 1 : pi - 1;
-    double acc = 0.0;
-    const int nzz = (DIM == 3) ? 2 : 1;
-    for (int az = 0; az < nzz; ++az) {
-      int cl = pl;
-      double wz = 1.0;
-      if (DIM == 3) {
-        cl = az ? ql : pl;
-        if (cl < 0 || cl >= cnz) continue;
-        wz = az ? 0.25 : 0.75;
-      }
-      for (int ay = 0; ay < 2; ++ay) {
-        const int cj = ay ? qj : pj;
-        if (cj < 0 || cj >= cny) continue;
-        const double wy = wz * (ay ? 0.25 : 0.75);
-        const size_t base = ((size_t)cl * cny + cj) * cnx;
-        acc += wy * 0.75 * ec[(base + pi) * ncols + c];
-        if (qi >= 0 && qi < cnx) acc += wy * 0.25 * ec[(base + qi) * ncols + c];
-      }
+    const bool hq = (qi >= 0 && qi < cnx);
+    S acc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const S* ep = ec + cb[q] * ncols + c;
+      S a = (S)0.75 * ep[(size_t)pi * ncols];
+      if (hq) a += (S)0.25 * ep[(size_t)qi * ncols];
+      acc += cw[q] * a;
     }
     x[(rowp + i) * ncols + c] += acc;
   }
 }
 
 // x = Ainv r on the coarsest level (nc points).
-__global__ __launch_bounds__(256) void k_dense_apply(int nc, const double* __restrict__ Ainv,
-                                                     const double* __restrict__ r,
-                                                     double* __restrict__ x, int ncols,
+template <typename S>
+__global__ __launch_bounds__(256) void k_dense_apply(int nc, const S* __restrict__ Ainv,
+                                                     const S* __restrict__ r,
+                                                     S* __restrict__ x, int ncols,
                                                      const DevStatus* st) {
   if (halted(st)) return;
   const int tot = nc * ncols;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
     const int i = e / ncols;
     const int c = e - i * ncols;
-    const double* a = Ainv + (size_t)i * nc;
-    double acc = 0.0;
+    const S* a = Ainv + (size_t)i * nc;
+    S acc = 0;
     for (int q = 0; q < nc; ++q) acc += a[q] * r[(size_t)q * ncols + c];
     x[(size_t)i * ncols + c] = acc;
   }
@@ -266,7 +296,8 @@ size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax) {
   for (int lv = 0; lv < levels; ++lv) {
     const size_t blk = align256(g.n() * cmax * sizeof(double));
     bytes += (lv == 0 ? 2 : 3) * blk;
-    if (lv == levels - 1) bytes += align256(g.n() * g.n() * sizeof(double));
+    if (lv == levels - 1)
+      bytes += align256(g.n() * g.n() * sizeof(double)) + align256(g.n() * g.n() * sizeof(float));
     g.nx /= 2;
     g.ny /= 2;
     if (g.dim == 3) g.nz /= 2;
@@ -315,6 +346,12 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
   ws += align256((size_t)mg.nc * mg.nc * sizeof(double));
   PLHR_HIP_CHECK(hipMemcpyAsync(mg.coarse_inv, A.data(), A.size() * sizeof(double),
                                 hipMemcpyHostToDevice, s));
+  // FP32 copy for the mixed-precision cycle
+  std::vector<float> A32(A.begin(), A.end());
+  mg.coarse_inv32 = (float*)ws;
+  ws += align256((size_t)mg.nc * mg.nc * sizeof(float));
+  PLHR_HIP_CHECK(hipMemcpyAsync(mg.coarse_inv32, A32.data(), A32.size() * sizeof(float),
+                                hipMemcpyHostToDevice, s));
   PLHR_HIP_CHECK(hipStreamSynchronize(s));
   return PLHR_OK;
 }
@@ -326,80 +363,107 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
     prof_end(cat, s);                         \
   } while (0)
 
-// One V-cycle at level `lev` on input r (ld ldr).  At level 0 the result
-// goes to out0/out1 (split by column); at coarser levels it is left in one
-// of the level's work buffers, whose address is returned.
-template <int DIM>
-static double* cycle(MG& mg, int lev, const double* r, int ldr, Blk out0, Blk out1, int split,
-                     int ncols, const DevStatus* st, hipStream_t s) {
+// One V-cycle at level `lev` on input r (ld ldr, element type RT).  Level
+// storage and arithmetic in S.  At level 0 the result goes to out0/out1
+// (FP64, split by column); at coarser levels it is left in one of the
+// level's work buffers, whose address is returned.
+template <int DIM, typename S, typename RT>
+static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int split, int ncols,
+                const DevStatus* st, hipStream_t s) {
   MGLevel& L = mg.lv[lev];
   const Grid& g = L.g;
   const int rows = g.ny * g.nz;
   const dim3 blk(256);
   const bool coarsest = (lev == (int)mg.lv.size() - 1);
-  const double nb = (double)g.n() * ncols * 8.0;        // one pass over this level
+  const double nb = (double)g.n() * ncols * sizeof(S);  // one pass over this level
   const double fl = (double)g.n() * ncols;
-  if (coarsest) {
+  S* Lx = reinterpret_cast<S*>(L.x);
+  S* Lt = reinterpret_cast<S*>(L.t);
+  const S* Ainv = (sizeof(S) == 4) ? reinterpret_cast<const S*>(mg.coarse_inv32)
+                                   : reinterpret_cast<const S*>(mg.coarse_inv);
+  if (coarsest) {  // lev > 0 here (a single level runs dense_only)
     const int tot = mg.nc * ncols;
     const int nbk = (tot + 255) / 256;
-    if (lev == 0) {
-      // single-level "cycle": dense solve on the finest grid
-      launch_copy(g.n(), r, ldr, L.t, ncols, ncols, s);
-      PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
-                  k_dense_apply, dim3(nbk), blk, 0, s, mg.nc, mg.coarse_inv, L.t, L.x, ncols, st);
-      if (split > 0) launch_copy(g.n(), L.x, ncols, out0.ptr, out0.ld, split, s);
-      if (split < ncols)
-        launch_copy(g.n(), L.x + split, ncols, out1.ptr, out1.ld, ncols - split, s);
-      return nullptr;
-    }
-    PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * fl,
-                k_dense_apply, dim3(nbk), blk, 0, s, mg.nc, mg.coarse_inv, r, L.x, ncols, st);
-    return L.x;
+    PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * sizeof(S) + 2.0 * nb, 2.0 * mg.nc * fl,
+                k_dense_apply<S>, dim3(nbk), blk, 0, s, mg.nc, Ainv,
+                reinterpret_cast<const S*>(r), Lx, ncols, st);
+    return Lx;
   }
-  const double diag = g.diag(), off = g.off(), om = mg.omega;
-  double* cur = L.x;
-  double* oth = L.t;
+  const S diag = (S)g.diag(), off = (S)g.off(), om = (S)mg.omega;
+  const double rb = sizeof(RT) / (double)sizeof(S);  // input pass relative to a level pass
+  S* cur = Lx;
+  S* oth = Lt;
   // pre-smoothing from a zero guess (nu_pre >= 1)
   for (int it = 0; it < mg.nu_pre; ++it) {
-    PROF_LAUNCH(KC_JACOBI, (it == 0 ? 2.0 : 3.0) * nb, (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl,
-                k_jacobi<DIM>, dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
-                it == 0 ? (const double*)nullptr : (const double*)cur, r, ldr, oth, ncols, oth,
-                ncols, ncols, ncols, st);
+    PROF_LAUNCH(KC_JACOBI, (it == 0 ? 1.0 + rb : 2.0 + rb) * nb,
+                (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, S, RT, S>), dim3(rows),
+                blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
+                it == 0 ? (const S*)nullptr : (const S*)cur, r, ldr, oth, ncols, oth, ncols,
+                ncols, ncols, st);
     std::swap(cur, oth);
   }
   // residual -> oth, restrict -> coarse r, coarse cycle, prolongate into cur
-  PROF_LAUNCH(KC_RESIDUAL, 3.0 * nb, (2.0 * DIM + 3.0) * fl, k_residual<DIM>, dim3(rows), blk, 0,
-              s, g.nx, g.ny, g.nz, diag, off, cur, r, ldr, oth, ncols, st);
+  PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, (2.0 * DIM + 3.0) * fl, (k_residual<DIM, S, RT>),
+              dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, cur, r, ldr, oth, ncols, st);
   MGLevel& C = mg.lv[lev + 1];
   const int crows = C.g.ny * C.g.nz;
+  S* Cr = reinterpret_cast<S*>(C.r);
   PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              k_restrict<DIM>, dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, C.r, ncols, st);
-  double* ec = cycle<DIM>(mg, lev + 1, C.r, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
-                          ncols, st, s);
+              (k_restrict<DIM, S>), dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, Cr,
+              ncols, st);
+  S* ec = cycle<DIM, S, S>(mg, lev + 1, Cr, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
+                           ncols, st, s);
   PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              k_prolong_add<DIM>, dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols, st);
-  // post-smoothing (nu_post >= 1); at level 0 the last sweep writes the output
+              (k_prolong_add<DIM, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols,
+              st);
+  // post-smoothing (nu_post >= 1); at level 0 the last sweep writes the
+  // FP64 output
   for (int it = 0; it < mg.nu_post; ++it) {
     if (it == mg.nu_post - 1 && lev == 0) {
-      PROF_LAUNCH(KC_JACOBI, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
-                  g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, out0.ptr, out0.ld, out1.ptr,
-                  out1.ld, split, ncols, st);
+      PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb + fl * 8.0, (2.0 * DIM + 5.0) * fl,
+                  (k_jacobi<DIM, S, RT, double>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag,
+                  off, om, cur, r, ldr, out0.ptr, out0.ld, out1.ptr, out1.ld, split, ncols, st);
       return nullptr;
     }
-    PROF_LAUNCH(KC_JACOBI, 3.0 * nb, (2.0 * DIM + 5.0) * fl, k_jacobi<DIM>, dim3(rows), blk, 0, s,
-                g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, oth, ncols, oth, ncols, ncols, ncols,
-                st);
+    PROF_LAUNCH(KC_JACOBI, (2.0 + rb) * nb, (2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, S, RT, S>),
+                dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, oth, ncols,
+                oth, ncols, ncols, ncols, st);
     std::swap(cur, oth);
   }
   return cur;
 }
 
+// A single level: T is the dense inverse of the whole (small) operator.
+static void dense_only(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split,
+                       int ncols, const DevStatus* st, hipStream_t s) {
+  MGLevel& L = mg.lv[0];
+  const double nb = (double)L.g.n() * ncols * 8.0;
+  launch_copy(L.g.n(), R, ldr, L.t, ncols, ncols, s);
+  const int nbk = (mg.nc * ncols + 255) / 256;
+  PROF_LAUNCH(KC_COARSE, (double)mg.nc * mg.nc * 8.0 + 2.0 * nb, 2.0 * mg.nc * L.g.n() * ncols,
+              k_dense_apply<double>, dim3(nbk), dim3(256), 0, s, mg.nc, mg.coarse_inv, L.t, L.x,
+              ncols, st);
+  if (split > 0) launch_copy(L.g.n(), L.x, ncols, out0.ptr, out0.ld, split, s);
+  if (split < ncols) launch_copy(L.g.n(), L.x + split, ncols, out1.ptr, out1.ld, ncols - split, s);
+}
+
 void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, int ncols,
-              const DevStatus* st, hipStream_t s) {
-  if (mg.lv[0].g.dim == 3)
-    cycle<3>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
-  else
-    cycle<2>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+              bool f32, const DevStatus* st, hipStream_t s) {
+  if (mg.lv.size() == 1) {
+    dense_only(mg, R, ldr, out0, out1, split, ncols, st, s);
+    return;
+  }
+  if (mg.lv[0].g.dim == 3) {
+    if (f32)
+      cycle<3, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+    else
+      cycle<3, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+  } else {
+    if (f32)
+      cycle<2, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+    else
+      cycle<2, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+  }
 }
 
 }  // namespace plhr

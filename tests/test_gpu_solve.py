@@ -81,3 +81,26 @@ def test_3d_multigrid_small_matches_brute_force():
     assert U.shape[1] == 6
     assert dense.subspace_sine(U, host(r.V)) < 1e-7
     S.close()
+
+
+def test_3d_multigrid_mixed_precision_matches_brute_force():
+    """Mixed mode (FP32 V-cycle, everything else FP64): the converged pairs
+    meet the FP64 tolerances, since the residuals, Grams and projected
+    problem stay in FP64 and T only shapes the search directions."""
+    from tests.gpu_util import dev, host
+    N = 12
+    w = wl.small_fd7(N, 4, 0.1, seed=(22, 0), levels=3)
+    w.k_extra = 3
+    ev = wl.fd7_closed_form(N, w.h)
+    w.sigma = wl.shift_between(ev, 5)
+    A = ops.fd_dirichlet(w.dims, w.h)
+    lam_b, _ = dense.nearest_pairs(A, None, w.sigma, w.k)
+    S = _solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=w.k, k_extra=w.k_extra,
+                tol=1e-11, max_iters=3000, precision="mixed",
+                precond={"levels": 3, "nu": 2, "omega": 2 / 3})
+    r = S.solve(dev(w.v0()))
+    assert r.converged
+    assert np.allclose(host(r.eigvals), lam_b, rtol=1e-10), (host(r.eigvals), lam_b)
+    _, U = dense.cluster_basis(A, None, w.sigma, w.k)
+    assert dense.subspace_sine(U, host(r.V)) < 1e-7
+    S.close()
