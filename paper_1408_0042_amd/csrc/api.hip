@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -318,7 +319,9 @@ void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int spli
 // Gram product on the matrix cores when the shape fits.
 void gram(plhr_ctx_s* c, const double* X, int ldx, int mx, const double* Y1, int ldy1, int my1,
           const double* Y2, int ldy2, int my, double* out, const DevStatus* st) {
-  if (c->use_mfma && gram_mfma_ok(mx, my))
+  auto a16 = [](const void* q) { return q == nullptr || ((uintptr_t)q & 15) == 0; };
+  const bool layout_ok = ((ldx | ldy1 | ldy2 | my1) & 1) == 0 && a16(X) && a16(Y1) && a16(Y2);
+  if (c->use_mfma && layout_ok && gram_mfma_ok(mx, my))
     launch_gram_mfma(c->n, X, ldx, mx, Y1, ldy1, my1, Y2, ldy2, my, c->gpart, c->gram_nblk, out,
                      st, c->stream);
   else
@@ -329,8 +332,9 @@ void gram(plhr_ctx_s* c, const double* X, int ldx, int mx, const double* Y1, int
 void transform(plhr_ctx_s* c, double* const* arrs, int narr, const DevStatus* st) {
   const int m = c->m;
   if (c->use_mfma && rowmul_mfma_ok(m, m)) {
+    // four 16-row tiles per block and pass; two blocks per compute unit
     const size_t ntiles = (c->n + 63) / 64;
-    const int nb = (int)(ntiles < 1024 ? ntiles : 1024);
+    const int nb = (int)(ntiles < 512 ? ntiles : 512);
     launch_rowmul_mfma(c->n, arrs, narr, m, m, c->sb.M, m, 0, 0, 0, 0, nullptr, nb, st, c->stream);
   } else {
     launch_transform(c->n, arrs, narr, m, m, c->sb.M, st, c->stream);

@@ -17,6 +17,7 @@
 // Every level works on point-major blocks of ncols columns; kernels assign
 // one workgroup per grid row so accesses stay contiguous.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -24,36 +25,63 @@
 
 namespace plhr {
 
-// Thread layout of the row kernels: `ncols` consecutive threads share one
-// grid point (thread t: column t % ncols, point t / ncols), P = blockDim /
-// ncols points per pass; the remaining blockDim % ncols threads idle.  No
-// division inside the loops.
+// Vector access: each thread handles W consecutive columns of one grid
+// point (W * sizeof(S) <= 16 bytes per load where the layout allows it).
+template <typename T, int N>
+using vec = T __attribute__((ext_vector_type(N)));
+
+template <int W, typename S, typename T>
+__device__ __forceinline__ vec<S, W> vload(const T* p) {
+  if constexpr (sizeof(T) * W <= 16) {
+    return __builtin_convertvector(*reinterpret_cast<const vec<T, W>*>(p), vec<S, W>);
+  } else {  // four doubles: two 16-byte loads
+    const vec<T, 2> a = *reinterpret_cast<const vec<T, 2>*>(p);
+    const vec<T, 2> b = *reinterpret_cast<const vec<T, 2>*>(p + 2);
+    return vec<S, W>{(S)a.x, (S)a.y, (S)b.x, (S)b.y};
+  }
+}
+template <int W, typename S, typename T>
+__device__ __forceinline__ void vstore(T* p, vec<S, W> v) {
+  if constexpr (sizeof(T) * W <= 16) {
+    *reinterpret_cast<vec<T, W>*>(p) = __builtin_convertvector(v, vec<T, W>);
+  } else {
+    *reinterpret_cast<vec<T, 2>*>(p) = vec<T, 2>{(T)v.x, (T)v.y};
+    *reinterpret_cast<vec<T, 2>*>(p + 2) = vec<T, 2>{(T)v.z, (T)v.w};
+  }
+}
+
+// Thread layout of the row kernels: ncols / W consecutive threads share
+// one grid point (thread t: columns W (t % (ncols/W)) .., point
+// t / (ncols/W)), P = blockDim / (ncols/W) points per pass; the remaining
+// threads idle.  No division inside the loops.
 struct RowLanes {
   int c, i0, P;
   bool on;
 };
+template <int W>
 __device__ __forceinline__ RowLanes row_lanes(int ncols) {
+  const int nl = ncols / W;
   RowLanes r;
-  r.P = blockDim.x / ncols;
-  r.c = threadIdx.x % ncols;
-  r.i0 = threadIdx.x / ncols;
+  r.P = blockDim.x / nl;
+  r.c = (threadIdx.x % nl) * W;
+  r.i0 = threadIdx.x / nl;
   r.on = r.i0 < r.P;
   return r;
 }
 
-template <int DIM, typename S>
-__device__ __forceinline__ S nb_sum(const S* xp, int i, int j, int l, int nx, int ny, int nz,
-                                    int ld) {
+template <int DIM, int W, typename S>
+__device__ __forceinline__ vec<S, W> nb_sum(const S* xp, int i, int j, int l, int nx, int ny,
+                                            int nz, int ld) {
   const ptrdiff_t sy = (ptrdiff_t)nx * ld;
   const ptrdiff_t sz = (ptrdiff_t)nx * ny * ld;
-  S nb = 0;
-  if (i > 0) nb += xp[-ld];
-  if (i < nx - 1) nb += xp[ld];
-  if (j > 0) nb += xp[-sy];
-  if (j < ny - 1) nb += xp[sy];
+  vec<S, W> nb = (S)0;
+  if (i > 0) nb += vload<W, S>(xp - ld);
+  if (i < nx - 1) nb += vload<W, S>(xp + ld);
+  if (j > 0) nb += vload<W, S>(xp - sy);
+  if (j < ny - 1) nb += vload<W, S>(xp + sy);
   if (DIM == 3) {
-    if (l > 0) nb += xp[-sz];
-    if (l < nz - 1) nb += xp[sz];
+    if (l > 0) nb += vload<W, S>(xp - sz);
+    if (l < nz - 1) nb += vload<W, S>(xp + sz);
   }
   return nb;
 }
@@ -61,8 +89,8 @@ __device__ __forceinline__ S nb_sum(const S* xp, int i, int j, int l, int nx, in
 // x_out = x_in + omega * (r - A x_in) / diag; x_in == nullptr means zero.
 // Level storage and arithmetic in S; r is read as RT (the FP64 input block
 // at level 0), the output written as OT; columns [0, split) go to o0, the
-// rest to o1.
-template <int DIM, typename S, typename RT, typename OT>
+// rest to o1 (split is a multiple of W).
+template <int DIM, int W, typename S, typename RT, typename OT>
 __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, S off, S omega,
                                                 const S* __restrict__ xin,
                                                 const RT* __restrict__ r, int ldr,
@@ -72,7 +100,7 @@ __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, 
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
-  const RowLanes ln = row_lanes(ncols);
+  const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
   const S w = omega / diag;
@@ -81,22 +109,22 @@ __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, 
   const int ldo = (c < split) ? ld0 : ld1;
   for (int i = ln.i0; i < nx; i += ln.P) {
     const size_t p = rowp + i;
-    const S rv = (S)r[p * ldr + c];
-    S v;
+    const vec<S, W> rv = vload<W, S>(r + p * ldr + c);
+    vec<S, W> v;
     if (xin) {
       const S* xp = xin + p * ncols + c;
-      const S xc = xp[0];
-      const S ax = diag * xc + off * nb_sum<DIM, S>(xp, i, j, l, nx, ny, nz, ncols);
+      const vec<S, W> xc = vload<W, S>(xp);
+      const vec<S, W> ax = diag * xc + off * nb_sum<DIM, W, S>(xp, i, j, l, nx, ny, nz, ncols);
       v = xc + w * (rv - ax);
     } else {
       v = w * rv;
     }
-    ob[p * ldo] = (OT)v;
+    vstore<W, S>(ob + p * ldo, v);
   }
 }
 
 // res = r - A x
-template <int DIM, typename S, typename RT>
+template <int DIM, int W, typename S, typename RT>
 __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, S diag, S off,
                                                   const S* __restrict__ x,
                                                   const RT* __restrict__ r, int ldr,
@@ -105,20 +133,21 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, S diag
   if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
-  const RowLanes ln = row_lanes(ncols);
+  const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
   const int c = ln.c;
   for (int i = ln.i0; i < nx; i += ln.P) {
     const size_t p = rowp + i;
     const S* xp = x + p * ncols + c;
-    const S ax = diag * xp[0] + off * nb_sum<DIM, S>(xp, i, j, l, nx, ny, nz, ncols);
-    res[p * ncols + c] = (S)r[p * ldr + c] - ax;
+    const vec<S, W> ax =
+        diag * vload<W, S>(xp) + off * nb_sum<DIM, W, S>(xp, i, j, l, nx, ny, nz, ncols);
+    vstore<W, S>(res + p * ncols + c, vload<W, S>(r + p * ldr + c) - ax);
   }
 }
 
 // Coarse r = P^T res / 2^d.  One workgroup per coarse row.
-template <int DIM, typename S>
+template <int DIM, int W, typename S>
 __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
                                                   const S* __restrict__ res,
                                                   S* __restrict__ rc, int ncols,
@@ -127,7 +156,7 @@ __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int cj = row % cny, cl = row / cny;
   const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
-  const RowLanes ln = row_lanes(ncols);
+  const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const int c = ln.c;
   const S norm = (DIM == 3) ? (S)0.125 : (S)0.25;
@@ -155,22 +184,23 @@ __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
   }
   for (int ci = ln.i0; ci < cnx; ci += ln.P) {
     const int f0 = 2 * ci - 1;
-    S acc = 0;
+    vec<S, W> acc = (S)0;
 #pragma unroll
     for (int q = 0; q < ((DIM == 3) ? 16 : 4); ++q) {
       const S* rp = res + rb[q] * ncols + c;
-      S a = (S)0.75 * (rp[(size_t)(f0 + 1) * ncols] + rp[(size_t)(f0 + 2) * ncols]);
-      if (f0 >= 0) a += (S)0.25 * rp[(size_t)f0 * ncols];
-      if (f0 + 3 < fnx) a += (S)0.25 * rp[(size_t)(f0 + 3) * ncols];
+      vec<S, W> a = (S)0.75 * (vload<W, S>(rp + (size_t)(f0 + 1) * ncols) +
+                               vload<W, S>(rp + (size_t)(f0 + 2) * ncols));
+      if (f0 >= 0) a += (S)0.25 * vload<W, S>(rp + (size_t)f0 * ncols);
+      if (f0 + 3 < fnx) a += (S)0.25 * vload<W, S>(rp + (size_t)(f0 + 3) * ncols);
       acc += rw[q] * a;
     }
     const size_t cp = ((size_t)cl * cny + cj) * cnx + ci;
-    rc[cp * ncols + c] = acc * norm;
+    vstore<W, S>(rc + cp * ncols + c, acc * norm);
   }
 }
 
 // x += P e (fine grid dims nx, ny, nz; coarse dims half).
-template <int DIM, typename S>
+template <int DIM, int W, typename S>
 __global__ __launch_bounds__(256) void k_prolong_add(int nx, int ny, int nz,
                                                      const S* __restrict__ ec,
                                                      S* __restrict__ x, int ncols,
@@ -179,7 +209,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nx, int ny, int nz,
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny, l = row / ny;
   const int cnx = nx / 2, cny = ny / 2, cnz = (DIM == 3) ? nz / 2 : 1;
-  const RowLanes ln = row_lanes(ncols);
+  const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const int c = ln.c;
   const size_t rowp = (size_t)row * nx;
@@ -202,15 +232,16 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nx, int ny, int nz,
   for (int i = ln.i0; i < nx; i += ln.P) {
     const int pi = i >> 1, qi = (i & 1) ? pi + 1 : pi - 1;
     const bool hq = (qi >= 0 && qi < cnx);
-    S acc = 0;
+    vec<S, W> acc = (S)0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const S* ep = ec + cb[q] * ncols + c;
-      S a = (S)0.75 * ep[(size_t)pi * ncols];
-      if (hq) a += (S)0.25 * ep[(size_t)qi * ncols];
+      vec<S, W> a = (S)0.75 * vload<W, S>(ep + (size_t)pi * ncols);
+      if (hq) a += (S)0.25 * vload<W, S>(ep + (size_t)qi * ncols);
       acc += cw[q] * a;
     }
-    x[(rowp + i) * ncols + c] += acc;
+    S* xp = x + (rowp + i) * ncols + c;
+    vstore<W, S>(xp, vload<W, S>(xp) + acc);
   }
 }
 
@@ -367,7 +398,7 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
 // storage and arithmetic in S.  At level 0 the result goes to out0/out1
 // (FP64, split by column); at coarser levels it is left in one of the
 // level's work buffers, whose address is returned.
-template <int DIM, typename S, typename RT>
+template <int DIM, int W, typename S, typename RT>
 static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int split, int ncols,
                 const DevStatus* st, hipStream_t s) {
   MGLevel& L = mg.lv[lev];
@@ -396,36 +427,36 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
   // pre-smoothing from a zero guess (nu_pre >= 1)
   for (int it = 0; it < mg.nu_pre; ++it) {
     PROF_LAUNCH(KC_JACOBI, (it == 0 ? 1.0 + rb : 2.0 + rb) * nb,
-                (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, S, RT, S>), dim3(rows),
+                (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>), dim3(rows),
                 blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
                 it == 0 ? (const S*)nullptr : (const S*)cur, r, ldr, oth, ncols, oth, ncols,
                 ncols, ncols, st);
     std::swap(cur, oth);
   }
   // residual -> oth, restrict -> coarse r, coarse cycle, prolongate into cur
-  PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, (2.0 * DIM + 3.0) * fl, (k_residual<DIM, S, RT>),
+  PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, (2.0 * DIM + 3.0) * fl, (k_residual<DIM, W, S, RT>),
               dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, cur, r, ldr, oth, ncols, st);
   MGLevel& C = mg.lv[lev + 1];
   const int crows = C.g.ny * C.g.nz;
   S* Cr = reinterpret_cast<S*>(C.r);
   PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              (k_restrict<DIM, S>), dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, Cr,
+              (k_restrict<DIM, W, S>), dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, Cr,
               ncols, st);
-  S* ec = cycle<DIM, S, S>(mg, lev + 1, Cr, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
+  S* ec = cycle<DIM, W, S, S>(mg, lev + 1, Cr, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
                            ncols, st, s);
   PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              (k_prolong_add<DIM, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols,
+              (k_prolong_add<DIM, W, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols,
               st);
   // post-smoothing (nu_post >= 1); at level 0 the last sweep writes the
   // FP64 output
   for (int it = 0; it < mg.nu_post; ++it) {
     if (it == mg.nu_post - 1 && lev == 0) {
       PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb + fl * 8.0, (2.0 * DIM + 5.0) * fl,
-                  (k_jacobi<DIM, S, RT, double>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag,
+                  (k_jacobi<DIM, W, S, RT, double>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag,
                   off, om, cur, r, ldr, out0.ptr, out0.ld, out1.ptr, out1.ld, split, ncols, st);
       return nullptr;
     }
-    PROF_LAUNCH(KC_JACOBI, (2.0 + rb) * nb, (2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, S, RT, S>),
+    PROF_LAUNCH(KC_JACOBI, (2.0 + rb) * nb, (2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>),
                 dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, oth, ncols,
                 oth, ncols, ncols, ncols, st);
     std::swap(cur, oth);
@@ -447,23 +478,44 @@ static void dense_only(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int
   if (split < ncols) launch_copy(L.g.n(), L.x + split, ncols, out1.ptr, out1.ld, ncols - split, s);
 }
 
+static bool fits(int w, const void* p) { return p == nullptr || ((uintptr_t)p % 16) == 0; }
+
+// Vector width: 16 bytes of the level type per load when every column
+// count, leading dimension and split is a multiple of it and the FP64
+// input/output blocks are 16-byte aligned; otherwise one element.
+static int pick_width(int w, const double* R, int ldr, Blk o0, Blk o1, int split, int ncols) {
+  if (ncols % w || ldr % w || split % w) return 1;
+  if ((o0.ptr && o0.ld % w) || (o1.ptr && o1.ld % w)) return 1;
+  if (!fits(w, R) || !fits(w, o0.ptr) || !fits(w, o1.ptr)) return 1;
+  return w;
+}
+
+template <int DIM>
+static void cycle_top(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, int ncols,
+                      bool f32, const DevStatus* st, hipStream_t s) {
+  if (f32) {
+    if (pick_width(4, R, ldr, out0, out1, split, ncols) == 4)
+      cycle<DIM, 4, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+    else
+      cycle<DIM, 1, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+  } else {
+    if (pick_width(2, R, ldr, out0, out1, split, ncols) == 2)
+      cycle<DIM, 2, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+    else
+      cycle<DIM, 1, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
+  }
+}
+
 void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, int ncols,
               bool f32, const DevStatus* st, hipStream_t s) {
   if (mg.lv.size() == 1) {
     dense_only(mg, R, ldr, out0, out1, split, ncols, st, s);
     return;
   }
-  if (mg.lv[0].g.dim == 3) {
-    if (f32)
-      cycle<3, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
-    else
-      cycle<3, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
-  } else {
-    if (f32)
-      cycle<2, float, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
-    else
-      cycle<2, double, double>(mg, 0, R, ldr, out0, out1, split, ncols, st, s);
-  }
+  if (mg.lv[0].g.dim == 3)
+    cycle_top<3>(mg, R, ldr, out0, out1, split, ncols, f32, st, s);
+  else
+    cycle_top<2>(mg, R, ldr, out0, out1, split, ncols, f32, st, s);
 }
 
 }  // namespace plhr
