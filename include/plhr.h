@@ -271,6 +271,93 @@ plhr_status plhr_debug_read(plhr_ctx ctx, int32_t which, double* dst, size_t cou
 /* Release the context and any workspace it allocated. NULL is ignored.   */
 void plhr_destroy(plhr_ctx ctx);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent problems solved together: the same iteration (Algorithm
+ * 3) advances every problem, each launch covering all of them (one
+ * workgroup per grid row or per chunk of points of one problem, one
+ * workgroup per problem for the projected problems).  The per-iteration
+ * launch sequence is captured once in a HIP graph and replayed.  The
+ * chunk size of the point-range kernels and the workgroup size of the
+ * grid-row kernels are picked by timing candidates on the first solve
+ * (plhr_batch_tuning reports the choice).  Converged problems stop
+ * working while the others continue.                                      */
+typedef struct plhr_batch_s* plhr_batch;
+
+/* Create a batch of nbatch problems A_b v = lambda v (B = I).
+ *   nbatch  number of problems, >= 1
+ *   A       host array of nbatch PLHR_OP_FD5_2D descriptors (each with its
+ *           own grid and potential; h and scale equal for all)
+ *   T       host descriptor of the V-cycle (applied to each problem's
+ *           Laplacian part; levels >= 2; every grid dimension divisible by
+ *           2^(levels-1), coarsest level <= 1024 points), or NULL for T = I
+ *   sigma   host array of nbatch finite shifts
+ *   k       wanted pairs per problem, 4 (k + k_extra) <= min n_b and <= 84
+ *   opt     host options (precision FP64), or NULL for defaults
+ *   stream  HIP stream for all work (NULL: the null stream)
+ *   out     host; receives the handle
+ * The library allocates the device memory it needs; the potentials are
+ * read at create and must stay valid until destroy.                      */
+plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_prec_desc* T,
+                              const double* sigma, int32_t k, const plhr_options* opt,
+                              void* stream, plhr_batch* out);
+
+/* Solve every problem from its start block.
+ *   V0       host array of nbatch device pointers; V0[b] is n_b x (k +
+ *            k_extra) doubles, point-major, full rank
+ *   eigvals  device, nbatch x k: row b holds problem b's eigenvalues
+ *            ordered by |lambda - sigma_b| (ties: smaller lambda)
+ *   V        host array of nbatch device pointers (n_b x k each,
+ *            B-orthonormal Ritz vectors), or NULL
+ *   rel_res  host, nbatch x k relative residuals, or NULL
+ *   iters    host, nbatch iteration counts, or NULL
+ *   status   host, nbatch per-problem status codes (PLHR_OK,
+ *            PLHR_ERR_NOT_CONVERGED, PLHR_ERR_BREAKDOWN, ...), or NULL
+ * Returns PLHR_OK when every problem converged, PLHR_ERR_NOT_CONVERGED
+ * when some reached max_iters (outputs still written), or the first
+ * device error of a problem.                                              */
+plhr_status plhr_batch_solve(plhr_batch b, const double* const* V0, double* eigvals,
+                             double* const* V, double* rel_res, int32_t* iters,
+                             int32_t* status);
+
+/* Hellmann-Feynman gradient of a loss of the eigenvalues with respect to
+ * each problem's potential (after plhr_batch_solve).
+ *   dL_dlambda  device, nbatch x k
+ *   dL_dpot     host array of nbatch device pointers (n_b doubles each)
+ *   accumulate  0: overwrite, 1: add                                     */
+plhr_status plhr_batch_eigvals_backward(plhr_batch b, const double* dL_dlambda,
+                                        double* const* dL_dpot, int32_t accumulate);
+
+/* Apply one operator to a block of every problem (no iteration state is
+ * used; the internal basis of the batch is overwritten, the results of
+ * the last solve needed by the backward are not).
+ *   which  0: Y = A X;  1: Y = (A - sigma B) X;  2: Y = T X
+ *   X, Y   host arrays of nbatch device pointers, n_b x ncols each
+ *   ncols  1 <= ncols <= 2 (k + k_extra)                                 */
+plhr_status plhr_batch_apply(plhr_batch b, int32_t which, const double* const* X,
+                             double* const* Y, int32_t ncols);
+
+/* What the tuner picked (valid after the first solve). */
+typedef struct {
+  int32_t chunk_points;  /* points per workgroup of the point-range kernels */
+  int32_t row_threads;   /* threads per workgroup of the grid-row kernels   */
+  int32_t use_graph;     /* 1 when iterations replay a captured HIP graph   */
+  int32_t nchunks;       /* point chunks over all problems                  */
+  double tuned_ms[8];    /* timed candidates: chunk sizes 512..4096, then
+                            row threads 64, 128, 256 (ms per sample)        */
+} plhr_batch_tuning;
+plhr_status plhr_batch_tuning_info(plhr_batch b, plhr_batch_tuning* out);
+
+/* Use (1, default) or bypass (0) the captured iteration graph.           */
+plhr_status plhr_batch_set_graph(plhr_batch b, int32_t use_graph);
+
+/* Launch profile of the batch (as plhr_profile_start/stop); profiling
+ * bypasses the graph while it is on.                                     */
+plhr_status plhr_batch_profile_start(plhr_batch b, int32_t category, int32_t max_launches);
+plhr_status plhr_batch_profile_stop(plhr_batch b, plhr_profile* out);
+
+/* Release the batch. NULL is ignored. */
+void plhr_batch_destroy(plhr_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,11 @@ KCAT_KERNELS = ["k_fd_apply", "k_jacobi", "k_residual", "k_restrict", "k_prolong
                 "k_ortho_small", "k_rq_small, k_conv_check", "k_resid_prep, k_xdots, k_copy"]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("chunk_points", C.c_int32), ("row_threads", C.c_int32), ("use_graph", C.c_int32),
+                ("nchunks", C.c_int32), ("tuned_ms", C.c_double * 8)]
+
+
 class PLHRError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -105,6 +110,18 @@ def load() -> C.CDLL:
         "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),
         "plhr_profile_stop": (C.c_int, [P, C.POINTER(Profile)]),
         "plhr_destroy": (None, [P]),
+        "plhr_batch_create": (C.c_int, [C.c_int32, C.POINTER(OpDesc), C.POINTER(PrecDesc),
+                                        C.POINTER(C.c_double), C.c_int32, C.POINTER(Options), P,
+                                        C.POINTER(P)]),
+        "plhr_batch_solve": (C.c_int, [P, C.POINTER(P), P, C.POINTER(P), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "plhr_batch_eigvals_backward": (C.c_int, [P, P, C.POINTER(P), C.c_int32]),
+        "plhr_batch_tuning_info": (C.c_int, [P, C.POINTER(BatchTuning)]),
+        "plhr_batch_apply": (C.c_int, [P, C.c_int32, C.POINTER(P), C.POINTER(P), C.c_int32]),
+        "plhr_batch_set_graph": (C.c_int, [P, C.c_int32]),
+        "plhr_batch_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),
+        "plhr_batch_profile_stop": (C.c_int, [P, C.POINTER(Profile)]),
+        "plhr_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -42,18 +42,36 @@ static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 static_assert(KC_COUNT == PLHR_KC_COUNT, "profile categories");
 static constexpr int kRefreshT = 10;  // iterations between T(A - sigma B)V refreshes
 
-// Per-launch event profiling (see KCat).  The driver points g_prof at the
-// active context's recorder for the duration of each entry point.
-struct Prof {
-  int cat = -2;  // -1: all categories; -2: off
-  std::vector<hipEvent_t> ev;
-  std::vector<int> evcat;
-  size_t used = 0;
-  double bytes[KC_COUNT] = {0}, flops[KC_COUNT] = {0};
-  long launches[KC_COUNT] = {0};
-  bool skip_end = false;
-};
 static thread_local Prof* g_prof = nullptr;
+void prof_attach(Prof* p) { g_prof = (p && p->cat != -2) ? p : nullptr; }
+
+Grid make_grid(const plhr_op_desc* A) {
+  Grid g;
+  g.nx = A->nx;
+  g.ny = A->ny;
+  g.nz = A->nz;
+  g.dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
+  g.h = A->h;
+  g.scale = A->scale;
+  return g;
+}
+
+double exact_norm1(const Grid& g, const std::vector<double>& pot) {
+  // max over points of |diag + pot| + (#interior neighbours) * scale / h^2
+  const double d = g.diag(), o = -g.off();
+  double best = 0.0;
+  for (int l = 0; l < g.nz; ++l)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        int nb = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1);
+        if (g.dim == 3) nb += (l > 0) + (l < g.nz - 1);
+        const size_t p = (size_t)i + (size_t)g.nx * (j + (size_t)g.ny * l);
+        const double v = fabs(d + (pot.empty() ? 0.0 : pot[p])) + nb * o;
+        if (v > best) best = v;
+      }
+  return best;
+}
+
 
 void prof_begin(int cat, double bytes, double flops, hipStream_t s) {
   Prof* p = g_prof;
@@ -76,6 +94,50 @@ void prof_end(int cat, hipStream_t s) {
   if (p->skip_end) return;
   (void)hipEventRecord(p->ev[p->used + 1], s);
   p->used += 2;
+}
+
+
+plhr_status prof_start(Prof& p, int category, int max_launches) {
+  if (category < -1 || category >= KC_COUNT || max_launches < 1) {
+    set_error("profile start: bad argument");
+    return PLHR_ERR_ARG;
+  }
+  const size_t need = 2 * (size_t)max_launches;
+  while (p.ev.size() < need) {
+    hipEvent_t e;
+    PLHR_HIP_CHECK(hipEventCreate(&e));
+    p.ev.push_back(e);
+  }
+  p.evcat.assign(p.ev.size() / 2 + 1, 0);
+  p.used = 0;
+  for (int i = 0; i < KC_COUNT; ++i) p.bytes[i] = p.flops[i] = 0.0, p.launches[i] = 0;
+  p.cat = category;
+  return PLHR_OK;
+}
+
+plhr_status prof_stop(Prof& p, hipStream_t stream, plhr_profile* out) {
+  PLHR_HIP_CHECK(hipStreamSynchronize(stream));
+  std::memset(out, 0, sizeof(*out));
+  for (size_t i = 0; i < p.used; i += 2) {
+    float ms = 0.f;
+    PLHR_HIP_CHECK(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+    out->total_ms[p.evcat[i / 2]] += ms;
+  }
+  long total = 0;
+  for (int i = 0; i < KC_COUNT; ++i) {
+    out->launches[i] = (int32_t)p.launches[i];
+    out->bytes[i] = p.bytes[i];
+    out->flops[i] = p.flops[i];
+    total += p.launches[i];
+  }
+  out->truncated = (p.used / 2 < (size_t)total) ? 1 : 0;
+  p.cat = -2;
+  return PLHR_OK;
+}
+
+void prof_release(Prof& p) {
+  for (hipEvent_t e : p.ev) (void)hipEventDestroy(e);
+  p.ev.clear();
 }
 
 }  // namespace plhr
@@ -211,16 +273,6 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
   return PLHR_OK;
 }
 
-Grid make_grid(const plhr_op_desc* A) {
-  Grid g;
-  g.nx = A->nx;
-  g.ny = A->ny;
-  g.nz = A->nz;
-  g.dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
-  g.h = A->h;
-  g.scale = A->scale;
-  return g;
-}
 
 Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s* c) {
   Layout L;
@@ -279,21 +331,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
   return L;
 }
 
-double exact_norm1(const Grid& g, const std::vector<double>& pot) {
-  // max over points of |diag + pot| + (#interior neighbours) * scale / h^2
-  const double d = g.diag(), o = -g.off();
-  double best = 0.0;
-  for (int l = 0; l < g.nz; ++l)
-    for (int j = 0; j < g.ny; ++j)
-      for (int i = 0; i < g.nx; ++i) {
-        int nb = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1);
-        if (g.dim == 3) nb += (l > 0) + (l < g.nz - 1);
-        const size_t p = (size_t)i + (size_t)g.nx * (j + (size_t)g.ny * l);
-        const double v = fabs(d + (pot.empty() ? 0.0 : pot[p])) + nb * o;
-        if (v > best) best = v;
-      }
-  return best;
-}
+
 
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
              Blk outc, int ncols, double shift, const DevStatus* st) {
@@ -822,22 +860,11 @@ plhr_status plhr_debug_read(plhr_ctx c, int32_t which, double* dst, size_t count
 }
 
 plhr_status plhr_profile_start(plhr_ctx c, int32_t category, int32_t max_launches) {
-  if (!c || category < -1 || category >= KC_COUNT || max_launches < 1) {
+  if (!c) {
     set_error("plhr_profile_start: bad argument");
     return PLHR_ERR_ARG;
   }
-  Prof& p = c->prof;
-  const size_t need = 2 * (size_t)max_launches;
-  while (p.ev.size() < need) {
-    hipEvent_t e;
-    PLHR_HIP_CHECK(hipEventCreate(&e));
-    p.ev.push_back(e);
-  }
-  p.evcat.assign(p.ev.size() / 2 + 1, 0);
-  p.used = 0;
-  for (int i = 0; i < KC_COUNT; ++i) p.bytes[i] = p.flops[i] = 0.0, p.launches[i] = 0;
-  p.cat = category;
-  return PLHR_OK;
+  return prof_start(c->prof, category, max_launches);
 }
 
 plhr_status plhr_profile_stop(plhr_ctx c, plhr_profile* out) {
@@ -845,31 +872,12 @@ plhr_status plhr_profile_stop(plhr_ctx c, plhr_profile* out) {
     set_error("plhr_profile_stop: NULL argument");
     return PLHR_ERR_ARG;
   }
-  Prof& p = c->prof;
-  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
-  std::memset(out, 0, sizeof(*out));
-  for (size_t i = 0; i + 1 < p.used + 1 && i < p.used; i += 2) {
-    float ms = 0.f;
-    PLHR_HIP_CHECK(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
-    out->total_ms[p.evcat[i / 2]] += ms;
-  }
-  for (int i = 0; i < KC_COUNT; ++i) {
-    out->launches[i] = (int32_t)p.launches[i];
-    out->bytes[i] = p.bytes[i];
-    out->flops[i] = p.flops[i];
-  }
-  out->truncated = (p.used / 2 < (size_t)[&] {
-    long s = 0;
-    for (int i = 0; i < KC_COUNT; ++i) s += p.launches[i];
-    return s;
-  }()) ? 1 : 0;
-  p.cat = -2;
-  return PLHR_OK;
+  return prof_stop(c->prof, c->stream, out);
 }
 
 void plhr_destroy(plhr_ctx c) {
   if (!c) return;
-  for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+  prof_release(c->prof);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->st_host) (void)hipHostFree(c->st_host);

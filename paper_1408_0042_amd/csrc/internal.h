@@ -85,6 +85,21 @@ enum KCat : int {
   KC_VEC = 15,           // residual formation, column reductions, copies
   KC_COUNT = 16  // PLHR_KC_COUNT
 };
+// Per-launch event profiling (see KCat): the entry points attach the
+// active context's recorder for the duration of each call.
+struct Prof {
+  int cat = -2;  // -1: all categories; -2: off
+  std::vector<hipEvent_t> ev;
+  std::vector<int> evcat;
+  size_t used = 0;
+  double bytes[KC_COUNT] = {0}, flops[KC_COUNT] = {0};
+  long launches[KC_COUNT] = {0};
+  bool skip_end = false;
+};
+void prof_attach(Prof* p);
+plhr_status prof_start(Prof& p, int category, int max_launches);
+plhr_status prof_stop(Prof& p, hipStream_t stream, plhr_profile* out);
+void prof_release(Prof& p);
 void prof_begin(int cat, double bytes, double flops, hipStream_t s);
 void prof_end(int cat, hipStream_t s);
 
@@ -237,6 +252,96 @@ struct SmallParams {
   double drop_tol;
   int lock;
 };
+
+// ------------------------------------------------------------- batches
+// Many independent 2-D problems packed point-major one after another
+// (k_batch.hip).  Tables built on the host, read by every batched launch.
+struct BProb {
+  int nx, ny;            // level-0 grid
+  size_t off;            // first level-0 point of the problem in packed arrays
+  const double* pot;     // potential (n_b values) or null
+  double sigma;
+  const double* lam;     // kint Rayleigh quotients used by residual epilogues
+  const DevStatus* st;   // per-problem status (halted problems skip work)
+  int ch0, nch;          // first point chunk and number of chunks
+};
+struct BLev {  // one problem at one multigrid level
+  int nx, ny;
+  size_t off;  // first point in the packed level arrays
+};
+struct RowMap {  // workgroup -> (problem, grid row)
+  int b, j;
+};
+struct Chunk {  // workgroup -> (problem, local points [p0, p1))
+  int b, p0, p1;
+};
+
+void launch_fd_b(const RowMap* rm, int nrows, const BProb* pr, double diag, double off,
+                 int use_sigma, const double* X, int ldx, Blk out, Blk outr, Blk outc, int ncols,
+                 int threads, hipStream_t s);
+void launch_jacobi_b(const RowMap* rm, int nrows, const BLev* lv, const BProb* pr, double diag,
+                     double off, double omega, const double* xin, const double* r, int ldr,
+                     Blk o0, Blk o1, int split, int ncols, int threads, hipStream_t s);
+void launch_residual_b(const RowMap* rm, int nrows, const BLev* lv, const BProb* pr,
+                       double diag, double off, const double* x, const double* r, int ldr,
+                       double* res, int ncols, int threads, hipStream_t s);
+void launch_restrict_b(const RowMap* rmc, int ncrows, const BLev* lf, const BLev* lc,
+                       const BProb* pr, const double* res, double* rc, int ncols, int threads,
+                       hipStream_t s);
+void launch_prolong_b(const RowMap* rm, int nrows, const BLev* lf, const BLev* lc,
+                      const BProb* pr, const double* ec, double* x, int ncols, int threads,
+                      hipStream_t s);
+void launch_dense_b(int nb, const BLev* lv, const BProb* pr, const double* const* inv,
+                    const double* r, double* x, int ncols, hipStream_t s);
+void launch_xdots_b(const Chunk* ch, int nch, const BProb* pr, const double* X, int ldx,
+                    const double* Y, int ldy, int ncols, double* part, hipStream_t s);
+void launch_resid_b(const Chunk* ch, int nch, const BProb* pr, const double* V, int ldv,
+                    const double* QV, int ldq, double* R, int ldr, int ncols, double* part,
+                    hipStream_t s);
+void launch_gram_b(const Chunk* ch, int nch, int nb, const BProb* pr, const double* X, int ldx,
+                   int mx, const double* Y1, int ldy1, int my1, const double* Y2, int ldy2,
+                   int my, double* gpart, double* out, size_t ostride, size_t ntot,
+                   hipStream_t s);
+void launch_rowmul_b(const Chunk* ch, int nch, const BProb* pr, double* const* X, int narr,
+                     int ld, int m, const double* Mall, size_t mstride, int kout, int mode,
+                     int kv, int kc, int pcol, double* part, size_t ntot, hipStream_t s);
+void launch_small_gemm_b(const Chunk* ch, int nch, const BProb* pr, const double* X, int ldx,
+                         int kin, const double* Call, size_t cstride, int kout, double* Y,
+                         int ldy, hipStream_t s);
+void launch_copy_in_b(const Chunk* ch, int nch, const BProb* pr, const double* const* src,
+                      int c, double* Z, int ldz, hipStream_t s);
+void launch_copy_out_b(const Chunk* ch, int nch, const BProb* pr, const double* X, int ldx,
+                       int c, double* const* dst, hipStream_t s);
+void launch_hf_b(const Chunk* ch, int nch, const BProb* pr, const double* V, int ldv, int k,
+                 const double* dl, const double* const* vbv, double* const* g, int accumulate,
+                 hipStream_t s);
+hipError_t batch_set_attributes(int m);
+Grid make_grid(const plhr_op_desc* A);
+// max over rows of sum |A_ij| for the stencil plus potential (host)
+double exact_norm1(const Grid& g, const std::vector<double>& pot);
+// Inverse of the coarsest-level operator of a V-cycle on grid g (host,
+// FP64); false if it is not positive definite.
+bool coarse_inverse(const Grid& g, std::vector<double>& inv);
+
+// One problem of a batch, for the batched single-workgroup kernels
+// (workgroup b works on problem b).
+struct BatchSmall {
+  SmallParams p;
+  SmallBufs b;
+  DevStatus* st;
+  const double* part;  // per-chunk partial column sums of this problem
+  int nblk;            // number of chunks
+  const double* HM;    // final Rayleigh-Ritz matrices
+};
+// Batched launchers (nb problems, device array bs).
+void launch_init_lam_b(const BatchSmall* bs, int nb, hipStream_t s);
+void launch_start_check_b(const BatchSmall* bs, int nb, hipStream_t s);
+void launch_conv_check_b(const BatchSmall* bs, int nb, hipStream_t s);
+void launch_ortho_small_b(const BatchSmall* bs, int nb, int m, hipStream_t s);
+void launch_rq_small_b(const BatchSmall* bs, int nb, int end_of_iteration, hipStream_t s);
+void launch_final_rr_b(const BatchSmall* bs, int nb, int kint, hipStream_t s);
+void launch_final_res_b(const BatchSmall* bs, int nb, hipStream_t s);
+void launch_tharm_small_b(const BatchSmall* bs, int nb, int m, int kint, hipStream_t s);
 
 void launch_init_lam(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                      DevStatus* st, hipStream_t s);

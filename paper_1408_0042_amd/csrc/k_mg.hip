@@ -319,6 +319,11 @@ static bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+bool coarse_inverse(const Grid& g, std::vector<double>& inv) {
+  coarse_dense(g, inv);
+  return spd_inverse(inv, (int)g.n());
+}
+
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax) {

@@ -56,7 +56,7 @@ __device__ void sum_partials(const double* __restrict__ part, int nblk, int nv, 
 }
 
 // ---------------------------------------------------------------- init
-__global__ void k_init_lam(SmallParams p, const double* __restrict__ part, int nblk,
+__device__ void k_init_lam_body(SmallParams p, const double* __restrict__ part, int nblk,
                            SmallBufs b, DevStatus* st) {
   __shared__ double red[256], sums[128];
   sum_partials(part, nblk, 2 * p.kint, sums, red);
@@ -81,9 +81,20 @@ __global__ void k_init_lam(SmallParams p, const double* __restrict__ part, int n
   }
 }
 
+__global__ __launch_bounds__(256) void k_init_lam(SmallParams p, const double* __restrict__ part, int nblk,
+                           SmallBufs b, DevStatus* st) {
+  k_init_lam_body(p, part, nblk, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(256) void k_init_lam_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_init_lam_body(q.p, q.part, q.nblk, q.b, q.st);
+}
+
+
 // Rank test of the start block: scaled Cholesky of G = V0^T B V0 (kint x
 // kint, in b.G); a pivot below drop_tol means linearly dependent columns.
-__global__ void k_start_check(SmallParams p, SmallBufs b, DevStatus* st) {
+__device__ void k_start_check_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (threadIdx.x != 0) return;
   const int n = p.kint;  // <= 25 (4 kint <= 100)
   __shared__ double G[25 * 25];
@@ -118,8 +129,18 @@ __global__ void k_start_check(SmallParams p, SmallBufs b, DevStatus* st) {
   }
 }
 
+__global__ __launch_bounds__(64) void k_start_check(SmallParams p, SmallBufs b, DevStatus* st) {
+  k_start_check_body(p, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(64) void k_start_check_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_start_check_body(q.p, q.b, q.st);
+}
+
+
 // ------------------------------------------------------- convergence test
-__global__ void k_conv_check(SmallParams p, const double* __restrict__ part, int nblk,
+__device__ void k_conv_check_body(SmallParams p, const double* __restrict__ part, int nblk,
                              SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   __shared__ double rel[128];
@@ -171,10 +192,21 @@ __global__ void k_conv_check(SmallParams p, const double* __restrict__ part, int
   }
 }
 
+__global__ __launch_bounds__(256) void k_conv_check(SmallParams p, const double* __restrict__ part, int nblk,
+                             SmallBufs b, DevStatus* st) {
+  k_conv_check_body(p, part, nblk, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(256) void k_conv_check_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_conv_check_body(q.p, q.part, q.nblk, q.b, q.st);
+}
+
+
 // --------------------------------------------- Cholesky-QR in slot order
 // LDS: Gs (m x m, Cholesky factor R in the upper triangle) | X (m x m,
 // R^-1) | d (m)
-__global__ __launch_bounds__(256) void k_ortho_small(SmallParams p, SmallBufs b, DevStatus* st) {
+__device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   extern __shared__ double sm[];
   const int m = p.m, kint = p.kint;
@@ -263,9 +295,19 @@ __global__ __launch_bounds__(256) void k_ortho_small(SmallParams p, SmallBufs b,
   }
 }
 
+__global__ __launch_bounds__(256) void k_ortho_small(SmallParams p, SmallBufs b, DevStatus* st) {
+  k_ortho_small_body(p, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(256) void k_ortho_small_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_ortho_small_body(q.p, q.b, q.st);
+}
+
+
 // --------------------------------------------------- Rayleigh quotients
 // part: nblk x 2kint, [v.v | v.(A - sigma B) v]
-__global__ void k_rq_small(SmallParams p, const double* __restrict__ part, int nblk,
+__device__ void k_rq_small_body(SmallParams p, const double* __restrict__ part, int nblk,
                            SmallBufs b, DevStatus* st, int end_of_iteration) {
   if (halted(st)) return;
   __shared__ double red[256], sums[128];
@@ -290,11 +332,22 @@ __global__ void k_rq_small(SmallParams p, const double* __restrict__ part, int n
   }
 }
 
+__global__ __launch_bounds__(256) void k_rq_small(SmallParams p, const double* __restrict__ part, int nblk,
+                           SmallBufs b, DevStatus* st, int end_of_iteration) {
+  k_rq_small_body(p, part, nblk, b, st, end_of_iteration);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(256) void k_rq_small_b(const BatchSmall* __restrict__ bs, int end_of_iteration) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_rq_small_body(q.p, q.part, q.nblk, q.b, q.st, end_of_iteration);
+}
+
+
 static constexpr int kTh = 64;  // one wavefront
 
 // ------------------------------------------------- final Rayleigh-Ritz
 // HM: kint x 2kint = [V^T (A - sigma B) V | V^T B V]
-__global__ __launch_bounds__(kTh) void k_final_rr(SmallParams p, const double* __restrict__ HM,
+__device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
                                                   SmallBufs b, DevStatus* st) {
   extern __shared__ double sm[];
   const int n = p.kint, k = p.k, t = threadIdx.x;
@@ -420,8 +473,19 @@ __global__ __launch_bounds__(kTh) void k_final_rr(SmallParams p, const double* _
   }
 }
 
+__global__ __launch_bounds__(kTh) void k_final_rr(SmallParams p, const double* __restrict__ HM,
+                                                  SmallBufs b, DevStatus* st) {
+  k_final_rr_body(p, HM, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(kTh) void k_final_rr_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_final_rr_body(q.p, q.HM, q.b, q.st);
+}
+
+
 // relative residuals of the returned pairs from column sums
-__global__ void k_final_res(SmallParams p, const double* __restrict__ part, int nblk,
+__device__ void k_final_res_body(SmallParams p, const double* __restrict__ part, int nblk,
                             SmallBufs b) {
   __shared__ double red[256], sums[128];
   const int c = threadIdx.x, k = p.k;
@@ -433,6 +497,17 @@ __global__ void k_final_res(SmallParams p, const double* __restrict__ part, int 
     b.vbv[c] = vv;
   }
 }
+
+__global__ __launch_bounds__(256) void k_final_res(SmallParams p, const double* __restrict__ part, int nblk,
+                            SmallBufs b) {
+  k_final_res_body(p, part, nblk, b);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(256) void k_final_res_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_final_res_body(q.p, q.part, q.nblk, q.b);
+}
+
 
 // ------------------------------------------------------------ launchers
 void launch_init_lam(const SmallParams& p, const double* part, int nblk, SmallBufs b,
@@ -473,12 +548,47 @@ void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallB
   hipLaunchKernelGGL(k_final_res, dim3(1), dim3(256), 0, s, p, part, nblk, b);
 }
 
+// ---------------------------------------------------------------- batched
+void launch_init_lam_b(const BatchSmall* bs, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_lam_b, dim3(nb), dim3(256), 0, s, bs);
+}
+void launch_start_check_b(const BatchSmall* bs, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_check_b, dim3(nb), dim3(64), 0, s, bs);
+}
+void launch_conv_check_b(const BatchSmall* bs, int nb, hipStream_t s) {
+  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  hipLaunchKernelGGL(k_conv_check_b, dim3(nb), dim3(256), 0, s, bs);
+  prof_end(KC_SMALL, s);
+}
+void launch_ortho_small_b(const BatchSmall* bs, int nb, int m, hipStream_t s) {
+  const size_t lds = ((size_t)2 * m * m + m) * sizeof(double);
+  const double m3 = (double)m * m * m;
+  prof_begin(KC_ORTHO, nb * 2.0 * m * m * 8.0, nb * 2.0 * m3 / 3.0, s);
+  hipLaunchKernelGGL(k_ortho_small_b, dim3(nb), dim3(256), lds, s, bs);
+  prof_end(KC_ORTHO, s);
+}
+void launch_rq_small_b(const BatchSmall* bs, int nb, int end_of_iteration, hipStream_t s) {
+  prof_begin(KC_SMALL, 0.0, 0.0, s);
+  hipLaunchKernelGGL(k_rq_small_b, dim3(nb), dim3(256), 0, s, bs, end_of_iteration);
+  prof_end(KC_SMALL, s);
+}
+void launch_final_rr_b(const BatchSmall* bs, int nb, int kint, hipStream_t s) {
+  const size_t lds = (3 * (size_t)kint * kint + kint) * sizeof(double);
+  hipLaunchKernelGGL(k_final_rr_b, dim3(nb), dim3(kTh), lds, s, bs);
+}
+void launch_final_res_b(const BatchSmall* bs, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_res_b, dim3(nb), dim3(256), 0, s, bs);
+}
+
 hipError_t small_set_attributes(int m, int kint) {
   hipError_t e = tharm_set_attributes(m, kint);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_ortho_small_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(((size_t)2 * m * m + m) * sizeof(double)));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_ortho_small,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(((size_t)2 * m * m + m) * sizeof(double)));
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(((size_t)2 * m * m + m) * sizeof(double)));
 }
 
 }  // namespace plhr

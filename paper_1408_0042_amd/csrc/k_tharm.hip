@@ -96,7 +96,7 @@ __device__ int kept_slots(const int* keep, int m, int* idx) {
 // ------------------------------------------------------------ reduction
 // LDS: H n*n | L n*n (L is written out once C is formed and the region
 // then holds Q) | u n | w n | red 256
-__global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b, DevStatus* st) {
+__device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   if (threadIdx.x == 0) st->tphase[0] = clock64();
   extern __shared__ double sm[];
@@ -273,6 +273,16 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b
   }
   if (t == 0) st->tphase[3] = clock64();
 }
+
+__global__ __launch_bounds__(kNT) void k_tharm_reduce(SmallParams p, SmallBufs b, DevStatus* st) {
+  k_tharm_reduce_body(p, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(kNT) void k_tharm_reduce_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_tharm_reduce_body(q.p, q.b, q.st);
+}
+
 
 // ------------------------------------------------------------ Francis QR
 // Double-shift QR on the upper Hessenberg H (n x n) with Schur vectors
@@ -495,7 +505,7 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
 
 
 // LDS: H (n + 1) x ld | Q (n + 1) x ld, ld = (n + 1) | 1
-__global__ __launch_bounds__(kQR) void k_tharm_qr(SmallParams p, SmallBufs b, DevStatus* st) {
+__device__ void k_tharm_qr_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   extern __shared__ double sm[];
   __shared__ int idx[256];
@@ -542,11 +552,21 @@ __global__ __launch_bounds__(kQR) void k_tharm_qr(SmallParams p, SmallBufs b, De
   if (t == 0) st->tphase[5] = clock64();
 }
 
+__global__ __launch_bounds__(kQR) void k_tharm_qr(SmallParams p, SmallBufs b, DevStatus* st) {
+  k_tharm_qr_body(p, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(kQR) void k_tharm_qr_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_tharm_qr_body(q.p, q.b, q.st);
+}
+
+
 // ---------------------------------------------------------- eigenvectors
 // LDS: T n*n | Q n*n | Xre n*ks | Xim n*ks | 5n doubles | 5n ints.  L is
 // read from the work area; once the eigenvectors of T are known, the T
 // region holds the real parts of Y and the Xre region the imaginary parts.
-__global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs b, DevStatus* st) {
+__device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
   extern __shared__ double sm[];
   __shared__ int idx[256];
@@ -885,6 +905,16 @@ __global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs 
   }
 }
 
+__global__ __launch_bounds__(kNT) void k_tharm_vectors(SmallParams p, SmallBufs b, DevStatus* st) {
+  k_tharm_vectors_body(p, b, st);
+}
+// batched: workgroup b runs problem b
+__global__ __launch_bounds__(kNT) void k_tharm_vectors_b(const BatchSmall* __restrict__ bs) {
+  const BatchSmall& q = bs[blockIdx.x];
+  k_tharm_vectors_body(q.p, q.b, q.st);
+}
+
+
 static size_t reduce_lds(int m) { return ((size_t)2 * m * (m | 1) + 2 * m + kNT) * sizeof(double); }
 static size_t qr_lds(int m) { return (size_t)2 * (m + 1) * ((m + 1) | 1) * sizeof(double); }
 static size_t vectors_lds(int m, int kint) {
@@ -893,15 +923,20 @@ static size_t vectors_lds(int m, int kint) {
 }
 
 hipError_t tharm_set_attributes(int m, int kint) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_tharm_reduce,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds(m));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_tharm_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)qr_lds(m));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_tharm_vectors,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)vectors_lds(m, kint));
+  const void* fr[2] = {(const void*)k_tharm_reduce, (const void*)k_tharm_reduce_b};
+  const void* fq[2] = {(const void*)k_tharm_qr, (const void*)k_tharm_qr_b};
+  const void* fv[2] = {(const void*)k_tharm_vectors, (const void*)k_tharm_vectors_b};
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = hipFuncSetAttribute(fr[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)reduce_lds(m));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(fq[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_lds(m));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(fv[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)vectors_lds(m, kint));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
@@ -919,6 +954,19 @@ void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStr
   prof_end(KC_THARM_QR, s);
   prof_begin(KC_THARM_VECTORS, 3.0 * mm * 8.0 + mm * 8.0, m3 + 2.0 * mm * p.kint, s);
   hipLaunchKernelGGL(k_tharm_vectors, dim3(1), dim3(kNT), vectors_lds(p.m, p.kint), s, p, b, st);
+  prof_end(KC_THARM_VECTORS, s);
+}
+
+void launch_tharm_small_b(const BatchSmall* bs, int nb, int m, int kint, hipStream_t s) {
+  const double m3 = (double)m * m * m, mm = (double)m * m;
+  prof_begin(KC_THARM_REDUCE, nb * 5.0 * mm * 8.0, nb * (1.0 / 3.0 + 2.0 + 14.0 / 3.0) * m3, s);
+  hipLaunchKernelGGL(k_tharm_reduce_b, dim3(nb), dim3(kNT), reduce_lds(m), s, bs);
+  prof_end(KC_THARM_REDUCE, s);
+  prof_begin(KC_THARM_QR, nb * 4.0 * mm * 8.0, nb * 20.0 * m3, s);
+  hipLaunchKernelGGL(k_tharm_qr_b, dim3(nb), dim3(kQR), qr_lds(m), s, bs);
+  prof_end(KC_THARM_QR, s);
+  prof_begin(KC_THARM_VECTORS, nb * 4.0 * mm * 8.0, nb * (m3 + 2.0 * mm * kint), s);
+  hipLaunchKernelGGL(k_tharm_vectors_b, dim3(nb), dim3(kNT), vectors_lds(m, kint), s, bs);
   prof_end(KC_THARM_VECTORS, s);
 }
 

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass
-from typing import Optional, Sequence
+from typing import List, NamedTuple, Optional, Sequence
 
 import numpy as np
 import torch
@@ -219,3 +219,167 @@ class _EigvalsWithStart(torch.autograd.Function):
         g = S.backward(grad_lam.detach().contiguous().to(torch.float64))
         S.close()
         return g, None, None
+
+
+class BatchResult(NamedTuple):
+    eigvals: torch.Tensor     # (nbatch, k)
+    V: List[torch.Tensor]     # n_b x k each
+    rel_res: np.ndarray       # (nbatch, k)
+    iters: np.ndarray         # (nbatch,)
+    status: np.ndarray        # (nbatch,) per-problem status codes
+    converged: bool
+
+
+class BatchSolver:
+    """Many independent 2-D problems scale*(-Laplacian) + diag(potential_b)
+    (5-point Dirichlet, spacing h) solved together by plhr_batch_*; each
+    problem has its own grid (dims[b]), potential and shift."""
+
+    def __init__(self, dims: Sequence[Sequence[int]], h: float, sigma: Sequence[float], k: int,
+                 scale: float = 1.0, potentials: Optional[Sequence[torch.Tensor]] = None,
+                 precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
+                 k_extra: int = 1, lock: bool = True, check_every: int = 10,
+                 drop_tol: float = 1e-12, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.nb = len(dims)
+        self.dims = [tuple(int(x) for x in d) for d in dims]
+        self.n = [d[0] * d[1] for d in self.dims]
+        self.k = int(k)
+        self.kint = int(k) + int(k_extra)
+        self.potentials = None
+        if potentials is not None:
+            self.potentials = [p.detach().contiguous() for p in potentials]
+            for p in self.potentials:
+                _require_cuda(p, "potential")
+        descs = (L.OpDesc * self.nb)()
+        for b, d in enumerate(self.dims):
+            descs[b].kind, descs[b].nx, descs[b].ny, descs[b].nz = L.OP_FD5_2D, d[0], d[1], 1
+            descs[b].dtype = L.F64
+            descs[b].h = float(h)
+            descs[b].scale = float(scale)
+            if self.potentials is not None:
+                descs[b].potential = self.potentials[b].data_ptr()
+        t = None
+        if precond is not None:
+            t = L.PrecDesc()
+            t.kind = L.PREC_MG_VCYCLE
+            t.levels = int(precond.get("levels", 5))
+            t.nu_pre = t.nu_post = int(precond.get("nu", 2))
+            t.omega = float(precond.get("omega", 2.0 / 3.0))
+        o = L.default_options()
+        o.tol, o.max_iters, o.k_extra = float(tol), int(max_iters), int(k_extra)
+        o.lock, o.check_every, o.drop_tol = int(bool(lock)), int(check_every), float(drop_tol)
+        sig = (C.c_double * self.nb)(*[float(x) for x in sigma])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = C.c_void_p()
+        L.check(self.lib.plhr_batch_create(self.nb, descs, C.byref(t) if t is not None else None,
+                                           sig, self.k, C.byref(o),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self._descs, self._t = descs, t
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.plhr_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on: bool):
+        L.check(self.lib.plhr_batch_set_graph(self.ctx, int(bool(on))))
+
+    def solve(self, V0: Sequence[torch.Tensor], allow_unconverged: bool = False) -> BatchResult:
+        if len(V0) != self.nb:
+            raise ValueError("one start block per problem")
+        for b, v in enumerate(V0):
+            _require_cuda(v, "V0")
+            if tuple(v.shape) != (self.n[b], self.kint):
+                raise ValueError(f"V0[{b}] must have shape {(self.n[b], self.kint)}")
+        v0p = (C.c_void_p * self.nb)(*[v.data_ptr() for v in V0])
+        ev = torch.empty((self.nb, self.k), dtype=torch.float64, device="cuda")
+        V = [torch.empty((n, self.k), dtype=torch.float64, device="cuda") for n in self.n]
+        vp = (C.c_void_p * self.nb)(*[v.data_ptr() for v in V])
+        rr = (C.c_double * (self.nb * self.k))()
+        its = (C.c_int32 * self.nb)()
+        sts = (C.c_int32 * self.nb)()
+        code = self.lib.plhr_batch_solve(self.ctx, v0p, C.c_void_p(ev.data_ptr()), vp, rr, its,
+                                         sts)
+        converged = code == L.OK
+        if not (converged or (allow_unconverged and code == L.ERR_NOT_CONVERGED)):
+            L.check(code)
+        return BatchResult(ev, V, np.array(rr[:]).reshape(self.nb, self.k), np.array(its[:]),
+                           np.array(sts[:]), converged)
+
+    def backward(self, dL_dlam: torch.Tensor, accumulate: bool = False) -> List[torch.Tensor]:
+        _require_cuda(dL_dlam, "dL_dlam")
+        if tuple(dL_dlam.shape) != (self.nb, self.k):
+            raise ValueError("dL_dlam must have shape (nbatch, k)")
+        g = [torch.zeros(n, dtype=torch.float64, device="cuda") for n in self.n]
+        gp = (C.c_void_p * self.nb)(*[x.data_ptr() for x in g])
+        L.check(self.lib.plhr_batch_eigvals_backward(self.ctx,
+                                                     C.c_void_p(dL_dlam.contiguous().data_ptr()),
+                                                     gp, int(accumulate)))
+        return g
+
+    def apply(self, which: str, X: Sequence[torch.Tensor]) -> List[torch.Tensor]:
+        w = {"A": 0, "A-sigma": 1, "T": 2}[which]
+        ncols = X[0].shape[1]
+        for b, x in enumerate(X):
+            _require_cuda(x, "X")
+            if tuple(x.shape) != (self.n[b], ncols):
+                raise ValueError("X[b] must be n_b x ncols")
+        Y = [torch.empty_like(x) for x in X]
+        xp = (C.c_void_p * self.nb)(*[x.data_ptr() for x in X])
+        yp = (C.c_void_p * self.nb)(*[y.data_ptr() for y in Y])
+        L.check(self.lib.plhr_batch_apply(self.ctx, w, xp, yp, int(ncols)))
+        return Y
+
+    def tuning(self) -> dict:
+        t = L.BatchTuning()
+        L.check(self.lib.plhr_batch_tuning_info(self.ctx, C.byref(t)))
+        return {"chunk_points": t.chunk_points, "row_threads": t.row_threads,
+                "use_graph": bool(t.use_graph), "nchunks": t.nchunks,
+                "tuned_ms": list(t.tuned_ms)}
+
+    def profile_start(self, category: int = -1, max_launches: int = 200000):
+        L.check(self.lib.plhr_batch_profile_start(self.ctx, int(category), int(max_launches)))
+
+    def profile_stop(self) -> dict:
+        pr = L.Profile()
+        L.check(self.lib.plhr_batch_profile_stop(self.ctx, C.byref(pr)))
+        out = {}
+        for i, name in enumerate(L.KCAT_NAMES):
+            out[name] = {"launches": pr.launches[i], "ms": pr.total_ms[i],
+                         "bytes": pr.bytes[i], "flops": pr.flops[i]}
+        out["truncated"] = bool(pr.truncated)
+        return out
+
+
+def batch_eigvals(potentials: Sequence[torch.Tensor], V0: Sequence[torch.Tensor],
+                  **opts) -> torch.Tensor:
+    """Differentiable (nbatch, k) eigenvalues of a batch (opts as for
+    BatchSolver, without potentials); backward gives dL/dpotential_b for
+    every problem from the batched Hellmann-Feynman kernel."""
+    return _BatchEigvals.apply(opts, V0, *potentials)
+
+
+class _BatchEigvals(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, opts, V0, *potentials):
+        S = BatchSolver(potentials=[p.detach() for p in potentials], **opts)
+        r = S.solve([v.detach().contiguous() for v in V0])
+        ctx.solver = S
+        return r.eigvals.clone()
+
+    @staticmethod
+    def backward(ctx, grad_lam):
+        S = ctx.solver
+        g = S.backward(grad_lam.detach().contiguous().to(torch.float64))
+        S.close()
+        return (None, None, *g)

@@ -1,0 +1,142 @@
+"""Batched solves (plhr_batch_*): every problem of a batch against the
+oracle's dense nearest pairs, graph replays against eager launches, the
+batch against the single-problem solver, and the batched Hellmann-Feynman
+backward against the dense reference gradient and finite differences."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense, hf, operators as ops
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(Ns, ngauss, seed):
+    """2-D -1/2 Laplacian + Gaussian wells (h = 1, grid units), shift 40% of
+    the way between the 5th and 6th distinct eigenvalues."""
+    out = []
+    for b, N in enumerate(Ns):
+        pot = wl.gaussian_potential(N, ngauss, (seed, b))
+        A = ops.fd_dirichlet((N, N), 1.0, 0.5, potential=pot)
+        ev = dense.all_eigenvalues(A)
+        u = np.unique(np.round(ev, 10))
+        sigma = float(u[4] + 0.4 * (u[5] - u[4]))
+        out.append((N, pot, A, sigma))
+    return out
+
+
+def _batch(probs, k, kx, tol, levels=3):
+    import torch
+    from paper_1408_0042_amd.plhr import BatchSolver
+    S = BatchSolver(dims=[(N, N) for N, *_ in probs], h=1.0, scale=0.5,
+                    sigma=[s for *_, s in probs], k=k, k_extra=kx, tol=tol, max_iters=4000,
+                    lock=False,
+                    potentials=[torch.from_numpy(p).cuda() for _, p, _, _ in probs],
+                    precond={"levels": levels, "nu": 2, "omega": 2 / 3}, check_every=10)
+    V0 = [torch.from_numpy(wl.start_block(N * N, k + kx, (80, b))).cuda()
+          for b, (N, *_) in enumerate(probs)]
+    return S, V0
+
+
+def test_batch_operators_match_oracle():
+    """Stencil and V-cycle of every problem of a batch against the oracle
+    (sparse product, oracle V-cycle) element by element."""
+    import torch
+    from oracle import mg
+    probs = _problems([16, 24, 32, 8], 6, 86)
+    S, _ = _batch(probs, 4, 3, 1e-10)
+    X = [wl.start_block(N * N, 7, (87, b)) for b, (N, *_) in enumerate(probs)]
+    Xd = [torch.from_numpy(x).cuda() for x in X]
+    YA = S.apply("A", Xd)
+    YS = S.apply("A-sigma", Xd)
+    YT = S.apply("T", Xd)
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        ref = A @ X[b]
+        assert np.abs(YA[b].cpu().numpy() - ref).max() <= 1e-14 * np.abs(ref).max()
+        ref2 = ref - sigma * X[b]
+        assert np.abs(YS[b].cpu().numpy() - ref2).max() <= 1e-14 * np.abs(ref2).max()
+        V = mg.VCycle("fd", (N, N), 1.0, 0.5, 3)
+        refT = V.apply(X[b])
+        assert np.abs(YT[b].cpu().numpy() - refT).max() <= 1e-13 * np.abs(refT).max(), b
+    S.close()
+
+
+def test_batch_matches_brute_force_and_graph_replays_match_eager():
+    probs = _problems([16, 24, 32, 16, 24], 6, 81)
+    k, kx = 4, 3
+    S, V0 = _batch(probs, k, kx, 1e-11)
+    r1 = S.solve(V0)
+    assert r1.converged, (r1.status, r1.iters)
+    lam1 = r1.eigvals.cpu().numpy()
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        lam_b, _ = dense.nearest_pairs(A, None, sigma, k)
+        assert np.allclose(lam1[b], lam_b, rtol=1e-10), (b, lam1[b], lam_b)
+        _, U = dense.cluster_basis(A, None, sigma, k)
+        assert dense.subspace_sine(U, r1.V[b].cpu().numpy()) < 1e-7, b
+        assert np.all(r1.rel_res[b] <= 1e-10), (b, r1.rel_res[b])
+    assert S.tuning()["use_graph"]
+    # eager launches, then the graph again: identical arithmetic, so the
+    # replays must reproduce the eager results
+    S.set_graph(False)
+    r2 = S.solve(V0)
+    S.set_graph(True)
+    r3 = S.solve(V0)
+    for r in (r2, r3):
+        assert np.array_equal(r.iters, r1.iters)
+        assert np.max(np.abs(r.eigvals.cpu().numpy() - lam1) / np.abs(lam1)) <= 1e-14
+    S.close()
+
+
+def test_batch_problem_equals_single_solver():
+    import torch
+    from paper_1408_0042_amd.plhr import Solver
+    probs = _problems([24, 32], 6, 82)
+    k, kx = 4, 3
+    S, V0 = _batch(probs, k, kx, 1e-11)
+    r = S.solve(V0)
+    S.close()
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        T = Solver(kind="fd5_2d", dims=(N, N), h=1.0, sigma=sigma, k=k, k_extra=kx, scale=0.5,
+                   potential=torch.from_numpy(pot).cuda(), tol=1e-11, max_iters=4000, lock=False,
+                   precond={"levels": 3, "nu": 2, "omega": 2 / 3})
+        rs = T.solve(V0[b])
+        T.close()
+        assert np.allclose(r.eigvals[b].cpu().numpy(), rs.eigvals.cpu().numpy(), rtol=1e-10)
+
+
+def test_batch_backward_matches_dense_gradient_and_finite_differences():
+    import torch
+    from paper_1408_0042_amd.plhr import batch_eigvals
+    probs = _problems([12, 16, 12], 5, 83)
+    k, kx = 4, 3
+    targets = np.array([[0.1, 0.2, 0.3, 0.4]] * len(probs)) + np.array([[0.0], [0.05], [0.1]])
+    pots = [torch.from_numpy(p).cuda().requires_grad_(True) for _, p, _, _ in probs]
+    V0 = [torch.from_numpy(wl.start_block(N * N, k + kx, (84, b))).cuda()
+          for b, (N, *_) in enumerate(probs)]
+    opts = dict(dims=[(N, N) for N, *_ in probs], h=1.0, scale=0.5,
+                sigma=[s for *_, s in probs], k=k, k_extra=kx, tol=1e-13, max_iters=20000,
+                lock=False,
+                precond={"levels": 2, "nu": 2, "omega": 2 / 3})
+    lam = batch_eigvals(pots, V0, **opts)
+    loss = ((lam - torch.from_numpy(targets).cuda()) ** 2).sum()
+    loss.backward()
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        g_gpu = pots[b].grad.cpu().numpy()
+        lam_ref, X = dense.nearest_pairs(A, None, sigma, k)
+        assert np.allclose(lam[b].detach().cpu().numpy(), lam_ref, rtol=1e-11)
+        _, dl = hf.loss_and_grad_targets(lam_ref, targets[b])
+        g_ref = hf.eigval_grad(X, dl)
+        assert np.max(np.abs(g_gpu - g_ref)) <= 1e-9 * np.max(np.abs(g_ref)), b
+        if b == 1:
+            eps = 1e-6
+
+            def loss_b(pv):
+                Ab = ops.fd_dirichlet((N, N), 1.0, 0.5, potential=pv)
+                return hf.loss_and_grad_targets(dense.nearest_pairs(Ab, None, sigma, k)[0],
+                                                targets[b])[0]
+            for x in np.random.default_rng(85).choice(N * N, 6, replace=False):
+                pp, pm = pot.copy(), pot.copy()
+                pp[x] += eps
+                pm[x] -= eps
+                fd = (loss_b(pp) - loss_b(pm)) / (2 * eps)
+                assert abs(fd - g_gpu[x]) <= 1e-7 * max(1.0, np.max(np.abs(g_ref)))

@@ -35,6 +35,7 @@ def test_stencil_parity(kind, dims, ncols):
 
 
 @pytest.mark.parametrize("kind,dims,levels,ncols", [("fd5_2d", (32, 32), 4, 5),
+                                                    ("fd5_2d", (16, 16), 3, 6),
                                                     ("fd7_3d", (16, 16, 8), 3, 4),
                                                     ("fd7_3d", (64, 64, 64), 5, 34)])
 def test_vcycle_parity(kind, dims, levels, ncols):
