@@ -294,7 +294,11 @@ class BatchSolver:
     def set_graph(self, on: bool):
         L.check(self.lib.plhr_batch_set_graph(self.ctx, int(bool(on))))
 
-    def solve(self, V0: Sequence[torch.Tensor], allow_unconverged: bool = False) -> BatchResult:
+    def solve(self, V0: Sequence[torch.Tensor], allow_unconverged: bool = False,
+              allow_failures: bool = False) -> BatchResult:
+        """allow_unconverged: return when some problems reached max_iters;
+        allow_failures: return also when some problems failed (their status
+        entries say how); otherwise such outcomes raise."""
         if len(V0) != self.nb:
             raise ValueError("one start block per problem")
         for b, v in enumerate(V0):
@@ -311,7 +315,8 @@ class BatchSolver:
         code = self.lib.plhr_batch_solve(self.ctx, v0p, C.c_void_p(ev.data_ptr()), vp, rr, its,
                                          sts)
         converged = code == L.OK
-        if not (converged or (allow_unconverged and code == L.ERR_NOT_CONVERGED)):
+        if not (converged or (allow_unconverged and code == L.ERR_NOT_CONVERGED) or
+                (allow_failures and code not in (L.ERR_ARG, L.ERR_HIP, L.ERR_STATE))):
             L.check(code)
         return BatchResult(ev, V, np.array(rr[:]).reshape(self.nb, self.k), np.array(its[:]),
                            np.array(sts[:]), converged)
