@@ -13,7 +13,7 @@
 // global work area (L2-resident):
 //   k_tharm_reduce  (256 threads) Cholesky of G_L, C, Householder
 //                   reduction of C to upper Hessenberg H = Q^T C Q
-//   k_tharm_qr      (two wavefronts) Francis double-shift QR of H to real
+//   k_tharm_qr      (four wavefronts) Francis double-shift QR of H to real
 //                   Schur form T, accumulating Q; 2x2 blocks with real
 //                   eigenvalues are split by a rotation
 //   k_tharm_vectors (256 threads) eigenvalues and their ordering by
@@ -47,7 +47,7 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 __device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
 
 constexpr int kNT = 256;  // threads of the parallel phases
-constexpr int kQR = 128;  // the QR workgroup (two wavefronts)
+constexpr int kQR = 256;  // the QR workgroup (four wavefronts)
 
 // 1/d from the hardware reciprocal estimate and two Newton steps (the
 // Householder coefficients need a few-ulp reciprocal, not an IEEE
@@ -95,13 +95,30 @@ __device__ int kept_slots(const int* keep, int m, int* idx) {
 
 // ------------------------------------------------------------ reduction
 // LDS: H n*n | L n*n (L is written out once C is formed and the region
-// then holds Q) | u n | w n | red 256
+// then holds Q) | u n | bv n | red 256
+//
+// Cholesky: right-looking on unscaled columns (the trailing update of
+// column j divides by the pivot, the scaling 1/sqrt(pivot) of column j is
+// applied once at the end), one barrier per column.  C = L^-1 G_R L^-T:
+// forward substitutions, one thread per column of G_R, then one thread per
+// row.  Householder reduction to Hessenberg form: each step reads the
+// column norm from per-wave partial sums left by the previous step, forms
+// Hu, u^T H and Qu in one pass (one thread per row of H, of Q and per
+// column of H) and applies H <- (I - beta u u^T) H (I - beta u u^T) as one
+// rank-2 update with the coefficient gamma = u^T H u, Q <- Q (I - beta u
+// u^T); two barriers per step.
+__device__ __forceinline__ double wave_sum(double a) {
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  return a;
+}
+
 __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
+  static_assert(kNT >= 3 * kMaxM, "one thread per row of H, of Q and per column of H");
   if (halted(st)) return;
   if (threadIdx.x == 0) st->tphase[0] = clock64();
   extern __shared__ double sm[];
   __shared__ int idx[256];
-  const int m = p.m, t = threadIdx.x;
+  const int m = p.m, t = threadIdx.x, wv = t >> 6;
   const int n = kept_slots(b.keep, m, idx);
   if (n < p.kint) {  // fewer independent basis vectors than wanted columns
     if (t == 0) {
@@ -116,8 +133,8 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   double* L = H + n * ld;
   double* Q = L;  // after L has been written out
   double* u = L + n * ld;
-  double* w = u + n;
-  double* red = w + n;
+  double* bv = u + n;
+  double* red = bv + n;
   const int ld2 = 2 * m;
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16) {
@@ -125,89 +142,105 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
       L[i * ld + c] = 0.5 * (b.GLR[(size_t)ia * ld2 + ic] + b.GLR[(size_t)ic * ld2 + ia]);
       H[i * ld + c] = b.GLR[(size_t)ia * ld2 + m + ic];
     }
-  __syncthreads();
-  // Cholesky G_L = L L^T (right-looking).  A pivot in [-1e-10, 1e-15] max
-  // diag (G_L singular to rounding: sigma an eigenvalue whose vector lies
-  // in span Z, xi = 0) is raised to 1e-15 max diag.  A pivot below
-  // -1e-10 max diag cannot come from an HPD G_L: the stored products of
-  // that slot no longer agree (T(A - sigma B)Z carried by linear
-  // combination has drifted from T applied to (A - sigma B)Z), and the
-  // slot is left out: its row and column of L become e_j and those of G_R
-  // zero, so that it contributes only tau = 0 (xi = infinity), never
-  // selected, and the remaining slots form the projected problem on
-  // their own span.
+  // Cholesky G_L = L L^T.  A pivot in [-1e-10, 1e-15] max diag (G_L
+  // singular to rounding: sigma an eigenvalue whose vector lies in span Z,
+  // xi = 0) is raised to 1e-15 max diag.  A pivot below -1e-10 max diag
+  // cannot come from an HPD G_L: the stored products of that slot no
+  // longer agree (T(A - sigma B)Z carried by linear combination has
+  // drifted from T applied to (A - sigma B)Z), and the slot is left out:
+  // its row and column of L become e_j and those of G_R zero, so that it
+  // contributes only tau = 0 (xi = infinity), never selected, and the
+  // remaining slots form the projected problem on their own span.
   __shared__ int dead[256];
   __shared__ int ndead;
+  double* dsc = bv;   // 1/sqrt(pivot) per column
+  double* djj = red;  // sqrt(pivot): the diagonal of L
+  for (int j = t; j < n; j += kNT) dead[j] = 0;
+  if (t == 0) ndead = 0;
+  __syncthreads();
   double maxd = 0.0;
   for (int j = 0; j < n; ++j) maxd = fmax(maxd, L[j * ld + j]);
   const double floor_ = fmax(1e-15 * maxd, 1e-300);
-  for (int j = t; j < n; j += kNT) dead[j] = 0;
-  if (t == 0) ndead = 0;
   for (int j = 0; j < n; ++j) {
     const double p0 = L[j * ld + j];
-    __syncthreads();
-    if (p0 < -1e-10 * maxd) {  // uniform
-      for (int i = j + 1 + t; i < n; i += kNT) L[i * ld + j] = 0.0;
-      for (int c = t; c < j; c += kNT) L[j * ld + c] = 0.0;
+    if (p0 < -1e-10 * maxd) {  // uniform; no update, so no barrier
       if (t == 0) {
-        L[j * ld + j] = 1.0;
         dead[j] = 1;
         ++ndead;
+        dsc[j] = 0.0;
       }
-      __syncthreads();
       continue;
     }
-    const double djj = sqrt(fmax(p0, floor_));
-    for (int i = j + 1 + t; i < n; i += kNT) L[i * ld + j] /= djj;
-    if (t == 0) L[j * ld + j] = djj;
-    __syncthreads();
+    const double pp = fmax(p0, floor_);
+    const double inv = 1.0 / pp;
+    if (t == 0) {
+      djj[j] = sqrt(pp);
+      dsc[j] = 1.0 / djj[j];
+    }
     for (int i = j + 1 + ty; i < n; i += 16) {
-      const double lij = L[i * ld + j];
+      const double lij = L[i * ld + j] * inv;
       for (int c = j + 1 + tx; c <= i; c += 16) L[i * ld + c] -= lij * L[c * ld + j];
     }
     __syncthreads();
   }
-  if (ndead) {  // uniform
-    for (int i = ty; i < n; i += 16)
-      for (int c = tx; c < n; c += 16)
-        if (dead[i] || dead[c]) H[i * ld + c] = 0.0;
-    if (t == 0) st->n_excluded += ndead;
-    __syncthreads();
-    if (n - ndead < p.kint) {
-      if (t == 0) {
-        st->error = PLHR_ERR_BREAKDOWN;
-        st->reason = kReasonVVanished;
-      }
-      return;
-    }
-  }
+  __syncthreads();
   for (int i = ty; i < n; i += 16)
-    for (int c = tx; c < n; c += 16)
-      if (c > i) L[i * ld + c] = 0.0;
+    for (int c = tx; c < n; c += 16) {
+      double v = 0.0;
+      if (dead[i] || dead[c])
+        v = (i == c) ? 1.0 : 0.0;
+      else if (c == i)  // the raised pivot, where it was raised
+        v = djj[c];
+      else if (c < i)
+        v = L[i * ld + c] * dsc[c];
+      L[i * ld + c] = v;
+      if (dead[i] || dead[c]) H[i * ld + c] = 0.0;
+    }
+  if (t == 0 && ndead) st->n_excluded += ndead;
+  if (ndead && n - ndead < p.kint) {  // uniform
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    return;
+  }
   if (t == 0) st->tphase[1] = clock64();
   __syncthreads();
-  // H <- L^-1 H (rows, right-looking forward substitution)
-  for (int i = 0; i < n; ++i) {
-    const double inv = 1.0 / L[i * ld + i];
-    for (int c = t; c < n; c += kNT) H[i * ld + c] *= inv;
-    __syncthreads();
-    for (int r = i + 1 + ty; r < n; r += 16) {
-      const double lri = L[r * ld + i];
-      for (int c = tx; c < n; c += 16) H[r * ld + c] -= lri * H[i * ld + c];
+  // H <- L^-1 H: column c by thread c
+  if (t < n) {
+    for (int i = 0; i < n; ++i) {
+      const double* Li = L + i * ld;
+      double s0 = H[i * ld + t], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int r = 0;
+      for (; r + 3 < i; r += 4) {
+        s0 -= Li[r] * H[r * ld + t];
+        s1 -= Li[r + 1] * H[(r + 1) * ld + t];
+        s2 -= Li[r + 2] * H[(r + 2) * ld + t];
+        s3 -= Li[r + 3] * H[(r + 3) * ld + t];
+      }
+      for (; r < i; ++r) s0 -= Li[r] * H[r * ld + t];
+      H[i * ld + t] = ((s0 + s1) + (s2 + s3)) / Li[i];
     }
-    __syncthreads();
   }
-  // H <- H L^-T (columns)
-  for (int i = 0; i < n; ++i) {
-    const double inv = 1.0 / L[i * ld + i];
-    for (int r = t; r < n; r += kNT) H[r * ld + i] *= inv;
-    __syncthreads();
-    for (int c = i + 1 + ty; c < n; c += 16) {
-      const double lci = L[c * ld + i];
-      for (int r = tx; r < n; r += 16) H[r * ld + c] -= lci * H[r * ld + i];
+  __syncthreads();
+  // H <- H L^-T: row r by thread r (x L^T = h)
+  if (t < n) {
+    double* Hr = H + t * ld;
+    for (int i = 0; i < n; ++i) {
+      const double* Li = L + i * ld;
+      double s0 = Hr[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int c = 0;
+      for (; c + 3 < i; c += 4) {
+        s0 -= Li[c] * Hr[c];
+        s1 -= Li[c + 1] * Hr[c + 1];
+        s2 -= Li[c + 2] * Hr[c + 2];
+        s3 -= Li[c + 3] * Hr[c + 3];
+      }
+      for (; c < i; ++c) s0 -= Li[c] * Hr[c];
+      Hr[i] = ((s0 + s1) + (s2 + s3)) / Li[i];
     }
-    __syncthreads();
   }
+  __syncthreads();
   // L (compact n x n) to the work area; its LDS region becomes Q = I
   double* gw = b.work;
   for (int e = t; e < n * n; e += kNT) {
@@ -217,52 +250,83 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   __syncthreads();
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16) Q[i * ld + c] = (i == c) ? 1.0 : 0.0;
-  __syncthreads();
   if (t == 0) st->tphase[2] = clock64();
-  // Householder reduction to upper Hessenberg form, Q accumulated
+  // Householder reduction to upper Hessenberg form, Q accumulated.
+  // red[0..3]: per-wave partial sums of H[i][k]^2, i >= k + 2, for step k;
+  // red[4..7]: per-wave partial sums of u_i (Hu)_i for gamma.
+  {
+    const double a = (t >= 2 && t < n) ? H[t * ld] * H[t * ld] : 0.0;
+    const double s = wave_sum(a);
+    if ((t & 63) == 0) red[wv] = s;
+  }
+  __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
-    double part = 0.0;
-    for (int i = k + 2 + t; i < n; i += kNT) part += H[i * ld + k] * H[i * ld + k];
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((t & 63) == 0) red[t >> 6] = part;
-    __syncthreads();
-    const double ss = (red[0] + red[1]) + (red[2] + red[3]);
+    const double ss = ((red[0] + red[1]) + red[2]) + red[3];
     const double x0 = H[(k + 1) * ld + k];
-    __syncthreads();
-    if (ss == 0.0) continue;  // column already reduced (uniform)
+    if (ss == 0.0) {  // column already reduced (uniform): next column's partials
+      __syncthreads();
+      const double a = (t >= k + 3 && t < n) ? H[t * ld + k + 1] * H[t * ld + k + 1] : 0.0;
+      const double s = wave_sum(a);
+      if ((t & 63) == 0) red[wv] = s;
+      __syncthreads();
+      continue;
+    }
     const double nrm = sqrt(x0 * x0 + ss);
     const double alpha = (x0 >= 0.0) ? -nrm : nrm;
     const double beta = 1.0 / (nrm * (nrm + fabs(x0)));  // 2 / (u.u)
-    for (int i = k + 1 + t; i < n; i += kNT) u[i] = (i == k + 1) ? x0 - alpha : H[i * ld + k];
-    __syncthreads();
-    // left: w_j = beta * sum_i u_i H_ij, j >= k; H -= u w^T
-    for (int j = k + t; j < n; j += kNT) {
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s += u[i] * H[i * ld + j];
-      w[j] = beta * s;
+    const double u1 = x0 - alpha;                        // u_{k+1}; u_i = H[i][k] below
+    const double* Hk = H + k;                            // column k, stride ld
+    double acc = 0.0;
+    if (t < 2 * n) {  // (Hu)_i for t < n, (Qu)_{t-n} otherwise
+      const double* X = (t < n) ? H + t * ld : Q + (t - n) * ld;
+      double a0 = X[k + 1] * u1, a1 = 0.0;
+      int q = k + 2;
+      for (; q + 1 < n; q += 2) {
+        a0 += X[q] * Hk[q * ld];
+        a1 += X[q + 1] * Hk[(q + 1) * ld];
+      }
+      if (q < n) a0 += X[q] * Hk[q * ld];
+      acc = a0 + a1;
+    } else if (t < 3 * n - k) {  // (u^T H)_j, j >= k
+      const int j = k + (t - 2 * n);
+      double a0 = u1 * H[(k + 1) * ld + j], a1 = 0.0;
+      int i = k + 2;
+      for (; i + 1 < n; i += 2) {
+        a0 += Hk[i * ld] * H[i * ld + j];
+        a1 += Hk[(i + 1) * ld] * H[(i + 1) * ld + j];
+      }
+      if (i < n) a0 += Hk[i * ld] * H[i * ld + j];
+      bv[j] = a0 + a1;
+    }
+    double ui = 0.0;
+    if (t >= k + 1 && t < n) {
+      ui = (t == k + 1) ? u1 : Hk[t * ld];
+      u[t] = ui;
+    }
+    {
+      const double s = wave_sum(ui * acc);  // ui = 0 off the rows of H
+      if ((t & 63) == 0) red[4 + wv] = s;
     }
     __syncthreads();
-    for (int i = k + 1 + ty; i < n; i += 16) {
-      const double ui = u[i];
-      for (int j = k + tx; j < n; j += 16) H[i * ld + j] -= ui * w[j];
+    const double gamma = ((red[4] + red[5]) + red[6]) + red[7];
+    double nxt = 0.0;
+    if (t < n) {
+      // H[i][j] -= beta u_i (u^T H)_j + (beta (Hu)_i - beta^2 gamma u_i) u_j
+      double* Hr = H + t * ld;
+      const double cu = beta * ui;
+      const double cv = beta * acc - beta * beta * gamma * ui;
+      if (t >= k + 1) Hr[k] = (t == k + 1) ? alpha : 0.0;
+      for (int j = k + 1; j < n; ++j) Hr[j] -= cu * bv[j] + cv * u[j];
+      if (t >= k + 3) nxt = Hr[k + 1] * Hr[k + 1];
+    } else if (t < 2 * n) {
+      double* Qr = Q + (t - n) * ld;
+      const double cz = beta * acc;
+      for (int j = k + 1; j < n; ++j) Qr[j] -= cz * u[j];
     }
-    __syncthreads();
-    // right: rows of H and Q: z_i = beta * sum_q X_iq u_q ; X -= z u^T
-    for (int r = t; r < 2 * n; r += kNT) {
-      const double* X = (r < n) ? H + r * ld : Q + (r - n) * ld;
-      double s = 0.0;
-      for (int q = k + 1; q < n; ++q) s += X[q] * u[q];
-      red[r] = beta * s;  // 2n <= 200 < 256
+    {
+      const double s = wave_sum(nxt);
+      if ((t & 63) == 0) red[wv] = s;
     }
-    __syncthreads();
-    for (int r = ty; r < 2 * n; r += 16) {
-      double* X = (r < n) ? H + r * ld : Q + (r - n) * ld;
-      const double z = red[r];
-      for (int q = k + 1 + tx; q < n; q += 16) X[q] -= z * u[q];
-    }
-    __syncthreads();
-    if (t == 0) H[(k + 1) * ld + k] = alpha;
-    for (int i = k + 2 + t; i < n; i += kNT) H[i * ld + k] = 0.0;
     __syncthreads();
   }
   // H and Q (n x n each, compact) to the work area after L
@@ -285,34 +349,80 @@ __global__ __launch_bounds__(kNT) void k_tharm_reduce_b(const BatchSmall* __rest
 
 
 // ------------------------------------------------------------ Francis QR
-// Double-shift QR on the upper Hessenberg H (n x n) with Schur vectors
-// accumulated into Q.  Deflation: the usual relative test, a normwise one
-// (a subdiagonal below ulp*||H|| is a backward-stable perturbation), and
-// a threshold that widens by 10x every 10 sweeps without deflation, up to
-// 1e8*ulp: degenerate eigenvalues of the pencil (symmetric grids) make
-// clusters of three or more equal tau, on which double-shift sweeps make
-// no progress, and the widened test accepts the tiny coupling inside such
-// a cluster, whose eigenvalues are equal to that accuracy.  Exceptional
-// shifts every 10 sweeps without deflation.
+// P = I - tau v v^T with v = (1, v1, v2) and P (x, y, z)^T = (beta, 0, 0)^T
+// (Sec. 5.1 of Golub & Van Loan), beta = -sign(x) ||(x, y, z)||; the
+// square root and reciprocal come from the hardware estimates refined by
+// Newton steps.  A zero vector gives P = I.
+__device__ __forceinline__ void householder3(double x, double y, double z, double& tau, double& v1,
+                                             double& v2) {
+  const double s = fabs(x) + fabs(y) + fabs(z);
+  const double ss = fma(z, z, fma(y, y, x * x));
+  double r = __builtin_amdgcn_rsq(ss);
+  double e = fma(-ss * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  e = fma(-ss * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  const double nrm = ss * r;
+  const double sg = (x >= 0.0) ? 1.0 : -1.0;
+  const double beta = -sg * nrm;
+  const double iv = fast_rcp(x - beta);
+  const bool zero = (s == 0.0);
+  tau = zero ? 0.0 : (beta - x) * (-sg * r);
+  v1 = zero ? 0.0 : y * iv;
+  v2 = zero ? 0.0 : z * iv;
+}
+
+// Francis double-shift QR of the upper Hessenberg H (n x n) to real Schur
+// form, accumulating Q <- Q P for every reflector (Sec. 7.5 of Golub & Van
+// Loan, standard deflation test on the subdiagonal, which is relaxed by a
+// factor 10 per 10 sweeps without deflation so that the iteration also
+// ends on a cluster, whose eigenvalues are equal to that accuracy).
+// Exceptional shifts every 10 sweeps without deflation.  Real 2 x 2 blocks
+// are split by a rotation.
 //
 // Layout: row stride ld >= n + 1 and n + 1 rows for each of H and Q
-// (Q = H + (n + 1) ld); row n and column n are padding.  A bulge step
-// k applies P = I - tau v v^T (v = (1, v1, v2) on indices k..k+2) as
-// H <- P H P, Q <- Q P in a single pass over disjoint groups of three
-// entries: the left update of each column outside the 3 x 3 block, the
-// right update of each row outside it, the right update of each row of
-// Q, and both updates of the block (one lane).  Every lane issues all of
-// its loads before the reflector is formed; groups that do not exist
-// (past n, or inside the block) point at the padding, so no lane
-// branches, and for the last step of a sweep (two rows) v2 = 0 makes the
-// third entry of each group a no-op.  One barrier per bulge step.
+// (Q = H + (n + 1) ld); row n and column n are padding that stays zero.
+//
+// A bulge step k applies P = I - tau v v^T (v = (1, v1, v2) on indices
+// k..k+2; v2 = 0 for the last step of a sweep) as H <- P H P, Q <- Q P.
+// The four wavefronts of the workgroup have fixed roles:
+//   waves 0, 1   the updates of disjoint 3-entry groups outside the 3 x 3
+//                block at (k, k): group g < 96 is the right update of row
+//                g of H when g <= min(k + 3, hi), otherwise the left update
+//                of column g - 5 in rows k..k+2 (the columns left of k - 1
+//                that this includes are exact zeros below the subdiagonal,
+//                which the update keeps zero); group 96 + i is row i of Q.
+//                Each lane runs groups t and t + 128.
+//   wave 2       lanes 0..2: the columns of P B P for the block B.
+//   wave 3       the reflector of step k + 1, computed during step k from B,
+//                P_k and the row below the block, which before step k is
+//                (0, 0, H[k+3][k+2]) with that entry read one step ahead
+//                (no lane writes row k + 3 then).
+// The reflectors pass through a double-buffered LDS slot.  Each step has
+// two barriers: after the first, every read of the block region is done
+// and wave 2 writes the new block; after the second, the step is complete.
+// Groups that do not exist point at the padding.
 __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, int* sweeps,
-                           int* steps) {
+                           int* steps, double* refl) {
   constexpr int NT = kQR;
-  constexpr int U = (kMaxM + NT) / NT;  // groups of each kind per lane
-  const int t = threadIdx.x, lane = t & 63;
+  static_assert(NT == 256, "four wavefronts");
+  static_assert(kMaxM + 5 <= 96 && 96 + kMaxM <= 2 * 128, "group index space");
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const double ulp = 2.220446049250313e-16;
   const double small = 1e-300;
+  const int QOFF = (n + 1) * ld;  // Q follows H in the LDS array
+  int tld[2], bQ[2], jL[2];
+  bool lok[2], isH[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int g = t + 128 * u;
+    isH[u] = (g < 96);
+    tld[u] = g * ld;
+    jL[u] = g - 5;
+    lok[u] = isH[u] && (g >= 5) && (g - 5 < n);
+    bQ[u] = (g >= 96 && g < 96 + n) ? QOFF + (g - 96) * ld : n * ld;
+  }
+  const int bc = t - 128;  // block column of the lanes of wave 2
   int hi = n - 1;
   int its = 0, total = 0, nsteps = 0;
   while (hi >= 0) {
@@ -398,101 +508,97 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
       h22 = H[hi * ld + hi];
     }
     const double tr = h11 + h22, det = h11 * h22 - h12 * h21;
-    double x = H[l * ld + l] * H[l * ld + l] + H[l * ld + l + 1] * H[(l + 1) * ld + l] -
-               tr * H[l * ld + l] + det;
-    double y = H[(l + 1) * ld + l] * (H[l * ld + l] + H[(l + 1) * ld + l + 1] - tr);
-    double z = H[(l + 1) * ld + l] * H[(l + 2) * ld + l + 1];
-    const int dummyR = n * ld;  // row n: padding
+    // first column of (H - s1)(H - s2) restricted to rows l..l+2
+    const double x = H[l * ld + l] * H[l * ld + l] + H[l * ld + l + 1] * H[(l + 1) * ld + l] -
+                     tr * H[l * ld + l] + det;
+    const double y = H[(l + 1) * ld + l] * (H[l * ld + l] + H[(l + 1) * ld + l + 1] - tr);
+    const double z = H[(l + 1) * ld + l] * H[(l + 2) * ld + l + 1];
+    double tau = 0.0, v1 = 0.0, v2 = 0.0, s3 = 0.0;
+    if (wv == 3) {
+      householder3(x, y, z, tau, v1, v2);
+      if (t == 192) {
+        refl[(l & 1) * 4 + 0] = tau;
+        refl[(l & 1) * 4 + 1] = v1;
+        refl[(l & 1) * 4 + 2] = v2;
+      }
+      const int r = (l + 3 <= n) ? l + 3 : n, c = (l + 2 <= n) ? l + 2 : n;
+      s3 = H[r * ld + c];
+    }
+    __syncthreads();
     for (int k = l; k <= hi - 1; ++k) {
       const bool three = (k < hi - 1);
       const int nr = three ? 3 : 2;
-      const int jlo = (k > l) ? k - 1 : l;
-      const int ihi = (k + 3 < hi) ? k + 3 : hi;
-      if (k > l) {
-        x = H[k * ld + k - 1];
-        y = H[(k + 1) * ld + k - 1];
-        const double zz = H[(k + 2) * ld + k - 1];
-        z = three ? zz : 0.0;
-      }
-      // groups: three entries each, at offset o, o + s, o + 2s; invalid
-      // groups point at padding
-      double aL[U][3], aR[U][3], aQ[U][3];
-      int oL[U], oR[U], oQ[U];
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0, sw = 0.0, w1 = 0.0, w2 = 0.0;
+      if (wv < 2) {
+        const int ihi = (k + 3 < hi) ? k + 3 : hi;
+        const double* rf = refl + (k & 1) * 4;
+        const double ta = rf[0], u1 = rf[1], u2 = rf[2];
+        const int kld = k * ld;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = jlo + t + NT * u;
-        const bool vl = (j < n) && (j < k || j >= k + nr);
-        oL[u] = k * ld + (vl ? j : n);
-        aL[u][0] = H[oL[u]];
-        aL[u][1] = H[oL[u] + ld];
-        aL[u][2] = H[oL[u] + 2 * ld];
-        const int i = t + NT * u;
-        const bool vr = (i <= ihi) && (i < k || i >= k + nr);
-        oR[u] = (vr ? i * ld : dummyR) + k;
-        aR[u][0] = H[oR[u]];
-        aR[u][1] = H[oR[u] + 1];
-        aR[u][2] = H[oR[u] + 2];
-        oQ[u] = ((i < n) ? i * ld : dummyR) + k;
-        aQ[u][0] = Q[oQ[u]];
-        aQ[u][1] = Q[oQ[u] + 1];
-        aQ[u][2] = Q[oQ[u] + 2];
-      }
-      double blk[3][3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) blk[r][c] = H[(k + r) * ld + k + c];
-      const double s = fabs(x) + fabs(y) + fabs(z);
-      if (s == 0.0) continue;  // uniform
-      const double ss = fma(z, z, fma(y, y, x * x));
-      double r = __builtin_amdgcn_rsq(ss);
-      double e = fma(-ss * r, r, 1.0);
-      r = fma(0.5 * r, e, r);
-      e = fma(-ss * r, r, 1.0);
-      r = fma(0.5 * r, e, r);
-      const double nrm = ss * r;
-      const double sg = (x >= 0.0) ? 1.0 : -1.0;
-      const double beta = -sg * nrm;
-      const double tau = (beta - x) * (-sg * r);
-      const double iv = fast_rcp(x - beta);
-      const double v1 = y * iv, v2 = three ? z * iv : 0.0;
-      const int sub = (k > l) ? k * ld + k - 1 : -1;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double sl = tau * (aL[u][0] + v1 * aL[u][1] + v2 * aL[u][2]);
-        const bool zs = (oL[u] == sub);
-        H[oL[u]] = aL[u][0] - sl;
-        H[oL[u] + ld] = zs ? 0.0 : aL[u][1] - sl * v1;
-        H[oL[u] + 2 * ld] = zs ? 0.0 : aL[u][2] - sl * v2;
-        const double sr = tau * (aR[u][0] + v1 * aR[u][1] + v2 * aR[u][2]);
-        H[oR[u]] = aR[u][0] - sr;
-        H[oR[u] + 1] = aR[u][1] - sr * v1;
-        H[oR[u] + 2] = aR[u][2] - sr * v2;
-        const double sq = tau * (aQ[u][0] + v1 * aQ[u][1] + v2 * aQ[u][2]);
-        Q[oQ[u]] = aQ[u][0] - sq;
-        Q[oQ[u] + 1] = aQ[u][1] - sq * v1;
-        Q[oQ[u] + 2] = aQ[u][2] - sq * v2;
-      }
-      if (t == NT - 1) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double sm = tau * (blk[0][c] + v1 * blk[1][c] + v2 * blk[2][c]);
-          blk[0][c] -= sm;
-          blk[1][c] -= sm * v1;
-          blk[2][c] -= sm * v2;
+        for (int u = 0; u < 2; ++u) {
+          const int g = t + 128 * u;
+          const bool isR = isH[u] && (g <= ihi);
+          const bool vR = isR && ((unsigned)(g - k) >= (unsigned)nr);
+          const bool vL = !isR && lok[u] && ((unsigned)(jL[u] - k) >= (unsigned)nr);
+          const int base = vR ? tld[u] + k : vL ? kld + jL[u] : bQ[u] + k;
+          const int str = vL ? ld : 1;
+          const bool zs = vL && (jL[u] == k - 1);  // the bulge column: rows k+1, k+2 vanish
+          const double a0 = H[base], a1 = H[base + str], a2 = H[base + 2 * str];
+          const double sm = ta * (a0 + u1 * a1 + u2 * a2);
+          H[base] = a0 - sm;
+          H[base + str] = zs ? 0.0 : a1 - sm * u1;
+          H[base + 2 * str] = zs ? 0.0 : a2 - sm * u2;
         }
-#pragma unroll
-        for (int rr = 0; rr < 3; ++rr) {
-          const double sm = tau * (blk[rr][0] + v1 * blk[rr][1] + v2 * blk[rr][2]);
-          blk[rr][0] -= sm;
-          blk[rr][1] -= sm * v1;
-          blk[rr][2] -= sm * v2;
+      } else if (wv == 2) {
+        if (bc < nr) {  // column bc of P B P = P (B p_bc)
+          const double* rf = refl + (k & 1) * 4;
+          const double ta = rf[0];
+          w1 = rf[1];
+          w2 = rf[2];
+          const double* Bp = H + k * ld + k;
+          const double bv0 = Bp[0] + w1 * Bp[1] + w2 * Bp[2];
+          const double bv1 = Bp[ld] + w1 * Bp[ld + 1] + w2 * Bp[ld + 2];
+          const double bv2 = Bp[2 * ld] + w1 * Bp[2 * ld + 1] + w2 * Bp[2 * ld + 2];
+          const double vc = (bc == 0) ? 1.0 : (bc == 1) ? w1 : w2;
+          const double tv = ta * vc;
+          q0 = Bp[bc] - tv * bv0;
+          q1 = Bp[ld + bc] - tv * bv1;
+          q2 = Bp[2 * ld + bc] - tv * bv2;
+          sw = ta * (q0 + w1 * q1 + w2 * q2);
         }
-#pragma unroll
-        for (int rr = 0; rr < 3; ++rr)
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            if (rr < nr && c < nr) H[(k + rr) * ld + k + c] = blk[rr][c];
+      } else {
+        // column 0 of P B P below the diagonal and the right-updated row
+        // below the block give the next step's x, y, z
+        const double* Bp = H + k * ld + k;
+        const double b00 = Bp[0], b01 = Bp[1], b02 = Bp[2];
+        const double b10 = Bp[ld], b11 = Bp[ld + 1], b12 = Bp[ld + 2];
+        const double b20 = Bp[2 * ld], b21 = Bp[2 * ld + 1], b22 = Bp[2 * ld + 2];
+        double s3n;
+        {
+          const int r = (k + 4 <= n) ? k + 4 : n, c = (k + 3 <= n) ? k + 3 : n;
+          s3n = H[r * ld + c];
+        }
+        const double bv0 = b00 + v1 * b01 + v2 * b02;
+        const double bv1 = b10 + v1 * b11 + v2 * b12;
+        const double bv2 = b20 + v1 * b21 + v2 * b22;
+        const double d0 = b00 - tau * bv0, d1 = b10 - tau * bv1, d2 = b20 - tau * bv2;
+        const double sd = tau * (d0 + v1 * d1 + v2 * d2);
+        const double sm3 = tau * (v2 * s3);
+        const bool th = (k + 1 < hi - 1);
+        householder3(d1 - sd * v1, d2 - sd * v2, th ? -sm3 : 0.0, tau, v1, v2);
+        if (t == 192) {
+          refl[((k + 1) & 1) * 4 + 0] = tau;
+          refl[((k + 1) & 1) * 4 + 1] = v1;
+          refl[((k + 1) & 1) * 4 + 2] = v2;
+        }
+        s3 = s3n;
+      }
+      __syncthreads();  // every read of the block region is done
+      if (wv == 2 && bc < nr) {
+        double* Op = H + k * ld + k + bc;
+        Op[0] = q0 - sw;
+        Op[ld] = q1 - sw * w1;
+        if (three) Op[2 * ld] = q2 - sw * w2;
       }
       __syncthreads();
     }
@@ -530,7 +636,8 @@ __device__ void k_tharm_qr_body(SmallParams p, SmallBufs b, DevStatus* st) {
   const double hn = block_fro(H, n, ld, red);
   if (t == 0) st->tphase[4] = clock64();
   int sweeps = 0, steps = 0;
-  const bool ok = francis_qr(H, Q, n, ld, hn > 0.0 ? hn : 1.0, &sweeps, &steps);
+  __shared__ double refl[8];
+  const bool ok = francis_qr(H, Q, n, ld, hn > 0.0 ? hn : 1.0, &sweeps, &steps, refl);
   if (t == 0) {
     st->tphase[10] = steps;
     st->tphase[11] = sweeps;

@@ -44,7 +44,7 @@ def test_batch_operators_match_oracle():
     import torch
     from oracle import mg
     probs = _problems([16, 24, 32, 8], 6, 86)
-    S, _ = _batch(probs, 4, 3, 1e-10)
+    S, _ = _batch(probs, 4, 5, 1e-10)
     X = [wl.start_block(N * N, 7, (87, b)) for b, (N, *_) in enumerate(probs)]
     Xd = [torch.from_numpy(x).cuda() for x in X]
     YA = S.apply("A", Xd)
@@ -63,7 +63,7 @@ def test_batch_operators_match_oracle():
 
 def test_batch_matches_brute_force_and_graph_replays_match_eager():
     probs = _problems([16, 24, 32, 16, 24], 6, 81)
-    k, kx = 4, 3
+    k, kx = 4, 5
     S, V0 = _batch(probs, k, kx, 1e-11)
     r1 = S.solve(V0)
     assert r1.converged, (r1.status, r1.iters)
@@ -91,7 +91,7 @@ def test_batch_problem_equals_single_solver():
     import torch
     from paper_1408_0042_amd.plhr import Solver
     probs = _problems([24, 32], 6, 82)
-    k, kx = 4, 3
+    k, kx = 4, 5
     S, V0 = _batch(probs, k, kx, 1e-11)
     r = S.solve(V0)
     S.close()
@@ -108,7 +108,7 @@ def test_batch_backward_matches_dense_gradient_and_finite_differences():
     import torch
     from paper_1408_0042_amd.plhr import batch_eigvals
     probs = _problems([12, 16, 12], 5, 83)
-    k, kx = 4, 3
+    k, kx = 4, 5
     targets = np.array([[0.1, 0.2, 0.3, 0.4]] * len(probs)) + np.array([[0.0], [0.05], [0.1]])
     pots = [torch.from_numpy(p).cuda().requires_grad_(True) for _, p, _, _ in probs]
     V0 = [torch.from_numpy(wl.start_block(N * N, k + kx, (84, b))).cuda()
