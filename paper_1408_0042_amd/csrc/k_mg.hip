@@ -69,8 +69,8 @@ __device__ __forceinline__ RowLanes row_lanes(int ncols) {
   return r;
 }
 
-template <int DIM, int W, typename S>
-__device__ __forceinline__ vec<S, W> nb_sum(const S* xp, int i, int j, int l, int nx, int ny,
+template <int DIM, int W, typename S, typename T>
+__device__ __forceinline__ vec<S, W> nb_sum(const T* xp, int i, int j, int l, int nx, int ny,
                                             int nz, int ld) {
   const ptrdiff_t sy = (ptrdiff_t)nx * ld;
   const ptrdiff_t sz = (ptrdiff_t)nx * ny * ld;
@@ -123,6 +123,31 @@ __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, 
   }
 }
 
+// The first two sweeps from a zero guess in one pass over r:
+//   x1 = w r,  x2 = x1 + w (r - A x1) = w (2 r - w A r),  w = omega / diag
+// (A x1 = w A r because w is a constant).
+template <int DIM, int W, typename S, typename RT>
+__global__ __launch_bounds__(256) void k_jacobi2z(int nx, int ny, int nz, S diag, S off, S omega,
+                                                  const RT* __restrict__ r, int ldr,
+                                                  S* __restrict__ o, int ncols,
+                                                  const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny, l = row / ny;
+  const RowLanes ln = row_lanes<W>(ncols);
+  if (!ln.on) return;
+  const size_t rowp = (size_t)row * nx;
+  const S w = omega / diag;
+  const int c = ln.c;
+  for (int i = ln.i0; i < nx; i += ln.P) {
+    const size_t p = rowp + i;
+    const RT* rp = r + p * ldr + c;
+    const vec<S, W> rv = vload<W, S>(rp);
+    const vec<S, W> ar = diag * rv + off * nb_sum<DIM, W, S>(rp, i, j, l, nx, ny, nz, ldr);
+    vstore<W, S>(o + p * ncols + c, w * ((S)2 * rv - w * ar));
+  }
+}
+
 // res = r - A x
 template <int DIM, int W, typename S, typename RT>
 __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, S diag, S off,
@@ -146,24 +171,28 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, S diag
   }
 }
 
-// Coarse r = P^T res / 2^d.  One workgroup per coarse row.
+// Coarse r = P^T res / 2^d.  One workgroup per coarse row (cj, cl): the
+// 4 (2-D) or 4 x 4 (3-D) fine rows under it are summed with their y/z
+// weights into an LDS row s (fine nx points x ncols), which the x weights
+// (1/4, 3/4, 3/4, 1/4) then reduce to the coarse row; every fine value is
+// read once per coarse row that covers it.
 template <int DIM, int W, typename S>
 __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
                                                   const S* __restrict__ res,
                                                   S* __restrict__ rc, int ncols,
                                                   const DevStatus* st) {
   if (halted(st)) return;
+  extern __shared__ unsigned char smem_r[];
+  S* srow = reinterpret_cast<S*>(smem_r);
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int cj = row % cny, cl = row / cny;
   const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
   const RowLanes ln = row_lanes<W>(ncols);
-  if (!ln.on) return;
   const int c = ln.c;
   const S norm = (DIM == 3) ? (S)0.125 : (S)0.25;
-  // the 4 fine rows (2-D) or 4 x 4 fine rows (3-D) under this coarse row,
-  // with their weights; rows outside the box get weight 0 and row 0
-  size_t rb[16];
-  S rw[16];
+  constexpr int NR = (DIM == 3) ? 16 : 4;
+  size_t rb[NR];
+  S rw[NR];
   int nrows = 0;
   for (int dz = 0; dz < ((DIM == 3) ? 4 : 1); ++dz) {
     int fl = 0;
@@ -182,20 +211,24 @@ __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
       ++nrows;
     }
   }
+  if (ln.on) {
+    for (int f = ln.i0; f < fnx; f += ln.P) {
+      vec<S, W> acc = (S)0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc += rw[q] * vload<W, S>(res + (rb[q] + f) * ncols + c);
+      vstore<W, S>(srow + (size_t)f * ncols + c, acc);
+    }
+  }
+  __syncthreads();
+  if (!ln.on) return;
   for (int ci = ln.i0; ci < cnx; ci += ln.P) {
     const int f0 = 2 * ci - 1;
-    vec<S, W> acc = (S)0;
-#pragma unroll
-    for (int q = 0; q < ((DIM == 3) ? 16 : 4); ++q) {
-      const S* rp = res + rb[q] * ncols + c;
-      vec<S, W> a = (S)0.75 * (vload<W, S>(rp + (size_t)(f0 + 1) * ncols) +
-                               vload<W, S>(rp + (size_t)(f0 + 2) * ncols));
-      if (f0 >= 0) a += (S)0.25 * vload<W, S>(rp + (size_t)f0 * ncols);
-      if (f0 + 3 < fnx) a += (S)0.25 * vload<W, S>(rp + (size_t)(f0 + 3) * ncols);
-      acc += rw[q] * a;
-    }
+    vec<S, W> a = (S)0.75 * (vload<W, S>(srow + (size_t)(f0 + 1) * ncols + c) +
+                             vload<W, S>(srow + (size_t)(f0 + 2) * ncols + c));
+    if (f0 >= 0) a += (S)0.25 * vload<W, S>(srow + (size_t)f0 * ncols + c);
+    if (f0 + 3 < fnx) a += (S)0.25 * vload<W, S>(srow + (size_t)(f0 + 3) * ncols + c);
     const size_t cp = ((size_t)cl * cny + cj) * cnx + ci;
-    vstore<W, S>(rc + cp * ncols + c, acc * norm);
+    vstore<W, S>(rc + cp * ncols + c, a * norm);
   }
 }
 
@@ -261,6 +294,275 @@ __global__ __launch_bounds__(256) void k_dense_apply(int nc, const S* __restrict
     for (int q = 0; q < nc; ++q) acc += a[q] * r[(size_t)q * ncols + c];
     x[(size_t)i * ncols + c] = acc;
   }
+}
+
+// ---------------------------------------- coarse levels, one launch, in LDS
+// The levels whose grids hold at most kCoarseMaxPts points (and the dense
+// coarsest solve) run as one V-cycle per launch: the columns are
+// independent, so workgroup g takes the column chunk [g cc, (g + 1) cc),
+// copies its right-hand side into LDS, runs the same sweeps, residual,
+// restriction, dense solve and prolongation as the row kernels on LDS
+// arrays (stride cc), one phase after another with a barrier between
+// phases, and writes the chunk of the first level's x buffer.  This
+// replaces about fifteen launches of a few microseconds each by one.
+constexpr int kCoarseNT = 512;
+constexpr int kCoarseMaxPts = 4096;
+constexpr size_t kCoarseMaxLds = 160 * 1024;
+constexpr int kCoarseMaxLev = 4;
+
+struct CoarseLev {
+  int nx, ny, nz, n;
+  float inx, inxy;  // 1/nx and 1/(nx ny) for the index arithmetic
+  double diag, off;
+};
+struct CoarseArgs {
+  CoarseLev lv[kCoarseMaxLev];
+  int nlev;  // levels handled; the last one is solved densely
+  int nu_pre, nu_post;
+  double omega;
+  const void* Ainv;  // nc x nc
+  int nc;
+  int ncols, cc;
+  const void* r0;  // first level: right-hand side (ld ncols)
+  void* x0;        // first level: result (ld ncols)
+};
+
+// Element e of an LDS level array (n points x cc columns): point p, column
+// c, grid indices i, j, l.  Float reciprocals are exact here: e and p stay
+// below 2^14 and the fractional margins exceed 1/512.
+struct CIdx {
+  int p, c, i, j, l;
+};
+template <int DIM>
+__device__ __forceinline__ CIdx cidx(int e, int cc, float icc, const CoarseLev& L) {
+  CIdx x;
+  x.p = (int)(((float)e + 0.5f) * icc);
+  x.c = e - x.p * cc;
+  x.l = (DIM == 3) ? (int)(((float)x.p + 0.5f) * L.inxy) : 0;
+  const int rem = x.p - x.l * L.nx * L.ny;
+  x.j = (int)(((float)rem + 0.5f) * L.inx);
+  x.i = rem - x.j * L.nx;
+  return x;
+}
+template <int DIM, typename S>
+__device__ __forceinline__ S cc_nb(const S* xp, const CIdx& q, const CoarseLev& L, int cc) {
+  const int sy = L.nx * cc, sz = L.nx * L.ny * cc;
+  S nb = 0;
+  if (q.i > 0) nb += xp[-cc];
+  if (q.i < L.nx - 1) nb += xp[cc];
+  if (q.j > 0) nb += xp[-sy];
+  if (q.j < L.ny - 1) nb += xp[sy];
+  if (DIM == 3) {
+    if (q.l > 0) nb += xp[-sz];
+    if (q.l < L.nz - 1) nb += xp[sz];
+  }
+  return nb;
+}
+
+// mode 0: out = xin + w (r - A xin), xin == nullptr meaning zero;
+// mode 1: out = w (2 r - w A r) (two sweeps from zero); mode 2: out = r - A xin
+template <int DIM, typename S>
+__device__ void cc_sweep(const CoarseLev& L, const S* xin, const S* r, S* out, int mode, S omega,
+                         int cc, float icc) {
+  const S diag = (S)L.diag, off = (S)L.off, w = omega / diag;
+  for (int e = threadIdx.x; e < L.n * cc; e += kCoarseNT) {
+    const CIdx q = cidx<DIM>(e, cc, icc, L);
+    const S rv = r[e];
+    S v;
+    if (mode == 1) {
+      v = w * ((S)2 * rv - w * (diag * rv + off * cc_nb<DIM, S>(r + e, q, L, cc)));
+    } else if (xin == nullptr) {
+      v = w * rv;
+    } else {
+      const S ax = diag * xin[e] + off * cc_nb<DIM, S>(xin + e, q, L, cc);
+      v = (mode == 2) ? rv - ax : xin[e] + w * (rv - ax);
+    }
+    out[e] = v;
+  }
+}
+
+// coarse r (level C) = P^T res (level F) / 2^d
+template <int DIM, typename S>
+__device__ void cc_restrict(const CoarseLev& F, const CoarseLev& C, const S* res, S* rc, int cc,
+                            float icc) {
+  const S norm = (DIM == 3) ? (S)0.125 : (S)0.25;
+  for (int e = threadIdx.x; e < C.n * cc; e += kCoarseNT) {
+    const CIdx q = cidx<DIM>(e, cc, icc, C);
+    S acc = 0;
+#pragma unroll
+    for (int dz = 0; dz < ((DIM == 3) ? 4 : 1); ++dz) {
+      int fl = (DIM == 3) ? 2 * q.l - 1 + dz : 0;
+      S wz = (DIM == 3) ? ((dz == 0 || dz == 3) ? (S)0.25 : (S)0.75) : (S)1;
+      if (fl < 0 || fl >= F.nz) wz = 0, fl = 0;
+#pragma unroll
+      for (int dy = 0; dy < 4; ++dy) {
+        int fj = 2 * q.j - 1 + dy;
+        S wy = wz * ((dy == 0 || dy == 3) ? (S)0.25 : (S)0.75);
+        if (fj < 0 || fj >= F.ny) wy = 0, fj = 0;
+#pragma unroll
+        for (int dx = 0; dx < 4; ++dx) {
+          int fi = 2 * q.i - 1 + dx;
+          S wx = (dx == 0 || dx == 3) ? (S)0.25 : (S)0.75;
+          if (fi < 0 || fi >= F.nx) wx = 0, fi = 0;
+          acc += (wy * wx) * res[(((size_t)fl * F.ny + fj) * F.nx + fi) * cc + q.c];
+        }
+      }
+    }
+    rc[e] = acc * norm;
+  }
+}
+
+// x (level F) += P e (level C)
+template <int DIM, typename S>
+__device__ void cc_prolong(const CoarseLev& F, const CoarseLev& C, const S* ec, S* x, int cc,
+                           float icc) {
+  for (int e = threadIdx.x; e < F.n * cc; e += kCoarseNT) {
+    const CIdx q = cidx<DIM>(e, cc, icc, F);
+    const int pi = q.i >> 1, qi = (q.i & 1) ? pi + 1 : pi - 1;
+    const int pj = q.j >> 1, qj = (q.j & 1) ? pj + 1 : pj - 1;
+    const int pl = q.l >> 1, ql = (q.l & 1) ? pl + 1 : pl - 1;
+    S acc = 0;
+#pragma unroll
+    for (int az = 0; az < ((DIM == 3) ? 2 : 1); ++az) {
+      int cl = (DIM == 3) ? (az ? ql : pl) : 0;
+      S wz = (DIM == 3) ? (az ? (S)0.25 : (S)0.75) : (S)1;
+      if (cl < 0 || cl >= C.nz) wz = 0, cl = 0;
+#pragma unroll
+      for (int ay = 0; ay < 2; ++ay) {
+        int cj = ay ? qj : pj;
+        S wy = wz * (ay ? (S)0.25 : (S)0.75);
+        if (cj < 0 || cj >= C.ny) wy = 0, cj = 0;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+          int ci = ax ? qi : pi;
+          S wx = ax ? (S)0.25 : (S)0.75;
+          if (ci < 0 || ci >= C.nx) wx = 0, ci = 0;
+          acc += (wy * wx) * ec[(((size_t)cl * C.ny + cj) * C.nx + ci) * cc + q.c];
+        }
+      }
+    }
+    x[e] += acc;
+  }
+}
+
+// LDS: per level x, t, r (n_q x cc each), then Ainv (nc x nc)
+template <int DIM, typename S>
+__global__ __launch_bounds__(kCoarseNT) void k_coarse_cycle(CoarseArgs a, const DevStatus* st) {
+  if (halted(st)) return;
+  extern __shared__ unsigned char smem_c[];
+  S* lds = reinterpret_cast<S*>(smem_c);
+  const int cc = a.cc, c0 = blockIdx.x * cc, ncols = a.ncols;
+  const float icc = 1.0f / (float)cc;
+  const S om = (S)a.omega;
+  S* X[kCoarseMaxLev];
+  S* T[kCoarseMaxLev];
+  S* R[kCoarseMaxLev];
+  S* Am;  // the coarsest inverse
+  {
+    S* q = lds;
+#pragma unroll
+    for (int l = 0; l < kCoarseMaxLev; ++l) {
+      const int sz = (l < a.nlev) ? a.lv[l].n * cc : 0;
+      X[l] = q;
+      T[l] = q + sz;
+      R[l] = q + 2 * sz;
+      q += 3 * sz;
+    }
+    Am = q;
+    const S* gA = reinterpret_cast<const S*>(a.Ainv);
+    for (int e = threadIdx.x; e < a.nc * a.nc; e += kCoarseNT) Am[e] = gA[e];
+    const S* r0 = reinterpret_cast<const S*>(a.r0);
+    for (int e = threadIdx.x; e < a.lv[0].n * cc; e += kCoarseNT) {
+      const int p = (int)(((float)e + 0.5f) * icc);
+      R[0][e] = r0[(size_t)p * ncols + c0 + (e - p * cc)];
+    }
+  }
+  __syncthreads();
+  unsigned inx = 0;  // bit l: level l's iterate is in X[l] (else T[l])
+#pragma unroll
+  for (int l = 0; l + 1 < kCoarseMaxLev; ++l) {
+    if (l + 1 >= a.nlev) break;
+    const CoarseLev& L = a.lv[l];
+    S* cur = X[l];
+    S* oth = T[l];
+    int it;
+    if (a.nu_pre >= 2) {
+      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 1, om, cc, icc);
+      it = 2;
+    } else {
+      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 0, om, cc, icc);
+      it = 1;
+    }
+    __syncthreads();
+    for (; it < a.nu_pre; ++it) {
+      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, om, cc, icc);
+      __syncthreads();
+      S* tmp = cur;
+      cur = oth;
+      oth = tmp;
+    }
+    cc_sweep<DIM, S>(L, cur, R[l], oth, 2, om, cc, icc);  // residual
+    __syncthreads();
+    cc_restrict<DIM, S>(L, a.lv[l + 1], oth, R[l + 1], cc, icc);
+    __syncthreads();
+    if (cur == X[l]) inx |= 1u << l;
+  }
+  {  // coarsest: x = Ainv r
+    const int lc = a.nlev - 1;
+    S* x = X[0];
+    const S* r = R[0];
+#pragma unroll
+    for (int l = 1; l < kCoarseMaxLev; ++l)
+      if (l == lc) x = X[l], r = R[l];
+    for (int e = threadIdx.x; e < a.nc * cc; e += kCoarseNT) {
+      const int i = (int)(((float)e + 0.5f) * icc);
+      const int c = e - i * cc;
+      const S* arow = Am + (size_t)i * a.nc;
+      S acc0 = 0, acc1 = 0;
+      int q = 0;
+      for (; q + 1 < a.nc; q += 2) {
+        acc0 += arow[q] * r[q * cc + c];
+        acc1 += arow[q + 1] * r[(q + 1) * cc + c];
+      }
+      if (q < a.nc) acc0 += arow[q] * r[q * cc + c];
+      x[e] = acc0 + acc1;
+    }
+    __syncthreads();
+    inx |= 1u << lc;
+  }
+#pragma unroll
+  for (int l = kCoarseMaxLev - 2; l >= 0; --l) {
+    if (l + 1 >= a.nlev) continue;
+    const CoarseLev& L = a.lv[l];
+    S* cur = (inx >> l & 1u) ? X[l] : T[l];
+    S* oth = (inx >> l & 1u) ? T[l] : X[l];
+    const S* ec = (inx >> (l + 1) & 1u) ? X[l + 1] : T[l + 1];
+    cc_prolong<DIM, S>(L, a.lv[l + 1], ec, cur, cc, icc);
+    __syncthreads();
+    for (int it = 0; it < a.nu_post; ++it) {
+      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, om, cc, icc);
+      __syncthreads();
+      S* tmp = cur;
+      cur = oth;
+      oth = tmp;
+    }
+    if (cur == X[l])
+      inx |= 1u << l;
+    else
+      inx &= ~(1u << l);
+  }
+  const S* res = (inx & 1u) ? X[0] : T[0];
+  S* x0 = reinterpret_cast<S*>(a.x0);
+  for (int e = threadIdx.x; e < a.lv[0].n * cc; e += kCoarseNT) {
+    const int p = (int)(((float)e + 0.5f) * icc);
+    x0[(size_t)p * ncols + c0 + (e - p * cc)] = res[e];
+  }
+}
+
+static size_t coarse_lds(const MG& mg, int lev, int cc, size_t es) {
+  size_t n = (size_t)mg.nc * mg.nc;
+  for (int q = lev; q < (int)mg.lv.size(); ++q) n += 3 * mg.lv[q].g.n() * cc;
+  return n * es;
 }
 
 // ---------------------------------------------------------------- host side
@@ -342,8 +644,30 @@ size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax) {
   return bytes;
 }
 
+static hipError_t coarse_set_attributes() {
+  const void* f[4] = {(const void*)k_coarse_cycle<3, double>, (const void*)k_coarse_cycle<3, float>,
+                      (const void*)k_coarse_cycle<2, double>, (const void*)k_coarse_cycle<2, float>};
+  for (const void* k : f) {
+    const hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseMaxLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_post, double omega,
                      int cmax, char*& ws, hipStream_t s) {
+  PLHR_HIP_CHECK(coarse_set_attributes());
+  {  // the restriction stages one fine row of cmax FP64 columns in LDS
+    Grid g = fine;
+    for (int lv = 0; lv + 1 < levels; ++lv) {
+      if ((size_t)g.nx * cmax * sizeof(double) > 65536) {
+        set_error("multigrid: a fine grid row of the block exceeds 64 KiB");
+        return PLHR_ERR_UNSUPPORTED;
+      }
+      g.nx /= 2;
+    }
+  }
   mg.levels = levels;
   mg.nu_pre = nu_pre;
   mg.nu_post = nu_post;
@@ -417,6 +741,49 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
   S* Lt = reinterpret_cast<S*>(L.t);
   const S* Ainv = (sizeof(S) == 4) ? reinterpret_cast<const S*>(mg.coarse_inv32)
                                    : reinterpret_cast<const S*>(mg.coarse_inv);
+  // every level from here down is small: one launch runs the rest of the
+  // cycle, one workgroup per column chunk, in LDS
+  {
+    const int nl_tot = (int)mg.lv.size() - lev;
+    bool small = lev > 0 && nl_tot >= 2 && nl_tot <= kCoarseMaxLev;
+    for (int q = lev; small && q < (int)mg.lv.size(); ++q)
+      small = mg.lv[q].g.n() <= (size_t)kCoarseMaxPts;
+    int cc = 0;
+    for (int w : {2, 1})
+      if (small && cc == 0 && ncols % w == 0 && coarse_lds(mg, lev, w, sizeof(S)) <= kCoarseMaxLds)
+        cc = w;
+    if (small && cc > 0) {
+      CoarseArgs a{};
+      a.nlev = nl_tot;
+      a.nu_pre = mg.nu_pre;
+      a.nu_post = mg.nu_post;
+      a.omega = mg.omega;
+      a.Ainv = Ainv;
+      a.nc = mg.nc;
+      a.ncols = ncols;
+      a.cc = cc;
+      a.r0 = r;
+      a.x0 = Lx;
+      double bytes = (double)mg.nc * mg.nc * sizeof(S) + 2.0 * g.n() * ncols * sizeof(S);
+      double flops = 2.0 * mg.nc * (double)mg.nc * ncols;
+      for (int q = 0; q < nl_tot; ++q) {
+        const MGLevel& M = mg.lv[lev + q];
+        CoarseLev& c = a.lv[q];
+        c.nx = M.g.nx;
+        c.ny = M.g.ny;
+        c.nz = M.g.nz;
+        c.n = (int)M.g.n();
+        c.inx = 1.0f / (float)M.g.nx;
+        c.inxy = 1.0f / (float)(M.g.nx * M.g.ny);
+        c.diag = M.g.diag();
+        c.off = M.g.off();
+        flops += 40.0 * (double)M.g.n() * ncols;
+      }
+      PROF_LAUNCH(KC_COARSE, bytes, flops, (k_coarse_cycle<DIM, S>), dim3(ncols / cc),
+                  dim3(kCoarseNT), coarse_lds(mg, lev, cc, sizeof(S)), s, a, st);
+      return Lx;
+    }
+  }
   if (coarsest) {  // lev > 0 here (a single level runs dense_only)
     const int tot = mg.nc * ncols;
     const int nbk = (tot + 255) / 256;
@@ -429,8 +796,16 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
   const double rb = sizeof(RT) / (double)sizeof(S);  // input pass relative to a level pass
   S* cur = Lx;
   S* oth = Lt;
-  // pre-smoothing from a zero guess (nu_pre >= 1)
-  for (int it = 0; it < mg.nu_pre; ++it) {
+  // pre-smoothing from a zero guess (nu_pre >= 1); the first two sweeps
+  // in one kernel
+  int it0 = 0;
+  if (mg.nu_pre >= 2) {
+    PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb, (2.0 * DIM + 6.0) * fl, (k_jacobi2z<DIM, W, S, RT>),
+                dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om, r, ldr, oth, ncols, st);
+    std::swap(cur, oth);
+    it0 = 2;
+  }
+  for (int it = it0; it < mg.nu_pre; ++it) {
     PROF_LAUNCH(KC_JACOBI, (it == 0 ? 1.0 + rb : 2.0 + rb) * nb,
                 (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>), dim3(rows),
                 blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
@@ -445,8 +820,8 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
   const int crows = C.g.ny * C.g.nz;
   S* Cr = reinterpret_cast<S*>(C.r);
   PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              (k_restrict<DIM, W, S>), dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth, Cr,
-              ncols, st);
+              (k_restrict<DIM, W, S>), dim3(crows), blk, (size_t)g.nx * ncols * sizeof(S), s,
+              C.g.nx, C.g.ny, C.g.nz, oth, Cr, ncols, st);
   S* ec = cycle<DIM, W, S, S>(mg, lev + 1, Cr, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
                            ncols, st, s);
   PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
