@@ -114,6 +114,7 @@ __device__ __forceinline__ double wave_sum(double a) {
 
 __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   static_assert(kNT >= 3 * kMaxM, "one thread per row of H, of Q and per column of H");
+  static_assert(8 + 88 + kMaxM <= kNT && kMaxM <= 88, "column buffers inside red");
   if (halted(st)) return;
   if (threadIdx.x == 0) st->tphase[0] = clock64();
   extern __shared__ double sm[];
@@ -206,41 +207,76 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   }
   if (t == 0) st->tphase[1] = clock64();
   __syncthreads();
-  // H <- L^-1 H: column c by thread c
-  if (t < n) {
-    for (int i = 0; i < n; ++i) {
-      const double* Li = L + i * ld;
-      double s0 = H[i * ld + t], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int r = 0;
-      for (; r + 3 < i; r += 4) {
-        s0 -= Li[r] * H[r * ld + t];
-        s1 -= Li[r + 1] * H[(r + 1) * ld + t];
-        s2 -= Li[r + 2] * H[(r + 2) * ld + t];
-        s3 -= Li[r + 3] * H[(r + 3) * ld + t];
+  // H <- L^-1 H and then H <- H L^-T, blocked by 16: the diagonal block
+  // is solved by one thread per column (per row), then the rows (columns)
+  // below it are updated by the whole workgroup, 16 x 16 threads.
+  constexpr int NB = 16;
+  for (int kb = 0; kb < n; kb += NB) {
+    const int ke = (kb + NB < n) ? kb + NB : n, nb = ke - kb;
+    if (t < n) {
+      for (int i = kb; i < ke; ++i) {
+        const double* Li = L + i * ld;
+        double s0 = H[i * ld + t], s1 = 0.0;
+        int r = kb;
+        for (; r + 1 < i; r += 2) {
+          s0 -= Li[r] * H[r * ld + t];
+          s1 -= Li[r + 1] * H[(r + 1) * ld + t];
+        }
+        if (r < i) s0 -= Li[r] * H[r * ld + t];
+        H[i * ld + t] = (s0 + s1) / Li[i];
       }
-      for (; r < i; ++r) s0 -= Li[r] * H[r * ld + t];
-      H[i * ld + t] = ((s0 + s1) + (s2 + s3)) / Li[i];
     }
-  }
-  __syncthreads();
-  // H <- H L^-T: row r by thread r (x L^T = h)
-  if (t < n) {
-    double* Hr = H + t * ld;
-    for (int i = 0; i < n; ++i) {
-      const double* Li = L + i * ld;
-      double s0 = Hr[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int c = 0;
-      for (; c + 3 < i; c += 4) {
-        s0 -= Li[c] * Hr[c];
-        s1 -= Li[c + 1] * Hr[c + 1];
-        s2 -= Li[c + 2] * Hr[c + 2];
-        s3 -= Li[c + 3] * Hr[c + 3];
+    __syncthreads();
+    for (int i = ke + ty; i < n; i += 16) {
+      double lr[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) lr[r] = (r < nb) ? L[i * ld + kb + r] : 0.0;
+      for (int c = tx; c < n; c += 16) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NB; r += 2) {
+          a0 += lr[r] * H[((kb + r < n) ? kb + r : n - 1) * ld + c];
+          a1 += lr[r + 1] * H[((kb + r + 1 < n) ? kb + r + 1 : n - 1) * ld + c];
+        }
+        H[i * ld + c] -= a0 + a1;
       }
-      for (; c < i; ++c) s0 -= Li[c] * Hr[c];
-      Hr[i] = ((s0 + s1) + (s2 + s3)) / Li[i];
     }
+    __syncthreads();
   }
-  __syncthreads();
+  for (int kb = 0; kb < n; kb += NB) {
+    const int ke = (kb + NB < n) ? kb + NB : n, nb = ke - kb;
+    if (t < n) {  // x L^T = h for row t
+      double* Hr = H + t * ld;
+      for (int i = kb; i < ke; ++i) {
+        const double* Li = L + i * ld;
+        double s0 = Hr[i], s1 = 0.0;
+        int c = kb;
+        for (; c + 1 < i; c += 2) {
+          s0 -= Li[c] * Hr[c];
+          s1 -= Li[c + 1] * Hr[c + 1];
+        }
+        if (c < i) s0 -= Li[c] * Hr[c];
+        Hr[i] = (s0 + s1) / Li[i];
+      }
+    }
+    __syncthreads();
+    for (int r = ty; r < n; r += 16) {
+      double hr[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) hr[c] = (c < nb) ? H[r * ld + kb + c] : 0.0;
+      for (int i = ke + tx; i < n; i += 16) {
+        const double* Li = L + i * ld + kb;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; c += 2) {
+          a0 += hr[c] * Li[(c < nb) ? c : 0];
+          a1 += hr[c + 1] * Li[(c + 1 < nb) ? c + 1 : 0];
+        }
+        H[r * ld + i] -= a0 + a1;
+      }
+    }
+    __syncthreads();
+  }
   // L (compact n x n) to the work area; its LDS region becomes Q = I
   double* gw = b.work;
   for (int e = t; e < n * n; e += kNT) {
@@ -251,22 +287,35 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16) Q[i * ld + c] = (i == c) ? 1.0 : 0.0;
   if (t == 0) st->tphase[2] = clock64();
-  // Householder reduction to upper Hessenberg form, Q accumulated.
-  // red[0..3]: per-wave partial sums of H[i][k]^2, i >= k + 2, for step k;
-  // red[4..7]: per-wave partial sums of u_i (Hu)_i for gamma.
+  // Householder reduction to upper Hessenberg form, Q accumulated.  Step
+  // k forms, with the same strided dot-product code in every thread,
+  // (Hu)_i for the rows of H (threads [0, n)), (Qu)_i for the rows of Q
+  // ([n, 2n)) and (u^T H)_j for the columns j >= k ([2n, 3n - k)); after
+  // a barrier every row of H and Q is updated by the same two-vector code,
+  //   H[i][j] -= beta u_i (u^T H)_j + (beta (Hu)_i - beta^2 gamma u_i) u_j,
+  //   Q[i][j] -= 0 + beta (Qu)_i u_j,   gamma = u^T H u,
+  // so no wavefront runs two code paths.  Column k is kept contiguous in
+  // ucol (written by the row owners during the previous step); u differs
+  // from it only in entry k + 1.  red[0..3]: per-wave partial sums of the
+  // squared column below the subdiagonal, red[4..7] of gamma.
+  double* ucb[2] = {red + 8, red + 8 + 88};
   {
-    const double a = (t >= 2 && t < n) ? H[t * ld] * H[t * ld] : 0.0;
-    const double s = wave_sum(a);
+    const double h = (t < n) ? H[t * ld] : 0.0;
+    if (t < n) ucb[0][t] = h;
+    const double s = wave_sum((t >= 2 && t < n) ? h * h : 0.0);
     if ((t & 63) == 0) red[wv] = s;
   }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
+    const double* ucol = ucb[k & 1];
+    double* ucn = ucb[(k + 1) & 1];
     const double ss = ((red[0] + red[1]) + red[2]) + red[3];
-    const double x0 = H[(k + 1) * ld + k];
-    if (ss == 0.0) {  // column already reduced (uniform): next column's partials
+    const double x0 = ucol[k + 1];
+    if (ss == 0.0) {  // column already reduced (uniform): next column
       __syncthreads();
-      const double a = (t >= k + 3 && t < n) ? H[t * ld + k + 1] * H[t * ld + k + 1] : 0.0;
-      const double s = wave_sum(a);
+      const double h = (t < n) ? H[t * ld + k + 1] : 0.0;
+      if (t < n) ucn[t] = h;
+      const double s = wave_sum((t >= k + 3 && t < n) ? h * h : 0.0);
       if ((t & 63) == 0) red[wv] = s;
       __syncthreads();
       continue;
@@ -274,54 +323,61 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
     const double nrm = sqrt(x0 * x0 + ss);
     const double alpha = (x0 >= 0.0) ? -nrm : nrm;
     const double beta = 1.0 / (nrm * (nrm + fabs(x0)));  // 2 / (u.u)
-    const double u1 = x0 - alpha;                        // u_{k+1}; u_i = H[i][k] below
-    const double* Hk = H + k;                            // column k, stride ld
-    double acc = 0.0;
-    if (t < 2 * n) {  // (Hu)_i for t < n, (Qu)_{t-n} otherwise
-      const double* X = (t < n) ? H + t * ld : Q + (t - n) * ld;
-      double a0 = X[k + 1] * u1, a1 = 0.0;
-      int q = k + 2;
-      for (; q + 1 < n; q += 2) {
-        a0 += X[q] * Hk[q * ld];
-        a1 += X[q + 1] * Hk[(q + 1) * ld];
-      }
-      if (q < n) a0 += X[q] * Hk[q * ld];
-      acc = a0 + a1;
-    } else if (t < 3 * n - k) {  // (u^T H)_j, j >= k
-      const int j = k + (t - 2 * n);
-      double a0 = u1 * H[(k + 1) * ld + j], a1 = 0.0;
-      int i = k + 2;
-      for (; i + 1 < n; i += 2) {
-        a0 += Hk[i * ld] * H[i * ld + j];
-        a1 += Hk[(i + 1) * ld] * H[(i + 1) * ld + j];
-      }
-      if (i < n) a0 += Hk[i * ld] * H[i * ld + j];
-      bv[j] = a0 + a1;
+    const double u1 = x0 - alpha;                        // u_{k+1}
+    const double du = u1 - x0;                           // u - ucol at entry k + 1
+    const bool isH = (t < n), isQ = (t >= n && t < 2 * n);
+    const bool isC = (t >= 2 * n && t < 3 * n - k);
+    const int len = n - k - 1;
+    const double* base = isH ? H + t * ld + (k + 1)
+                         : isQ ? Q + (t - n) * ld + (k + 1)
+                         : isC ? H + (k + 1) * ld + (k + t - 2 * n)
+                               : H;
+    const int str = isC ? ld : 1;
+    const double* uv = ucol + (k + 1);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = 0;
+    for (; q + 3 < len; q += 4) {
+      a0 += base[q * str] * uv[q];
+      a1 += base[(q + 1) * str] * uv[q + 1];
+      a2 += base[(q + 2) * str] * uv[q + 2];
+      a3 += base[(q + 3) * str] * uv[q + 3];
     }
+    for (; q < len; ++q) a0 += base[q * str] * uv[q];
+    const double acc = ((a0 + a1) + (a2 + a3)) + base[0] * du;
+    if (isC) bv[k + (t - 2 * n)] = acc;
     double ui = 0.0;
     if (t >= k + 1 && t < n) {
-      ui = (t == k + 1) ? u1 : Hk[t * ld];
+      ui = (t == k + 1) ? u1 : ucol[t];
       u[t] = ui;
     }
     {
-      const double s = wave_sum(ui * acc);  // ui = 0 off the rows of H
+      const double s = wave_sum(isH ? ui * acc : 0.0);
       if ((t & 63) == 0) red[4 + wv] = s;
     }
     __syncthreads();
     const double gamma = ((red[4] + red[5]) + red[6]) + red[7];
     double nxt = 0.0;
-    if (t < n) {
-      // H[i][j] -= beta u_i (u^T H)_j + (beta (Hu)_i - beta^2 gamma u_i) u_j
-      double* Hr = H + t * ld;
-      const double cu = beta * ui;
-      const double cv = beta * acc - beta * beta * gamma * ui;
-      if (t >= k + 1) Hr[k] = (t == k + 1) ? alpha : 0.0;
-      for (int j = k + 1; j < n; ++j) Hr[j] -= cu * bv[j] + cv * u[j];
-      if (t >= k + 3) nxt = Hr[k + 1] * Hr[k + 1];
-    } else if (t < 2 * n) {
-      double* Qr = Q + (t - n) * ld;
-      const double cz = beta * acc;
-      for (int j = k + 1; j < n; ++j) Qr[j] -= cz * u[j];
+    if (t < 2 * n) {
+      double* Xr = isH ? H + t * ld : Q + (t - n) * ld;
+      const double s1 = isH ? beta * ui : 0.0;
+      const double s2 = isH ? beta * acc - beta * beta * gamma * ui : beta * acc;
+      if (isH && t >= k + 1) Xr[k] = (t == k + 1) ? alpha : 0.0;
+      int j = k + 1;
+      for (; j + 3 < n; j += 4) {
+        const double x0_ = Xr[j], x1_ = Xr[j + 1], x2_ = Xr[j + 2], x3_ = Xr[j + 3];
+        const double b0 = bv[j], b1 = bv[j + 1], b2 = bv[j + 2], b3 = bv[j + 3];
+        const double c0 = u[j], c1 = u[j + 1], c2 = u[j + 2], c3 = u[j + 3];
+        Xr[j] = x0_ - (s1 * b0 + s2 * c0);
+        Xr[j + 1] = x1_ - (s1 * b1 + s2 * c1);
+        Xr[j + 2] = x2_ - (s1 * b2 + s2 * c2);
+        Xr[j + 3] = x3_ - (s1 * b3 + s2 * c3);
+      }
+      for (; j < n; ++j) Xr[j] -= s1 * bv[j] + s2 * u[j];
+      if (isH) {
+        const double h = Xr[k + 1];
+        ucn[t] = h;
+        if (t >= k + 3) nxt = h * h;
+      }
     }
     {
       const double s = wave_sum(nxt);
