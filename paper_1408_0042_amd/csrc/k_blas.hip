@@ -121,7 +121,7 @@ __global__ void k_gram(size_t n, const double* __restrict__ X, int ldx, int mx,
                        const double* __restrict__ Y2, int ldy2, int my,
                        double* __restrict__ part, const DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ double sh[];
+  extern __shared__ __attribute__((aligned(16))) double sh[];
   const int mxp = (mx + 3) & ~3, myp = (my + 3) & ~3;
   double* sx = sh;                 // kTR x mxp
   double* sy = sh + kTR * mxp;     // kTR x myp
@@ -230,7 +230,7 @@ __global__ void k_rowmul(size_t n, ArrPtrs arrs, int narr, int ld, int m, const 
                          int kout, int mode, int kv, int kc, int pcol, double* __restrict__ part,
                          const DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ double sh[];
+  extern __shared__ __attribute__((aligned(16))) double sh[];
   double* sM = sh;                    // m x kout
   double* sX = sM + m * kout;         // kRB x m
   double* sV = sX + kRB * m;          // kRB x kc (mode 1)

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_restrict(int cnx, int cny, int cnz,
                                                   S* __restrict__ rc, int ncols,
                                                   const DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ unsigned char smem_r[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_r[];
   S* srow = reinterpret_cast<S*>(smem_r);
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int cj = row % cny, cl = row / cny;
@@ -449,7 +449,7 @@ __device__ void cc_prolong(const CoarseLev& F, const CoarseLev& C, const S* ec, 
 template <int DIM, typename S>
 __global__ __launch_bounds__(kCoarseNT) void k_coarse_cycle(CoarseArgs a, const DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ unsigned char smem_c[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_c[];
   S* lds = reinterpret_cast<S*>(smem_c);
   const int cc = a.cc, c0 = blockIdx.x * cc, ncols = a.ncols;
   const float icc = 1.0f / (float)cc;

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_conv_check_b(const BatchSmall* __restri
 // R^-1) | d (m)
 __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   const int m = p.m, kint = p.kint;
   double* Gs = sm;
   double* X = Gs + m * m;
@@ -349,7 +349,7 @@ static constexpr int kTh = 64;  // one wavefront
 // HM: kint x 2kint = [V^T (A - sigma B) V | V^T B V]
 __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
                                                   SmallBufs b, DevStatus* st) {
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   const int n = p.kint, k = p.k, t = threadIdx.x;
   double* L = sm;           // n x n
   double* C = L + n * n;    // n x n

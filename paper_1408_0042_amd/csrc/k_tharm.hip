@@ -117,7 +117,7 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   static_assert(8 + 88 + kMaxM <= kNT && kMaxM <= 88, "column buffers inside red");
   if (halted(st)) return;
   if (threadIdx.x == 0) st->tphase[0] = clock64();
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   __shared__ int idx[256];
   const int m = p.m, t = threadIdx.x, wv = t >> 6;
   const int n = kept_slots(b.keep, m, idx);
@@ -669,7 +669,7 @@ __device__ bool francis_qr(double* H, double* Q, int n, int ld, double hnorm, in
 // LDS: H (n + 1) x ld | Q (n + 1) x ld, ld = (n + 1) | 1
 __device__ void k_tharm_qr_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   __shared__ int idx[256];
   const int t = threadIdx.x;
   const int n = kept_slots(b.keep, p.m, idx);
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(kQR) void k_tharm_qr_b(const BatchSmall* __restrict
 // region holds the real parts of Y and the Xre region the imaginary parts.
 __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   __shared__ int idx[256];
   const int m = p.m, kint = p.kint, t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;

@@ -84,21 +84,25 @@ __device__ __forceinline__ void gram_body(size_t pb, size_t pe, const double* __
       }
     }
   };
-  double2 av, bv[kJPW];
-  load(pb, av, bv);
-  for (size_t p0 = pb; p0 < pe; p0 += 4) {
-    double2 an, bn[kJPW];
-    load(p0 + 4, an, bn);  // rows past pe load zeros
+  // a ring of kDepth steps of operands in registers: slot d is consumed
+  // and refilled with the step kDepth steps ahead (rows past pe load
+  // zeros), so kDepth x 4 rows of loads are in flight behind the MFMAs
+  constexpr int kDepth = 4;
+  double2 av[kDepth], bv[kDepth][kJPW];
 #pragma unroll
-    for (int q = 0; q < kJPW; ++q) {
-      acc[0][2 * q] = mfma(av.x, bv[q].x, acc[0][2 * q]);
-      acc[0][2 * q + 1] = mfma(av.x, bv[q].y, acc[0][2 * q + 1]);
-      acc[1][2 * q] = mfma(av.y, bv[q].x, acc[1][2 * q]);
-      acc[1][2 * q + 1] = mfma(av.y, bv[q].y, acc[1][2 * q + 1]);
+  for (int d = 0; d < kDepth; ++d) load(pb + 4 * d, av[d], bv[d]);
+  for (size_t p0 = pb; p0 < pe; p0 += 4 * kDepth) {
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+#pragma unroll
+      for (int q = 0; q < kJPW; ++q) {
+        acc[0][2 * q] = mfma(av[d].x, bv[d][q].x, acc[0][2 * q]);
+        acc[0][2 * q + 1] = mfma(av[d].x, bv[d][q].y, acc[0][2 * q + 1]);
+        acc[1][2 * q] = mfma(av[d].y, bv[d][q].x, acc[1][2 * q]);
+        acc[1][2 * q + 1] = mfma(av[d].y, bv[d][q].y, acc[1][2 * q + 1]);
+      }
+      load(p0 + 4 * (kDepth + d), av[d], bv[d]);
     }
-    av = an;
-#pragma unroll
-    for (int q = 0; q < kJPW; ++q) bv[q] = bn[q];
   }
   // lane (li, lk) holds D[4r + lk][li] of each tile: output row
   // 32 wi + 2(4r + lk) + a, column 32 jp + 2 li + b
@@ -143,7 +147,7 @@ __device__ __forceinline__ void rowmul_body(size_t pbeg, size_t pend, size_t fir
                                             size_t stride, ArrPtrs arrs, int narr, int ld, int m,
                                             const double* __restrict__ M, int kout, int mode,
                                             int kv, int kc, int pcol, double* __restrict__ part) {
-  extern __shared__ double sh[];
+  extern __shared__ __attribute__((aligned(16))) double sh[];
   const int kq = m / 4;               // m = 4 kint
   const int sms = TJ * 16 + 4;        // padded row stride of B in LDS
   double* sM = sh;                    // m x sms
