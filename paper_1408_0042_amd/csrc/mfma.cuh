@@ -176,60 +176,74 @@ __device__ __forceinline__ void rowmul_body(size_t pbeg, size_t pend, size_t fir
   const size_t ntiles = (pend - pbeg + 15) / 16;
   const size_t n = pend;
   const double* sB = sM + (lk * kq) * sms + li;
-  for (size_t tile = first + w; tile < ntiles; tile += stride) {
+  // work items (tile, array) of this wavefront in order; the operands of
+  // item it + 1 are loaded into registers while item it is multiplied
+  const size_t nmine = (first + w < ntiles) ? (ntiles - first - w + stride - 1) / stride : 0;
+  const size_t nitems = nmine * (size_t)narr;
+  auto fetch = [&](size_t it, double* A) {
+    const size_t tile = first + w + stride * (it / narr);
+    const int a = (int)(it % narr);
     const size_t p0 = pbeg + tile * 16;
-    const bool rowok = (p0 + li < n);
-    double vkeep[TJ][4];
-    for (int a = 0; a < narr; ++a) {
-      double* Xa = arrs.a[a];
-      double A[kMaxKq];
-      const double* src = Xa + (p0 + li) * ld + lk * kq;
-      if (rowok && vec2 && ((((uintptr_t)Xa) & 15) == 0)) {
+    const bool rowok = (it < nitems) && (p0 + li < n);
+    const double* Xa = arrs.a[a];
+    const double* src = Xa + (rowok ? (p0 + li) * ld + lk * kq : 0);
+    if (rowok && vec2 && ((((uintptr_t)Xa) & 15) == 0)) {
 #pragma unroll
-        for (int j = 0; j < kMaxKq; j += 2)
-          if (j < kq) {
-            const double2 v = *reinterpret_cast<const double2*>(src + j);
-            A[j] = v.x;
-            if (j + 1 < kMaxKq) A[j + 1] = v.y;
-          }
-      } else {
-#pragma unroll
-        for (int j = 0; j < kMaxKq; ++j) A[j] = (rowok && j < kq) ? src[j] : 0.0;
-      }
-      d4 acc[TJ];
-#pragma unroll
-      for (int t = 0; t < TJ; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < kMaxKq; ++kk) {
-        if (kk < kq) {
-#pragma unroll
-          for (int t = 0; t < TJ; ++t) acc[t] = mfma(A[kk], sB[kk * sms + t * 16], acc[t]);
+      for (int j = 0; j < kMaxKq; j += 2)
+        if (j < kq) {
+          const double2 v = *reinterpret_cast<const double2*>(src + j);
+          A[j] = v.x;
+          if (j + 1 < kMaxKq) A[j + 1] = v.y;
         }
-      }
-      // lane (li, lk) holds D[4r + lk][t 16 + li]
+    } else {
 #pragma unroll
-      for (int t = 0; t < TJ; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 4 * r + lk, col = t * 16 + li;
-          const double v = acc[t][r];
-          if (p0 + row >= n || col >= kout) continue;
-          double* dst = Xa + (p0 + row) * ld;
-          if (mode == 0) {
-            dst[col] = v;
-          } else if (col < kc) {
-            dst[col] = v;
-            if (a == 0) vkeep[t][r] = v;
-            if (a == 1) {
-              const double vv = vkeep[t][r];
-              dsum[t][0] += vv * vv;
-              dsum[t][1] += vv * v;
-            }
-          } else {
-            dst[pcol + col - kc] = v;
-          }
-        }
+      for (int j = 0; j < kMaxKq; ++j) A[j] = (rowok && j < kq) ? src[j] : 0.0;
     }
+  };
+  double vkeep[TJ][4];
+  double Acur[kMaxKq], Anext[kMaxKq];
+  if (nitems > 0) fetch(0, Acur);
+  for (size_t it = 0; it < nitems; ++it) {
+    fetch(it + 1, Anext);  // past the last item: zeros, no load
+    const size_t tile = first + w + stride * (it / narr);
+    const int a = (int)(it % narr);
+    const size_t p0 = pbeg + tile * 16;
+    double* Xa = arrs.a[a];
+    d4 acc[TJ];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kMaxKq; ++kk) {
+      if (kk < kq) {
+#pragma unroll
+        for (int t = 0; t < TJ; ++t) acc[t] = mfma(Acur[kk], sB[kk * sms + t * 16], acc[t]);
+      }
+    }
+    // lane (li, lk) holds D[4r + lk][t 16 + li]
+#pragma unroll
+    for (int t = 0; t < TJ; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * r + lk, col = t * 16 + li;
+        const double v = acc[t][r];
+        if (p0 + row >= n || col >= kout) continue;
+        double* dst = Xa + (p0 + row) * ld;
+        if (mode == 0) {
+          dst[col] = v;
+        } else if (col < kc) {
+          dst[col] = v;
+          if (a == 0) vkeep[t][r] = v;
+          if (a == 1) {
+            const double vv = vkeep[t][r];
+            dsum[t][0] += vv * vv;
+            dsum[t][1] += vv * v;
+          }
+        } else {
+          dst[pcol + col - kc] = v;
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < kMaxKq; ++j) Acur[j] = Anext[j];
   }
   if (mode == 1 && part) {
     // lanes with the same li (and t) hold the same column: sum over lk by
