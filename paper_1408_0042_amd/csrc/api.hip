@@ -458,19 +458,22 @@ plhr_status read_status(plhr_ctx_s* c) {
 plhr_status device_error(plhr_ctx_s* c) {
   const int e = c->st_host->error;
   if (e == 0) return PLHR_OK;
+  set_error(std::string("device check failed: ") + reason_text(c->st_host->reason) +
+            " (iteration " + std::to_string(c->st_host->iter) + ")");
+  return (plhr_status)e;
+}
+
+}  // namespace
+
+const char* plhr::reason_text(int r) {
   static const char* why[] = {"unspecified",
                               "the start block is rank deficient",
                               "the projected eigensolver did not converge",
                               "a wanted residual is not finite",
                               "V^T B V of the final Rayleigh-Ritz step is not positive definite",
                               "every column of V became linearly dependent"};
-  const int r = c->st_host->reason;
-  set_error(std::string("device check failed: ") + why[(r >= 0 && r <= 5) ? r : 0] +
-            " (iteration " + std::to_string(c->st_host->iter) + ")");
-  return (plhr_status)e;
+  return why[(r >= 0 && r <= 5) ? r : 0];
 }
-
-}  // namespace
 
 extern "C" {
 

@@ -758,6 +758,7 @@ plhr_status plhr_batch_solve(plhr_batch c, const double* const* V0, double* eigv
   PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
   PLHR_HIP_CHECK(hipGetLastError());
   plhr_status ret = PLHR_OK;
+  int first_bad = -1;
   for (int b = 0; b < c->nb; ++b) {
     if (rel_res)
       for (int j = 0; j < k; ++j) rel_res[(size_t)b * k + j] = rr[(size_t)b * kint + j];
@@ -766,9 +767,12 @@ plhr_status plhr_batch_solve(plhr_batch c, const double* const* V0, double* eigv
     if (c->st_host[b].error && !err[b]) sb = c->st_host[b].error;  // failed in the final step
     if (status) status[b] = sb;
     if (sb != PLHR_OK && (ret == PLHR_OK || ret == PLHR_ERR_NOT_CONVERGED)) ret = (plhr_status)sb;
+    if (sb != PLHR_OK && sb != PLHR_ERR_NOT_CONVERGED && first_bad < 0) first_bad = b;
   }
   if (ret != PLHR_OK && ret != PLHR_ERR_NOT_CONVERGED)
-    set_error("plhr_batch_solve: a problem failed (see the per-problem status)");
+    set_error("plhr_batch_solve: problem " + std::to_string(first_bad) + " failed: " +
+              reason_text(c->st_host[first_bad].reason) + " (iteration " +
+              std::to_string(c->st_host[first_bad].iter) + "; see the per-problem status)");
   else if (ret == PLHR_ERR_NOT_CONVERGED)
     set_error("plhr_batch_solve: some problems did not converge within max_iters");
   c->finished = true;

@@ -59,6 +59,8 @@ enum : int {
   kReasonFinalGram = 4,   // V^T B V of the final Rayleigh-Ritz is not HPD
   kReasonVVanished = 5    // every column of V became dependent
 };
+// Text of a DevStatus reason code (for error messages).
+const char* reason_text(int reason);
 
 // ---------------------------------------------------- launch profiling
 // Kernel categories for per-launch HIP-event timing.  When a context turns

@@ -362,18 +362,48 @@ __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
     U[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Cholesky of M
+  // M and C scaled to unit diagonal of M; Cholesky of M in column order
+  // with the trial-space dropping rule: a column of V that is numerically
+  // dependent on the earlier ones (two columns converged to the same
+  // eigenvector) is left out: its row and column of L become e_j and those
+  // of C zero, so it yields an eigenvalue that the ordering skips and no
+  // component in the other eigenvectors.  Fewer than k independent columns
+  // is a breakdown.
+  __shared__ int drop[128];
+  __shared__ double dsc[128];
+  for (int j = t; j < n; j += kTh) {
+    const double g = L[j * n + j];
+    dsc[j] = (g > 0.0 && g < INFINITY) ? 1.0 / sqrt(g) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += kTh) {
+    const int i = e / n, j = e - i * n;
+    const double f = dsc[i] * dsc[j];
+    L[e] *= f;
+    C[e] *= f;
+  }
+  __syncthreads();
+  int nkept = 0;
   for (int j = 0; j < n; ++j) {
     const double piv = L[j * n + j];
-    if (!(piv > 0.0)) {
-      if (t == 0) {
-        st->error = PLHR_ERR_NOT_HPD;
-        st->reason = kReasonFinalGram;
-      }
-      return;
-    }
-    const double d = sqrt(piv);
     __syncthreads();
+    if (!(piv > p.drop_tol)) {  // uniform
+      for (int i = t; i < n; i += kTh) {
+        if (i > j) L[i * n + j] = 0.0;
+        if (i < j) L[j * n + i] = 0.0;
+        C[i * n + j] = 0.0;
+        C[j * n + i] = 0.0;
+      }
+      if (t == 0) {
+        L[j * n + j] = 1.0;
+        drop[j] = 1;
+      }
+      __syncthreads();
+      continue;
+    }
+    ++nkept;
+    if (t == 0) drop[j] = 0;
+    const double d = sqrt(piv);
     for (int i = j + 1 + t; i < n; i += kTh) L[i * n + j] /= d;
     if (t == 0) L[j * n + j] = d;
     __syncthreads();
@@ -383,6 +413,13 @@ __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
       if (c <= i) L[i * n + c] -= L[i * n + j] * L[c * n + j];
     }
     __syncthreads();
+  }
+  if (nkept < k) {  // uniform
+    if (t == 0) {
+      st->error = PLHR_ERR_NOT_HPD;
+      st->reason = kReasonFinalGram;
+    }
+    return;
   }
   // C <- L^-1 C L^-T
   for (int c = t; c < n; c += kTh)
@@ -444,15 +481,17 @@ __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
         __syncthreads();
       }
   }
-  for (int i = t; i < n; i += kTh) ev[i] = C[i * n + i];
+  for (int i = t; i < n; i += kTh) ev[i] = drop[i] ? INFINITY : C[i * n + i];
   __syncthreads();
-  // X = L^-T U (in U): back substitution per column
+  // X = D L^-T U (in U): back substitution per column, then the scaling
   for (int c = t; c < n; c += kTh)
     for (int i = n - 1; i >= 0; --i) {
       double s = U[i * n + c];
       for (int q = i + 1; q < n; ++q) s -= L[q * n + i] * U[q * n + c];
       U[i * n + c] = s / L[i * n + i];
     }
+  __syncthreads();
+  for (int e = t; e < n * n; e += kTh) U[e] *= dsc[e / n];
   __syncthreads();
   if (t == 0) {
     // order by |theta - sigma| (= |ev|), ties to the smaller theta
