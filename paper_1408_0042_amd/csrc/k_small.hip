@@ -243,42 +243,52 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     return;
   }
   // right-looking Cholesky in slot order; a numerically dependent column
-  // (V included) adds nothing to span(Z) and is dropped
+  // (V included) adds nothing to span(Z) and is dropped.  Rows of R stay
+  // unscaled during the elimination (the update of step j divides by the
+  // pivot) and are scaled by 1/sqrt(pivot) once at the end: one barrier
+  // per kept column.  A dropped column takes no barrier: the decision is
+  // uniform and column j is read by no later step.
+  __shared__ double rsc[256];  // 1/sqrt(pivot) of each kept slot
   for (int j = 0; j < m; ++j) {
     if (!valid[j]) continue;
     const double piv = Gs[j * m + j];
-    __syncthreads();
     if (!(piv > p.drop_tol)) {
       if (t == 0) valid[j] = 0;
-      __syncthreads();
       continue;
     }
-    const double rjj = sqrt(piv);
-    for (int l = j + 1 + t; l < m; l += nt)
-      if (valid[l]) Gs[j * m + l] /= rjj;
-    if (t == 0) Gs[j * m + j] = rjj;
-    __syncthreads();
+    const double ip = 1.0 / piv;
+    if (t == 0) rsc[j] = 1.0 / sqrt(piv);
     for (int i = j + 1 + ty; i < m; i += 16) {
       if (!valid[i]) continue;
-      const double rji = Gs[j * m + i];
+      const double gji = Gs[j * m + i] * ip;
       for (int l = i + tx; l < m; l += 16)
-        if (valid[l]) Gs[i * m + l] -= rji * Gs[j * m + l];
+        if (valid[l]) Gs[i * m + l] -= gji * Gs[j * m + l];
     }
     __syncthreads();
   }
-  // X = R^-1 by right-looking back substitution over the kept slots
+  __syncthreads();
+  // R (upper, kept slots only; zero elsewhere) in place
+  for (int i = ty; i < m; i += 16)
+    for (int l = tx; l < m; l += 16)
+      Gs[i * m + l] = (valid[i] && valid[l] && l >= i) ? Gs[i * m + l] * rsc[i] : 0.0;
+  __syncthreads();
+  // X = R^-1 by right-looking back substitution over the kept slots, rows
+  // unscaled until the end (step i subtracts R[r][i] / R[i][i] times row i
+  // from the rows above): one barrier per kept slot
   for (int i = m - 1; i >= 0; --i) {
     if (!valid[i]) continue;
     const double inv = 1.0 / Gs[i * m + i];
-    for (int c = t; c < m; c += nt) X[i * m + c] *= inv;
-    __syncthreads();
     for (int r = ty; r < i; r += 16) {
       if (!valid[r]) continue;
-      const double rri = Gs[r * m + i];
-      for (int c = tx; c < m; c += 16) X[r * m + c] -= rri * X[i * m + c];
+      const double f = Gs[r * m + i] * inv;
+      for (int c = tx; c < m; c += 16) X[r * m + c] -= f * X[i * m + c];
     }
     __syncthreads();
   }
+  for (int i = ty; i < m; i += 16)
+    for (int c = tx; c < m; c += 16)
+      if (valid[i]) X[i * m + c] /= Gs[i * m + i];
+  __syncthreads();
   // M = D R^-1 on the kept slots, zero elsewhere
   for (int i = ty; i < m; i += 16)
     for (int c = tx; c < m; c += 16)

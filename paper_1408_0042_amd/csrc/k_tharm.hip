@@ -896,17 +896,22 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   }
   __syncthreads();
   const int nsel = nsel_s;
-  // Q <- L^-T Q (solve L^T Y = Q, right-looking from the last row)
+  // Q <- L^-T Q (solve L^T Y = Q, right-looking from the last row); the
+  // rows stay unscaled until the end (step i subtracts L[i][r] / L[i][i]
+  // times row i from the rows above it): one barrier per row
   for (int i = n - 1; i >= 0; --i) {
     const double inv = 1.0 / L[i * n + i];
-    for (int c = t; c < n; c += kNT) Q[i * ld + c] *= inv;
-    __syncthreads();
     for (int r = ty; r < i; r += 16) {
-      const double lir = L[i * n + r];
-      for (int c = tx; c < n; c += 16) Q[r * ld + c] -= lir * Q[i * ld + c];
+      const double f = L[i * n + r] * inv;
+      for (int c = tx; c < n; c += 16) Q[r * ld + c] -= f * Q[i * ld + c];
     }
     __syncthreads();
   }
+  for (int i = ty; i < n; i += 16) {
+    const double inv = 1.0 / L[i * n + i];
+    for (int c = tx; c < n; c += 16) Q[i * ld + c] *= inv;
+  }
+  __syncthreads();
   if (t == 0) st->tphase[8] = clock64();
   // eigenvectors of T: 16 lanes per selected unit; lane l owns the
   // entries j with j % 16 == l (it alone writes and reads them), so the
