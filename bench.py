@@ -67,6 +67,37 @@ def pick_sigma(N, h, mode):
     return u[i - 1] + 0.4 * (u[i] - u[i - 1]), ev
 
 
+# HBM traffic per launch of a kernel, from two profiler passes over
+# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --precision fp64 --batch 0
+# --max-iters 20 --copy-mib 256`: FETCH_SIZE, then WRITE_SIZE (KiB per
+# dispatch).  Each counter is scaled by what it reads for kernels of known
+# traffic in the same run: a 256 MiB device copy reads 131089 KiB of
+# FETCH_SIZE for 262144 KiB fetched (factor 2.0), a 256 MiB fill 262144 KiB
+# of WRITE_SIZE (factor 1.0).  Keyed on the kernel category and the trial
+# subspace width m; the SHA-256 of the kernel's source when the counters
+# were taken voids the figure (traffic null) once that source changes.
+FETCH_FACTOR = 2.0
+WRITE_FACTOR = 1.0
+MEASURED_TRAFFIC = {
+    ("tharm_qr", 80): {"source": "paper_1408_0042_amd/csrc/k_tharm.hip",
+                       "sha256": "64886ac48ff79ea16c8612204945c0dc11755dba1dd5afc17ac6ec1090c0af12",
+                       "fetch_kib": 60.3125, "write_kib": 101.09375},
+}
+
+
+def measured_traffic(cat, m):
+    """HBM bytes per launch of category `cat` at trial width m, or None when
+    not measured or when the kernel's source differs from the one measured."""
+    e = MEASURED_TRAFFIC.get((cat, m))
+    if e is None:
+        return None
+    import hashlib
+    with open(os.path.join(ROOT, e["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
+            return None
+    return 1024.0 * (FETCH_FACTOR * e["fetch_kib"] + WRITE_FACTOR * e["write_kib"])
+
+
 # categories whose work is a dense contraction (matrix cores)
 CONTRACTIONS = ("gram", "transform", "update")
 # single-workgroup kernels: plain ALU work on one compute unit
@@ -204,6 +235,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first fill and copy this many MiB on the device: kernels of known "
+                         "traffic that calibrate the HBM byte counters of a profiler run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +257,12 @@ def main():
     fixed = args.shift == "quarter"
     # the k eigenvalues nearest sigma, from the closed form
     ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:k])
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib * 131072, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     V0 = torch.from_numpy(wl.start_block(w.n, k + kx, w.v0_seed)).to("cuda")
     torch.cuda.synchronize()
 
@@ -277,6 +317,8 @@ def main():
         roof["algorithmic_per_launch"] = ((p["bytes"] if roof["unit"] == "GB/s" else p["flops"])
                                           / max(1, p["launches"]))
         roof["share_of_step"] = p["ms"] / (1e3 * el)
+        # per launch at the full trial width m = 4 (k + kx), in bytes
+        roof["traffic"] = measured_traffic(dom, 4 * (k + kx))
         kernels = {}
         for c in cats:
             e = roofline_entry(c, prof_all[c])
