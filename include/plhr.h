@@ -52,7 +52,8 @@ typedef enum {
 typedef enum {
   PLHR_OP_IDENTITY = 0,
   PLHR_OP_FD5_2D = 1, /* scale*(-Laplacian) 5-point, Dirichlet, + diag(V)   */
-  PLHR_OP_FD7_3D = 2  /* scale*(-Laplacian) 7-point, Dirichlet, + diag(V)   */
+  PLHR_OP_FD7_3D = 2, /* scale*(-Laplacian) 7-point, Dirichlet, + diag(V)  */
+  PLHR_OP_DIAG = 3    /* diag(d), d in `potential`: a lumped mass for B    */
 } plhr_op_kind;
 
 typedef enum { PLHR_F64 = 0 } plhr_dtype;
@@ -64,7 +65,11 @@ typedef enum { PLHR_F64 = 0 } plhr_dtype;
  *   nx, ny, nz interior points per direction (>= 1)
  *   h          grid spacing (> 0)
  *   scale      factor multiplying the negative discrete Laplacian (> 0)
- *   potential  device, n doubles, or NULL for none: A += diag(potential)  */
+ *   potential  device, n doubles, or NULL for none: A += diag(potential);
+ *              for PLHR_OP_DIAG the diagonal itself (not NULL)
+ * A PLHR_OP_DIAG descriptor is used only as B: its nx, ny, nz must be
+ * those of A and every diagonal entry positive and finite (checked at
+ * plhr_create, PLHR_ERR_ARG otherwise); h and scale are ignored.       */
 typedef struct {
   int32_t kind;
   int32_t dtype;
@@ -164,7 +169,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
 /* Create a solver for the k eigenpairs of A v = lambda B v nearest sigma
  * (Algorithm 3 for these real operators).
  *   A          host descriptor of A (FD5_2D or FD7_3D)
- *   B          host descriptor of B, or NULL for the identity
+ *   B          host descriptor of B: NULL or PLHR_OP_IDENTITY for the
+ *              identity, or PLHR_OP_DIAG for a positive diagonal B (the
+ *              diagonal is read once at create and must stay allocated)
  *   T          host descriptor of the HPD preconditioner, or NULL for I
  *   sigma      finite real shift
  *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n; a trial
@@ -206,7 +213,7 @@ plhr_status plhr_solve(plhr_ctx ctx, const double* V0, double* eigvals, double* 
                        double* rel_res, int32_t* iters);
 
 /* Hellmann-Feynman gradient of L(lambda) with respect to the diagonal
- * potential of A: for B = I and A = L + diag(pot),
+ * potential of A: for A = L + diag(pot) and B independent of pot,
  *     dL/dpot_x = sum_j dL/dlambda_j * |v_j(x)|^2 / (v_j^* B v_j)
  * over the k pairs returned by the last plhr_finish.
  *   dL_dlambda  device, k doubles

@@ -1,5 +1,16 @@
 // C ABI of libplhr and the host driver of the block PLHR iteration
-// (Algorithm 3 of the paper for real symmetric A, B = I and an SPD T).
+// (Algorithm 3 of the paper for real symmetric A, B = I or a positive
+// diagonal B, and an SPD T).
+//
+// A diagonal B = diag(b) is handled by running the iteration in the
+// variables u = B^1/2 v, where the pencil becomes (S A S, I) with
+// S = B^-1/2 and the preconditioner S^-1 T S^-1 = B^1/2 T B^1/2: every
+// B-inner product of Algorithm 3 is then the Euclidean one of the u's,
+// and the iterates are those of the original pencil mapped by B^1/2 (the
+// Gram matrices, the projected problem and the Ritz values are identical).
+// The stencil applies S A S directly, T gets the scaling on its input and
+// output, residual norms are formed in the original variables, and the
+// returned vectors are mapped back (v = S u).
 //
 // Device data layout (point-major, n rows):
 //   Z, QZ, TQZ  n x m, m = 4 kint columns in slots V | W | S | P
@@ -26,6 +37,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -149,6 +161,10 @@ struct plhr_ctx_s {
   hipStream_t stream = nullptr;
   Grid grid;
   const double* pot = nullptr;
+  // diagonal B (caller's b, n doubles) and the workspace copies of b^1/2,
+  // b^-1/2; Rs stages the scaled preconditioner input (n x 2 kint)
+  const double* bdiag = nullptr;
+  double *bsq = nullptr, *bisq = nullptr, *Rs = nullptr;
   int prec_kind = PLHR_PREC_IDENTITY;
   MG mg;
   double sigma = 0.0;
@@ -216,8 +232,22 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     return PLHR_ERR_ARG;
   }
   if (B && B->kind != PLHR_OP_IDENTITY) {
-    set_error("B: only the identity is supported by this build");
-    return PLHR_ERR_UNSUPPORTED;
+    if (B->kind != PLHR_OP_DIAG) {
+      set_error("B: only the identity and PLHR_OP_DIAG are supported");
+      return PLHR_ERR_UNSUPPORTED;
+    }
+    if (B->dtype != PLHR_F64) {
+      set_error("B: only PLHR_F64 is supported");
+      return PLHR_ERR_UNSUPPORTED;
+    }
+    if (!B->potential) {
+      set_error("B: PLHR_OP_DIAG carries its diagonal in `potential`, which is NULL");
+      return PLHR_ERR_ARG;
+    }
+    if (B->nx != A->nx || B->ny != A->ny || B->nz != A->nz) {
+      set_error("B: the grid dimensions must be those of A");
+      return PLHR_ERR_ARG;
+    }
   }
   if (!std::isfinite(sigma)) {
     set_error("sigma must be finite");
@@ -274,7 +304,8 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
 }
 
 
-Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s* c) {
+Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag,
+              plhr_ctx_s* c) {
   Layout L;
   const size_t n = g.n();
   const int m = 4 * kint;
@@ -294,6 +325,12 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
   size_t ofc = L.take((size_t)kint * kint * 8), oft = L.take(kint * 8), ovbv = L.take(kint * 8);
   size_t owork = L.take((size_t)4 * m * m * 8);
   size_t ost = L.take(sizeof(DevStatus));
+  size_t obsq = 0, obisq = 0, oRs = 0;
+  if (bdiag) {
+    obsq = L.take(n * 8);
+    obisq = L.take(n * 8);
+    oRs = L.take(n * 2 * kint * 8);
+  }
   size_t omg = L.bytes;
   if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint);
   if (c) {
@@ -326,6 +363,11 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
     c->sb.work = (double*)(b + owork);
     c->sb.scratch = nullptr;
     c->st = (DevStatus*)(b + ost);
+    if (bdiag) {
+      c->bsq = (double*)(b + obsq);
+      c->bisq = (double*)(b + obisq);
+      c->Rs = (double*)(b + oRs);
+    }
     (void)omg;
   }
   return L;
@@ -335,16 +377,16 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, plhr_ctx_s
 
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
              Blk outc, int ncols, double shift, const DevStatus* st) {
-  launch_fd_apply(c->grid, c->pot, shift, X, ldx, out, outr, colshift, c->sigma, outc, ncols, st,
-                  c->stream);
+  launch_fd_apply(c->grid, c->pot, c->bisq, shift, X, ldx, out, outr, colshift, c->sigma, outc,
+                  ncols, st, c->stream);
 }
 
 // T applied to ncols columns of R (ld ldr); output split at `split`.
 // `direction`: the result only spans search directions (W, S), so the
 // mixed mode may compute it with the FP32 V-cycle; products that enter the
 // T-harmonic Grams (T(A - sigma B)Z) always use the FP64 V-cycle.
-void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split, int ncols,
-             const DevStatus* st, bool direction = false) {
+void precond_raw(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split,
+                 int ncols, const DevStatus* st, bool direction) {
   if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
     const bool f32 = direction && c->opt.precision == PLHR_PREC_MIXED;
     mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, f32, st, c->stream);
@@ -352,6 +394,20 @@ void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int spli
     if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream);
     if (split < ncols) launch_copy(c->n, Rin + split, ldr, o1.ptr, o1.ld, ncols - split, c->stream);
   }
+}
+
+// With a diagonal B the iteration's preconditioner is B^1/2 T B^1/2.
+void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split, int ncols,
+             const DevStatus* st, bool direction = false) {
+  if (!c->bdiag) {
+    precond_raw(c, Rin, ldr, o0, o1, split, ncols, st, direction);
+    return;
+  }
+  launch_rowscale(c->n, c->bsq, Rin, ldr, c->Rs, ncols, ncols, c->stream);
+  precond_raw(c, c->Rs, ncols, o0, o1, split, ncols, st, direction);
+  if (split > 0) launch_rowscale(c->n, c->bsq, o0.ptr, o0.ld, o0.ptr, o0.ld, split, c->stream);
+  if (split < ncols)
+    launch_rowscale(c->n, c->bsq, o1.ptr, o1.ld, o1.ptr, o1.ld, ncols - split, c->stream);
 }
 
 // Gram product on the matrix cores when the shape fits.
@@ -416,7 +472,8 @@ void enqueue_iteration(plhr_ctx_s* c) {
   int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
   // residuals of the current block, convergence and locking
-  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, R, kint, kint, c->part, st,
+  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, R, kint, kint, c->bdiag,
+                         c->part, st,
                          s);
   launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
   // W = T (A V - B V Lam)
@@ -510,7 +567,8 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
     return PLHR_ERR_ARG;
   }
   const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
-  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, nullptr);
+  const bool bd = B && B->kind == PLHR_OP_DIAG;
+  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, nullptr);
   *ws_bytes = L.bytes;
   return PLHR_OK;
 }
@@ -541,7 +599,9 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->n = c->grid.n();
   const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
   c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
-  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, nullptr);
+  const bool bd = B && B->kind == PLHR_OP_DIAG;
+  if (bd) c->bdiag = B->potential;
+  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, nullptr);
   if (workspace) {
     if (ws_bytes < L.bytes) {
       set_error("workspace smaller than plhr_workspace_size");
@@ -565,7 +625,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     c->own_ws = true;
   }
   c->ws_bytes = L.bytes;
-  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, c);
+  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c);
   // norms for the relative residual
   std::vector<double> pot;
   if (c->pot) {
@@ -579,6 +639,37 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   }
   c->normA1 = exact_norm1(c->grid, pot);
   c->normB1 = 1.0;
+  if (bd) {
+    // B = diag(b): b > 0 and finite, ||B||_1 = max b, and the scalings
+    std::vector<double> bh(c->n), sq(c->n), isq(c->n);
+    hipError_t e = hipMemcpy(bh.data(), c->bdiag, c->n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_error(std::string("reading the diagonal of B failed: ") + hipGetErrorString(e));
+      plhr_destroy(c);
+      return PLHR_ERR_HIP;
+    }
+    double bmax = 0.0;
+    for (size_t p = 0; p < c->n; ++p) {
+      if (!(bh[p] > 0.0) || !std::isfinite(bh[p])) {
+        set_error("B: every diagonal entry must be positive and finite (entry " +
+                  std::to_string(p) + ")");
+        plhr_destroy(c);
+        return PLHR_ERR_ARG;
+      }
+      bmax = std::max(bmax, bh[p]);
+      sq[p] = std::sqrt(bh[p]);
+      isq[p] = 1.0 / sq[p];
+    }
+    c->normB1 = bmax;
+    e = hipMemcpy(c->bsq, sq.data(), c->n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->bisq, isq.data(), c->n * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      set_error(std::string("uploading the scalings of B failed: ") + hipGetErrorString(e));
+      plhr_destroy(c);
+      return PLHR_ERR_HIP;
+    }
+  }
   if (mgp) {
     char* wp = c->ws + L.bytes - mg_workspace_bytes(c->grid, T->levels, 2 * c->kint);
     s = mg_setup(c->mg, c->grid, T->levels, T->nu_pre, T->nu_post, T->omega, 2 * c->kint, wp,
@@ -630,7 +721,10 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   PLHR_HIP_CHECK(hipMemsetAsync(c->QZ, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->TQZ, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
-  launch_copy(n, V0, kint, c->Z, m, kint, s);
+  if (c->bdiag)
+    launch_rowscale(n, c->bsq, V0, kint, c->Z, m, kint, s);  // u = B^1/2 v
+  else
+    launch_copy(n, V0, kint, c->Z, m, kint, s);
   const Blk none{nullptr, 0};
   stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr);
   precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
@@ -707,9 +801,15 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
   const Blk none{nullptr, 0};
   stencil(c, c->Vfin, k, Blk{c->QVfin, k}, none, nullptr, none, k, c->sigma, nullptr);
   const int nb = launch_coldots(n, c->Vfin, k, c->QVfin, k, k, c->sb.final_theta, c->sigma,
-                                c->part, s);
+                                c->bdiag, c->part, s);
   SmallParams fp = c->sp;
   launch_final_res(fp, c->part, nb, c->sb, s);
+  if (c->bdiag) {
+    // v^* B v = u^* u for the gradient, then v = B^-1/2 u
+    const int nx = launch_xdots(n, c->Vfin, k, c->QVfin, k, k, c->part, s);
+    launch_colsum_first(c->part, nx, k, c->sb.vbv, s);
+    launch_rowscale(n, c->bisq, c->Vfin, k, c->Vfin, k, k, s);
+  }
   if (eigvals)
     PLHR_HIP_CHECK(hipMemcpyAsync(eigvals, c->sb.final_theta, k * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
@@ -770,10 +870,17 @@ plhr_status plhr_apply(plhr_ctx c, int32_t which, const double* X, double* Y, in
   }
   const Blk none{nullptr, 0};
   if (which == 0 || which == 1) {
-    stencil(c, X, ncols, Blk{Y, ncols}, none, nullptr, none, ncols, which == 1 ? c->sigma : 0.0,
-            nullptr);
+    // with a diagonal B: A X = B^1/2 (S A S)(B^1/2 X), and the same with the shift
+    const double* Xin = X;
+    if (c->bdiag) {
+      launch_rowscale(c->n, c->bsq, X, ncols, c->Rs, ncols, ncols, c->stream);
+      Xin = c->Rs;
+    }
+    stencil(c, Xin, ncols, Blk{Y, ncols}, none, nullptr, none, ncols,
+            which == 1 ? c->sigma : 0.0, nullptr);
+    if (c->bdiag) launch_rowscale(c->n, c->bsq, Y, ncols, Y, ncols, ncols, c->stream);
   } else if (which == 2) {
-    precond(c, X, ncols, Blk{Y, ncols}, none, ncols, ncols, nullptr, true);
+    precond_raw(c, X, ncols, Blk{Y, ncols}, none, ncols, ncols, nullptr, true);
   } else {
     set_error("plhr_apply: which must be 0, 1 or 2");
     return PLHR_ERR_ARG;
@@ -794,7 +901,12 @@ plhr_status plhr_get_state(plhr_ctx c, double* lam, double* V) {
   }
   PLHR_HIP_CHECK(hipMemcpyAsync(lam, c->sb.lam, c->kint * sizeof(double), hipMemcpyDeviceToHost,
                                 c->stream));
-  if (V) launch_copy(c->n, c->Z, c->m, V, c->kint, c->kint, c->stream);
+  if (V) {
+    if (c->bdiag)
+      launch_rowscale(c->n, c->bisq, c->Z, c->m, V, c->kint, c->kint, c->stream);
+    else
+      launch_copy(c->n, c->Z, c->m, V, c->kint, c->kint, c->stream);
+  }
   PLHR_HIP_CHECK(hipGetLastError());
   PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
   return PLHR_OK;

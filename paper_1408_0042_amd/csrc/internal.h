@@ -124,12 +124,13 @@ struct Blk {
 
 // ------------------------------------------------------------- launchers
 // Stencil: out = scale*(-Lap)X + pot.*X - shift*X  (shift = sigma for
-// (A - sigma I)X, 0 for AX).  Optional extra outputs:
+// (A - sigma I)X, 0 for AX).  With sc != null (n doubles) the operator is
+// S A S - shift I, S = diag(sc).  Optional extra outputs:
 //   out_r (if ptr != null): out_r[:, c] = out[:, c] - X[:, c] * (colshift[c] - csub)
 //   out_c (if ptr != null): out_c[:, c] = out[:, c]
-void launch_fd_apply(const Grid& g, const double* pot, double shift, const double* X, int ldx,
-                     Blk out, Blk out_r, const double* colshift, double csub, Blk out_c,
-                     int ncols, const DevStatus* st, hipStream_t s);
+void launch_fd_apply(const Grid& g, const double* pot, const double* sc, double shift,
+                     const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
+                     double csub, Blk out_c, int ncols, const DevStatus* st, hipStream_t s);
 
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {
@@ -159,10 +160,11 @@ void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, i
 // Dense level-0 helpers (k_blas.hip)
 // residual prep: R[:, c] = QV[:, c] - V[:, c] * (lam[c] - sigma); partial
 // sums of |R|^2 and |V|^2 per column per block written to part
-// (nblk x 2c).  Returns the number of blocks used.
+// (nblk x 2c); with row weights bw != null, of bw.*R^2 and V^2./bw.
+// Returns the number of blocks used.
 int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
-                      const double* lam, double sigma, double* R, int ldr, int ncols, double* part,
-                      const DevStatus* st, hipStream_t s);
+                      const double* lam, double sigma, double* R, int ldr, int ncols,
+                      const double* bw, double* part, const DevStatus* st, hipStream_t s);
 int resid_prep_blocks(size_t n);
 
 // Split-K Gram: out(i, j) = sum_p X[p, i] * Y[p, j] for i < mx, j < my,
@@ -197,10 +199,14 @@ void launch_small_gemm(size_t n, const double* X, int ldx, int kin, const double
 
 // copy n x c block with leading dimensions
 void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s);
+// Y = diag(w) X, n x c (Y may alias X with ldy == ldx)
+void launch_rowscale(size_t n, const double* w, const double* X, int ldx, double* Y, int ldy,
+                     int c, hipStream_t s);
 
-// column partial sums of |X|^2, X.*Y (nblk x 2c) for final residuals:
+// column partial sums for final residuals (as launch_resid_prep, no R):
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
-                   const double* lam, double sigma, double* part, hipStream_t s);
+                   const double* lam, double sigma, const double* bw, double* part,
+                   hipStream_t s);
 
 // partial column sums of x.x and x.y (nblk x 2c)
 int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, int ncols,
@@ -360,6 +366,8 @@ void launch_final_rr(const SmallParams& p, const double* HM, SmallBufs b, DevSta
                      hipStream_t s);
 void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                       hipStream_t s);
+// out[c] = sum over blocks of the first of the two launch_xdots sums, c < k
+void launch_colsum_first(const double* part, int nblk, int k, double* out, hipStream_t s);
 hipError_t small_set_attributes(int m, int kint);
 hipError_t tharm_set_attributes(int m, int kint);
 

@@ -35,11 +35,15 @@ __device__ __forceinline__ void block_colsum(double (&acc)[NV], int ncols, doubl
   }
 }
 
-// R = QV - V * (lam - sigma); partial |R|^2, |V|^2 per column.
+// R = QV - V * (lam - sigma); partial |R|^2, |V|^2 per column.  With row
+// weights bw (a diagonal mass b, the blocks in the variables u = b^1/2 v)
+// the sums are the norms of the residual and of the vector in the
+// original variables: sum b R^2 and sum V^2 / b.
 __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __restrict__ V,
                                                     int ldv, const double* __restrict__ QV, int ldq,
                                                     const double* __restrict__ lam, double sigma,
                                                     double* __restrict__ R, int ldr, int ncols,
+                                                    const double* __restrict__ bw,
                                                     double* __restrict__ part,
                                                     const DevStatus* st) {
   if (halted(st)) return;
@@ -57,19 +61,26 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
       const double v = V[p * ldv + c];
       const double r = QV[p * ldq + c] - v * sh;
       if (R) R[p * ldr + c] = r;
-      acc[0] += r * r;
-      acc[1] += v * v;
+      if (bw) {
+        const double b = bw[p];
+        acc[0] += b * (r * r);
+        acc[1] += (v * v) / b;
+      } else {
+        acc[0] += r * r;
+        acc[1] += v * v;
+      }
     }
   }
   block_colsum<2>(acc, ncols, part);
 }
 
 int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
-                      const double* lam, double sigma, double* R, int ldr, int ncols, double* part,
-                      const DevStatus* st, hipStream_t s) {
-  prof_begin(KC_VEC, (double)n * ncols * 8.0 * (R ? 3.0 : 2.0), 5.0 * n * ncols, s);
+                      const double* lam, double sigma, double* R, int ldr, int ncols,
+                      const double* bw, double* part, const DevStatus* st, hipStream_t s) {
+  prof_begin(KC_VEC, (double)n * ncols * 8.0 * (R ? 3.0 : 2.0) + (bw ? n * 8.0 : 0.0),
+             5.0 * n * ncols, s);
   hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, V, ldv, QV, ldq, lam,
-                     sigma, R, ldr, ncols, part, st);
+                     sigma, R, ldr, ncols, bw, part, st);
   prof_end(KC_VEC, s);
   return kRedBlocks;
 }
@@ -104,9 +115,10 @@ int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, i
 
 // Column sums for the final residual check: |QX - X*(lam - sigma)|^2, |X|^2.
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
-                   const double* lam, double sigma, double* part, hipStream_t s) {
+                   const double* lam, double sigma, const double* bw, double* part,
+                   hipStream_t s) {
   hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, X, ldx, QX, ldq, lam,
-                     sigma, (double*)nullptr, 0, c, part, (const DevStatus*)nullptr);
+                     sigma, (double*)nullptr, 0, c, bw, part, (const DevStatus*)nullptr);
   return kRedBlocks;
 }
 
@@ -410,6 +422,30 @@ void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, 
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, n, X, ldx, Y, ldy, c);
+}
+
+// Y = diag(w) X (rows scaled; Y may be X with the same leading dimension).
+__global__ __launch_bounds__(256) void k_rowscale(size_t n, const double* __restrict__ w,
+                                                  const double* X, int ldx, double* Y, int ldy,
+                                                  int c) {
+  const size_t tot = n * (size_t)c;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = e / c;
+    const int j = (int)(e - p * c);
+    Y[p * ldy + j] = w[p] * X[p * ldx + j];
+  }
+}
+
+void launch_rowscale(size_t n, const double* w, const double* X, int ldx, double* Y, int ldy,
+                     int c, hipStream_t s) {
+  if (c <= 0 || n == 0) return;
+  const size_t tot = n * (size_t)c;
+  const size_t want = (tot + 255) / 256;
+  const int nb = (int)(want < 4096 ? want : 4096);
+  prof_begin(KC_VEC, (double)n * c * 16.0 + n * 8.0, (double)n * c, s);
+  hipLaunchKernelGGL(k_rowscale, dim3(nb), dim3(256), 0, s, n, w, X, ldx, Y, ldy, c);
+  prof_end(KC_VEC, s);
 }
 
 // Hellmann-Feynman: g[x] (+)= sum_j dl[j] * V[x, j]^2 / vbv[j]

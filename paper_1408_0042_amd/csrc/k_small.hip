@@ -597,6 +597,19 @@ void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallB
   hipLaunchKernelGGL(k_final_res, dim3(1), dim3(256), 0, s, p, part, nblk, b);
 }
 
+// out[c] = the first of the two column sums of launch_xdots, c < k
+// (k <= 64): u^* u of the returned vectors in the variables where B = I.
+__global__ __launch_bounds__(256) void k_colsum_first(const double* __restrict__ part, int nblk,
+                                                      int k, double* __restrict__ out) {
+  __shared__ double red[256], sums[128];
+  sum_partials(part, nblk, 2 * k, sums, red);
+  if ((int)threadIdx.x < k) out[threadIdx.x] = sums[threadIdx.x];
+}
+
+void launch_colsum_first(const double* part, int nblk, int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum_first, dim3(1), dim3(256), 0, s, part, nblk, k, out);
+}
+
 // ---------------------------------------------------------------- batched
 void launch_init_lam_b(const BatchSmall* bs, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_init_lam_b, dim3(nb), dim3(256), 0, s, bs);

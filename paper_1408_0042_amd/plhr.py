@@ -39,16 +39,18 @@ class SolveResult:
 
 
 class Solver:
-    """Block PLHR for the k eigenpairs of A v = lambda v nearest sigma.
+    """Block PLHR for the k eigenpairs of A v = lambda B v nearest sigma.
 
     kind: "fd5_2d" or "fd7_3d"; dims: interior grid points; h: spacing;
     scale: factor on the negative Laplacian; potential: optional (n,) float64
-    device tensor added to the diagonal; precond: None (T = I) or a dict
-    {"levels", "nu", "omega"} for the multigrid V-cycle.
+    device tensor added to the diagonal; mass: optional (n,) float64 device
+    tensor, positive, the diagonal of B (None: B = I); precond: None (T = I)
+    or a dict {"levels", "nu", "omega"} for the multigrid V-cycle.
     """
 
     def __init__(self, kind: str, dims: Sequence[int], h: float, sigma: float, k: int,
                  scale: float = 1.0, potential: Optional[torch.Tensor] = None,
+                 mass: Optional[torch.Tensor] = None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
                  drop_tol: float = 1e-12, precision: str = "fp64",
@@ -75,6 +77,17 @@ class Solver:
             a.potential = potential.data_ptr()
         self.n = int(np.prod(dims))
         self.dims = dims
+        self.mass = mass
+        bdesc = None
+        if mass is not None:
+            _require_cuda(mass, "mass")
+            if tuple(mass.shape) != (self.n,):
+                raise ValueError(f"mass must have shape {(self.n,)}")
+            bdesc = L.OpDesc()
+            bdesc.kind, bdesc.dtype = L.OP_DIAG, L.F64
+            bdesc.nx, bdesc.ny, bdesc.nz = a.nx, a.ny, a.nz
+            bdesc.h, bdesc.scale = 1.0, 1.0
+            bdesc.potential = mass.data_ptr()
         self.k = int(k)
         self.kint = int(k) + int(k_extra)
         self.sigma = float(sigma)
@@ -93,9 +106,10 @@ class Solver:
         o.precision = L.PRECISION_MIXED if precision == "mixed" else L.PRECISION_FP64
         self.opts = o
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self._a, self._t = a, t
+        self._a, self._t, self._b = a, t, bdesc
         ctx = C.c_void_p()
-        L.check(self.lib.plhr_create(C.byref(a), None, C.byref(t) if t is not None else None,
+        L.check(self.lib.plhr_create(C.byref(a), C.byref(bdesc) if bdesc is not None else None,
+                                     C.byref(t) if t is not None else None,
                                      self.sigma, self.k, C.byref(o),
                                      C.c_void_p(self.stream.cuda_stream), None, 0,
                                      C.byref(ctx)))

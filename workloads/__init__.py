@@ -170,6 +170,15 @@ def gaussian_potential(N: int, ngauss: int, seed: Tuple[int, ...], d: int = 2) -
     return V.ravel()
 
 
+def mass_density(N: int, seed: Tuple[int, ...], d: int = 2, contrast: float = 4.0) -> np.ndarray:
+    """A positive, smoothly varying diagonal mass b on an N^d grid (a
+    membrane or medium of variable density): 1 plus (contrast - 1) times
+    a sum of 3 positive Gaussian bumps scaled to peak 1, so that
+    1 <= b <= contrast.  Returned x-fastest, length N^d."""
+    bump = -gaussian_potential(N, 3, seed, d)
+    return 1.0 + (contrast - 1.0) * bump / bump.max()
+
+
 def batched_problem(b: int, sizes=(64, 96, 128, 160)):
     """Problem b of the batched set: grid size N_b, potential, targets."""
     g = rng(5, 2)
