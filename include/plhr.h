@@ -53,7 +53,10 @@ typedef enum {
   PLHR_OP_IDENTITY = 0,
   PLHR_OP_FD5_2D = 1, /* scale*(-Laplacian) 5-point, Dirichlet, + diag(V)   */
   PLHR_OP_FD7_3D = 2, /* scale*(-Laplacian) 7-point, Dirichlet, + diag(V)  */
-  PLHR_OP_DIAG = 3    /* diag(d), d in `potential`: a lumped mass for B    */
+  PLHR_OP_DIAG = 3,   /* diag(d), d in `potential`: a lumped mass for B    */
+  PLHR_OP_Q1_2D = 4,  /* scale*K, bilinear elements, Dirichlet, + diag(V)  */
+  PLHR_OP_Q1_3D = 5,  /* scale*K, trilinear elements, Dirichlet, + diag(V) */
+  PLHR_OP_Q1_MASS = 6 /* consistent mass M of the Q1 elements of A (B only) */
 } plhr_op_kind;
 
 typedef enum { PLHR_F64 = 0 } plhr_dtype;
@@ -69,7 +72,18 @@ typedef enum { PLHR_F64 = 0 } plhr_dtype;
  *              for PLHR_OP_DIAG the diagonal itself (not NULL)
  * A PLHR_OP_DIAG descriptor is used only as B: its nx, ny, nz must be
  * those of A and every diagonal entry positive and finite (checked at
- * plhr_create, PLHR_ERR_ARG otherwise); h and scale are ignored.       */
+ * plhr_create, PLHR_ERR_ARG otherwise); h and scale are ignored.
+ * PLHR_OP_Q1_2D/3D (the finite-element model problem of Section 6.1):
+ * stiffness K of bilinear/trilinear elements of size h on a uniform mesh
+ * with Dirichlet boundary, unknowns at the interior nodes (nx = elements
+ * per side - 1), K = sum over directions of the tensor products of the
+ * 1-D matrices (1/h)[-1 2 -1] and (h/6)[1 4 1]; the potential adds to
+ * the diagonal as given (pass m_x V_x for a lumped-mass potential).
+ * PLHR_OP_Q1_MASS is used only as B with a Q1 A (whose grid and h it
+ * takes; its own fields are ignored): the consistent mass, the tensor
+ * product of (h/6)[1 4 1].  A preconditioner with a Q1 A is the V-cycle
+ * of the finite-difference Laplacian on the same nodes (spectrally
+ * equivalent to K; T's scale does not change the iteration).           */
 typedef struct {
   int32_t kind;
   int32_t dtype;
@@ -170,8 +184,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
  * (Algorithm 3 for these real operators).
  *   A          host descriptor of A (FD5_2D or FD7_3D)
  *   B          host descriptor of B: NULL or PLHR_OP_IDENTITY for the
- *              identity, or PLHR_OP_DIAG for a positive diagonal B (the
- *              diagonal is read once at create and must stay allocated)
+ *              identity, PLHR_OP_DIAG for a positive diagonal B with a
+ *              finite-difference A (the diagonal is read once at create
+ *              and must stay allocated), or PLHR_OP_Q1_MASS with a Q1 A
  *   T          host descriptor of the HPD preconditioner, or NULL for I
  *   sigma      finite real shift
  *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n; a trial

@@ -17,7 +17,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOT_HPD, ERR_BREAKDOWN, ERR_NOT_CONVE
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_HPD",
                 5: "ERR_BREAKDOWN", 6: "ERR_NOT_CONVERGED", 7: "ERR_STATE"}
 
-OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG = 0, 1, 2, 3
+OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG, OP_Q1_2D, OP_Q1_3D, OP_Q1_MASS = 0, 1, 2, 3, 4, 5, 6
 F64 = 0
 PREC_IDENTITY, PREC_MG_VCYCLE = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1

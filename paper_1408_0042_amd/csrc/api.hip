@@ -62,10 +62,41 @@ Grid make_grid(const plhr_op_desc* A) {
   g.nx = A->nx;
   g.ny = A->ny;
   g.nz = A->nz;
-  g.dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
+  g.dim = (A->kind == PLHR_OP_FD7_3D || A->kind == PLHR_OP_Q1_3D) ? 3 : 2;
+  g.q1 = (A->kind == PLHR_OP_Q1_2D || A->kind == PLHR_OP_Q1_3D);
   g.h = A->h;
   g.scale = A->scale;
   return g;
+}
+
+// ||A||_1 and ||B||_1 (B = the consistent mass) of the finite-element
+// pencil: largest absolute row sums of the stencils (A is symmetric).
+void q1_norms(const Grid& g, const std::vector<double>& pot, double* nA, double* nB) {
+  const Q1Weights w = q1_weights(g);
+  double ba = 0.0, bb = 0.0;
+  const int zl = (g.dim == 3) ? -1 : 0, zh = (g.dim == 3) ? 1 : 0;
+  for (int l = 0; l < g.nz; ++l)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        const size_t p = (size_t)i + (size_t)g.nx * (j + (size_t)g.ny * l);
+        double ra = 0.0, rb = 0.0;
+        for (int dz = zl; dz <= zh; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              if (i + dx < 0 || i + dx >= g.nx || j + dy < 0 || j + dy >= g.ny || l + dz < 0 ||
+                  l + dz >= g.nz)
+                continue;
+              const int o = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+              double a = w.a[o];
+              if (o == 13 && !pot.empty()) a += pot[p];
+              ra += fabs(a);
+              rb += fabs(w.m[o]);
+            }
+        ba = std::max(ba, ra);
+        bb = std::max(bb, rb);
+      }
+  *nA = ba;
+  *nB = bb;
 }
 
 double exact_norm1(const Grid& g, const std::vector<double>& pot) {
@@ -165,6 +196,10 @@ struct plhr_ctx_s {
   // b^-1/2; Rs stages the scaled preconditioner input (n x 2 kint)
   const double* bdiag = nullptr;
   double *bsq = nullptr, *bisq = nullptr, *Rs = nullptr;
+  // B = the consistent Q1 mass (a stencil): B Z carried with Z, QZ, TQZ
+  // through the transform and the updates, fresh B V and B V_final
+  bool bst = false;
+  double *BZ = nullptr, *BVf = nullptr, *BVfin = nullptr;
   int prec_kind = PLHR_PREC_IDENTITY;
   MG mg;
   double sigma = 0.0;
@@ -215,15 +250,17 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("A descriptor is NULL");
     return PLHR_ERR_ARG;
   }
-  if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D) {
-    set_error("A: only PLHR_OP_FD5_2D and PLHR_OP_FD7_3D are supported");
+  if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D && A->kind != PLHR_OP_Q1_2D &&
+      A->kind != PLHR_OP_Q1_3D) {
+    set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D and PLHR_OP_Q1_3D are supported");
     return PLHR_ERR_UNSUPPORTED;
   }
   if (A->dtype != PLHR_F64) {
     set_error("A: only PLHR_F64 is supported");
     return PLHR_ERR_UNSUPPORTED;
   }
-  if (A->nx < 1 || A->ny < 1 || A->nz < 1 || (A->kind == PLHR_OP_FD5_2D && A->nz != 1)) {
+  const bool a2d = (A->kind == PLHR_OP_FD5_2D || A->kind == PLHR_OP_Q1_2D);
+  if (A->nx < 1 || A->ny < 1 || A->nz < 1 || (a2d && A->nz != 1)) {
     set_error("A: grid dimensions must be >= 1 (nz = 1 in 2-D)");
     return PLHR_ERR_ARG;
   }
@@ -232,15 +269,24 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     return PLHR_ERR_ARG;
   }
   if (B && B->kind != PLHR_OP_IDENTITY) {
-    if (B->kind != PLHR_OP_DIAG) {
-      set_error("B: only the identity and PLHR_OP_DIAG are supported");
+    if (B->kind != PLHR_OP_DIAG && B->kind != PLHR_OP_Q1_MASS) {
+      set_error("B: only the identity, PLHR_OP_DIAG and PLHR_OP_Q1_MASS are supported");
+      return PLHR_ERR_UNSUPPORTED;
+    }
+    const bool aq1 = (A->kind == PLHR_OP_Q1_2D || A->kind == PLHR_OP_Q1_3D);
+    if (B->kind == PLHR_OP_Q1_MASS && !aq1) {
+      set_error("B: PLHR_OP_Q1_MASS needs a finite-element A (PLHR_OP_Q1_2D/3D)");
+      return PLHR_ERR_ARG;
+    }
+    if (B->kind == PLHR_OP_DIAG && aq1) {
+      set_error("B: PLHR_OP_DIAG is supported with a finite-difference A only");
       return PLHR_ERR_UNSUPPORTED;
     }
     if (B->dtype != PLHR_F64) {
       set_error("B: only PLHR_F64 is supported");
       return PLHR_ERR_UNSUPPORTED;
     }
-    if (!B->potential) {
+    if (B->kind == PLHR_OP_DIAG && !B->potential) {
       set_error("B: PLHR_OP_DIAG carries its diagonal in `potential`, which is NULL");
       return PLHR_ERR_ARG;
     }
@@ -289,7 +335,7 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
       return PLHR_ERR_ARG;
     }
     const int f = 1 << (T->levels - 1);
-    const int dim = (A->kind == PLHR_OP_FD7_3D) ? 3 : 2;
+    const int dim = a2d ? 2 : 3;
     if (A->nx % f || A->ny % f || (dim == 3 && A->nz % f)) {
       set_error("T: every grid dimension must be divisible by 2^(levels-1)");
       return PLHR_ERR_ARG;
@@ -304,7 +350,7 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
 }
 
 
-Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag,
+Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag, bool bst,
               plhr_ctx_s* c) {
   Layout L;
   const size_t n = g.n();
@@ -330,6 +376,12 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
     obsq = L.take(n * 8);
     obisq = L.take(n * 8);
     oRs = L.take(n * 2 * kint * 8);
+  }
+  size_t oBZ = 0, oBVf = 0, oBVfin = 0;
+  if (bst) {
+    oBZ = L.take(n * m * 8);
+    oBVf = L.take(n * kint * 8);
+    oBVfin = L.take(n * k * 8);
   }
   size_t omg = L.bytes;
   if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint);
@@ -368,6 +420,11 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
       c->bisq = (double*)(b + obisq);
       c->Rs = (double*)(b + oRs);
     }
+    if (bst) {
+      c->BZ = (double*)(b + oBZ);
+      c->BVf = (double*)(b + oBVf);
+      c->BVfin = (double*)(b + oBVfin);
+    }
     (void)omg;
   }
   return L;
@@ -375,10 +432,16 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
 
 
 
+// (A - shift B)X and its fused outputs; outb (B X) exists only when B is
+// a stencil (the finite-element mass).
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
-             Blk outc, int ncols, double shift, const DevStatus* st) {
-  launch_fd_apply(c->grid, c->pot, c->bisq, shift, X, ldx, out, outr, colshift, c->sigma, outc,
-                  ncols, st, c->stream);
+             Blk outc, int ncols, double shift, const DevStatus* st, Blk outb = Blk{nullptr, 0}) {
+  if (c->grid.q1)
+    launch_q1_apply(c->grid, c->pot, shift, c->bst, X, ldx, out, outr, colshift, c->sigma, outc,
+                    outb, ncols, st, c->stream);
+  else
+    launch_fd_apply(c->grid, c->pot, c->bisq, shift, X, ldx, out, outr, colshift, c->sigma, outc,
+                    ncols, st, c->stream);
 }
 
 // T applied to ncols columns of R (ld ldr); output split at `split`.
@@ -464,23 +527,27 @@ void enqueue_iteration(plhr_ctx_s* c) {
   // must stay consistent with each other (the orthonormalising transform
   // divides by small pivots and would amplify any mismatch into P), so
   // they are refreshed together, every kRefreshT iterations.
+  double* BZ = c->BZ;  // null unless B is a stencil
+  const bool bst = c->bst;
   if (c->host_iter % kRefreshT == kRefreshT - 1) {
-    stencil(c, Z, m, Blk{QZ, m}, none, nullptr, none, kint, c->sigma, st);
+    stencil(c, Z, m, Blk{QZ, m}, none, nullptr, none, kint, c->sigma, st,
+            bst ? Blk{BZ, m} : none);
     precond(c, QZ, m, Blk{TQZ, m}, none, kint, kint, st);
   }
-  stencil(c, Z, m, Blk{c->QVf, kint}, none, nullptr, none, kint, c->sigma, st);
-  int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s);
+  stencil(c, Z, m, Blk{c->QVf, kint}, none, nullptr, none, kint, c->sigma, st,
+          bst ? Blk{c->BVf, kint} : none);
+  int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s, bst ? c->BVf : nullptr, kint);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
   // residuals of the current block, convergence and locking
   nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, R, kint, kint, c->bdiag,
-                         c->part, st,
+                         bst ? c->BVf : nullptr, kint, c->part, st,
                          s);
   launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
   // W = T (A V - B V Lam)
   precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st, true);
   // QW = (A - sigma) W;  R = [QW - W (Lam - sigma) | QW]
   stencil(c, Z + kint, m, Blk{QZ + kint, m}, Blk{R, 2 * kint}, c->sb.lam, Blk{R + kint, 2 * kint},
-          kint, c->sigma, st);
+          kint, c->sigma, st, bst ? Blk{BZ + kint, m} : none);
   // S = T (A W - B W Lam), TQW = T (A - sigma) W
   if (c->opt.precision == PLHR_PREC_MIXED) {
     precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
@@ -489,18 +556,20 @@ void enqueue_iteration(plhr_ctx_s* c) {
     precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, Blk{TQZ + kint, m}, kint, 2 * kint, st);
   }
   // QS = (A - sigma) S ; TQS = T QS
-  stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st);
+  stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st,
+          bst ? Blk{BZ + 2 * kint, m} : none);
   precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
   // B-orthonormalise Z = [V W S P] (Cholesky-QR in slot order)
-  gram(c, Z, m, m, Z, m, m, nullptr, 0, m, c->sb.G, st);
+  gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
   launch_ortho_small(c->sp, c->sb, st, s);
-  double* arrs[3] = {Z, QZ, TQZ};
-  transform(c, arrs, 3, st);
-  // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | Zhat]
-  gram(c, TQZ, m, m, QZ, m, m, Z, m, 2 * m, c->sb.GLR, st);
+  double* arrs[4] = {Z, QZ, TQZ, BZ};
+  const int narr = bst ? 4 : 3;
+  transform(c, arrs, narr, st);
+  // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]
+  gram(c, TQZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
   launch_tharm_small(c->sp, c->sb, st, s);
   // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
-  nb = update(c, arrs, 3, st);
+  nb = update(c, arrs, narr, st);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
   ++c->host_iter;
 }
@@ -568,7 +637,8 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
   }
   const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
-  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, nullptr);
+  const bool bs = B && B->kind == PLHR_OP_Q1_MASS;
+  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, bs, nullptr);
   *ws_bytes = L.bytes;
   return PLHR_OK;
 }
@@ -601,7 +671,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   if (bd) c->bdiag = B->potential;
-  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, nullptr);
+  c->bst = B && B->kind == PLHR_OP_Q1_MASS;
+  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr);
   if (workspace) {
     if (ws_bytes < L.bytes) {
       set_error("workspace smaller than plhr_workspace_size");
@@ -625,7 +696,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     c->own_ws = true;
   }
   c->ws_bytes = L.bytes;
-  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c);
+  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, c);
   // norms for the relative residual
   std::vector<double> pot;
   if (c->pot) {
@@ -639,6 +710,11 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   }
   c->normA1 = exact_norm1(c->grid, pot);
   c->normB1 = 1.0;
+  if (c->grid.q1) {
+    double nb1 = 1.0;
+    q1_norms(c->grid, pot, &c->normA1, &nb1);
+    if (c->bst) c->normB1 = nb1;
+  }
   if (bd) {
     // B = diag(b): b > 0 and finite, ||B||_1 = max b, and the scalings
     std::vector<double> bh(c->n), sq(c->n), isq(c->n);
@@ -720,17 +796,19 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   PLHR_HIP_CHECK(hipMemsetAsync(c->Z, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->QZ, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->TQZ, 0, n * m * sizeof(double), s));
+  if (c->bst) PLHR_HIP_CHECK(hipMemsetAsync(c->BZ, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
   if (c->bdiag)
     launch_rowscale(n, c->bsq, V0, kint, c->Z, m, kint, s);  // u = B^1/2 v
   else
     launch_copy(n, V0, kint, c->Z, m, kint, s);
   const Blk none{nullptr, 0};
-  stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr);
+  stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr,
+          c->bst ? Blk{c->BZ, m} : none);
   precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
-  const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s);
+  const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s, c->bst ? c->BZ : nullptr, m);
   launch_init_lam(c->sp, c->part, nb, c->sb, c->st, s);
-  gram(c, c->Z, m, kint, c->Z, m, kint, nullptr, 0, kint, c->sb.G, nullptr);
+  gram(c, c->Z, m, kint, c->bst ? c->BZ : c->Z, m, kint, nullptr, 0, kint, c->sb.G, nullptr);
   launch_start_check(c->sp, c->sb, c->st, s);
   PLHR_HIP_CHECK(hipGetLastError());
   c->started = true;
@@ -792,18 +870,25 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
   hipStream_t s = c->stream;
   // H = V^T (A - sigma) V, M = V^T V, from a fresh (A - sigma)V
   const Blk none0{nullptr, 0};
-  stencil(c, c->Z, m, Blk{c->QZ, m}, none0, nullptr, none0, kint, c->sigma, nullptr);
+  stencil(c, c->Z, m, Blk{c->QZ, m}, none0, nullptr, none0, kint, c->sigma, nullptr,
+          c->bst ? Blk{c->BZ, m} : none0);
   const int gnb = c->gram_nblk;
-  gram(c, c->Z, m, kint, c->QZ, m, kint, c->Z, m, 2 * kint, c->HM, nullptr);
+  gram(c, c->Z, m, kint, c->QZ, m, kint, c->bst ? c->BZ : c->Z, m, 2 * kint, c->HM, nullptr);
   (void)gnb;
   launch_final_rr(c->sp, c->HM, c->sb, c->st, s);
   launch_small_gemm(n, c->Z, m, kint, c->sb.final_C, k, c->Vfin, k, s);
   const Blk none{nullptr, 0};
-  stencil(c, c->Vfin, k, Blk{c->QVfin, k}, none, nullptr, none, k, c->sigma, nullptr);
+  stencil(c, c->Vfin, k, Blk{c->QVfin, k}, none, nullptr, none, k, c->sigma, nullptr,
+          c->bst ? Blk{c->BVfin, k} : none);
   const int nb = launch_coldots(n, c->Vfin, k, c->QVfin, k, k, c->sb.final_theta, c->sigma,
-                                c->bdiag, c->part, s);
+                                c->bdiag, c->bst ? c->BVfin : nullptr, k, c->part, s);
   SmallParams fp = c->sp;
   launch_final_res(fp, c->part, nb, c->sb, s);
+  if (c->bst) {
+    // v^* B v for the gradient
+    const int nx = launch_xdots(n, c->Vfin, k, c->QVfin, k, k, c->part, s, c->BVfin, k);
+    launch_colsum_first(c->part, nx, k, c->sb.vbv, s);
+  }
   if (c->bdiag) {
     // v^* B v = u^* u for the gradient, then v = B^-1/2 u
     const int nx = launch_xdots(n, c->Vfin, k, c->QVfin, k, k, c->part, s);

@@ -111,6 +111,10 @@ struct Grid {
   int dim = 2;
   double h = 1.0;
   double scale = 1.0;
+  // bilinear/trilinear finite elements (interior nodes, element size h);
+  // the multigrid preconditioner still uses the finite-difference
+  // Laplacian of this grid (diag/off below), a spectrally equivalent HPD T
+  bool q1 = false;
   size_t n() const { return (size_t)nx * ny * nz; }
   double diag() const { return scale * 2.0 * dim / (h * h); }
   double off() const { return -scale / (h * h); }
@@ -131,6 +135,19 @@ struct Blk {
 void launch_fd_apply(const Grid& g, const double* pot, const double* sc, double shift,
                      const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
                      double csub, Blk out_c, int ncols, const DevStatus* st, hipStream_t s);
+
+// Q1 finite elements: stencil weights of scale*K and of M by offset
+// (dz+1)*9 + (dy+1)*3 + (dx+1); out = (A - shift B)X with B = M when
+// bmass (else I); extra outputs as for launch_fd_apply plus out_b = B X;
+// out_r subtracts (B X)(colshift - csub).
+struct Q1Weights {
+  double a[27];
+  double m[27];
+};
+Q1Weights q1_weights(const Grid& g);
+void launch_q1_apply(const Grid& g, const double* pot, double shift, bool bmass, const double* X,
+                     int ldx, Blk out, Blk out_r, const double* colshift, double csub, Blk out_c,
+                     Blk out_b, int ncols, const DevStatus* st, hipStream_t s);
 
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {
@@ -162,9 +179,11 @@ void mg_apply(MG& mg, const double* R, int ldr, Blk out0, Blk out1, int split, i
 // sums of |R|^2 and |V|^2 per column per block written to part
 // (nblk x 2c); with row weights bw != null, of bw.*R^2 and V^2./bw.
 // Returns the number of blocks used.
+// BV != null (ld ldb) replaces V in the shift term: R = QV - BV (lam - sigma).
 int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
                       const double* lam, double sigma, double* R, int ldr, int ncols,
-                      const double* bw, double* part, const DevStatus* st, hipStream_t s);
+                      const double* bw, const double* BV, int ldb, double* part,
+                      const DevStatus* st, hipStream_t s);
 int resid_prep_blocks(size_t n);
 
 // Split-K Gram: out(i, j) = sum_p X[p, i] * Y[p, j] for i < mx, j < my,
@@ -205,12 +224,12 @@ void launch_rowscale(size_t n, const double* w, const double* X, int ldx, double
 
 // column partial sums for final residuals (as launch_resid_prep, no R):
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
-                   const double* lam, double sigma, const double* bw, double* part,
-                   hipStream_t s);
+                   const double* lam, double sigma, const double* bw, const double* BX, int ldb,
+                   double* part, hipStream_t s);
 
-// partial column sums of x.x and x.y (nblk x 2c)
+// partial column sums of x.(Bx) and x.y (nblk x 2c); BX null: B = I
 int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, int ncols,
-                 double* part, hipStream_t s);
+                 double* part, hipStream_t s, const double* BX = nullptr, int ldb = 0);
 
 // Hellmann-Feynman: g[x] (+)= sum_j dl[j] * V[x,j]^2 / vbv[j]
 void launch_hf(size_t n, const double* V, int ldv, int k, const double* dl, const double* vbv,

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
                                                     const double* __restrict__ lam, double sigma,
                                                     double* __restrict__ R, int ldr, int ncols,
                                                     const double* __restrict__ bw,
+                                                    const double* __restrict__ BV, int ldb,
                                                     double* __restrict__ part,
                                                     const DevStatus* st) {
   if (halted(st)) return;
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
     const double sh = lam[c] - sigma;
     for (size_t p = pb + r0; p < pe; p += rpi) {
       const double v = V[p * ldv + c];
-      const double r = QV[p * ldq + c] - v * sh;
+      const double r = QV[p * ldq + c] - (BV ? BV[p * ldb + c] : v) * sh;
       if (R) R[p * ldr + c] = r;
       if (bw) {
         const double b = bw[p];
@@ -76,18 +77,21 @@ __global__ __launch_bounds__(256) void k_resid_prep(size_t n, const double* __re
 
 int launch_resid_prep(size_t n, const double* V, int ldv, const double* QV, int ldq,
                       const double* lam, double sigma, double* R, int ldr, int ncols,
-                      const double* bw, double* part, const DevStatus* st, hipStream_t s) {
+                      const double* bw, const double* BV, int ldb, double* part,
+                      const DevStatus* st, hipStream_t s) {
   prof_begin(KC_VEC, (double)n * ncols * 8.0 * (R ? 3.0 : 2.0) + (bw ? n * 8.0 : 0.0),
              5.0 * n * ncols, s);
   hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, V, ldv, QV, ldq, lam,
-                     sigma, R, ldr, ncols, bw, part, st);
+                     sigma, R, ldr, ncols, bw, BV, ldb, part, st);
   prof_end(KC_VEC, s);
   return kRedBlocks;
 }
 
-// Partial column sums of x.x and x.y (for Rayleigh quotients).
+// Partial column sums of x.(Bx) and x.y (for Rayleigh quotients); BX
+// null means B = I.
 __global__ __launch_bounds__(256) void k_xdots(size_t n, const double* __restrict__ X, int ldx,
-                                               const double* __restrict__ Y, int ldy, int ncols,
+                                               const double* __restrict__ Y, int ldy,
+                                               const double* __restrict__ BX, int ldb, int ncols,
                                                double* __restrict__ part) {
   const int rpi = blockDim.x / ncols;
   const int t = threadIdx.x;
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(256) void k_xdots(size_t n, const double* __restric
     const size_t pe = (pb + chunk < n) ? pb + chunk : n;
     for (size_t p = pb + r0; p < pe; p += rpi) {
       const double x = X[p * ldx + c];
-      acc[0] += x * x;
+      acc[0] += x * (BX ? BX[p * ldb + c] : x);
       acc[1] += x * Y[p * ldy + c];
     }
   }
@@ -108,17 +112,18 @@ __global__ __launch_bounds__(256) void k_xdots(size_t n, const double* __restric
 }
 
 int launch_xdots(size_t n, const double* X, int ldx, const double* Y, int ldy, int ncols,
-                 double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_xdots, dim3(kRedBlocks), dim3(256), 0, s, n, X, ldx, Y, ldy, ncols, part);
+                 double* part, hipStream_t s, const double* BX, int ldb) {
+  hipLaunchKernelGGL(k_xdots, dim3(kRedBlocks), dim3(256), 0, s, n, X, ldx, Y, ldy, BX, ldb,
+                     ncols, part);
   return kRedBlocks;
 }
 
 // Column sums for the final residual check: |QX - X*(lam - sigma)|^2, |X|^2.
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
-                   const double* lam, double sigma, const double* bw, double* part,
-                   hipStream_t s) {
+                   const double* lam, double sigma, const double* bw, const double* BX, int ldb,
+                   double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_resid_prep, dim3(kRedBlocks), dim3(256), 0, s, n, X, ldx, QX, ldq, lam,
-                     sigma, (double*)nullptr, 0, c, bw, part, (const DevStatus*)nullptr);
+                     sigma, (double*)nullptr, 0, c, bw, BX, ldb, part, (const DevStatus*)nullptr);
   return kRedBlocks;
 }
 
@@ -312,9 +317,10 @@ __global__ void k_rowmul(size_t n, ArrPtrs arrs, int narr, int ld, int m, const 
                 if (a == 0) sV[r * kc + col] = v;
                 if (a == 1) {
                   const double vv = sV[r * kc + col];
-                  dacc[0][j] += vv * vv;
+                  if (narr < 4) dacc[0][j] += vv * vv;
                   dacc[1][j] += vv * v;
                 }
+                if (a == 3) dacc[0][j] += sV[r * kc + col] * v;  // v.(Bv)
               } else {
                 X[(p0 + r) * ld + pcol + (col - kc)] = v;
               }

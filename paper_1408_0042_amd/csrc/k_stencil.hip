@@ -99,4 +99,106 @@ void launch_fd_apply(const Grid& g, const double* pot, const double* sc, double 
   prof_end(KC_STENCIL, s);
 }
 
+
+// Bilinear (2-D) / trilinear (3-D) finite elements on a uniform mesh with
+// Dirichlet boundary, interior nodes only: the stiffness and the
+// consistent mass are tensor products of the 1-D element matrices, so
+// both are 9- / 27-point stencils whose weights depend only on the offset
+// (the finite-element model problem of Section 6).  One pass gives
+//   out  = (A - shift B) X,  A = scale K + diag(pot),  B = M (bmass) or I
+//   outb = B X                                  (if outb.ptr)
+//   outr = out - (B X) (colshift - csub)        (if out_r.ptr)
+//   outc = out                                  (if out_c.ptr)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_q1_apply(
+    int nx, int ny, int nz, Q1Weights w, const double* __restrict__ pot, double shift, int bmass,
+    const double* __restrict__ X, int ldx, double* __restrict__ out, int ldo,
+    double* __restrict__ outr, int ldr, const double* __restrict__ colshift, double csub,
+    double* __restrict__ outc, int ldc, double* __restrict__ outb, int ldb, int ncols,
+    const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny;
+  const int l = row / ny;
+  const int nelem = nx * ncols;
+  const size_t rowp = (size_t)row * nx;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ldx;
+  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ldx;
+  const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
+  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
+    const int i = e / ncols;
+    const int c = e - i * ncols;
+    const size_t p = rowp + i;
+    const double* xp = X + p * ldx + c;
+    double ka = 0.0, mb = 0.0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      if (l + dz < 0 || l + dz >= nz) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (j + dy < 0 || j + dy >= ny) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (i + dx < 0 || i + dx >= nx) continue;
+          const int o = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          const double xv = xp[dz * sz + dy * sy + dx * ldx];
+          ka += w.a[o] * xv;
+          mb += w.m[o] * xv;
+        }
+      }
+    }
+    const double xc = xp[0];
+    if (pot) ka += pot[p] * xc;
+    const double bx = bmass ? mb : xc;
+    const double y = ka - shift * bx;
+    out[p * ldo + c] = y;
+    if (outb) outb[p * ldb + c] = bx;
+    if (outr) outr[p * ldr + c] = y - bx * (colshift[c] - csub);
+    if (outc) outc[p * ldc + c] = y;
+  }
+}
+
+Q1Weights q1_weights(const Grid& g) {
+  // 1-D element matrices on interior nodes: K1 = (1/h)[-1 2 -1],
+  // M1 = (h/6)[1 4 1]; K = sum_a M1 x .. x K1(a) x .. x M1, M = M1 x .. x M1
+  const double h = g.h;
+  const double k1[3] = {-1.0 / h, 2.0 / h, -1.0 / h};
+  const double m1[3] = {h / 6.0, 4.0 * h / 6.0, h / 6.0};
+  Q1Weights w{};
+  for (int dz = 0; dz < 3; ++dz)
+    for (int dy = 0; dy < 3; ++dy)
+      for (int dx = 0; dx < 3; ++dx) {
+        const int o = dz * 9 + dy * 3 + dx;
+        if (g.dim == 2) {
+          if (dz != 1) continue;
+          w.a[o] = g.scale * (k1[dx] * m1[dy] + m1[dx] * k1[dy]);
+          w.m[o] = m1[dx] * m1[dy];
+        } else {
+          w.a[o] = g.scale * (k1[dx] * m1[dy] * m1[dz] + m1[dx] * k1[dy] * m1[dz] +
+                              m1[dx] * m1[dy] * k1[dz]);
+          w.m[o] = m1[dx] * m1[dy] * m1[dz];
+        }
+      }
+  return w;
+}
+
+void launch_q1_apply(const Grid& g, const double* pot, double shift, bool bmass, const double* X,
+                     int ldx, Blk out, Blk out_r, const double* colshift, double csub, Blk out_c,
+                     Blk out_b, int ncols, const DevStatus* st, hipStream_t s) {
+  const int rows = g.ny * g.nz;
+  const double nc = (double)g.n() * ncols * 8.0;
+  const int npt = (g.dim == 3) ? 27 : 9;
+  prof_begin(KC_STENCIL,
+             nc * (2 + (out_r.ptr ? 1 : 0) + (out_c.ptr ? 1 : 0) + (out_b.ptr ? 1 : 0)) +
+                 (pot ? g.n() * 8.0 : 0.0),
+             (double)g.n() * ncols * (4.0 * npt + 4.0), s);
+  const Q1Weights w = q1_weights(g);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_q1_apply<3>, dim3(rows), dim3(256), 0, s, g.nx, g.ny, g.nz, w, pot,
+                       shift, (int)bmass, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift,
+                       csub, out_c.ptr, out_c.ld, out_b.ptr, out_b.ld, ncols, st);
+  else
+    hipLaunchKernelGGL(k_q1_apply<2>, dim3(rows), dim3(256), 0, s, g.nx, g.ny, g.nz, w, pot,
+                       shift, (int)bmass, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift,
+                       csub, out_c.ptr, out_c.ld, out_b.ptr, out_b.ld, ncols, st);
+  prof_end(KC_STENCIL, s);
+}
+
 }  // namespace plhr

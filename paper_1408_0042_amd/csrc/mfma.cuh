@@ -135,8 +135,9 @@ __device__ __forceinline__ void gram_body(size_t pb, size_t pe, const double* __
 // mode 1 (Ritz-vector update) with Y (m x kc): the product uses
 //   [Y | Y with rows < kv zeroed]  (kout = 2 kc),
 // columns [0, kc) (new V) go to slots [0, kc), columns [kc, 2kc) (new P)
-// to slots [pcol, pcol + kc); for arrays 0 and 1 the column sums of v*v
-// and v*(Qv) are accumulated into part (nblk x 2kc).
+// to slots [pcol, pcol + kc); the column sums of v*(Bv) and v*(Qv) are
+// accumulated into part (nblk x 2kc): v from array 0, Qv from array 1,
+// Bv from array 3 when there are four arrays (else B = I).
 static constexpr int kMaxKq = (kMaxM + 3) / 4;
 
 // Rows [pbeg, pend) of the arrays (pbeg a multiple of 16; tiles of 16
@@ -235,9 +236,10 @@ __device__ __forceinline__ void rowmul_body(size_t pbeg, size_t pend, size_t fir
           if (a == 0) vkeep[t][r] = v;
           if (a == 1) {
             const double vv = vkeep[t][r];
-            dsum[t][0] += vv * vv;
+            if (narr < 4) dsum[t][0] += vv * vv;
             dsum[t][1] += vv * v;
           }
+          if (a == 3) dsum[t][0] += vkeep[t][r] * v;  // v.(Bv) with B X as array 3
         } else {
           dst[pcol + col - kc] = v;
         }

@@ -41,10 +41,13 @@ class SolveResult:
 class Solver:
     """Block PLHR for the k eigenpairs of A v = lambda B v nearest sigma.
 
-    kind: "fd5_2d" or "fd7_3d"; dims: interior grid points; h: spacing;
-    scale: factor on the negative Laplacian; potential: optional (n,) float64
-    device tensor added to the diagonal; mass: optional (n,) float64 device
-    tensor, positive, the diagonal of B (None: B = I); precond: None (T = I)
+    kind: "fd5_2d", "fd7_3d" (finite differences) or "q1_2d", "q1_3d"
+    (bilinear/trilinear finite elements, interior nodes); dims: interior
+    grid points (nodes); h: spacing (element size); scale: factor on the
+    negative Laplacian (on the stiffness); potential: optional (n,) float64
+    device tensor added to the diagonal; mass: None (B = I), an (n,)
+    float64 positive device tensor (B = diag(mass), finite differences),
+    or "q1" (B = the consistent finite-element mass); precond: None (T = I)
     or a dict {"levels", "nu", "omega"} for the multigrid V-cycle.
     """
 
@@ -66,6 +69,12 @@ class Solver:
         elif kind == "fd7_3d":
             assert len(dims) == 3
             a.kind, a.nx, a.ny, a.nz = L.OP_FD7_3D, dims[0], dims[1], dims[2]
+        elif kind == "q1_2d":
+            assert len(dims) == 2
+            a.kind, a.nx, a.ny, a.nz = L.OP_Q1_2D, dims[0], dims[1], 1
+        elif kind == "q1_3d":
+            assert len(dims) == 3
+            a.kind, a.nx, a.ny, a.nz = L.OP_Q1_3D, dims[0], dims[1], dims[2]
         else:
             raise ValueError(f"unknown operator kind {kind}")
         a.dtype = L.F64
@@ -79,7 +88,14 @@ class Solver:
         self.dims = dims
         self.mass = mass
         bdesc = None
-        if mass is not None:
+        if isinstance(mass, str):
+            if mass != "q1":
+                raise ValueError("mass must be None, a tensor or 'q1'")
+            bdesc = L.OpDesc()
+            bdesc.kind, bdesc.dtype = L.OP_Q1_MASS, L.F64
+            bdesc.nx, bdesc.ny, bdesc.nz = a.nx, a.ny, a.nz
+            bdesc.h, bdesc.scale = a.h, 1.0
+        elif mass is not None:
             _require_cuda(mass, "mass")
             if tuple(mass.shape) != (self.n,):
                 raise ValueError(f"mass must have shape {(self.n,)}")
