@@ -137,6 +137,12 @@ typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
  *   precision    PLHR_PREC_FP64 or PLHR_PREC_MIXED            (FP64)
  *   lock         soft locking of converged columns            (1)
  *   check_every  iterations between host convergence checks   (1)
+ *   ortho_passes Cholesky-QR passes of the B-orthonormalisation of
+ *                [V W S P] per iteration: 0 or 1 for one, 2 for a second
+ *                pass on the result (CholQR2), which restores the
+ *                B-orthogonality a single pass loses when the block is
+ *                ill-conditioned (converged columns without locking) at
+ *                the price of one more Gram and transform       (1)
  *   drop_tol     squared relative norm below which a W/S/P column is
  *                dropped during B-orthonormalisation          (1e-12) */
 typedef struct {
@@ -146,7 +152,7 @@ typedef struct {
   int32_t precision;
   int32_t lock;
   int32_t check_every;
-  int32_t reserved0;
+  int32_t ortho_passes;
   double drop_tol;
 } plhr_options;
 

@@ -37,7 +37,7 @@ class PrecDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("k_extra", C.c_int32),
                 ("precision", C.c_int32), ("lock", C.c_int32), ("check_every", C.c_int32),
-                ("reserved0", C.c_int32), ("drop_tol", C.c_double)]
+                ("ortho_passes", C.c_int32), ("drop_tol", C.c_double)]
 
 
 class IterInfo(C.Structure):

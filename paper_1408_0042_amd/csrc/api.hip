@@ -316,11 +316,11 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
   }
   if (opt) {
     if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
-        !(opt->drop_tol > 0.0) ||
+        !(opt->drop_tol > 0.0) || opt->ortho_passes < 0 || opt->ortho_passes > 2 ||
         (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED)) {
       set_error(
           "invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, "
-          "precision FP64 or MIXED)");
+          "ortho_passes 0..2, precision FP64 or MIXED)");
       return PLHR_ERR_ARG;
     }
   }
@@ -560,11 +560,13 @@ void enqueue_iteration(plhr_ctx_s* c) {
           bst ? Blk{BZ + 2 * kint, m} : none);
   precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
   // B-orthonormalise Z = [V W S P] (Cholesky-QR in slot order)
-  gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-  launch_ortho_small(c->sp, c->sb, st, s);
   double* arrs[4] = {Z, QZ, TQZ, BZ};
   const int narr = bst ? 4 : 3;
-  transform(c, arrs, narr, st);
+  for (int pass = 0; pass < std::max(1, c->opt.ortho_passes); ++pass) {
+    gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
+    launch_ortho_small(c->sp, c->sb, st, s);
+    transform(c, arrs, narr, st);
+  }
   // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]
   gram(c, TQZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
   launch_tharm_small(c->sp, c->sb, st, s);

@@ -56,7 +56,7 @@ class Solver:
                  mass: Optional[torch.Tensor] = None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
-                 drop_tol: float = 1e-12, precision: str = "fp64",
+                 drop_tol: float = 1e-12, precision: str = "fp64", ortho_passes: int = 1,
                  stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
         if not torch.cuda.is_available():
@@ -117,6 +117,7 @@ class Solver:
         o = L.default_options()
         o.tol, o.max_iters, o.k_extra = float(tol), int(max_iters), int(k_extra)
         o.lock, o.check_every, o.drop_tol = int(bool(lock)), int(check_every), float(drop_tol)
+        o.ortho_passes = int(ortho_passes)
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         o.precision = L.PRECISION_MIXED if precision == "mixed" else L.PRECISION_FP64

@@ -127,3 +127,48 @@ def test_fe_backward_matches_dense_gradient_and_finite_differences():
         fd = (hf.loss_and_grad_targets(pairs(pp)[0], targets)[0]
               - hf.loss_and_grad_targets(pairs(pm)[0], targets)[0]) / (2 * eps)
         assert abs(fd - g[x]) <= 1e-6 * max(1.0, np.max(np.abs(g_ref)))
+
+
+def test_fe_first_steps_match_oracle():
+    """Same start block, pencil (K, M) and T: the Rayleigh quotients of the
+    first iterations equal those of the oracle's Algorithm 3."""
+    from oracle import mg, plhr
+    from tests.gpu_util import dev
+    Nel, k, kx = 17, 4, 2
+    n1 = Nel - 1
+    A, M = ops.fe_q1(Nel, 2)
+    u = np.unique(np.round(cf.fe_q1_eigs(Nel, 2), 8))
+    sigma = float(u[4] + 0.4 * (u[5] - u[4]))
+    V0 = wl.start_block(n1 * n1, k + kx, (117, 0))
+    T = mg.VCycle("fd", (n1, n1), 1.0 / Nel, 1.0, 3)
+    o = plhr.BPLHR(plhr.Problem(A=A, B=M, T=T.apply, sigma=sigma), V0, k, real=True, lock=False)
+    S = _solver(kind="q1_2d", dims=(n1, n1), h=1.0 / Nel, sigma=sigma, k=k, k_extra=kx,
+                lock=False, mass="q1", precond={"levels": 3, "nu": 2, "omega": 2 / 3})
+    S.start(dev(V0))
+    lam_g, _ = S.state()
+    assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-12)
+    for it in range(3):
+        o.step()
+        S.iterate(1)
+        lam_g, _ = S.state()
+        assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-8), (it, lam_g, o.lam)
+    S.close()
+
+
+def test_fe_3d_without_locking_converges_with_cholqr2():
+    """The case that drifts without locking after a single Cholesky-QR
+    pass per iteration converges with the second pass (CholQR2)."""
+    from tests.gpu_util import dev, host
+    Nel, k, kx = 9, 6, 3
+    n1 = Nel - 1
+    A, M = ops.fe_q1(Nel, 3)
+    u = np.unique(np.round(cf.fe_q1_eigs(Nel, 3), 8))
+    sigma = float(u[2] + 0.4 * (u[3] - u[2]))
+    lam_b, _ = dense.nearest_pairs(A, M, sigma, k)
+    S = _solver(kind="q1_3d", dims=(n1,) * 3, h=1.0 / Nel, sigma=sigma, k=k, k_extra=kx,
+                tol=1e-10, max_iters=2000, lock=False, mass="q1", ortho_passes=2,
+                precond={"levels": 2, "nu": 2, "omega": 2 / 3})
+    r = S.solve(dev(wl.start_block(n1 ** 3, k + kx, (113, 0))))
+    assert r.converged and r.iters < 200, r.iters
+    assert np.allclose(host(r.eigvals), lam_b, rtol=1e-10)
+    S.close()
