@@ -290,7 +290,7 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
       set_error("B: PLHR_OP_DIAG carries its diagonal in `potential`, which is NULL");
       return PLHR_ERR_ARG;
     }
-    if (B->nx != A->nx || B->ny != A->ny || B->nz != A->nz) {
+    if (B->kind == PLHR_OP_DIAG && (B->nx != A->nx || B->ny != A->ny || B->nz != A->nz)) {
       set_error("B: the grid dimensions must be those of A");
       return PLHR_ERR_ARG;
     }

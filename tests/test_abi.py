@@ -68,3 +68,45 @@ def test_workspace_size_and_validation():
     assert _ws(a, None, 1.0, 20)[0] == 0                  # m = 84, the largest supported
     assert _ws(a, None, 1.0, 21)[0] == L.ERR_UNSUPPORTED  # m = 88: projected problem too large
     assert b"4*(k + k_extra)" in L.load().plhr_last_error()
+
+
+def _ws_b(a, b, k=4, o=None):
+    sz = C.c_size_t()
+    code = L.load().plhr_workspace_size(C.byref(a), C.byref(b) if b is not None else None, None,
+                                        1.0, k, C.byref(o) if o else None, C.byref(sz))
+    return code, sz.value
+
+
+def test_generalized_pencil_descriptors_are_validated_on_the_host():
+    N = 16
+    a = _fd3(N)
+    n, kint = N ** 3, 5
+    base = _ws_b(a, None)
+    assert base[0] == L.OK
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz = L.OP_DIAG, L.F64, N, N, N
+    d.potential = 4096                    # a device address; never read by the size query
+    code, sz = _ws_b(a, d)
+    assert code == L.OK and sz >= base[1] + (2 * n + 2 * n * kint) * 8
+    d.potential = None
+    assert _ws_b(a, d)[0] == L.ERR_ARG     # the diagonal is required
+    d.potential, d.nz = 4096, N - 1
+    assert _ws_b(a, d)[0] == L.ERR_ARG     # grid must match A
+    q = L.OpDesc()
+    q.kind, q.dtype, q.nx, q.ny, q.nz, q.h, q.scale = L.OP_Q1_3D, L.F64, N, N, N, 1 / (N + 1), 1.0
+    mass = L.OpDesc()
+    mass.kind, mass.dtype = L.OP_Q1_MASS, L.F64
+    assert _ws_b(a, mass)[0] == L.ERR_ARG  # the consistent mass needs a Q1 A
+    code, sz = _ws_b(q, mass)
+    q_plain = _ws_b(q, None)
+    assert code == L.OK and sz >= q_plain[1] + (n * 4 * kint + n * kint + n * 4) * 8
+    d.nz = N
+    assert _ws_b(q, d)[0] == L.ERR_UNSUPPORTED   # diagonal B with finite elements
+    q2 = L.OpDesc()
+    q2.kind, q2.dtype, q2.nx, q2.ny, q2.nz, q2.h, q2.scale = L.OP_Q1_2D, L.F64, N, N, 2, 0.1, 1.0
+    assert _ws_b(q2, None)[0] == L.ERR_ARG       # 2-D needs nz = 1
+    o = L.default_options()
+    o.ortho_passes = 3
+    assert _ws_b(a, None, o=o)[0] == L.ERR_ARG
+    o.ortho_passes = 2
+    assert _ws_b(a, None, o=o)[0] == L.OK
