@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--ortho-passes", type=int, default=1,
+                    help="Cholesky-QR passes of the B-orthonormalisation per iteration (2: CholQR2)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first fill and copy this many MiB on the device: kernels of known "
                          "traffic that calibrate the HBM byte counters of a profiler run")
@@ -271,7 +273,7 @@ def main():
         solves with events around the dominant kernel only."""
         solver = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=sigma, k=k, k_extra=kx,
                         tol=1e-8, max_iters=args.max_iters, check_every=args.check_every,
-                        lock=bool(args.lock), precision=precision,
+                        lock=bool(args.lock), precision=precision, ortho_passes=args.ortho_passes,
                         precond={"levels": w.mg_levels, "nu": 2, "omega": 2.0 / 3.0})
         lams = []
 
@@ -350,7 +352,8 @@ def main():
         "config": {"workload": f"fd7_3d {N}^3 Dirichlet Laplacian, B=I, k={k}+{kx}, "
                                f"T=V-cycle({w.mg_levels} levels, 2+2 Jacobi), "
                                f"sigma={sigma:.6f} ({args.shift}), lock={args.lock}",
-                   "n": w.n, "k": k, "k_extra": kx, "precision": primary, "iterations": iters,
+                   "n": w.n, "k": k, "k_extra": kx, "precision": primary,
+                   "ortho_passes": args.ortho_passes, "iterations": iters,
                    "converged": conv, "matches_closed_form": correct},
         "roofline": roof,
         "kernels": kernels,
