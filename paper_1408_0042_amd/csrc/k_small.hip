@@ -25,6 +25,10 @@
 
 namespace plhr {
 
+// rows (or columns) of an m x m matrix, m <= kMaxM, a lane of a 16 x 16
+// thread tile visits with stride 16
+constexpr int kOrthoSpan = (kMaxM + 15) / 16;
+
 __device__ __forceinline__ int slot_valid(int s, int kint, const int* active, int have_p) {
   if (s < kint) return 1;
   const int j = s % kint;
@@ -258,11 +262,22 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     }
     const double ip = 1.0 / piv;
     if (t == 0) rsc[j] = 1.0 / sqrt(piv);
-    for (int i = j + 1 + ty; i < m; i += 16) {
-      if (!valid[i]) continue;
-      const double gji = Gs[j * m + i] * ip;
-      for (int l = i + tx; l < m; l += 16)
-        if (valid[l]) Gs[i * m + l] -= gji * Gs[j * m + l];
+    // rows and columns of slots left out at the start are exact zeros and
+    // stay zero under the update, and a column dropped at step j' is read
+    // by no later step: no per-element test of `valid` is needed
+    const double* gj = Gs + j * m;
+#pragma unroll
+    for (int a = 0; a < kOrthoSpan; ++a) {
+      const int i = j + 1 + ty + 16 * a;
+      if (i < m) {
+        const double gji = gj[i] * ip;
+        double* gi = Gs + i * m;
+#pragma unroll
+        for (int c = 0; c < kOrthoSpan; ++c) {
+          const int l = i + tx + 16 * c;
+          if (l < m) gi[l] -= gji * gj[l];
+        }
+      }
     }
     __syncthreads();
   }
@@ -275,13 +290,31 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   // X = R^-1 by right-looking back substitution over the kept slots, rows
   // unscaled until the end (step i subtracts R[r][i] / R[i][i] times row i
   // from the rows above): one barrier per kept slot
+  // (R is zero in the rows and columns of slots that are not kept, so
+  // their updates subtract zero)
+  __shared__ double dinv[256];
+  for (int i = t; i < m; i += nt) dinv[i] = valid[i] ? 1.0 / Gs[i * m + i] : 0.0;
+  __syncthreads();
   for (int i = m - 1; i >= 0; --i) {
     if (!valid[i]) continue;
-    const double inv = 1.0 / Gs[i * m + i];
-    for (int r = ty; r < i; r += 16) {
-      if (!valid[r]) continue;
-      const double f = Gs[r * m + i] * inv;
-      for (int c = tx; c < m; c += 16) X[r * m + c] -= f * X[i * m + c];
+    const double inv = dinv[i];
+    double xi[kOrthoSpan];
+#pragma unroll
+    for (int c = 0; c < kOrthoSpan; ++c) {
+      const int cc = tx + 16 * c;
+      xi[c] = (cc < m) ? X[i * m + cc] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < kOrthoSpan; ++a) {
+      const int r = ty + 16 * a;
+      if (r < i) {
+        const double f = Gs[r * m + i] * inv;
+#pragma unroll
+        for (int c = 0; c < kOrthoSpan; ++c) {
+          const int cc = tx + 16 * c;
+          if (cc < m) X[r * m + cc] -= f * xi[c];
+        }
+      }
     }
     __syncthreads();
   }
