@@ -1006,10 +1006,33 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   }
   __syncthreads();
   if (t == 0) st->tphase[9] = clock64();
-  // y = L^-T (Q x): Q x first, real parts into the T region (free after
-  // the back substitution), then imaginary parts into the Xre region (free
-  // once the real parts are formed); then L, staged in the Q region (free
-  // after Q x), solves L^T y = Q x for the nsel columns only
+  // Q <- L^-T Q (solve L^T Y = Q), with L staged in the T region (free
+  // after the back substitution); right-looking from the last row, the
+  // rows unscaled until the end (step i subtracts L[i][r] / L[i][i] times
+  // row i from the rows above it): one barrier per row
+  double* Ls = T;
+  for (int e = t; e < n * n; e += kNT) {
+    const int i = e / n, j = e - i * n;
+    Ls[i * ld + j] = L[e];
+    if (i == j) kyc[i] = 1.0 / L[e];
+  }
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const double inv = kyc[i];
+    for (int r = ty; r < i; r += 16) {
+      const double f = Ls[i * ld + r] * inv;
+      for (int c = tx; c < n; c += 16) Q[r * ld + c] -= f * Q[i * ld + c];
+    }
+    __syncthreads();
+  }
+  for (int i = ty; i < n; i += 16) {
+    const double inv = kyc[i];
+    for (int c = tx; c < n; c += 16) Q[i * ld + c] *= inv;
+  }
+  __syncthreads();
+  // y = (L^-T Q) x: real parts into the T region (L is no longer needed),
+  // then imaginary parts into the Xre region (free once the real parts
+  // are formed)
   double* Yre = T;
   double* Yim = Xre;
   for (int e = t; e < n * nsel; e += kNT) {
@@ -1026,51 +1049,6 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
     double sim = 0.0;
     for (int q = 0; q < n; ++q) sim += Q[i * ld + q] * Xim[q * ks + u];
     Yim[i * ks + u] = sim;
-  }
-  __syncthreads();
-  double* Ls = Q;  // L (n x n, row stride ld) in LDS, 1 / L[i][i] in kyc
-  for (int e = t; e < n * n; e += kNT) {
-    const int i = e / n, j = e - i * n;
-    Ls[i * ld + j] = L[e];
-    if (i == j) kyc[i] = 1.0 / L[e];
-  }
-  // the (at most two) output columns of this lane, nsel <= kint <= 32
-  static_assert(kMaxM / 4 <= 32, "two columns per lane");
-  const int u0 = (tx < nsel) ? selcol[order[tx]] : -1;
-  const int u1 = (tx + 16 < nsel) ? selcol[order[tx + 16]] : -1;
-  __syncthreads();
-  // right-looking from the last row; rows unscaled until the end (step i
-  // subtracts L[i][r] / L[i][i] times row i from the rows above it): one
-  // barrier per row
-  for (int i = n - 1; i >= 0; --i) {
-    const double inv = kyc[i];
-    const double yr0 = (u0 >= 0) ? Yre[i * ks + u0] : 0.0;
-    const double yi0 = (u0 >= 0) ? Yim[i * ks + u0] : 0.0;
-    const double yr1 = (u1 >= 0) ? Yre[i * ks + u1] : 0.0;
-    const double yi1 = (u1 >= 0) ? Yim[i * ks + u1] : 0.0;
-    for (int r = ty; r < i; r += 16) {
-      const double f = Ls[i * ld + r] * inv;
-      if (u0 >= 0) {
-        Yre[r * ks + u0] -= f * yr0;
-        Yim[r * ks + u0] -= f * yi0;
-      }
-      if (u1 >= 0) {
-        Yre[r * ks + u1] -= f * yr1;
-        Yim[r * ks + u1] -= f * yi1;
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = ty; i < n; i += 16) {
-    const double inv = kyc[i];
-    if (u0 >= 0) {
-      Yre[i * ks + u0] *= inv;
-      Yim[i * ks + u0] *= inv;
-    }
-    if (u1 >= 0) {
-      Yre[i * ks + u1] *= inv;
-      Yim[i * ks + u1] *= inv;
-    }
   }
   for (int e = t; e < m * kint; e += kNT) b.Y[e] = 0.0;
   __syncthreads();
