@@ -80,7 +80,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 80): {"source": "paper_1408_0042_amd/csrc/k_tharm.hip",
-                       "sha256": "64886ac48ff79ea16c8612204945c0dc11755dba1dd5afc17ac6ec1090c0af12",
+                       "sha256": "15160822d3081480bc6ce130718c039a99b4641d68e4efa83778842e71152f0c",
                        "fetch_kib": 60.3125, "write_kib": 101.09375},
 }
 
