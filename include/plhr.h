@@ -56,7 +56,8 @@ typedef enum {
   PLHR_OP_DIAG = 3,   /* diag(d), d in `potential`: a lumped mass for B    */
   PLHR_OP_Q1_2D = 4,  /* scale*K, bilinear elements, Dirichlet, + diag(V)  */
   PLHR_OP_Q1_3D = 5,  /* scale*K, trilinear elements, Dirichlet, + diag(V) */
-  PLHR_OP_Q1_MASS = 6 /* consistent mass M of the Q1 elements of A (B only) */
+  PLHR_OP_Q1_MASS = 6, /* consistent mass M of the Q1 elements of A (B only) */
+  PLHR_OP_CSR = 7      /* general sparse symmetric matrix (CSR), A or B     */
 } plhr_op_kind;
 
 typedef enum { PLHR_F64 = 0 } plhr_dtype;
@@ -83,7 +84,11 @@ typedef enum { PLHR_F64 = 0 } plhr_dtype;
  * takes; its own fields are ignored): the consistent mass, the tensor
  * product of (h/6)[1 4 1].  A preconditioner with a Q1 A is the V-cycle
  * of the finite-difference Laplacian on the same nodes (spectrally
- * equivalent to K; T's scale does not change the iteration).           */
+ * equivalent to K; T's scale does not change the iteration).
+ * PLHR_OP_CSR: any sparse symmetric A (the potential, if given, adds to
+ * its diagonal) and, as B, any sparse symmetric positive definite matrix
+ * of the same n; with a CSR operator T must be the identity (the
+ * multigrid preconditioner needs a grid).                              */
 typedef struct {
   int32_t kind;
   int32_t dtype;
@@ -92,6 +97,14 @@ typedef struct {
   double h;
   double scale;
   const double* potential;
+  /* PLHR_OP_CSR only (device arrays, caller-owned, read at create and by
+   * every product): n = nx rows (ny = nz = 1), row i holds the entries
+   * values[row_ptr[i] .. row_ptr[i+1]) in columns col_idx[..]; the matrix
+   * must be symmetric (B also positive definite); nnz = row_ptr[n].   */
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+  int64_t nnz;
 } plhr_op_desc;
 
 /* Preconditioner kinds (Section 5: T must be Hermitian positive definite). */

@@ -17,7 +17,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOT_HPD, ERR_BREAKDOWN, ERR_NOT_CONVE
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_HPD",
                 5: "ERR_BREAKDOWN", 6: "ERR_NOT_CONVERGED", 7: "ERR_STATE"}
 
-OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG, OP_Q1_2D, OP_Q1_3D, OP_Q1_MASS = 0, 1, 2, 3, 4, 5, 6
+OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG, OP_Q1_2D, OP_Q1_3D, OP_Q1_MASS, OP_CSR = 0, 1, 2, 3, 4, 5, 6, 7
 F64 = 0
 PREC_IDENTITY, PREC_MG_VCYCLE = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
@@ -26,7 +26,8 @@ PRECISION_FP64, PRECISION_MIXED = 0, 1
 class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nz", C.c_int32), ("reserved0", C.c_int32), ("h", C.c_double),
-                ("scale", C.c_double), ("potential", C.c_void_p)]
+                ("scale", C.c_double), ("potential", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("values", C.c_void_p), ("nnz", C.c_int64)]
 
 
 class PrecDesc(C.Structure):

@@ -62,6 +62,10 @@ Grid make_grid(const plhr_op_desc* A) {
   g.nx = A->nx;
   g.ny = A->ny;
   g.nz = A->nz;
+  if (A->kind == PLHR_OP_CSR) {  // no grid: n = nx rows
+    g.ny = g.nz = 1;
+    return g;
+  }
   g.dim = (A->kind == PLHR_OP_FD7_3D || A->kind == PLHR_OP_Q1_3D) ? 3 : 2;
   g.q1 = (A->kind == PLHR_OP_Q1_2D || A->kind == PLHR_OP_Q1_3D);
   g.h = A->h;
@@ -97,6 +101,41 @@ void q1_norms(const Grid& g, const std::vector<double>& pot, double* nA, double*
       }
   *nA = ba;
   *nB = bb;
+}
+
+// Largest absolute row sum of a symmetric CSR matrix (its 1-norm), the
+// potential added to the diagonal; the arrays are read from the device.
+plhr_status csr_norm1(const plhr_op_desc* M, const std::vector<double>& pot, double* out) {
+  const int n = M->nx;
+  std::vector<int32_t> rp(n + 1);
+  if (hipMemcpy(rp.data(), M->row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return PLHR_ERR_HIP;
+  const long long nnz = rp[n];
+  if (rp[0] != 0 || nnz != M->nnz || nnz < 0) return PLHR_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return PLHR_ERR_ARG;
+  std::vector<int32_t> ci(nnz > 0 ? nnz : 1);
+  std::vector<double> v(nnz > 0 ? nnz : 1);
+  if (nnz > 0 &&
+      (hipMemcpy(ci.data(), M->col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+           hipSuccess ||
+       hipMemcpy(v.data(), M->values, nnz * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+    return PLHR_ERR_HIP;
+  double best = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = 0.0, d = pot.empty() ? 0.0 : pot[i];
+    for (long long q = rp[i]; q < rp[i + 1]; ++q) {
+      if (ci[q] < 0 || ci[q] >= n || !std::isfinite(v[q])) return PLHR_ERR_ARG;
+      if (ci[q] == i)
+        d += v[q];
+      else
+        r += fabs(v[q]);
+    }
+    best = std::max(best, r + fabs(d));
+  }
+  *out = best;
+  return PLHR_OK;
 }
 
 double exact_norm1(const Grid& g, const std::vector<double>& pot) {
@@ -200,6 +239,9 @@ struct plhr_ctx_s {
   // through the transform and the updates, fresh B V and B V_final
   bool bst = false;
   double *BZ = nullptr, *BVf = nullptr, *BVfin = nullptr;
+  // general sparse operators (A, and B when it is CSR)
+  bool csr = false;
+  CsrMat Acsr{}, Bcsr{};
   int prec_kind = PLHR_PREC_IDENTITY;
   MG mg;
   double sigma = 0.0;
@@ -251,9 +293,16 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     return PLHR_ERR_ARG;
   }
   if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D && A->kind != PLHR_OP_Q1_2D &&
-      A->kind != PLHR_OP_Q1_3D) {
-    set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D and PLHR_OP_Q1_3D are supported");
+      A->kind != PLHR_OP_Q1_3D && A->kind != PLHR_OP_CSR) {
+    set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D, PLHR_OP_Q1_3D and "
+              "PLHR_OP_CSR are supported");
     return PLHR_ERR_UNSUPPORTED;
+  }
+  const bool acsr = (A->kind == PLHR_OP_CSR);
+  if (acsr && (!A->row_ptr || !A->col_idx || !A->values || A->nnz < 0 || A->nx < 1 ||
+               A->ny != 1 || A->nz != 1)) {
+    set_error("A: PLHR_OP_CSR needs row_ptr, col_idx, values, nnz >= 0 and n = nx (ny = nz = 1)");
+    return PLHR_ERR_ARG;
   }
   if (A->dtype != PLHR_F64) {
     set_error("A: only PLHR_F64 is supported");
@@ -264,13 +313,23 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("A: grid dimensions must be >= 1 (nz = 1 in 2-D)");
     return PLHR_ERR_ARG;
   }
-  if (!(A->h > 0.0) || !std::isfinite(A->h) || !(A->scale > 0.0) || !std::isfinite(A->scale)) {
+  if (!acsr && (!(A->h > 0.0) || !std::isfinite(A->h) || !(A->scale > 0.0) ||
+                !std::isfinite(A->scale))) {
     set_error("A: h and scale must be positive and finite");
     return PLHR_ERR_ARG;
   }
   if (B && B->kind != PLHR_OP_IDENTITY) {
-    if (B->kind != PLHR_OP_DIAG && B->kind != PLHR_OP_Q1_MASS) {
-      set_error("B: only the identity, PLHR_OP_DIAG and PLHR_OP_Q1_MASS are supported");
+    if (B->kind != PLHR_OP_DIAG && B->kind != PLHR_OP_Q1_MASS && B->kind != PLHR_OP_CSR) {
+      set_error("B: only the identity, PLHR_OP_DIAG, PLHR_OP_Q1_MASS and PLHR_OP_CSR are supported");
+      return PLHR_ERR_UNSUPPORTED;
+    }
+    if (B->kind == PLHR_OP_CSR &&
+        (!acsr || !B->row_ptr || !B->col_idx || !B->values || B->nnz < 0 || B->nx != A->nx)) {
+      set_error("B: PLHR_OP_CSR needs a CSR A of the same n and its row_ptr, col_idx, values");
+      return PLHR_ERR_ARG;
+    }
+    if (acsr && B->kind != PLHR_OP_CSR) {
+      set_error("B: with a CSR A, B must be the identity or CSR");
       return PLHR_ERR_UNSUPPORTED;
     }
     const bool aq1 = (A->kind == PLHR_OP_Q1_2D || A->kind == PLHR_OP_Q1_3D);
@@ -328,6 +387,10 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     if (T->kind != PLHR_PREC_MG_VCYCLE) {
       set_error("T: unknown preconditioner kind");
       return PLHR_ERR_ARG;
+    }
+    if (acsr) {
+      set_error("T: the multigrid V-cycle needs a grid operator; use the identity with CSR");
+      return PLHR_ERR_UNSUPPORTED;
     }
     if (T->levels < 1 || T->nu_pre < 1 || T->nu_pre != T->nu_post || !(T->omega > 0.0) ||
         T->omega > 1.0) {
@@ -436,7 +499,10 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
 // a stencil (the finite-element mass).
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
              Blk outc, int ncols, double shift, const DevStatus* st, Blk outb = Blk{nullptr, 0}) {
-  if (c->grid.q1)
+  if (c->csr)
+    launch_csr_apply((int)c->n, c->Acsr, c->Bcsr, c->pot, shift, X, ldx, out, outr, colshift,
+                     c->sigma, outc, outb, ncols, st, c->stream);
+  else if (c->grid.q1)
     launch_q1_apply(c->grid, c->pot, shift, c->bst, X, ldx, out, outr, colshift, c->sigma, outc,
                     outb, ncols, st, c->stream);
   else
@@ -639,7 +705,7 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
   }
   const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
-  const bool bs = B && B->kind == PLHR_OP_Q1_MASS;
+  const bool bs = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
   Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, bs, nullptr);
   *ws_bytes = L.bytes;
   return PLHR_OK;
@@ -673,7 +739,11 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   if (bd) c->bdiag = B->potential;
-  c->bst = B && B->kind == PLHR_OP_Q1_MASS;
+  c->bst = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
+  c->csr = (A->kind == PLHR_OP_CSR);
+  if (c->csr) c->Acsr = CsrMat{A->row_ptr, A->col_idx, A->values, (long long)A->nnz};
+  if (B && B->kind == PLHR_OP_CSR)
+    c->Bcsr = CsrMat{B->row_ptr, B->col_idx, B->values, (long long)B->nnz};
   Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr);
   if (workspace) {
     if (ws_bytes < L.bytes) {
@@ -710,8 +780,19 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
       return PLHR_ERR_HIP;
     }
   }
-  c->normA1 = exact_norm1(c->grid, pot);
+  c->normA1 = c->csr ? 0.0 : exact_norm1(c->grid, pot);
   c->normB1 = 1.0;
+  if (c->csr) {
+    plhr_status e1 = csr_norm1(A, pot, &c->normA1);
+    if (e1 == PLHR_OK && B && B->kind == PLHR_OP_CSR) e1 = csr_norm1(B, {}, &c->normB1);
+    if (e1 != PLHR_OK) {
+      set_error(e1 == PLHR_ERR_HIP ? "reading the CSR arrays failed"
+                                   : "CSR: row_ptr must start at 0, be nondecreasing and end at "
+                                     "nnz; columns in [0, n); finite values");
+      plhr_destroy(c);
+      return e1;
+    }
+  }
   if (c->grid.q1) {
     double nb1 = 1.0;
     q1_norms(c->grid, pot, &c->normA1, &nb1);

@@ -149,6 +149,18 @@ void launch_q1_apply(const Grid& g, const double* pot, double shift, bool bmass,
                      int ldx, Blk out, Blk out_r, const double* colshift, double csub, Blk out_c,
                      Blk out_b, int ncols, const DevStatus* st, hipStream_t s);
 
+// General sparse matrix (CSR, device arrays); row_ptr null means absent.
+struct CsrMat {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+  long long nnz;
+};
+void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot, double shift,
+                      const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
+                      double csub, Blk out_c, Blk out_b, int ncols, const DevStatus* st,
+                      hipStream_t s);
+
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {
   Grid g;

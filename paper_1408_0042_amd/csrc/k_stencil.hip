@@ -201,4 +201,60 @@ void launch_q1_apply(const Grid& g, const double* pot, double shift, bool bmass,
   prof_end(KC_STENCIL, s);
 }
 
+
+// General sparse (CSR) block products on point-major blocks: one thread
+// per (row, column) element; the lanes of one row share its index and
+// value loads, and neighbouring columns of a gathered row of X are
+// contiguous.  out = (A - shift B)X with B the CSR matrix Bm (or I when
+// Bm.row_ptr is null); extra outputs as for the Q1 stencil.
+__global__ __launch_bounds__(256) void k_csr_apply(
+    int n, CsrMat Am, CsrMat Bm, const double* __restrict__ pot, double shift,
+    const double* __restrict__ X, int ldx, double* __restrict__ out, int ldo,
+    double* __restrict__ outr, int ldr, const double* __restrict__ colshift, double csub,
+    double* __restrict__ outc, int ldc, double* __restrict__ outb, int ldb, int ncols,
+    const DevStatus* st) {
+  if (halted(st)) return;
+  const size_t tot = (size_t)n * ncols;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ncols);
+    const int c = (int)(e - (size_t)i * ncols);
+    double ka = 0.0;
+    for (int q = Am.row_ptr[i]; q < Am.row_ptr[i + 1]; ++q)
+      ka += Am.values[q] * X[(size_t)Am.col_idx[q] * ldx + c];
+    const double xc = X[(size_t)i * ldx + c];
+    if (pot) ka += pot[i] * xc;
+    double bx = xc;
+    if (Bm.row_ptr) {
+      bx = 0.0;
+      for (int q = Bm.row_ptr[i]; q < Bm.row_ptr[i + 1]; ++q)
+        bx += Bm.values[q] * X[(size_t)Bm.col_idx[q] * ldx + c];
+    }
+    const double y = ka - shift * bx;
+    out[(size_t)i * ldo + c] = y;
+    if (outb) outb[(size_t)i * ldb + c] = bx;
+    if (outr) outr[(size_t)i * ldr + c] = y - bx * (colshift[c] - csub);
+    if (outc) outc[(size_t)i * ldc + c] = y;
+  }
+}
+
+void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot, double shift,
+                      const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
+                      double csub, Blk out_c, Blk out_b, int ncols, const DevStatus* st,
+                      hipStream_t s) {
+  const double nc = (double)n * ncols * 8.0;
+  const double nnz = (double)A.nnz + (B.row_ptr ? (double)B.nnz : 0.0);
+  prof_begin(KC_STENCIL,
+             nc * (2 + (out_r.ptr ? 1 : 0) + (out_c.ptr ? 1 : 0) + (out_b.ptr ? 1 : 0)) +
+                 nnz * 12.0 + (n + 1.0) * 4.0 * (B.row_ptr ? 2.0 : 1.0) + (pot ? n * 8.0 : 0.0),
+             2.0 * nnz * ncols + 4.0 * (double)n * ncols, s);
+  const size_t tot = (size_t)n * ncols;
+  const size_t want = (tot + 255) / 256;
+  const int nb = (int)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(k_csr_apply, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, n, A, B, pot, shift, X,
+                     ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift, csub, out_c.ptr,
+                     out_c.ld, out_b.ptr, out_b.ld, ncols, st);
+  prof_end(KC_STENCIL, s);
+}
+
 }  // namespace plhr

@@ -20,6 +20,19 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _csr_fields(desc, csr, n: int, name: str):
+    """Fill the CSR fields of an operator descriptor from device tensors."""
+    rp, ci, v = csr
+    _require_cuda(rp, name + " row_ptr", torch.int32)
+    _require_cuda(ci, name + " col_idx", torch.int32)
+    _require_cuda(v, name + " values", torch.float64)
+    if rp.numel() != n + 1 or ci.numel() != v.numel():
+        raise ValueError(f"{name}: row_ptr needs n + 1 entries and col_idx/values nnz each")
+    desc.row_ptr, desc.col_idx, desc.values = rp.data_ptr(), ci.data_ptr(), v.data_ptr()
+    desc.nnz = int(v.numel())
+    return (rp, ci, v)
+
+
 def _require_cuda(t: torch.Tensor, name: str, dtype=torch.float64):
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -49,11 +62,14 @@ class Solver:
     float64 positive device tensor (B = diag(mass), finite differences),
     or "q1" (B = the consistent finite-element mass); precond: None (T = I)
     or a dict {"levels", "nu", "omega"} for the multigrid V-cycle.
+    kind "csr": a general sparse symmetric A given as csr = (row_ptr int32,
+    col_idx int32, values float64) device tensors, dims = (n,); mass may
+    then be a CSR triple for B; T must be the identity.
     """
 
     def __init__(self, kind: str, dims: Sequence[int], h: float, sigma: float, k: int,
                  scale: float = 1.0, potential: Optional[torch.Tensor] = None,
-                 mass: Optional[torch.Tensor] = None,
+                 mass=None, csr=None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
                  drop_tol: float = 1e-12, precision: str = "fp64", ortho_passes: int = 1,
@@ -75,6 +91,10 @@ class Solver:
         elif kind == "q1_3d":
             assert len(dims) == 3
             a.kind, a.nx, a.ny, a.nz = L.OP_Q1_3D, dims[0], dims[1], dims[2]
+        elif kind == "csr":
+            assert len(dims) == 1 and csr is not None
+            a.kind, a.nx, a.ny, a.nz = L.OP_CSR, dims[0], 1, 1
+            self._csr = _csr_fields(a, csr, dims[0], "csr")
         else:
             raise ValueError(f"unknown operator kind {kind}")
         a.dtype = L.F64
@@ -88,7 +108,12 @@ class Solver:
         self.dims = dims
         self.mass = mass
         bdesc = None
-        if isinstance(mass, str):
+        if isinstance(mass, (tuple, list)):
+            bdesc = L.OpDesc()
+            bdesc.kind, bdesc.dtype = L.OP_CSR, L.F64
+            bdesc.nx, bdesc.ny, bdesc.nz = a.nx, 1, 1
+            self._bcsr = _csr_fields(bdesc, mass, a.nx, "mass")
+        elif isinstance(mass, str):
             if mass != "q1":
                 raise ValueError("mass must be None, a tensor or 'q1'")
             bdesc = L.OpDesc()

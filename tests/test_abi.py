@@ -110,3 +110,29 @@ def test_generalized_pencil_descriptors_are_validated_on_the_host():
     assert _ws_b(a, None, o=o)[0] == L.ERR_ARG
     o.ortho_passes = 2
     assert _ws_b(a, None, o=o)[0] == L.OK
+
+
+def test_csr_descriptors_are_validated_on_the_host():
+    n = 4096
+    a = L.OpDesc()
+    a.kind, a.dtype, a.nx, a.ny, a.nz = L.OP_CSR, L.F64, n, 1, 1
+    assert _ws_b(a, None)[0] == L.ERR_ARG              # arrays missing
+    a.row_ptr, a.col_idx, a.values, a.nnz = 4096, 8192, 12288, 7 * n   # device addresses
+    code, sz = _ws_b(a, None)
+    assert code == L.OK and sz >= 3 * n * 4 * 5 * 8
+    t = L.PrecDesc()
+    t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = L.PREC_MG_VCYCLE, 2, 2, 2, 2 / 3
+    sz2 = C.c_size_t()
+    code = L.load().plhr_workspace_size(C.byref(a), None, C.byref(t), 1.0, 4, None,
+                                        C.byref(sz2))
+    assert code == L.ERR_UNSUPPORTED                    # the V-cycle needs a grid
+    b = L.OpDesc()
+    b.kind, b.dtype, b.nx, b.ny, b.nz = L.OP_CSR, L.F64, n, 1, 1
+    b.row_ptr, b.col_idx, b.values, b.nnz = 4096, 8192, 12288, n
+    assert _ws_b(a, b)[0] == L.OK
+    b.nx = n - 1
+    assert _ws_b(a, b)[0] == L.ERR_ARG                  # n must match
+    b.nx = n
+    assert _ws_b(_fd3(16), b)[0] == L.ERR_ARG           # a CSR B needs a CSR A
+    a.ny = 2
+    assert _ws_b(a, None)[0] == L.ERR_ARG               # n = nx rows only
