@@ -29,7 +29,9 @@ throughput and ratio to FP64 go in the `mixed` object.
 
 Printed: one JSON line with the metric, a roofline entry for the kernel
 that takes the most time (HIP events around each of its launches inside
-the timed region), the same figures for every kernel, and the CPU oracle
+the timed region), the same figures for every kernel, the HBM rate of the
+sparse-times-block product (the benchmark operator as a CSR matrix, and
+the same product through the grid stencil) in `spmm`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -157,6 +159,47 @@ def cpu_baseline(w, sigma, k, kx, lock, gpu_iters, budget_s):
                       f"workload, extrapolated to the GPU's {gpu_iters} iterations"}
 
 
+def spmm_leg(w, sigma, k, kx, reps=20):
+    """HBM rate of the sparse-times-block product: (A - sigma I)X for the
+    benchmark operator given as a CSR matrix (no grid), on a block of the
+    iteration's width k + kx, against the grid stencil of the same product.
+    Algorithmic bytes per launch: X read and Y written once, the CSR
+    arrays (8 + 4 bytes per entry, 4 per row pointer) once."""
+    import scipy.sparse as sp
+    import torch
+    import workloads as wl
+    from paper_1408_0042_amd import _lib as L
+    from paper_1408_0042_amd.plhr import Solver
+    N = w.dims[0]
+    one = sp.diags([-np.ones(N - 1), 2.0 * np.ones(N), -np.ones(N - 1)], [-1, 0, 1]) / w.h**2
+    eye = sp.identity(N)
+    A = (sp.kron(sp.kron(eye, eye), one) + sp.kron(sp.kron(eye, one), eye) +
+         sp.kron(sp.kron(one, eye), eye)).tocsr()
+    A.sort_indices()
+    csr = (torch.from_numpy(A.indptr.astype(np.int32)).cuda(),
+           torch.from_numpy(A.indices.astype(np.int32)).cuda(),
+           torch.from_numpy(A.data.astype(np.float64)).cuda())
+    X = torch.from_numpy(wl.start_block(w.n, k + kx, (7, 7))).cuda()
+    cat = L.KCAT_NAMES.index("stencil")
+    out = {}
+    for name, kw in (("csr", dict(kind="csr", dims=(w.n,), h=1.0, csr=csr)),
+                     ("stencil", dict(kind="fd7_3d", dims=w.dims, h=w.h))):
+        S = Solver(sigma=sigma, k=k, k_extra=kx, **kw)
+        S.apply("A-sigma", X)
+        S.profile_start(cat, 4 * reps)
+        for _ in range(reps):
+            S.apply("A-sigma", X)
+        p = S.profile_stop()["stencil"]
+        S.close()
+        gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        out[name] = {"us_per_launch": 1e3 * p["ms"] / p["launches"], "achieved": gbs,
+                     "frac": gbs / HBM_PEAK_GBS,
+                     "algorithmic_per_launch": p["bytes"] / p["launches"]}
+    return {"workload": f"(A - sigma I)X, 7-point Laplacian {N}^3 as CSR "
+                        f"(n {w.n}, nnz {A.nnz}), X n x {k + kx}",
+            "unit": "GB/s", "peak": HBM_PEAK_GBS, "csr": out["csr"], "stencil": out["stencil"]}
+
+
 def run_batched(nb, steps, warmup):
     """The batched leg: nb independent 2-D problems -1/2 Laplacian + V_b
     (Dirichlet, h = 1, grid sizes drawn from {64, 96, 128, 160}, 16
@@ -233,6 +276,7 @@ def main():
     ap.add_argument("--max-iters", type=int, default=5000)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-spmm", action="store_true", help="skip the sparse-times-block leg")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--ortho-passes", type=int, default=1,
@@ -366,6 +410,8 @@ def main():
                         "kernels": {c: v["ms_per_step"] for c, v in other["kernels"].items()}}
     if args.batch > 0:
         out["batched"] = run_batched(args.batch, args.batch_steps, 1)
+    if not args.no_spmm:
+        out["spmm"] = spmm_leg(w, sigma, k, kx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, sigma, k, kx, args.lock, int(np.median(iters)),
                                        args.cpu_budget)

@@ -220,8 +220,9 @@ __global__ __launch_bounds__(256) void k_csr_apply(
     const int i = (int)(e / ncols);
     const int c = (int)(e - (size_t)i * ncols);
     double ka = 0.0;
-    for (int q = Am.row_ptr[i]; q < Am.row_ptr[i + 1]; ++q)
-      ka += Am.values[q] * X[(size_t)Am.col_idx[q] * ldx + c];
+    const int q0 = Am.row_ptr[i], q1 = Am.row_ptr[i + 1];
+#pragma unroll 4
+    for (int q = q0; q < q1; ++q) ka += Am.values[q] * X[(size_t)Am.col_idx[q] * ldx + c];
     const double xc = X[(size_t)i * ldx + c];
     if (pot) ka += pot[i] * xc;
     double bx = xc;
@@ -248,9 +249,11 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
              nc * (2 + (out_r.ptr ? 1 : 0) + (out_c.ptr ? 1 : 0) + (out_b.ptr ? 1 : 0)) +
                  nnz * 12.0 + (n + 1.0) * 4.0 * (B.row_ptr ? 2.0 : 1.0) + (pot ? n * 8.0 : 0.0),
              2.0 * nnz * ncols + 4.0 * (double)n * ncols, s);
+  // one element per lane: the gathers of a lane's row are its only
+  // dependent loads
   const size_t tot = (size_t)n * ncols;
   const size_t want = (tot + 255) / 256;
-  const int nb = (int)(want < 8192 ? want : 8192);
+  const int nb = (int)(want < (size_t)1 << 30 ? want : (size_t)1 << 30);
   hipLaunchKernelGGL(k_csr_apply, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, n, A, B, pot, shift, X,
                      ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift, csub, out_c.ptr,
                      out_c.ld, out_b.ptr, out_b.ld, ncols, st);
