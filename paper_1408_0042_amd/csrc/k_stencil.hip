@@ -70,6 +70,60 @@ __global__ __launch_bounds__(256) void k_fd_apply(
   }
 }
 
+// The same product two columns per lane (16-byte loads and stores) for
+// blocks whose column count, leading dimensions and column offsets are
+// even; the arithmetic of each column is that of k_fd_apply.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fd_apply2(
+    int nx, int ny, int nz, double diag, double off, const double* __restrict__ pot,
+    double shift, const double* __restrict__ X, int ldx, double* __restrict__ out, int ldo,
+    double* __restrict__ outr, int ldr, const double* __restrict__ colshift, double csub,
+    double* __restrict__ outc, int ldc, int ncols, const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny;
+  const int l = row / ny;
+  const int nc2 = ncols / 2;
+  const int nelem = nx * nc2;
+  const size_t rowp = (size_t)row * nx;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ldx;
+  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ldx;
+  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
+    const int i = e / nc2;
+    const int c = 2 * (e - i * nc2);
+    const size_t p = rowp + i;
+    const double* xp = X + p * ldx + c;
+    const double2 xc = *reinterpret_cast<const double2*>(xp);
+    double nbx = 0.0, nby = 0.0;
+    auto add = [&](const double* q) {
+      const double2 v = *reinterpret_cast<const double2*>(q);
+      nbx += v.x;
+      nby += v.y;
+    };
+    if (i > 0) add(xp - ldx);
+    if (i < nx - 1) add(xp + ldx);
+    if (j > 0) add(xp - sy);
+    if (j < ny - 1) add(xp + sy);
+    if (DIM == 3) {
+      if (l > 0) add(xp - sz);
+      if (l < nz - 1) add(xp + sz);
+    }
+    double d = diag - shift;
+    if (pot) d += pot[p];
+    const double yx = d * xc.x + off * nbx;
+    const double yy = d * xc.y + off * nby;
+    *reinterpret_cast<double2*>(out + p * ldo + c) = double2{yx, yy};
+    if (outr)
+      *reinterpret_cast<double2*>(outr + p * ldr + c) =
+          double2{yx - xc.x * (colshift[c] - csub), yy - xc.y * (colshift[c + 1] - csub)};
+    if (outc) *reinterpret_cast<double2*>(outc + p * ldc + c) = double2{yx, yy};
+  }
+}
+
+static bool even16(const void* q, int ld) {
+  return q == nullptr || ((((uintptr_t)q) & 15) == 0 && (ld & 1) == 0);
+}
+
 void launch_fd_apply(const Grid& g, const double* pot, const double* sc, double shift,
                      const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
                      double csub, Blk out_c, int ncols, const DevStatus* st, hipStream_t s) {
@@ -80,6 +134,19 @@ void launch_fd_apply(const Grid& g, const double* pot, const double* sc, double 
              nc * (2 + (out_r.ptr ? 1 : 0) + (out_c.ptr ? 1 : 0)) + (pot ? g.n() * 8.0 : 0.0) +
                  (sc ? g.n() * 8.0 : 0.0),
              (double)g.n() * ncols * (2.0 * g.dim + 3.0 + (sc ? 2.0 * g.dim + 3.0 : 0.0)), s);
+  if (!sc && (ncols & 1) == 0 && even16(X, ldx) && even16(out.ptr, out.ld) &&
+      even16(out_r.ptr, out_r.ld) && even16(out_c.ptr, out_c.ld)) {
+    if (g.dim == 3)
+      hipLaunchKernelGGL(k_fd_apply2<3>, grid, block, 0, s, g.nx, g.ny, g.nz, g.diag(), g.off(),
+                         pot, shift, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift, csub,
+                         out_c.ptr, out_c.ld, ncols, st);
+    else
+      hipLaunchKernelGGL(k_fd_apply2<2>, grid, block, 0, s, g.nx, g.ny, g.nz, g.diag(), g.off(),
+                         pot, shift, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift, csub,
+                         out_c.ptr, out_c.ld, ncols, st);
+    prof_end(KC_STENCIL, s);
+    return;
+  }
 #define PLHR_FD_LAUNCH(D, S)                                                                   \
   hipLaunchKernelGGL((k_fd_apply<D, S>), grid, block, 0, s, g.nx, g.ny, g.nz, g.diag(), g.off(), \
                      pot, sc, shift, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift,     \
