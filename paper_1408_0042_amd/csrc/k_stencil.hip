@@ -306,6 +306,57 @@ __global__ __launch_bounds__(256) void k_csr_apply(
   }
 }
 
+// Two columns per lane (16-byte gathers) when the column count, leading
+// dimensions and column offsets are even; per column the arithmetic of
+// k_csr_apply.
+__global__ __launch_bounds__(256) void k_csr_apply2(
+    int n, CsrMat Am, CsrMat Bm, const double* __restrict__ pot, double shift,
+    const double* __restrict__ X, int ldx, double* __restrict__ out, int ldo,
+    double* __restrict__ outr, int ldr, const double* __restrict__ colshift, double csub,
+    double* __restrict__ outc, int ldc, double* __restrict__ outb, int ldb, int ncols,
+    const DevStatus* st) {
+  if (halted(st)) return;
+  const int nc2 = ncols / 2;
+  const size_t tot = (size_t)n * nc2;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / nc2);
+    const int c = 2 * (int)(e - (size_t)i * nc2);
+    double kx = 0.0, ky = 0.0;
+    const int q0 = Am.row_ptr[i], q1 = Am.row_ptr[i + 1];
+#pragma unroll 4
+    for (int q = q0; q < q1; ++q) {
+      const double a = Am.values[q];
+      const double2 v = *reinterpret_cast<const double2*>(X + (size_t)Am.col_idx[q] * ldx + c);
+      kx += a * v.x;
+      ky += a * v.y;
+    }
+    const double2 xc = *reinterpret_cast<const double2*>(X + (size_t)i * ldx + c);
+    if (pot) {
+      kx += pot[i] * xc.x;
+      ky += pot[i] * xc.y;
+    }
+    double bx = xc.x, by = xc.y;
+    if (Bm.row_ptr) {
+      bx = 0.0;
+      by = 0.0;
+      for (int q = Bm.row_ptr[i]; q < Bm.row_ptr[i + 1]; ++q) {
+        const double b = Bm.values[q];
+        const double2 v = *reinterpret_cast<const double2*>(X + (size_t)Bm.col_idx[q] * ldx + c);
+        bx += b * v.x;
+        by += b * v.y;
+      }
+    }
+    const double yx = kx - shift * bx, yy = ky - shift * by;
+    *reinterpret_cast<double2*>(out + (size_t)i * ldo + c) = double2{yx, yy};
+    if (outb) *reinterpret_cast<double2*>(outb + (size_t)i * ldb + c) = double2{bx, by};
+    if (outr)
+      *reinterpret_cast<double2*>(outr + (size_t)i * ldr + c) =
+          double2{yx - bx * (colshift[c] - csub), yy - by * (colshift[c + 1] - csub)};
+    if (outc) *reinterpret_cast<double2*>(outc + (size_t)i * ldc + c) = double2{yx, yy};
+  }
+}
+
 void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot, double shift,
                       const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
                       double csub, Blk out_c, Blk out_b, int ncols, const DevStatus* st,
@@ -316,6 +367,18 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
              nc * (2 + (out_r.ptr ? 1 : 0) + (out_c.ptr ? 1 : 0) + (out_b.ptr ? 1 : 0)) +
                  nnz * 12.0 + (n + 1.0) * 4.0 * (B.row_ptr ? 2.0 : 1.0) + (pot ? n * 8.0 : 0.0),
              2.0 * nnz * ncols + 4.0 * (double)n * ncols, s);
+  if ((ncols & 1) == 0 && even16(X, ldx) && even16(out.ptr, out.ld) &&
+      even16(out_r.ptr, out_r.ld) && even16(out_c.ptr, out_c.ld) &&
+      even16(out_b.ptr, out_b.ld)) {
+    const size_t tot2 = (size_t)n * (ncols / 2);
+    const size_t want2 = (tot2 + 255) / 256;
+    const int nb2 = (int)(want2 < (size_t)1 << 30 ? want2 : (size_t)1 << 30);
+    hipLaunchKernelGGL(k_csr_apply2, dim3(nb2 > 0 ? nb2 : 1), dim3(256), 0, s, n, A, B, pot,
+                       shift, X, ldx, out.ptr, out.ld, out_r.ptr, out_r.ld, colshift, csub,
+                       out_c.ptr, out_c.ld, out_b.ptr, out_b.ld, ncols, st);
+    prof_end(KC_STENCIL, s);
+    return;
+  }
   // one element per lane: the gathers of a lane's row are its only
   // dependent loads
   const size_t tot = (size_t)n * ncols;
