@@ -41,8 +41,18 @@ __global__ __launch_bounds__(256) void k_gram_reduce8(const double* __restrict__
   const int t = threadIdx.x;
   const int e = blockIdx.x * 32 + (t & 31), g = t >> 5;
   double s = 0.0;
-  if (e < total)
-    for (int q = g; q < nblk; q += 8) s += part[(size_t)q * total + e];
+  if (e < total) {
+    // eight loads in flight, added in the same order as one at a time
+    int q = g;
+    for (; q + 56 < nblk; q += 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + 8 * u) * total + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < nblk; q += 8) s += part[(size_t)q * total + e];
+  }
   red[g][t & 31] = s;
   __syncthreads();
   if (t < 32 && e < total) {

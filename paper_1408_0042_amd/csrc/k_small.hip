@@ -47,8 +47,18 @@ __device__ void sum_partials(const double* __restrict__ part, int nblk, int nv, 
   const int per = nt / nv;           // threads per value
   const int v = t % nv, s = t / nv;
   double acc = 0.0;
-  if (s < per)
-    for (int q = s; q < nblk; q += per) acc += part[(size_t)q * nv + v];
+  if (s < per) {
+    // eight loads in flight, added in the same order as one at a time
+    int q = s;
+    for (; q + 7 * per < nblk; q += 8 * per) {
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = part[(size_t)(q + u * per) * nv + v];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += w[u];
+    }
+    for (; q < nblk; q += per) acc += part[(size_t)q * nv + v];
+  }
   red[t] = acc;
   __syncthreads();
   if (t < nv) {
