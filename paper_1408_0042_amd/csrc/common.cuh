@@ -20,4 +20,40 @@ __device__ __forceinline__ bool halted(const DevStatus* st) {
   return st != nullptr && (st->done | st->error);
 }
 
+// Copy a compact n x n matrix from global memory into LDS with row stride
+// ld, every thread of the workgroup taking elements t, t + nt, ...; eight
+// loads are in flight before the stores, and the (row, column) of an
+// element is advanced incrementally instead of divided out.
+__device__ __forceinline__ void load_square(const double* __restrict__ g, double* s, int n,
+                                            int ld) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int tot = n * n;
+  const int di = nt / n, dj = nt - di * n;
+  int e = t, i = t / n, j = t - (t / n) * n;
+  for (; e + 7 * nt < tot; e += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = g[e + u * nt];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s[i * ld + j] = v[u];
+      i += di;
+      j += dj;
+      if (j >= n) {
+        j -= n;
+        ++i;
+      }
+    }
+  }
+  for (; e < tot; e += nt) {
+    s[i * ld + j] = g[e];
+    i += di;
+    j += dj;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
+  }
+}
+
 }  // namespace plhr

@@ -682,11 +682,8 @@ __device__ void k_tharm_qr_body(SmallParams p, SmallBufs b, DevStatus* st) {
   const double* gQ = b.work + 2 * n * n;
   for (int e = t; e < 2 * (n + 1) * ld; e += kQR) sm[e] = 0.0;
   __syncthreads();
-  for (int e = t; e < n * n; e += kQR) {
-    const int i = e / n, j = e - i * n;
-    H[i * ld + j] = gH[e];
-    Q[i * ld + j] = gQ[e];
-  }
+  load_square(gH, H, n, ld);
+  load_square(gQ, Q, n, ld);
   __syncthreads();
   __shared__ double red[kQR / 64];
   const double hn = block_fro(H, n, ld, red);
@@ -753,11 +750,8 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   int* selcol = rnk + n;
   int* selkind = selcol + n;
   int* order = selkind + n;
-  for (int e = t; e < n * n; e += kNT) {
-    const int i = e / n, j = e - i * n;
-    T[i * ld + j] = b.work[n * n + e];
-    Q[i * ld + j] = b.work[2 * n * n + e];
-  }
+  load_square(b.work + n * n, T, n, ld);
+  load_square(b.work + 2 * n * n, Q, n, ld);
   __syncthreads();
   __shared__ double red[kNT / 64];
   const double hn = block_fro(T, n, ld, red);
@@ -1011,11 +1005,9 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   // rows unscaled until the end (step i subtracts L[i][r] / L[i][i] times
   // row i from the rows above it): one barrier per row
   double* Ls = T;
-  for (int e = t; e < n * n; e += kNT) {
-    const int i = e / n, j = e - i * n;
-    Ls[i * ld + j] = L[e];
-    if (i == j) kyc[i] = 1.0 / L[e];
-  }
+  load_square(L, Ls, n, ld);
+  __syncthreads();
+  for (int i = t; i < n; i += kNT) kyc[i] = 1.0 / Ls[i * ld + i];
   __syncthreads();
   for (int i = n - 1; i >= 0; --i) {
     const double inv = kyc[i];
