@@ -241,12 +241,27 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   }
   if (t == 0) flag = 0;
   __syncthreads();
-  for (int i = ty; i < m; i += 16)
-    for (int j = tx; j < m; j += 16) {
-      const int e = i * m + j;
-      Gs[e] = (valid[i] && valid[j]) ? b.G[e] * d[i] * d[j] : 0.0;
-      X[e] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+  for (int a = 0; a < kOrthoSpan; ++a) {
+    const int i = ty + 16 * a;
+    if (i < m) {
+      double g[kOrthoSpan];
+#pragma unroll
+      for (int q = 0; q < kOrthoSpan; ++q) {  // loads first, then the uses
+        const int j = tx + 16 * q;
+        g[q] = (j < m) ? b.G[i * m + j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kOrthoSpan; ++q) {
+        const int j = tx + 16 * q;
+        if (j < m) {
+          const int e = i * m + j;
+          Gs[e] = (valid[i] && valid[j]) ? g[q] * d[i] * d[j] : 0.0;
+          X[e] = (i == j) ? 1.0 : 0.0;
+        }
+      }
     }
+  }
   if (t < kint && valid[t]) flag = 1;
   __syncthreads();
   if (!flag) {  // every V column vanished

@@ -137,12 +137,35 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   double* bv = u + n;
   double* red = bv + n;
   const int ld2 = 2 * m;
-  for (int i = ty; i < n; i += 16)
-    for (int c = tx; c < n; c += 16) {
-      const int ia = idx[i], ic = idx[c];
-      L[i * ld + c] = 0.5 * (b.GLR[(size_t)ia * ld2 + ic] + b.GLR[(size_t)ic * ld2 + ia]);
-      H[i * ld + c] = b.GLR[(size_t)ia * ld2 + m + ic];
+  // fixed-trip (predicated) loops: every global load of a lane is issued
+  // before the first is used
+  static_assert(kMaxM <= 6 * 16, "six rows and columns per lane");
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const int i = ty + 16 * a;
+    if (i < n) {
+      const int ia = idx[i];
+      double g1[6], g2[6], g3[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int c = tx + 16 * q;
+        if (c < n) {
+          const int ic = idx[c];
+          g1[q] = b.GLR[(size_t)ia * ld2 + ic];
+          g2[q] = b.GLR[(size_t)ic * ld2 + ia];
+          g3[q] = b.GLR[(size_t)ia * ld2 + m + ic];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int c = tx + 16 * q;
+        if (c < n) {
+          L[i * ld + c] = 0.5 * (g1[q] + g2[q]);
+          H[i * ld + c] = g3[q];
+        }
+      }
     }
+  }
   // Cholesky G_L = L L^T.  A pivot in [-1e-10, 1e-15] max diag (G_L
   // singular to rounding: sigma an eigenvalue whose vector lies in span Z,
   // xi = 0) is raised to 1e-15 max diag.  A pivot below -1e-10 max diag
