@@ -778,10 +778,40 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   __syncthreads();
   __shared__ double red[kNT / 64];
   const double hn = block_fro(T, n, ld, red);
-  if (t == 0) {
-    st->tphase[6] = clock64();
-    // eigenvalues tau from the 1x1 and 2x2 blocks; a complex block's
-    // leader is the member with Im tau < 0 (its xi has Im > 0)
+  if (t == 0) st->tphase[6] = clock64();
+  // eigenvalues tau from the 1x1 and 2x2 blocks; a complex block's leader
+  // is the member with Im tau < 0 (its xi has Im > 0).  In the real Schur
+  // form the QR returns no two consecutive subdiagonal entries are
+  // nonzero, so every position classifies itself; the walk from the top
+  // by one lane remains for a form that breaks this.
+  __shared__ int nzsub[kMaxM + 1];
+  for (int q = t; q < n; q += kNT) nzsub[q] = (q + 1 < n && T[(q + 1) * ld + q] != 0.0);
+  __syncthreads();
+  int bad = 0;
+  for (int q = t; q + 1 < n; q += kNT) bad |= (nzsub[q] && nzsub[q + 1]);
+  bad = __syncthreads_or(bad);
+  if (!bad) {
+    for (int q = t; q < n; q += kNT) {
+      if (nzsub[q]) {
+        const double a = T[q * ld + q], bb = T[q * ld + q + 1], c = T[(q + 1) * ld + q],
+                     dd = T[(q + 1) * ld + q + 1];
+        const double pq = 0.5 * (a - dd);
+        const double disc = pq * pq + bb * c;
+        const double mu = 0.5 * (a + dd);
+        const double nu = sqrt(fmax(-disc, 0.0));
+        tre[q] = mu;
+        tim[q] = -nu;
+        tre[q + 1] = mu;
+        tim[q + 1] = nu;
+        unitsz[q] = 2;
+        unitsz[q + 1] = 0;
+      } else if (!(q > 0 && nzsub[q - 1])) {
+        tre[q] = T[q * ld + q];
+        tim[q] = 0.0;
+        unitsz[q] = 1;
+      }
+    }
+  } else if (t == 0) {
     int q = 0;
     while (q < n) {
       if (q + 1 < n && T[(q + 1) * ld + q] != 0.0) {
@@ -841,10 +871,25 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
   }
   __syncthreads();
   __shared__ int nsel_s;
+  // units by rank, and xi by rank for the host (zero past the last unit)
+  int isunit = 0;
+  for (int q = t; q < n; q += kNT)
+    if (unitsz[q]) {
+      order[rnk[q]] = q;
+      ++isunit;
+      const int rk = rnk[q];
+      if (rk < m) {
+        b.xi[rk] = (kya[q] < INFINITY) ? kyb[q] : INFINITY;
+        b.xi[m + rk] = -kyc[q];
+      }
+    }
+  static_assert(kMaxM <= kNT, "one slot per lane");
+  const int nu = __syncthreads_count(isunit);  // isunit is 0 or 1
+  for (int r = nu + t; r < m; r += kNT) {
+    b.xi[r] = 0.0;
+    b.xi[m + r] = 0.0;
+  }
   if (t == 0) {
-    int nu = 0;
-    for (int q = 0; q < n; ++q)
-      if (unitsz[q]) order[rnk[q]] = q, ++nu;
     int cnt = 0, nreal = 0, npair = 0, ntil = 0;
     for (int r = 0; r < nu && cnt < kint; ++r) {
       const int q = order[r];
@@ -895,20 +940,7 @@ __device__ void k_tharm_vectors_body(SmallParams p, SmallBufs b, DevStatus* st) 
         b.kinds[c] = 2;
       }
     }
-    for (int r = 0; r < m; ++r) {
-      b.xi[r] = 0.0;
-      b.xi[m + r] = 0.0;
-    }
-    int r2 = 0;
-    for (int q = 0; q < n; ++q) {
-      if (!unitsz[q]) continue;
-      const int rk = rnk[q];
-      if (rk < m) {
-        b.xi[rk] = (kya[q] < INFINITY) ? kyb[q] : INFINITY;
-        b.xi[m + rk] = -kyc[q];
-      }
-      ++r2;
-    }
+
     st->tphase[7] = clock64();
   }
   __syncthreads();
