@@ -82,8 +82,8 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 80): {"source": "paper_1408_0042_amd/csrc/k_tharm.hip",
-                       "sha256": "15160822d3081480bc6ce130718c039a99b4641d68e4efa83778842e71152f0c",
-                       "fetch_kib": 60.3125, "write_kib": 101.09375},
+                       "sha256": "2b5d7c1e9982a9c3c488c96cbb41edb5db7f62c530fa644c7c87465d9186d03b",
+                       "fetch_kib": 62.0, "write_kib": 101.09375},
 }
 
 
