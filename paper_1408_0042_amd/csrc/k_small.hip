@@ -286,7 +286,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
       continue;
     }
     const double ip = 1.0 / piv;
-    if (t == 0) rsc[j] = 1.0 / sqrt(piv);
+    if (t == 0) rsc[j] = piv;  // 1 / sqrt(pivot) after the loop, by all lanes
     // rows and columns of slots left out at the start are exact zeros and
     // stay zero under the update, and a column dropped at step j' is read
     // by no later step: no per-element test of `valid` is needed
@@ -306,6 +306,8 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     }
     __syncthreads();
   }
+  for (int j = t; j < m; j += nt)
+    if (valid[j]) rsc[j] = 1.0 / sqrt(rsc[j]);
   __syncthreads();
   // R (upper, kept slots only; zero elsewhere) in place
   for (int i = ty; i < m; i += 16)

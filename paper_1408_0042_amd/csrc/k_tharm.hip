@@ -197,16 +197,19 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
     }
     const double pp = fmax(p0, floor_);
     const double inv = 1.0 / pp;
-    if (t == 0) {
-      djj[j] = sqrt(pp);
-      dsc[j] = 1.0 / djj[j];
-    }
+    if (t == 0) djj[j] = pp;  // its square root after the loop, by all lanes
     for (int i = j + 1 + ty; i < n; i += 16) {
       const double lij = L[i * ld + j] * inv;
       for (int c = j + 1 + tx; c <= i; c += 16) L[i * ld + c] -= lij * L[c * ld + j];
     }
     __syncthreads();
   }
+  __syncthreads();
+  for (int j = t; j < n; j += kNT)
+    if (!dead[j]) {
+      djj[j] = sqrt(djj[j]);
+      dsc[j] = 1.0 / djj[j];
+    }
   __syncthreads();
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16) {
