@@ -82,8 +82,8 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 80): {"source": "paper_1408_0042_amd/csrc/k_tharm.hip",
-                       "sha256": "2b5d7c1e9982a9c3c488c96cbb41edb5db7f62c530fa644c7c87465d9186d03b",
-                       "fetch_kib": 62.0, "write_kib": 101.09375},
+                       "sha256": "4e1d7bb777cec5f93ff941eda4e87384f4ba6ca9961334946cd5ec779ff8972f",
+                       "fetch_kib": 61.9375, "write_kib": 101.09375},
 }
 
 

@@ -56,4 +56,23 @@ __device__ __forceinline__ void load_square(const double* __restrict__ g, double
   }
 }
 
+// The reverse: LDS (row stride ld) to a compact n x n matrix in global
+// memory, with the same incremental indexing.
+__device__ __forceinline__ void store_square(const double* s, double* __restrict__ g, int n,
+                                             int ld) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int tot = n * n;
+  const int di = nt / n, dj = nt - di * n;
+  int i = t / n, j = t - (t / n) * n;
+  for (int e = t; e < tot; e += nt) {
+    g[e] = s[i * ld + j];
+    i += di;
+    j += dj;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
+  }
+}
+
 }  // namespace plhr

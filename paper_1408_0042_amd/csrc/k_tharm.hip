@@ -305,10 +305,7 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
   }
   // L (compact n x n) to the work area; its LDS region becomes Q = I
   double* gw = b.work;
-  for (int e = t; e < n * n; e += kNT) {
-    const int i = e / n, j = e - i * n;
-    gw[e] = L[i * ld + j];
-  }
+  store_square(L, gw, n, ld);
   __syncthreads();
   for (int i = ty; i < n; i += 16)
     for (int c = tx; c < n; c += 16) Q[i * ld + c] = (i == c) ? 1.0 : 0.0;
@@ -412,11 +409,8 @@ __device__ void k_tharm_reduce_body(SmallParams p, SmallBufs b, DevStatus* st) {
     __syncthreads();
   }
   // H and Q (n x n each, compact) to the work area after L
-  for (int e = t; e < n * n; e += kNT) {
-    const int i = e / n, j = e - i * n;
-    gw[n * n + e] = H[i * ld + j];
-    gw[2 * n * n + e] = Q[i * ld + j];
-  }
+  store_square(H, gw + n * n, n, ld);
+  store_square(Q, gw + 2 * n * n, n, ld);
   if (t == 0) st->tphase[3] = clock64();
 }
 
@@ -730,11 +724,8 @@ __device__ void k_tharm_qr_body(SmallParams p, SmallBufs b, DevStatus* st) {
   }
   double* oH = b.work + n * n;
   double* oQ = b.work + 2 * n * n;
-  for (int e = t; e < n * n; e += kQR) {
-    const int i = e / n, j = e - i * n;
-    oH[e] = H[i * ld + j];
-    oQ[e] = Q[i * ld + j];
-  }
+  store_square(H, oH, n, ld);
+  store_square(Q, oQ, n, ld);
   if (t == 0) st->tphase[5] = clock64();
 }
 
