@@ -31,7 +31,8 @@ Printed: one JSON line with the metric, a roofline entry for the kernel
 that takes the most time (HIP events around each of its launches inside
 the timed region), the same figures for every kernel, the HBM rate of the
 sparse-times-block product (the benchmark operator as a CSR matrix, and
-the same product through the grid stencil) in `spmm`, and the CPU oracle
+the same product through the grid stencil) in `spmm`, that of the complex
+Bloch-periodic product (96^3, 32 columns) in `bloch`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -200,6 +201,39 @@ def spmm_leg(w, sigma, k, kx, reps=20):
             "unit": "GB/s", "peak": HBM_PEAK_GBS, "csr": out["csr"], "stencil": out["stencil"]}
 
 
+def bloch_leg(N=96, ncols=32, reps=20):
+    """HBM rate of the complex Bloch-periodic block product (plhr_op_apply):
+    (-1/2 Laplacian_theta + V - sigma I)X on the N^3 periodic box, theta =
+    2 pi (0.1, 0.2, 0.3), 64 Gaussian wells, X n x ncols complex128.
+    Algorithmic bytes per launch: X read and Y written once (16 bytes per
+    entry), the potential read once.  HIP events on the stream the
+    product is launched on (torch's current stream)."""
+    import torch
+    import workloads as wl
+    from paper_1408_0042_amd.plhr import bloch_apply
+    n = N ** 3
+    dims = (N, N, N)
+    th = wl.bloch_thetas()
+    pot = torch.from_numpy(wl.periodic_gaussian_potential(N, 64, (3, 1))).cuda()
+    X = torch.from_numpy(wl.start_block(n, ncols, (3, 0), dtype=np.complex128)).cuda()
+    Y = torch.empty_like(X)
+    bloch_apply(X, dims, thetas=th, potential=pot, shift=1.5, out=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bloch_apply(X, dims, thetas=th, potential=pot, shift=1.5, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    alg = 2.0 * n * ncols * 16 + n * 8.0
+    gbs = alg / (us * 1e-6) / 1e9
+    return {"workload": f"(-1/2 Laplacian_theta + V - sigma)X, Bloch-periodic {N}^3 "
+                        f"(n {n}), X n x {ncols} complex128",
+            "unit": "GB/s", "peak": HBM_PEAK_GBS, "us_per_launch": us, "achieved": gbs,
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_per_launch": alg}
+
+
 def run_batched(nb, steps, warmup):
     """The batched leg: nb independent 2-D problems -1/2 Laplacian + V_b
     (Dirichlet, h = 1, grid sizes drawn from {64, 96, 128, 160}, 16
@@ -276,7 +310,7 @@ def main():
     ap.add_argument("--max-iters", type=int, default=5000)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-spmm", action="store_true", help="skip the sparse-times-block leg")
+    ap.add_argument("--no-spmm", action="store_true", help="skip the sparse-times-block and Bloch legs")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--ortho-passes", type=int, default=1,
@@ -412,6 +446,7 @@ def main():
         out["batched"] = run_batched(args.batch, args.batch_steps, 1)
     if not args.no_spmm:
         out["spmm"] = spmm_leg(w, sigma, k, kx)
+        out["bloch"] = bloch_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, sigma, k, kx, args.lock, int(np.median(iters)),
                                        args.cpu_budget)

@@ -57,15 +57,20 @@ typedef enum {
   PLHR_OP_Q1_2D = 4,  /* scale*K, bilinear elements, Dirichlet, + diag(V)  */
   PLHR_OP_Q1_3D = 5,  /* scale*K, trilinear elements, Dirichlet, + diag(V) */
   PLHR_OP_Q1_MASS = 6, /* consistent mass M of the Q1 elements of A (B only) */
-  PLHR_OP_CSR = 7      /* general sparse symmetric matrix (CSR), A or B     */
+  PLHR_OP_CSR = 7,     /* general sparse symmetric matrix (CSR), A or B     */
+  PLHR_OP_BLOCH7_3D = 8 /* scale*(-Laplacian_theta) 7-point, Bloch-periodic,
+                           complex, + diag(V): plhr_op_apply only          */
 } plhr_op_kind;
 
-typedef enum { PLHR_F64 = 0 } plhr_dtype;
+typedef enum {
+  PLHR_F64 = 0, /* real double                                       */
+  PLHR_C128 = 1 /* complex double, interleaved (re, im) per entry    */
+} plhr_dtype;
 
 /* Operator descriptor.  Grid points are numbered x-fastest,
  * p = i + nx*(j + ny*l); a 2-D grid has nz = 1.
  *   kind       one of plhr_op_kind
- *   dtype      PLHR_F64
+ *   dtype      PLHR_F64 (PLHR_C128 for PLHR_OP_BLOCH7_3D)
  *   nx, ny, nz interior points per direction (>= 1)
  *   h          grid spacing (> 0)
  *   scale      factor multiplying the negative discrete Laplacian (> 0)
@@ -105,6 +110,9 @@ typedef struct {
   const int32_t* col_idx;
   const double* values;
   int64_t nnz;
+  /* PLHR_OP_BLOCH7_3D only: the Bloch phase per period in x, y, z (the
+   * quasi-momentum times the box length); the other kinds ignore it.   */
+  double theta[3];
 } plhr_op_desc;
 
 /* Preconditioner kinds (Section 5: T must be Hermitian positive definite). */
@@ -263,6 +271,32 @@ plhr_status plhr_eigvals_backward(plhr_ctx ctx, const double* dL_dlambda, double
  *   X, Y   device, n x ncols doubles, point-major; must not overlap
  *   ncols  1 <= ncols <= 2*(k + k_extra)                                  */
 plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, int32_t ncols);
+
+/* Apply an operator given by its descriptor alone (no context, no
+ * solver state):  Y = (A - shift I) X.
+ * Supported: PLHR_OP_BLOCH7_3D with dtype PLHR_C128, the complex
+ * Hermitian model Hamiltonian of the complex iteration (Algorithm 2,
+ * Section 4) standing in for the periodic Kohn-Sham operators of
+ * Section 6.3 at one quasi-momentum:
+ *   scale * (-Laplacian_theta) + diag(potential) on an nx x ny x nz
+ *   periodic box of spacing h, 7-point stencil; the neighbour across a
+ *   face in direction d is the point at the other end times
+ *   exp(+i theta[d]) going forward, exp(-i theta[d]) going backward.
+ *   A          host descriptor; potential is a device array of n real
+ *              doubles or NULL; h, scale > 0 and theta finite
+ *   shift      real, finite
+ *   X, Y       device, n x ncols complex128 entries (interleaved re, im:
+ *              2*n*ncols doubles), point-major; must not overlap
+ *   ncols      >= 0 (0: nothing is done); nx*ncols < 2^31
+ *   stream     hipStream_t the product is enqueued on (NULL: the null
+ *              stream).  Asynchronous: returns after the launch.
+ * PLHR_ERR_ARG for a NULL or invalid argument, PLHR_ERR_UNSUPPORTED for
+ * any other operator kind or dtype (the real operators are applied
+ * through a context, plhr_apply), PLHR_ERR_HIP if the launch fails.
+ * plhr_create rejects PLHR_OP_BLOCH7_3D (PLHR_ERR_UNSUPPORTED): the
+ * solver runs Algorithm 3, in real arithmetic.                          */
+plhr_status plhr_op_apply(const plhr_op_desc* A, double shift, const void* X, void* Y,
+                          int32_t ncols, void* stream);
 
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)

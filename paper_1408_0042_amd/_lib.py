@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
                 5: "ERR_BREAKDOWN", 6: "ERR_NOT_CONVERGED", 7: "ERR_STATE"}
 
 OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG, OP_Q1_2D, OP_Q1_3D, OP_Q1_MASS, OP_CSR = 0, 1, 2, 3, 4, 5, 6, 7
-F64 = 0
+OP_BLOCH7_3D = 8
+F64, C128 = 0, 1
 PREC_IDENTITY, PREC_MG_VCYCLE = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 
@@ -27,7 +28,8 @@ class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nz", C.c_int32), ("reserved0", C.c_int32), ("h", C.c_double),
                 ("scale", C.c_double), ("potential", C.c_void_p), ("row_ptr", C.c_void_p),
-                ("col_idx", C.c_void_p), ("values", C.c_void_p), ("nnz", C.c_int64)]
+                ("col_idx", C.c_void_p), ("values", C.c_void_p), ("nnz", C.c_int64),
+                ("theta", C.c_double * 3)]
 
 
 class PrecDesc(C.Structure):
@@ -106,6 +108,7 @@ def load() -> C.CDLL:
         "plhr_solve": (C.c_int, [P, P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "plhr_eigvals_backward": (C.c_int, [P, P, P, C.c_int32]),
         "plhr_apply": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
+        "plhr_op_apply": (C.c_int, [C.POINTER(OpDesc), C.c_double, P, P, C.c_int32, P]),
         "plhr_get_state": (C.c_int, [P, C.POINTER(C.c_double), P]),
         "plhr_debug_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
         "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),

@@ -295,7 +295,7 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
   if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D && A->kind != PLHR_OP_Q1_2D &&
       A->kind != PLHR_OP_Q1_3D && A->kind != PLHR_OP_CSR) {
     set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D, PLHR_OP_Q1_3D and "
-              "PLHR_OP_CSR are supported");
+              "PLHR_OP_CSR are supported (PLHR_OP_BLOCH7_3D: plhr_op_apply only)");
     return PLHR_ERR_UNSUPPORTED;
   }
   const bool acsr = (A->kind == PLHR_OP_CSR);
@@ -1156,6 +1156,47 @@ plhr_status plhr_profile_stop(plhr_ctx c, plhr_profile* out) {
     return PLHR_ERR_ARG;
   }
   return prof_stop(c->prof, c->stream, out);
+}
+
+plhr_status plhr_op_apply(const plhr_op_desc* A, double shift, const void* X, void* Y,
+                          int32_t ncols, void* stream) {
+  if (!A || (ncols > 0 && (!X || !Y))) {
+    set_error("plhr_op_apply: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (A->kind != PLHR_OP_BLOCH7_3D || A->dtype != PLHR_C128) {
+    set_error("plhr_op_apply: only PLHR_OP_BLOCH7_3D with PLHR_C128 is supported (the real "
+              "operators are applied through a context, plhr_apply)");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (A->nx < 1 || A->ny < 1 || A->nz < 1 || ncols < 0) {
+    set_error("plhr_op_apply: need nx, ny, nz >= 1 and ncols >= 0");
+    return PLHR_ERR_ARG;
+  }
+  if (!(A->h > 0.0) || !(A->scale > 0.0) || !std::isfinite(A->h) || !std::isfinite(A->scale) ||
+      !std::isfinite(shift) || !std::isfinite(A->theta[0]) || !std::isfinite(A->theta[1]) ||
+      !std::isfinite(A->theta[2])) {
+    set_error("plhr_op_apply: h and scale must be positive and finite, theta and shift finite");
+    return PLHR_ERR_ARG;
+  }
+  if ((int64_t)A->nx * ncols >= (int64_t(1) << 31) ||
+      (int64_t)A->ny * A->nz >= (int64_t(1) << 31)) {
+    set_error("plhr_op_apply: nx*ncols and ny*nz must be below 2^31");
+    return PLHR_ERR_ARG;
+  }
+  if (ncols == 0) return PLHR_OK;
+  const size_t bytes = (size_t)A->nx * A->ny * A->nz * ncols * 16;
+  const char* xb = static_cast<const char*>(X);
+  const char* yb = static_cast<const char*>(Y);
+  if (xb < yb + bytes && yb < xb + bytes) {
+    set_error("plhr_op_apply: X and Y overlap");
+    return PLHR_ERR_ARG;
+  }
+  launch_bloch_apply(A->nx, A->ny, A->nz, A->h, A->scale, A->theta, A->potential, shift,
+                     static_cast<const double*>(X), static_cast<double*>(Y), ncols,
+                     static_cast<hipStream_t>(stream));
+  PLHR_HIP_CHECK(hipGetLastError());
+  return PLHR_OK;
 }
 
 void plhr_destroy(plhr_ctx c) {

@@ -160,6 +160,11 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
                       const double* X, int ldx, Blk out, Blk out_r, const double* colshift,
                       double csub, Blk out_c, Blk out_b, int ncols, const DevStatus* st,
                       hipStream_t s);
+// Y = (scale (-Laplacian_theta) + diag(pot) - shift I) X on a Bloch-periodic
+// box, complex128 blocks (interleaved re, im), n x ncols point-major.
+void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const double* theta,
+                        const double* pot, double shift, const double* X, double* Y, int ncols,
+                        hipStream_t s);
 
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {

@@ -252,6 +252,38 @@ class Solver:
         return np.array(lam[:]), V
 
 
+def bloch_apply(X: torch.Tensor, dims: Sequence[int], h: float = 1.0, thetas=(0.0, 0.0, 0.0),
+                scale: float = 0.5, potential: Optional[torch.Tensor] = None, shift: float = 0.0,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Y = (scale*(-Laplacian_theta) + diag(potential) - shift I) X on the
+    Bloch-periodic nx x ny x nz box (plhr_op_apply), X a complex128 device
+    block (n, ncols), enqueued on torch's current stream."""
+    nx, ny, nz = (tuple(dims) + (1, 1))[:3]
+    n = nx * ny * nz
+    _require_cuda(X, "X", torch.complex128)
+    if X.dim() != 2 or X.shape[0] != n:
+        raise ValueError(f"X must be ({n}, ncols)")
+    if out is None:
+        out = torch.empty_like(X)
+    _require_cuda(out, "out", torch.complex128)
+    if out.shape != X.shape:
+        raise ValueError("out must have the shape of X")
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz = L.OP_BLOCH7_3D, L.C128, nx, ny, nz
+    d.h, d.scale = float(h), float(scale)
+    if potential is not None:
+        _require_cuda(potential, "potential")
+        if potential.numel() != n:
+            raise ValueError(f"potential needs {n} entries")
+        d.potential = potential.data_ptr()
+    d.theta[0], d.theta[1], d.theta[2] = (float(t) for t in thetas)
+    lib = L.load()
+    L.check(lib.plhr_op_apply(C.byref(d), float(shift), C.c_void_p(X.data_ptr()),
+                              C.c_void_p(out.data_ptr()), int(X.shape[1]),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return out
+
+
 def eigvals(potential: torch.Tensor, V0: torch.Tensor, **opts) -> torch.Tensor:
     """Differentiable eigenvalues of scale*(-Laplacian) + diag(potential)
     nearest sigma (opts as for Solver).  backward() returns dL/dpotential

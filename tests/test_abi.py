@@ -136,3 +136,36 @@ def test_csr_descriptors_are_validated_on_the_host():
     assert _ws_b(_fd3(16), b)[0] == L.ERR_ARG           # a CSR B needs a CSR A
     a.ny = 2
     assert _ws_b(a, None)[0] == L.ERR_ARG               # n = nx rows only
+
+
+def test_bloch_op_apply_arguments_are_validated_on_the_host():
+    """plhr_op_apply rejects bad descriptors before any launch; an empty
+    block (ncols = 0) is a valid no-op; the solver does not take the
+    complex operator."""
+    lib = L.load()
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz, d.h, d.scale = L.OP_BLOCH7_3D, L.C128, 8, 8, 8, 1.0, 0.5
+    d.theta[0], d.theta[1], d.theta[2] = 0.6, 1.2, 1.8
+    X, Y = C.c_void_p(4096), C.c_void_p(4096 + 8 ** 3 * 4 * 16)   # device addresses
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 0, None) == L.OK
+    assert lib.plhr_op_apply(None, 0.0, X, Y, 4, None) == L.ERR_ARG
+    assert lib.plhr_op_apply(C.byref(d), 0.0, None, Y, 4, None) == L.ERR_ARG
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, C.c_void_p(4096 + 16), 4, None) == L.ERR_ARG
+    assert lib.plhr_op_apply(C.byref(d), float("nan"), X, Y, 4, None) == L.ERR_ARG
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, -1, None) == L.ERR_ARG
+    d.theta[1] = float("inf")
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 4, None) == L.ERR_ARG
+    d.theta[1] = 1.2
+    d.h = 0.0
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 4, None) == L.ERR_ARG
+    d.h, d.nz = 1.0, 0
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 4, None) == L.ERR_ARG
+    d.nz, d.nx = 8, 1 << 20
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 1 << 12, None) == L.ERR_ARG  # nx*ncols
+    d.nx = 8
+    d.dtype = L.F64
+    assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 4, None) == L.ERR_UNSUPPORTED
+    d.dtype = L.C128
+    assert _ws_b(d, None)[0] == L.ERR_UNSUPPORTED       # Algorithm 3 is real
+    f = _fd3(8)
+    assert lib.plhr_op_apply(C.byref(f), 0.0, X, Y, 4, None) == L.ERR_UNSUPPORTED

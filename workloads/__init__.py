@@ -170,6 +170,34 @@ def gaussian_potential(N: int, ngauss: int, seed: Tuple[int, ...], d: int = 2) -
     return V.ravel()
 
 
+def periodic_gaussian_potential(N: int, ngauss: int, seed: Tuple[int, ...],
+                                d: int = 3) -> np.ndarray:
+    """Sum of negative Gaussians on an N^d periodic box (grid units, points
+    at 0..N-1): depth U(1, 4), width U(0.5, 1.5), centres U[0, N)^d, each
+    coordinate difference taken to its nearest periodic image.  Returned
+    x-fastest, length N^d."""
+    g = rng(*seed)
+    depth = g.uniform(1.0, 4.0, ngauss)
+    width = g.uniform(0.5, 1.5, ngauss)
+    centres = g.uniform(0.0, float(N), (ngauss, d))
+    axes = [np.arange(N, dtype=np.float64)] * d
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")[::-1]   # mesh[0] = x (fastest)
+    V = np.zeros((N,) * d)
+    for a in range(ngauss):
+        r2 = np.zeros((N,) * d)
+        for i in range(d):
+            dx = np.abs(mesh[i] - centres[a, i])
+            dx = np.minimum(dx, N - dx)
+            r2 += dx * dx
+        V -= depth[a] * np.exp(-r2 / (2.0 * width[a] ** 2))
+    return V.ravel()
+
+
+def bloch_thetas() -> Tuple[float, float, float]:
+    """Bloch phases per period of the periodic model: 2 pi (0.1, 0.2, 0.3)."""
+    return (2.0 * math.pi * 0.1, 2.0 * math.pi * 0.2, 2.0 * math.pi * 0.3)
+
+
 def mass_density(N: int, seed: Tuple[int, ...], d: int = 2, contrast: float = 4.0) -> np.ndarray:
     """A positive, smoothly varying diagonal mass b on an N^d grid (a
     membrane or medium of variable density): 1 plus (contrast - 1) times
