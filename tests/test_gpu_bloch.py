@@ -1,9 +1,9 @@
 """Bloch-periodic complex block products (plhr_op_apply) against the
 oracle's sparse Bloch Hamiltonian: element by element on small boxes
-(ragged column counts, one- and two-point directions, potential and
-shift), an empty block, and at the periodic model's full size (96^3,
-32 columns) on sampled rows, face and corner points included, plus
-Hermitian symmetry of the product there."""
+(ragged and wide column counts, one- and two-point directions,
+potential and shift), an empty block, and at the periodic model's full
+size (96^3, 32 columns) on sampled rows, face and corner points
+included, plus Hermitian symmetry of the product there."""
 import numpy as np
 import pytest
 
@@ -25,7 +25,7 @@ def _apply(X, dims, **kw):
 
 @pytest.mark.parametrize("dims,ncols", [((8, 6, 5), 1), ((8, 6, 5), 7), ((12, 10, 9), 33),
                                         ((1, 4, 3), 5), ((2, 2, 2), 3), ((16, 16, 16), 32),
-                                        ((5, 1, 1), 2)])
+                                        ((5, 1, 1), 2), ((160, 3, 2), 12), ((40, 3, 2), 50)])
 def test_bloch_block_product_matches_oracle(dims, ncols):
     n = int(np.prod(dims))
     pot = wl.periodic_gaussian_potential(max(dims), 4, (130, n), d=3)
