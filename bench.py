@@ -32,7 +32,8 @@ that takes the most time (HIP events around each of its launches inside
 the timed region), the same figures for every kernel, the HBM rate of the
 sparse-times-block product (the benchmark operator as a CSR matrix, and
 the same product through the grid stencil) in `spmm`, that of the complex
-Bloch-periodic product (96^3, 32 columns) in `bloch`, and the CPU oracle
+Bloch-periodic product (96^3, 32 columns) and of one V-cycle of its
+Laplacian part in `bloch`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -228,10 +229,40 @@ def bloch_leg(N=96, ncols=32, reps=20):
     us = 1e3 * e0.elapsed_time(e1) / reps
     alg = 2.0 * n * ncols * 16 + n * 8.0
     gbs = alg / (us * 1e-6) / 1e9
-    return {"workload": f"(-1/2 Laplacian_theta + V - sigma)X, Bloch-periodic {N}^3 "
-                        f"(n {n}), X n x {ncols} complex128",
-            "unit": "GB/s", "peak": HBM_PEAK_GBS, "us_per_launch": us, "achieved": gbs,
-            "frac": gbs / HBM_PEAK_GBS, "algorithmic_per_launch": alg}
+    out = {"workload": f"(-1/2 Laplacian_theta + V - sigma)X, Bloch-periodic {N}^3 "
+                       f"(n {n}), X n x {ncols} complex128",
+           "unit": "GB/s", "peak": HBM_PEAK_GBS, "us_per_launch": us, "achieved": gbs,
+           "frac": gbs / HBM_PEAK_GBS, "algorithmic_per_launch": alg}
+    # one V-cycle of the Bloch Laplacian (5 levels, 2+2 sweeps): algorithmic
+    # passes of n_l x ncols complex128 per level: pre-sweeps 2 + 3, residual
+    # 3, restriction 1 + 1/8, prolongation 2 + 1/8, post-sweeps 3 + 3; the
+    # coarsest level reads r and writes x once, and its inverse
+    from paper_1408_0042_amd.plhr import BlochPrecond
+    levels, nu = 5, 2
+    T = BlochPrecond(dims, thetas=th, levels=levels, nu=nu, max_cols=ncols)
+    T.apply(X, out=Y)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        T.apply(X, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    usv = 1e3 * e0.elapsed_time(e1) / reps
+    T.close()
+    per_level = (2 + 3 * (nu - 1)) + 3 + 1.125 + 2.125 + 3 * nu
+    algv, nl = 0.0, n
+    for lev in range(levels):
+        algv += (per_level if lev < levels - 1 else 2.0) * nl * ncols * 16
+        if lev == levels - 1:
+            algv += nl * nl * 16.0
+        nl //= 8
+    out["vcycle"] = {"workload": f"one V-cycle of -1/2 Laplacian_theta, {levels} levels "
+                                 f"({N}^3 to {N >> (levels - 1)}^3), {nu}+{nu} Jacobi, "
+                                 f"X n x {ncols} complex128",
+                     "us_per_apply": usv, "achieved": algv / (usv * 1e-6) / 1e9,
+                     "frac": algv / (usv * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_per_apply": algv}
+    return out
 
 
 def run_batched(nb, steps, warmup):

@@ -298,6 +298,45 @@ plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, 
 plhr_status plhr_op_apply(const plhr_op_desc* A, double shift, const void* X, void* Y,
                           int32_t ncols, void* stream);
 
+/* Multigrid preconditioner of the complex Bloch operator (Section 5: T
+ * Hermitian positive definite; Appendix A's V-cycle on the Laplacian part
+ * of the operator), standing alone for the complex iteration.  One V-cycle
+ * applied to a block: every level the same Bloch stencil (spacing 2^l h,
+ * the same phases, no potential), nu_pre weighted-Jacobi sweeps from zero,
+ * the residual restricted by R = P^H / 8, the coarse correction, nu_post
+ * sweeps; P is cell-centred trilinear interpolation (3/4 from the parent,
+ * 1/4 from the parent's neighbour in each direction) and picks up
+ * exp(+/- i theta[d]) across a periodic face; the coarsest level is solved
+ * with the inverse of its dense matrix, formed at create.               */
+typedef struct plhr_bloch_prec_s* plhr_bloch_prec;
+
+/* Create the hierarchy.
+ *   A         host descriptor, PLHR_OP_BLOCH7_3D / PLHR_C128 (potential
+ *             ignored: T acts on the Laplacian part)
+ *   T         host, PLHR_PREC_MG_VCYCLE; levels >= 1, nu_pre == nu_post
+ *             >= 1, 0 < omega <= 1; nx, ny, nz divisible by
+ *             2^(levels - 1); the coarsest grid at most 1024 points
+ *   max_cols  widest block apply will take (>= 1)
+ *   stream    hipStream_t of every apply (NULL: the null stream)
+ * Allocates its level buffers (3 blocks per coarse level, 2 on the finest,
+ * of n_l x max_cols complex128) and the coarse inverse on the current
+ * device; released by plhr_bloch_prec_destroy.
+ * PLHR_ERR_ARG / PLHR_ERR_UNSUPPORTED for bad or unsupported descriptors,
+ * PLHR_ERR_NOT_HPD if the coarsest operator is not positive definite (all
+ * phases zero), PLHR_ERR_HIP if an allocation or copy fails.            */
+plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* T,
+                                   int32_t max_cols, void* stream, plhr_bloch_prec* out);
+
+/* Y = T X, one V-cycle per column, enqueued on the stream given at create
+ * (asynchronous).  X, Y: device, n x ncols complex128 (interleaved),
+ * point-major, not overlapping; 0 <= ncols <= max_cols (0: nothing is
+ * done).  Calls on one handle must not overlap in time (they share its
+ * level buffers).                                                         */
+plhr_status plhr_bloch_prec_apply(plhr_bloch_prec p, const void* X, void* Y, int32_t ncols);
+
+/* Release the hierarchy (after the work enqueued on its stream is done). */
+void plhr_bloch_prec_destroy(plhr_bloch_prec p);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

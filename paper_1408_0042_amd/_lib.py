@@ -109,6 +109,10 @@ def load() -> C.CDLL:
         "plhr_eigvals_backward": (C.c_int, [P, P, P, C.c_int32]),
         "plhr_apply": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
         "plhr_op_apply": (C.c_int, [C.POINTER(OpDesc), C.c_double, P, P, C.c_int32, P]),
+        "plhr_bloch_prec_create": (C.c_int, [C.POINTER(OpDesc), C.POINTER(PrecDesc), C.c_int32,
+                                             P, C.POINTER(P)]),
+        "plhr_bloch_prec_apply": (C.c_int, [P, P, P, C.c_int32]),
+        "plhr_bloch_prec_destroy": (None, [P]),
         "plhr_get_state": (C.c_int, [P, C.POINTER(C.c_double), P]),
         "plhr_debug_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
         "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),

@@ -165,6 +165,20 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
 void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const double* theta,
                         const double* pot, double shift, const double* X, double* Y, int ncols,
                         hipStream_t s);
+// Bloch V-cycle pieces (complex128 blocks, n_l x ncols point-major):
+// out = alpha w + beta (r - A_l w) with A_l the level's Bloch stencil of
+// coefficient cs = scale/h_l^2 (w = NULL: w = 0); rc = P^H res / 8 onto the
+// coarse grid nxc x nyc x nzc; x += P ec on the fine grid nx x ny x nz;
+// x = Ainv r on the coarsest level.
+void launch_bloch_level(int nx, int ny, int nz, double cs, const double* theta, const double* w,
+                        const double* r, double alpha, double beta, double* out, int ncols,
+                        hipStream_t s);
+void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const double* res,
+                           double* rc, int ncols, hipStream_t s);
+void launch_bloch_prolong_add(int nx, int ny, int nz, const double* theta, const double* ec,
+                              double* x, int ncols, hipStream_t s);
+void launch_bloch_dense(int nc, const double* Ainv, const double* r, double* x, int ncols,
+                        hipStream_t s);
 
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {

@@ -284,6 +284,60 @@ def bloch_apply(X: torch.Tensor, dims: Sequence[int], h: float = 1.0, thetas=(0.
     return out
 
 
+class BlochPrecond:
+    """One multigrid V-cycle for the Bloch operator scale*(-Laplacian_theta)
+    on the periodic nx x ny x nz box (plhr_bloch_prec_*): apply(X) returns
+    T X for a complex128 device block (n, ncols), ncols <= max_cols, on
+    torch's current stream at construction."""
+
+    def __init__(self, dims: Sequence[int], h: float = 1.0, thetas=(0.0, 0.0, 0.0),
+                 scale: float = 0.5, levels: int = 3, nu: int = 2, omega: float = 2.0 / 3.0,
+                 max_cols: int = 32):
+        self.lib = L.load()
+        self.handle = None
+        nx, ny, nz = (tuple(dims) + (1, 1))[:3]
+        self.n = nx * ny * nz
+        self.max_cols = int(max_cols)
+        d = L.OpDesc()
+        d.kind, d.dtype, d.nx, d.ny, d.nz = L.OP_BLOCH7_3D, L.C128, nx, ny, nz
+        d.h, d.scale = float(h), float(scale)
+        d.theta[0], d.theta[1], d.theta[2] = (float(t) for t in thetas)
+        t = L.PrecDesc()
+        t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = (L.PREC_MG_VCYCLE, int(levels), int(nu),
+                                                           int(nu), float(omega))
+        hdl = C.c_void_p()
+        self.stream = torch.cuda.current_stream()
+        L.check(self.lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), self.max_cols,
+                                                C.c_void_p(self.stream.cuda_stream),
+                                                C.byref(hdl)))
+        self.handle = hdl
+
+    def apply(self, X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _require_cuda(X, "X", torch.complex128)
+        if X.dim() != 2 or X.shape[0] != self.n:
+            raise ValueError(f"X must be ({self.n}, ncols)")
+        if out is None:
+            out = torch.empty_like(X)
+        _require_cuda(out, "out", torch.complex128)
+        if out.shape != X.shape:
+            raise ValueError("out must have the shape of X")
+        L.check(self.lib.plhr_bloch_prec_apply(self.handle, C.c_void_p(X.data_ptr()),
+                                               C.c_void_p(out.data_ptr()), int(X.shape[1])))
+        return out
+
+    def close(self):
+        if self.handle is not None:
+            self.stream.synchronize()
+            self.lib.plhr_bloch_prec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def eigvals(potential: torch.Tensor, V0: torch.Tensor, **opts) -> torch.Tensor:
     """Differentiable eigenvalues of scale*(-Laplacian) + diag(potential)
     nearest sigma (opts as for Solver).  backward() returns dL/dpotential

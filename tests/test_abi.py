@@ -169,3 +169,36 @@ def test_bloch_op_apply_arguments_are_validated_on_the_host():
     assert _ws_b(d, None)[0] == L.ERR_UNSUPPORTED       # Algorithm 3 is real
     f = _fd3(8)
     assert lib.plhr_op_apply(C.byref(f), 0.0, X, Y, 4, None) == L.ERR_UNSUPPORTED
+
+
+def test_bloch_preconditioner_arguments_are_validated_on_the_host():
+    """plhr_bloch_prec_create checks its descriptors, the coarsening and the
+    positive definiteness of the coarse operator before touching the
+    device: with every phase 0 the constant vector is in the null space."""
+    lib = L.load()
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz, d.h, d.scale = L.OP_BLOCH7_3D, L.C128, 16, 16, 16, 1.0, 0.5
+    t = L.PrecDesc()
+    t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = L.PREC_MG_VCYCLE, 3, 2, 2, 2 / 3
+    h = C.c_void_p()
+
+    def create(cols=8):
+        return lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), cols, None, C.byref(h))
+    assert create() == L.ERR_NOT_HPD                     # theta = 0: singular
+    d.theta[0], d.theta[1], d.theta[2] = 0.6, 1.2, 1.8
+    assert create(0) == L.ERR_ARG                        # max_cols
+    t.nu_post = 1
+    assert create() == L.ERR_ARG                         # T must be Hermitian
+    t.nu_post, t.levels = 2, 6
+    assert create() == L.ERR_ARG                         # 16 not divisible by 32
+    t.levels = 40
+    assert create() == L.ERR_ARG
+    t.levels = 1
+    assert create() == L.ERR_UNSUPPORTED                 # 4096 coarse points
+    t.levels, t.omega = 3, 0.0
+    assert create() == L.ERR_ARG
+    t.omega, t.kind = 2 / 3, L.PREC_IDENTITY
+    assert create() == L.ERR_UNSUPPORTED
+    t.kind, d.dtype = L.PREC_MG_VCYCLE, L.F64
+    assert create() == L.ERR_UNSUPPORTED
+    assert lib.plhr_bloch_prec_apply(None, None, None, 0) == L.ERR_ARG
