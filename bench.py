@@ -32,8 +32,9 @@ that takes the most time (HIP events around each of its launches inside
 the timed region), the same figures for every kernel, the HBM rate of the
 sparse-times-block product (the benchmark operator as a CSR matrix, and
 the same product through the grid stencil) in `spmm`, that of the complex
-Bloch-periodic product (96^3, 32 columns) and of one V-cycle of its
-Laplacian part in `bloch`, and the CPU oracle
+Bloch-periodic product (96^3, 32 columns), of one V-cycle of its
+Laplacian part and the FP64 matrix-core rate of the complex Gram of a
+128-column basis in `bloch`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -262,6 +263,25 @@ def bloch_leg(N=96, ncols=32, reps=20):
                      "us_per_apply": usv, "achieved": algv / (usv * 1e-6) / 1e9,
                      "frac": algv / (usv * 1e-6) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_per_apply": algv}
+    # the Hermitian Gram Z^H Z of a trial basis of m = 4 (k + k_extra) =
+    # 128 complex columns (k = 32) on the matrix cores: 8 n m^2 flops
+    from paper_1408_0042_amd.plhr import gram_c128
+    m = 128
+    del Y
+    Z = torch.from_numpy(wl.start_block(n, m, (3, 4), dtype=np.complex128)).cuda()
+    G = gram_c128(Z)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        gram_c128(Z, out=G)
+    e1.record()
+    torch.cuda.synchronize()
+    usg = 1e3 * e0.elapsed_time(e1) / 5
+    fl = 8.0 * n * m * m
+    out["gram"] = {"workload": f"Z^H Z, Z n x {m} complex128 (n {n})", "unit": "TFLOP/s",
+                   "bound": "mfma", "peak": 78.6, "us_per_launch": usg,
+                   "achieved": fl / (usg * 1e-6) / 1e12,
+                   "frac": fl / (usg * 1e-6) / 1e12 / 78.6, "algorithmic_flops": fl}
     return out
 
 

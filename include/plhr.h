@@ -337,6 +337,24 @@ plhr_status plhr_bloch_prec_apply(plhr_bloch_prec p, const void* X, void* Y, int
 /* Release the hierarchy (after the work enqueued on its stream is done). */
 void plhr_bloch_prec_destroy(plhr_bloch_prec p);
 
+/* Hermitian Gram product G = X^H Y of complex128 blocks on the FP64 matrix
+ * cores: the Gram products of the complex iteration (Z^H B Z of the
+ * orthonormalisation, Section 4; the T-harmonic Grams of eq. (3.5)).
+ *   n        rows, >= 0 (0 gives G = 0)
+ *   X, Y     device, n x mx and n x my complex128 (interleaved re, im),
+ *            point-major; may be the same block
+ *   G        device, mx x my complex128, row-major, overwritten
+ *   1 <= mx, my <= 1024
+ *   workspace device scratch of at least plhr_gram_c128_workspace(n, mx,
+ *            my) bytes, caller-owned, contents not preserved
+ *   stream   hipStream_t (NULL: the null stream); asynchronous
+ * X, Y, G and the workspace must be 16-byte aligned.  The sum over rows
+ * runs in a fixed order (deterministic).  PLHR_ERR_ARG for a NULL,
+ * misaligned or out-of-range argument or a short workspace.              */
+plhr_status plhr_gram_c128_workspace(int64_t n, int32_t mx, int32_t my, size_t* bytes);
+plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, int32_t my,
+                           void* G, void* workspace, size_t ws_bytes, void* stream);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

@@ -296,4 +296,37 @@ plhr_status plhr_bloch_prec_apply(plhr_bloch_prec p, const void* X, void* Y, int
 
 void plhr_bloch_prec_destroy(plhr_bloch_prec p) { delete p; }
 
+plhr_status plhr_gram_c128_workspace(int64_t n, int32_t mx, int32_t my, size_t* bytes) {
+  if (!bytes || n < 0 || mx < 1 || my < 1 || mx > 1024 || my > 1024) {
+    set_error("plhr_gram_c128_workspace: need bytes != NULL, n >= 0, 1 <= mx, my <= 1024");
+    return PLHR_ERR_ARG;
+  }
+  *bytes = cgram_workspace_bytes((size_t)n, mx, my);
+  return PLHR_OK;
+}
+
+plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, int32_t my,
+                           void* G, void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  const plhr_status st = plhr_gram_c128_workspace(n, mx, my, &need);
+  if (st != PLHR_OK) return st;
+  if (!G || !workspace || (n > 0 && (!X || !Y))) {
+    set_error("plhr_gram_c128: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (ws_bytes < need) {
+    set_error("plhr_gram_c128: workspace smaller than plhr_gram_c128_workspace");
+    return PLHR_ERR_ARG;
+  }
+  if (((uintptr_t)X | (uintptr_t)Y | (uintptr_t)G | (uintptr_t)workspace) & 15) {
+    set_error("plhr_gram_c128: X, Y, G and the workspace must be 16-byte aligned");
+    return PLHR_ERR_ARG;
+  }
+  launch_cgram((size_t)n, static_cast<const double*>(X), mx, static_cast<const double*>(Y), my,
+               static_cast<double*>(G), static_cast<double*>(workspace),
+               static_cast<hipStream_t>(stream));
+  PLHR_HIP_CHECK(hipGetLastError());
+  return PLHR_OK;
+}
+
 }  // extern "C"

@@ -273,6 +273,11 @@ struct ArrPtrs {
 
 // Matrix-core versions (k_mfma.hip); *_ok tells whether the shape fits.
 int gram_mfma_ok(int mx, int my);
+// G = X^H Y for complex128 blocks on the matrix cores (mx, my complex
+// columns); ws holds cgram_workspace_bytes(n, mx, my) bytes.
+size_t cgram_workspace_bytes(size_t n, int mx, int my);
+void launch_cgram(size_t n, const double* X, int mx, const double* Y, int my, double* G,
+                  double* ws, hipStream_t s);
 void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
                       int my1, const double* Y2, int ldy2, int my, double* part, int nblk,
                       double* out, const DevStatus* st, hipStream_t s);

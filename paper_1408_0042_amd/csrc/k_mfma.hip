@@ -12,6 +12,7 @@
 // 4-row slice of X read transposed, B the matching slice of Y.  For the
 // row product K is the column index of X: A is a 16-row by 4-column tile
 // of X, B a 4 x 16 tile of M.
+#include <algorithm>
 #include <cstdint>
 
 #include "mfma.cuh"
@@ -80,6 +81,53 @@ void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* 
   hipLaunchKernelGGL(k_gram_reduce8, dim3((total + 31) / 32), dim3(256), 0, s, part, nblk, total,
                      out, st);
   prof_end(KC_GRAM_REDUCE, s);
+}
+
+// Complex Hermitian Gram from the real Gram of the interleaved views:
+// with X' and Y' the (re, im)-interleaved real blocks, G'(2a+s, 2b+t) =
+// sum_p X'[p, 2a+s] Y'[p, 2b+t], and
+//   (X^H Y)(a, b) = G'(2a, 2b) + G'(2a+1, 2b+1)
+//                   + i (G'(2a, 2b+1) - G'(2a+1, 2b)).
+// Gc is one mxc x myc chunk of G' (row-major, even sizes) whose first
+// entry is G'(2 a0, 2 b0); G is mx x ldg complex, row-major.
+__global__ __launch_bounds__(256) void k_cgram_combine(const double* __restrict__ Gc, int mxc,
+                                                       int myc, int a0, int b0,
+                                                       double2* __restrict__ G, int ldg) {
+  const int ha = mxc / 2, hb = myc / 2;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ha * hb; t += gridDim.x * blockDim.x) {
+    const int a = t / hb, b = t - a * hb;
+    const double* r0 = Gc + (size_t)(2 * a) * myc + 2 * b;
+    const double* r1 = r0 + myc;
+    G[(size_t)(a0 + a) * ldg + b0 + b] = make_double2(r0[0] + r1[1], r0[1] - r1[0]);
+  }
+}
+
+size_t cgram_workspace_bytes(size_t n, int mx, int my) {
+  const int nblk = gram_blocks(n);
+  const int cx = std::min(2 * mx, 128), cy = std::min(2 * my, 192);
+  return ((size_t)nblk * cx * cy * 8 + 255) / 256 * 256 + (size_t)cx * cy * 8;
+}
+
+// G = X^H Y (complex128, n x mx and n x my, point-major): the real Gram of
+// the interleaved views in chunks of at most 128 x 192 real columns (the
+// MFMA Gram's shape limits), each combined into its block of G.
+void launch_cgram(size_t n, const double* X, int mx, const double* Y, int my, double* G,
+                  double* ws, hipStream_t s) {
+  const int nblk = gram_blocks(n);
+  const int cx = std::min(2 * mx, 128), cy = std::min(2 * my, 192);
+  double* part = ws;
+  double* gc = ws + ((size_t)nblk * cx * cy * 8 + 255) / 256 * 256 / 8;
+  for (int x0 = 0; x0 < 2 * mx; x0 += cx) {
+    const int mxc = std::min(cx, 2 * mx - x0);
+    for (int y0 = 0; y0 < 2 * my; y0 += cy) {
+      const int myc = std::min(cy, 2 * my - y0);
+      launch_gram_mfma(n, X + x0, 2 * mx, mxc, Y + y0, 2 * my, myc, nullptr, 0, myc, part, nblk,
+                       gc, nullptr, s);
+      const int tot = (mxc / 2) * (myc / 2);
+      hipLaunchKernelGGL(k_cgram_combine, dim3((tot + 255) / 256), dim3(256), 0, s, gc, mxc,
+                         myc, x0 / 2, y0 / 2, reinterpret_cast<double2*>(G), my);
+    }
+  }
 }
 
 template <int TJ>

@@ -284,6 +284,32 @@ def bloch_apply(X: torch.Tensor, dims: Sequence[int], h: float = 1.0, thetas=(0.
     return out
 
 
+def gram_c128(X: torch.Tensor, Y: Optional[torch.Tensor] = None,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """G = X^H Y for complex128 device blocks (n, mx) and (n, my) on the
+    matrix cores (plhr_gram_c128); Y = None means Y = X.  Enqueued on
+    torch's current stream."""
+    Y = X if Y is None else Y
+    _require_cuda(X, "X", torch.complex128)
+    _require_cuda(Y, "Y", torch.complex128)
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[0] != Y.shape[0]:
+        raise ValueError("X and Y must be (n, mx) and (n, my)")
+    n, mx, my = X.shape[0], X.shape[1], Y.shape[1]
+    if out is None:
+        out = torch.empty((mx, my), dtype=torch.complex128, device=X.device)
+    _require_cuda(out, "out", torch.complex128)
+    if tuple(out.shape) != (mx, my):
+        raise ValueError(f"out must be ({mx}, {my})")
+    lib = L.load()
+    need = C.c_size_t()
+    L.check(lib.plhr_gram_c128_workspace(n, mx, my, C.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device=X.device)
+    L.check(lib.plhr_gram_c128(n, C.c_void_p(X.data_ptr()), mx, C.c_void_p(Y.data_ptr()), my,
+                               C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), need.value,
+                               C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return out
+
+
 class BlochPrecond:
     """One multigrid V-cycle for the Bloch operator scale*(-Laplacian_theta)
     on the periodic nx x ny x nz box (plhr_bloch_prec_*): apply(X) returns

@@ -202,3 +202,18 @@ def test_bloch_preconditioner_arguments_are_validated_on_the_host():
     t.kind, d.dtype = L.PREC_MG_VCYCLE, L.F64
     assert create() == L.ERR_UNSUPPORTED
     assert lib.plhr_bloch_prec_apply(None, None, None, 0) == L.ERR_ARG
+
+
+def test_complex_gram_arguments_are_validated_on_the_host():
+    lib = L.load()
+    sz = C.c_size_t()
+    assert lib.plhr_gram_c128_workspace(1000, 128, 128, C.byref(sz)) == L.OK
+    assert sz.value >= 128 * 128 * 8
+    assert lib.plhr_gram_c128_workspace(-1, 4, 4, C.byref(sz)) == L.ERR_ARG
+    assert lib.plhr_gram_c128_workspace(10, 0, 4, C.byref(sz)) == L.ERR_ARG
+    assert lib.plhr_gram_c128_workspace(10, 4, 2000, C.byref(sz)) == L.ERR_ARG
+    lib.plhr_gram_c128_workspace(1000, 8, 8, C.byref(sz))
+    X, G, W = C.c_void_p(4096), C.c_void_p(1 << 20), C.c_void_p(1 << 24)
+    assert lib.plhr_gram_c128(1000, X, 8, X, 8, G, W, sz.value - 1, None) == L.ERR_ARG
+    assert lib.plhr_gram_c128(1000, X, 8, None, 8, G, W, sz.value, None) == L.ERR_ARG
+    assert lib.plhr_gram_c128(1000, C.c_void_p(4104), 8, X, 8, G, W, sz.value, None) == L.ERR_ARG
