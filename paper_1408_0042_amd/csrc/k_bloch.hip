@@ -223,6 +223,68 @@ __global__ __launch_bounds__(256) void k_bloch_restrict(int nxc, int nyc, int nz
   }
 }
 
+// The same restriction with the fine rows staged: workgroup (jc, lc)
+// first combines its 16 fine rows (4 taps in z times 4 in y) into one fine
+// row in LDS, reading each fine row with coalesced loads, then applies the
+// x taps from LDS.  A fine row is read by 4 workgroups instead of each
+// fine value by 8 gathers.  Needs nxf * ncols * 16 bytes of LDS.
+__global__ __launch_bounds__(256) void k_bloch_restrict_lds(int nxc, int nyc, int nzc,
+                                                            double2 fx, double2 fy, double2 fz,
+                                                            const double2* __restrict__ res,
+                                                            double2* __restrict__ rc,
+                                                            int ncols) {
+  extern __shared__ double2 srow[];
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int jc = row % nyc;
+  const int lc = row / nyc;
+  const int nxf = 2 * nxc, nyf = 2 * nyc;
+  const BlochTaps ty = restrict_taps(jc, nyc, fy);
+  const BlochTaps tz = restrict_taps(lc, nzc, fz);
+  double2 wyz[16];
+  size_t rows[16];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      wyz[4 * a + b] = cmul(tz.w[a], ty.w[b]);
+      rows[4 * a + b] = ((size_t)tz.f[a] * nyf + ty.f[b]) * nxf * ncols;
+    }
+  const int nf = nxf * ncols;
+  for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+    double2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = res[rows[q] + e];
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      acc = make_double2(acc.x + (wyz[q].x * v[q].x - wyz[q].y * v[q].y),
+                         acc.y + (wyz[q].x * v[q].y + wyz[q].y * v[q].x));
+    srow[e] = acc;
+  }
+  __syncthreads();
+  const int nelem = nxc * ncols;
+  int i = threadIdx.x / ncols;
+  int c = threadIdx.x - i * ncols;
+  const int di = blockDim.x / ncols, dc = blockDim.x - di * ncols;
+  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
+    const BlochTaps tx = restrict_taps(i, nxc, fx);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v = srow[tx.f[q] * ncols + c];
+      acc = make_double2(acc.x + (tx.w[q].x * v.x - tx.w[q].y * v.y),
+                         acc.y + (tx.w[q].x * v.y + tx.w[q].y * v.x));
+    }
+    rc[((size_t)row * nxc + i) * ncols + c] = make_double2(0.125 * acc.x, 0.125 * acc.y);
+    c += dc;
+    i += di;
+    if (c >= ncols) {
+      c -= ncols;
+      ++i;
+    }
+  }
+}
+
 // The two coarse points feeding fine point f of one direction under P:
 // its parent f/2 with 3/4 and the parent's neighbour on f's side with 1/4,
 // wrapped across the periodic face with exp(-/+ i theta).
@@ -317,6 +379,14 @@ void launch_bloch_level(int nx, int ny, int nz, double cs, const double* theta, 
 
 void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const double* res,
                            double* rc, int ncols, hipStream_t s) {
+  const size_t lds = (size_t)2 * nxc * ncols * sizeof(double2);
+  if (lds <= 65536) {
+    hipLaunchKernelGGL(k_bloch_restrict_lds, dim3(nyc * nzc), dim3(256), lds, s, nxc, nyc, nzc,
+                       phase(theta[0]), phase(theta[1]), phase(theta[2]),
+                       reinterpret_cast<const double2*>(res), reinterpret_cast<double2*>(rc),
+                       ncols);
+    return;
+  }
   hipLaunchKernelGGL(k_bloch_restrict, dim3(nyc * nzc), dim3(256), 0, s, nxc, nyc, nzc,
                      phase(theta[0]), phase(theta[1]), phase(theta[2]),
                      reinterpret_cast<const double2*>(res), reinterpret_cast<double2*>(rc), ncols);
