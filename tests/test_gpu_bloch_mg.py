@@ -1,7 +1,8 @@
 """The multigrid preconditioner of the complex Bloch operator
 (plhr_bloch_prec_*) against the oracle's Bloch V-cycle, element by element:
 cubic and non-cubic boxes (a coarsest grid with one point in a direction),
-one to three levels, one and two sweeps, ragged column counts, the
+one to three levels, one and two sweeps, ragged column counts, a block
+whose fine rows exceed the restriction's LDS staging, the
 periodic model's full grid (96^3, 5 levels); T Hermitian and positive
 definite on random blocks; an empty block."""
 import numpy as np
@@ -30,6 +31,7 @@ def _gpu_T(X, dims, h, scale, levels, nu, omega):
     ((16, 8, 4), 0.8, 1.0, 3, 1, 0.6, 33),
     ((6, 4, 2), 1.0, 0.5, 1, 2, 2 / 3, 3),
     ((12, 12, 12), 1.0, 0.5, 2, 2, 2 / 3, 1),
+    ((16, 4, 4), 1.0, 0.5, 2, 2, 2 / 3, 300),   # fine rows over 64 KB: gathering restriction
 ])
 def test_bloch_vcycle_matches_oracle(dims, h, scale, levels, nu, omega, ncols):
     n = int(np.prod(dims))
