@@ -372,8 +372,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU layout is described in the design notes but not implemented",
+        print(f"bench.py: the solver runs on one GPU only (asked for {args.gpus}); sharding "
+              "over several GPUs is not implemented",
               file=sys.stderr)
         sys.exit(2)
 

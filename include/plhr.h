@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   PLHR_OK = 0,
   PLHR_ERR_ARG = 1,           /* invalid argument or descriptor                 */
-  PLHR_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement    */
+  PLHR_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement   */
   PLHR_ERR_HIP = 3,           /* a HIP runtime call failed                      */
   PLHR_ERR_NOT_HPD = 4,       /* Gram/projected matrix not positive definite    */
   PLHR_ERR_BREAKDOWN = 5,     /* the V block became rank deficient              */
