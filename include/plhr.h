@@ -316,7 +316,7 @@ typedef struct plhr_bloch_prec_s* plhr_bloch_prec;
  *   T         host, PLHR_PREC_MG_VCYCLE; levels >= 1, nu_pre == nu_post
  *             >= 1, 0 < omega <= 1; nx, ny, nz divisible by
  *             2^(levels - 1); the coarsest grid at most 1024 points
- *   max_cols  widest block apply will take (>= 1)
+ *   max_cols  widest block apply will take (1 .. 2^22)
  *   stream    hipStream_t of every apply (NULL: the null stream)
  * Allocates its level buffers (3 blocks per coarse level, 2 on the finest,
  * of n_l x max_cols complex128) and the coarse inverse on the current

@@ -182,9 +182,10 @@ plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* 
               "0 < omega <= 1");
     return PLHR_ERR_ARG;
   }
-  if (max_cols < 1 || (int64_t)A->nx * max_cols >= (int64_t(1) << 31) ||
+  if (max_cols < 1 || max_cols > (1 << 22) || (int64_t)A->nx * max_cols >= (int64_t(1) << 31) ||
       (int64_t)A->ny * A->nz >= (int64_t(1) << 31)) {
-    set_error("plhr_bloch_prec_create: need max_cols >= 1, nx*max_cols and ny*nz below 2^31");
+    set_error("plhr_bloch_prec_create: need 1 <= max_cols <= 2^22, nx*max_cols and ny*nz below "
+              "2^31");
     return PLHR_ERR_ARG;
   }
   if (T->levels > 16) {

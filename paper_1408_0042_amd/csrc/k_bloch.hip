@@ -349,20 +349,29 @@ __global__ __launch_bounds__(256) void k_bloch_prolong_add(int nx, int ny, int n
 }
 
 // x = Ainv r on the coarsest level (nc points, Ainv row-major complex).
+// Workgroup (i, column chunk of 64): its 256 lanes are 64 columns by 4
+// slices of the sum over q (q = slice mod 4), combined through LDS.
 __global__ __launch_bounds__(256) void k_bloch_dense(int nc, const double2* __restrict__ Ainv,
                                                      const double2* __restrict__ r,
                                                      double2* __restrict__ x, int ncols) {
-  const int tot = nc * ncols;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
-    const int i = e / ncols;
-    const int c = e - i * ncols;
-    const double2* a = Ainv + (size_t)i * nc;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < nc; ++q) {
+  __shared__ double2 part[4][64];
+  const int i = blockIdx.x;
+  const int cl = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + cl;
+  const double2* a = Ainv + (size_t)i * nc;
+  double2 acc = make_double2(0.0, 0.0);
+  if (c < ncols) {
+    for (int q = sl; q < nc; q += 4) {
       const double2 m = a[q], v = r[(size_t)q * ncols + c];
       acc = make_double2(acc.x + (m.x * v.x - m.y * v.y), acc.y + (m.x * v.y + m.y * v.x));
     }
-    x[(size_t)i * ncols + c] = acc;
+  }
+  part[sl][cl] = acc;
+  __syncthreads();
+  if (sl == 0 && c < ncols) {
+    const double2 p1 = part[1][cl], p2 = part[2][cl], p3 = part[3][cl];
+    x[(size_t)i * ncols + c] =
+        make_double2(((acc.x + p1.x) + p2.x) + p3.x, ((acc.y + p1.y) + p2.y) + p3.y);
   }
 }
 
@@ -401,9 +410,7 @@ void launch_bloch_prolong_add(int nx, int ny, int nz, const double* theta, const
 
 void launch_bloch_dense(int nc, const double* Ainv, const double* r, double* x, int ncols,
                         hipStream_t s) {
-  const int tot = nc * ncols;
-  const int nb = std::min((tot + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_bloch_dense, dim3(nb), dim3(256), 0, s, nc,
+  hipLaunchKernelGGL(k_bloch_dense, dim3(nc, (ncols + 63) / 64), dim3(256), 0, s, nc,
                      reinterpret_cast<const double2*>(Ainv), reinterpret_cast<const double2*>(r),
                      reinterpret_cast<double2*>(x), ncols);
 }
