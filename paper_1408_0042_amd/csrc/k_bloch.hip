@@ -348,6 +348,74 @@ __global__ __launch_bounds__(256) void k_bloch_prolong_add(int nx, int ny, int n
   }
 }
 
+// The same prolongation with the coarse rows staged: workgroup (j, l)
+// first combines its 4 coarse rows (2 taps in z times 2 in y) into one
+// coarse row in LDS, then interpolates in x from LDS.  Needs
+// nxc * ncols * 16 bytes of LDS.
+__global__ __launch_bounds__(256) void k_bloch_prolong_add_lds(int nx, int ny, int nz,
+                                                               double2 fx, double2 fy,
+                                                               double2 fz,
+                                                               const double2* __restrict__ ec,
+                                                               double2* __restrict__ x,
+                                                               int ncols) {
+  extern __shared__ double2 crow[];
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny;
+  const int l = row / ny;
+  const int nxc = nx / 2, nyc = ny / 2, nzc = nz / 2;
+  int cy[2], cz[2];
+  double2 wy[2], wz[2];
+  prolong_taps(j, nyc, fy, cy, wy);
+  prolong_taps(l, nzc, fz, cz, wz);
+  double2 wyz[4];
+  size_t rows[4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      wyz[2 * a + b] = cmul(wz[a], wy[b]);
+      rows[2 * a + b] = ((size_t)cz[a] * nyc + cy[b]) * nxc * ncols;
+    }
+  const int ncr = nxc * ncols;
+  for (int e = threadIdx.x; e < ncr; e += blockDim.x) {
+    double2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = ec[rows[q] + e];
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      acc = make_double2(acc.x + (wyz[q].x * v[q].x - wyz[q].y * v[q].y),
+                         acc.y + (wyz[q].x * v[q].y + wyz[q].y * v[q].x));
+    crow[e] = acc;
+  }
+  __syncthreads();
+  const int nelem = nx * ncols;
+  int i = threadIdx.x / ncols;
+  int c = threadIdx.x - i * ncols;
+  const int di = blockDim.x / ncols, dc = blockDim.x - di * ncols;
+  for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
+    int cx[2];
+    double2 wx[2];
+    prolong_taps(i, nxc, fx, cx, wx);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double2 v = crow[cx[q] * ncols + c];
+      acc = make_double2(acc.x + (wx[q].x * v.x - wx[q].y * v.y),
+                         acc.y + (wx[q].x * v.y + wx[q].y * v.x));
+    }
+    const size_t o = ((size_t)row * nx + i) * ncols + c;
+    const double2 x0 = x[o];
+    x[o] = make_double2(x0.x + acc.x, x0.y + acc.y);
+    c += dc;
+    i += di;
+    if (c >= ncols) {
+      c -= ncols;
+      ++i;
+    }
+  }
+}
+
 // x = Ainv r on the coarsest level (nc points, Ainv row-major complex).
 // Workgroup (i, column chunk of 64): its 256 lanes are 64 columns by 4
 // slices of the sum over q (q = slice mod 4), combined through LDS.
@@ -403,6 +471,14 @@ void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const
 
 void launch_bloch_prolong_add(int nx, int ny, int nz, const double* theta, const double* ec,
                               double* x, int ncols, hipStream_t s) {
+  const size_t lds = (size_t)(nx / 2) * ncols * sizeof(double2);
+  if (lds <= 65536) {
+    hipLaunchKernelGGL(k_bloch_prolong_add_lds, dim3(ny * nz), dim3(256), lds, s, nx, ny, nz,
+                       phase(theta[0]), phase(theta[1]), phase(theta[2]),
+                       reinterpret_cast<const double2*>(ec), reinterpret_cast<double2*>(x),
+                       ncols);
+    return;
+  }
   hipLaunchKernelGGL(k_bloch_prolong_add, dim3(ny * nz), dim3(256), 0, s, nx, ny, nz,
                      phase(theta[0]), phase(theta[1]), phase(theta[2]),
                      reinterpret_cast<const double2*>(ec), reinterpret_cast<double2*>(x), ncols);

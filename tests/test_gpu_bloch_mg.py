@@ -2,7 +2,7 @@
 (plhr_bloch_prec_*) against the oracle's Bloch V-cycle, element by element:
 cubic and non-cubic boxes (a coarsest grid with one point in a direction),
 one to three levels, one and two sweeps, ragged column counts, a block
-whose fine rows exceed the restriction's LDS staging, the
+whose rows exceed the LDS staging of the transfers, the
 periodic model's full grid (96^3, 5 levels); T Hermitian and positive
 definite on random blocks; an empty block."""
 import numpy as np
@@ -31,7 +31,7 @@ def _gpu_T(X, dims, h, scale, levels, nu, omega):
     ((16, 8, 4), 0.8, 1.0, 3, 1, 0.6, 33),
     ((6, 4, 2), 1.0, 0.5, 1, 2, 2 / 3, 3),
     ((12, 12, 12), 1.0, 0.5, 2, 2, 2 / 3, 1),
-    ((16, 4, 4), 1.0, 0.5, 2, 2, 2 / 3, 300),   # fine rows over 64 KB: gathering restriction
+    ((16, 4, 4), 1.0, 0.5, 2, 2, 2 / 3, 600),   # rows over 64 KB: gathering transfers
 ])
 def test_bloch_vcycle_matches_oracle(dims, h, scale, levels, nu, omega, ncols):
     n = int(np.prod(dims))
