@@ -235,9 +235,10 @@ def bloch_leg(N=96, ncols=32, reps=20):
            "unit": "GB/s", "peak": HBM_PEAK_GBS, "us_per_launch": us, "achieved": gbs,
            "frac": gbs / HBM_PEAK_GBS, "algorithmic_per_launch": alg}
     # one V-cycle of the Bloch Laplacian (5 levels, 2+2 sweeps): algorithmic
-    # passes of n_l x ncols complex128 per level: pre-sweeps 2 + 3, residual
-    # 3, restriction 1 + 1/8, prolongation 2 + 1/8, post-sweeps 3 + 3; the
-    # coarsest level reads r and writes x once, and its inverse
+    # passes of n_l x ncols complex128 per level: the two pre-sweeps from
+    # zero in one pass over r (read r, write w: 2), residual 3, restriction
+    # 1 + 1/8, prolongation 2 + 1/8, post-sweeps 3 + 3; the coarsest level
+    # reads r and writes x once, and its inverse
     from paper_1408_0042_amd.plhr import BlochPrecond
     levels, nu = 5, 2
     T = BlochPrecond(dims, thetas=th, levels=levels, nu=nu, max_cols=ncols)
@@ -250,7 +251,7 @@ def bloch_leg(N=96, ncols=32, reps=20):
     torch.cuda.synchronize()
     usv = 1e3 * e0.elapsed_time(e1) / reps
     T.close()
-    per_level = (2 + 3 * (nu - 1)) + 3 + 1.125 + 2.125 + 3 * nu
+    per_level = (2 + 3 * max(0, nu - 2)) + 3 + 1.125 + 2.125 + 3 * nu
     algv, nl = 0.0, n
     for lev in range(levels):
         algv += (per_level if lev < levels - 1 else 2.0) * nl * ncols * 16

@@ -125,9 +125,17 @@ struct plhr_bloch_prec_s {
     const double bj = omega / L.diag;
     double* cur = L.x;
     double* oth = L.t;
-    // pre-smoothing from w = 0
-    launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, nullptr, r, 0.0, bj, cur, ncols, stream);
-    for (int it = 1; it < nu; ++it) {
+    // pre-smoothing from w = 0; the first two sweeps in one pass over r:
+    // w1 = bj r and w2 = w1 + bj (r - A w1) = (2 bj - bj^2) r + bj^2 (r - A r)
+    int it0 = 1;
+    if (nu >= 2) {
+      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, r, r, 2.0 * bj - bj * bj, bj * bj, cur,
+                         ncols, stream);
+      it0 = 2;
+    } else {
+      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, nullptr, r, 0.0, bj, cur, ncols, stream);
+    }
+    for (int it = it0; it < nu; ++it) {
       launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 1.0, bj, oth, ncols, stream);
       std::swap(cur, oth);
     }
