@@ -355,6 +355,25 @@ plhr_status plhr_gram_c128_workspace(int64_t n, int32_t mx, int32_t my, size_t* 
 plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, int32_t my,
                            void* G, void* workspace, size_t ws_bytes, void* stream);
 
+/* Cholesky-QR orthonormalisation of a complex block (the orthonormalising
+ * step of the complex iteration, Section 4, with B = I):
+ *   Z^H Z = R^H R (R upper triangular, real positive diagonal), Q = Z R^-1,
+ * so that Q^H Q = I and span Q = span Z.
+ *   n        rows, >= m
+ *   Z        device, n x m complex128 (interleaved), point-major; read only
+ *   m        columns, 1 <= m <= 64
+ *   Q        device, n x m complex128, written; must not overlap Z
+ *   R        device, m x m complex128 row-major (lower part zero), or NULL
+ *   workspace device scratch of plhr_cholqr_c128_workspace(n, m) bytes
+ *   stream   hipStream_t (NULL: the null stream)
+ * Synchronises the stream to report a breakdown: PLHR_ERR_NOT_HPD when
+ * Z^H Z is not positive definite to rounding (dependent columns; Q and R
+ * are then unspecified).  Pointers 16-byte aligned; PLHR_ERR_ARG for a
+ * NULL, misaligned, overlapping or out-of-range argument.                */
+plhr_status plhr_cholqr_c128_workspace(int64_t n, int32_t m, size_t* bytes);
+plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void* R,
+                             void* workspace, size_t ws_bytes, void* stream);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

@@ -338,4 +338,62 @@ plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, 
   return PLHR_OK;
 }
 
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+plhr_status plhr_cholqr_c128_workspace(int64_t n, int32_t m, size_t* bytes) {
+  if (!bytes || n < 1 || m < 1 || m > 64 || n < m) {
+    set_error("plhr_cholqr_c128_workspace: need bytes != NULL, 1 <= m <= 64, n >= m");
+    return PLHR_ERR_ARG;
+  }
+  *bytes = al256(cgram_workspace_bytes((size_t)n, m, m)) + 2 * al256((size_t)m * m * 16) + 256;
+  return PLHR_OK;
+}
+
+plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void* R,
+                             void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  const plhr_status st = plhr_cholqr_c128_workspace(n, m, &need);
+  if (st != PLHR_OK) return st;
+  if (!Z || !Q || !workspace) {
+    set_error("plhr_cholqr_c128: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (ws_bytes < need) {
+    set_error("plhr_cholqr_c128: workspace smaller than plhr_cholqr_c128_workspace");
+    return PLHR_ERR_ARG;
+  }
+  if (((uintptr_t)Z | (uintptr_t)Q | (uintptr_t)R | (uintptr_t)workspace) & 15) {
+    set_error("plhr_cholqr_c128: Z, Q, R and the workspace must be 16-byte aligned");
+    return PLHR_ERR_ARG;
+  }
+  const size_t bytes = (size_t)n * m * 16;
+  const char* zb = static_cast<const char*>(Z);
+  const char* qb = static_cast<const char*>(Q);
+  if (zb < qb + bytes && qb < zb + bytes) {
+    set_error("plhr_cholqr_c128: Z and Q overlap");
+    return PLHR_ERR_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+  double* gws = reinterpret_cast<double*>(w);
+  w += al256(cgram_workspace_bytes((size_t)n, m, m));
+  double* G = reinterpret_cast<double*>(w);
+  w += al256((size_t)m * m * 16);
+  double* Rinv = reinterpret_cast<double*>(w);
+  w += al256((size_t)m * m * 16);
+  int* fail = reinterpret_cast<int*>(w);
+  const double* Zd = static_cast<const double*>(Z);
+  launch_cgram((size_t)n, Zd, m, Zd, m, G, gws, s);
+  PLHR_HIP_CHECK(launch_cholqr_tail((size_t)n, m, Zd, G, static_cast<double*>(R), Rinv, fail,
+                                    static_cast<double*>(Q), s));
+  int hf = 0;
+  PLHR_HIP_CHECK(hipMemcpyAsync(&hf, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+  PLHR_HIP_CHECK(hipStreamSynchronize(s));
+  if (hf) {
+    set_error("plhr_cholqr_c128: Z^H Z is not positive definite (dependent columns)");
+    return PLHR_ERR_NOT_HPD;
+  }
+  return PLHR_OK;
+}
+
 }  // extern "C"

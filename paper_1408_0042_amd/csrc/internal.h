@@ -278,6 +278,10 @@ int gram_mfma_ok(int mx, int my);
 size_t cgram_workspace_bytes(size_t n, int mx, int my);
 void launch_cgram(size_t n, const double* X, int mx, const double* Y, int my, double* G,
                   double* ws, hipStream_t s);
+// Complex Cholesky-QR tail: R and R^-1 from G = Z^H Z (one workgroup,
+// m <= 64; *fail = 1 if G is not positive definite), then Q = Z R^-1.
+hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G, double* R,
+                              double* Rinv, int* fail, double* Q, hipStream_t s);
 void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
                       int my1, const double* Y2, int ldy2, int my, double* part, int nblk,
                       double* out, const DevStatus* st, hipStream_t s);

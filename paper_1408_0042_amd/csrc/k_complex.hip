@@ -1,0 +1,125 @@
+// Cholesky-QR orthonormalisation of a complex block (the orthonormalising
+// step of the complex iteration, Section 4): with G = Z^H Z = R^H R (R
+// upper triangular with a real positive diagonal), Q = Z R^-1.
+//
+//   k_cchol_inv  one workgroup: R and R^-1 from G, in LDS (m <= 64)
+//   k_cright     Q = Z R^-1, rows of the block spread over workgroups,
+//                R^-1 in LDS; Q[p, b] sums Z[p, a] R^-1[a, b] over a <= b
+#include <cmath>
+
+#include "common.cuh"
+
+namespace plhr {
+
+namespace {
+__device__ __forceinline__ double2 cmac(double2 acc, double2 a, double2 b) {
+  return make_double2(acc.x + (a.x * b.x - a.y * b.y), acc.y + (a.x * b.y + a.y * b.x));
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_cchol_inv(int m, const double2* __restrict__ G,
+                                                   double2* __restrict__ R,
+                                                   double2* __restrict__ Rinv,
+                                                   int* __restrict__ fail) {
+  extern __shared__ double2 sh[];
+  double2* A = sh;          // m x m: G, then R in its upper triangle
+  double2* X = sh + m * m;  // m x m: R^-1
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  for (int e = t; e < m * m; e += blockDim.x) A[e] = G[e];
+  if (t == 0) bad = 0;
+  __syncthreads();
+  double maxd = 0.0;
+  for (int j = 0; j < m; ++j) maxd = fmax(maxd, A[j * m + j].x);
+  for (int j = 0; j < m; ++j) {
+    const double d = A[j * m + j].x;  // the same value in every lane
+    if (!(d > 1e-14 * maxd)) {        // uniform: not positive definite to rounding
+      if (t == 0) bad = 1;
+      break;
+    }
+    const double rd = sqrt(d), inv = 1.0 / rd;
+    __syncthreads();
+    for (int i = j + t; i < m; i += blockDim.x) {
+      const double2 a = A[j * m + i];
+      A[j * m + i] = (i == j) ? make_double2(rd, 0.0) : make_double2(a.x * inv, a.y * inv);
+    }
+    __syncthreads();
+    // trailing update of the upper triangle: A[r][c] -= conj(R[j][r]) R[j][c]
+    const int w = m - j - 1;
+    for (int e = t; e < w * w; e += blockDim.x) {
+      const int r = j + 1 + e / w, c = j + 1 + e % w;
+      if (c < r) continue;
+      const double2 u = A[j * m + r], v = A[j * m + c];
+      const double2 a = A[r * m + c];
+      A[r * m + c] = make_double2(a.x - (u.x * v.x + u.y * v.y), a.y - (u.x * v.y - u.y * v.x));
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int failed = bad;
+  if (!failed && t < m) {
+    // column t of R^-1 by back substitution: R X = e_t
+    const int c = t;
+    for (int i = c; i >= 0; --i) {
+      double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      for (int k = i + 1; k <= c; ++k) {
+        const double2 r = A[i * m + k], x = X[k * m + c];
+        s = make_double2(s.x - (r.x * x.x - r.y * x.y), s.y - (r.x * x.y + r.y * x.x));
+      }
+      const double rii = A[i * m + i].x;
+      X[i * m + c] = make_double2(s.x / rii, s.y / rii);
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < m * m; e += blockDim.x) {
+    const int i = e / m, c = e - i * m;
+    const bool up = (c >= i) && !failed;
+    if (R) R[e] = up ? A[e] : make_double2(0.0, 0.0);
+    Rinv[e] = up ? X[e] : make_double2(0.0, 0.0);
+  }
+  if (t == 0) *fail = failed;
+}
+
+__global__ __launch_bounds__(256) void k_cright(size_t n, int m, const double2* __restrict__ Z,
+                                                const double2* __restrict__ Rinv,
+                                                double2* __restrict__ Q) {
+  extern __shared__ double2 ri[];
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) ri[e] = Rinv[e];
+  __syncthreads();
+  const int rpb = blockDim.x / m;  // rows per pass of the workgroup
+  const int lr = threadIdx.x / m, b = threadIdx.x - lr * m;
+  if (lr >= rpb) return;
+  for (size_t p = (size_t)blockIdx.x * rpb + lr; p < n; p += (size_t)gridDim.x * rpb) {
+    const double2* z = Z + p * m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int a = 0; a <= b; ++a) acc = cmac(acc, z[a], ri[a * m + b]);
+    Q[p * m + b] = acc;
+  }
+}
+
+static bool cchol_attr_done = false;
+
+hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G, double* R,
+                              double* Rinv, int* fail, double* Q, hipStream_t s) {
+  const size_t lds = (size_t)2 * m * m * sizeof(double2);
+  if (!cchol_attr_done) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_cchol_inv,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(2 * 64 * 64 * sizeof(double2)));
+    if (e != hipSuccess) return e;
+    cchol_attr_done = true;
+  }
+  hipLaunchKernelGGL(k_cchol_inv, dim3(1), dim3(256), lds, s, m,
+                     reinterpret_cast<const double2*>(G), reinterpret_cast<double2*>(R),
+                     reinterpret_cast<double2*>(Rinv), fail);
+  const int rpb = 256 / m;
+  size_t nb = (n + rpb - 1) / rpb;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_cright, dim3((unsigned)nb), dim3(256), (size_t)m * m * sizeof(double2), s,
+                     n, m, reinterpret_cast<const double2*>(Z),
+                     reinterpret_cast<const double2*>(Rinv), reinterpret_cast<double2*>(Q));
+  return hipGetLastError();
+}
+
+}  // namespace plhr

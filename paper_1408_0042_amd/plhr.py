@@ -310,6 +310,26 @@ def gram_c128(X: torch.Tensor, Y: Optional[torch.Tensor] = None,
     return out
 
 
+def cholqr_c128(Z: torch.Tensor):
+    """Q, R with Z = Q R, Q^H Q = I, R upper triangular with a real positive
+    diagonal (plhr_cholqr_c128), for a complex128 device block (n, m),
+    m <= 64.  Synchronises torch's current stream."""
+    _require_cuda(Z, "Z", torch.complex128)
+    if Z.dim() != 2:
+        raise ValueError("Z must be (n, m)")
+    n, m = Z.shape
+    Q = torch.empty_like(Z)
+    R = torch.empty((m, m), dtype=torch.complex128, device=Z.device)
+    lib = L.load()
+    need = C.c_size_t()
+    L.check(lib.plhr_cholqr_c128_workspace(n, m, C.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device=Z.device)
+    L.check(lib.plhr_cholqr_c128(n, C.c_void_p(Z.data_ptr()), m, C.c_void_p(Q.data_ptr()),
+                                 C.c_void_p(R.data_ptr()), C.c_void_p(ws.data_ptr()), need.value,
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return Q, R
+
+
 class BlochPrecond:
     """One multigrid V-cycle for the Bloch operator scale*(-Laplacian_theta)
     on the periodic nx x ny x nz box (plhr_bloch_prec_*): apply(X) returns

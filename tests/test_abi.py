@@ -217,3 +217,17 @@ def test_complex_gram_arguments_are_validated_on_the_host():
     assert lib.plhr_gram_c128(1000, X, 8, X, 8, G, W, sz.value - 1, None) == L.ERR_ARG
     assert lib.plhr_gram_c128(1000, X, 8, None, 8, G, W, sz.value, None) == L.ERR_ARG
     assert lib.plhr_gram_c128(1000, C.c_void_p(4104), 8, X, 8, G, W, sz.value, None) == L.ERR_ARG
+
+
+def test_complex_cholqr_arguments_are_validated_on_the_host():
+    lib = L.load()
+    sz = C.c_size_t()
+    assert lib.plhr_cholqr_c128_workspace(1000, 64, C.byref(sz)) == L.OK and sz.value > 0
+    assert lib.plhr_cholqr_c128_workspace(1000, 65, C.byref(sz)) == L.ERR_ARG
+    assert lib.plhr_cholqr_c128_workspace(10, 20, C.byref(sz)) == L.ERR_ARG   # n < m
+    lib.plhr_cholqr_c128_workspace(1000, 8, C.byref(sz))
+    Z, Q, W = C.c_void_p(4096), C.c_void_p(1 << 24), C.c_void_p(1 << 26)
+    assert lib.plhr_cholqr_c128(1000, Z, 8, Q, None, W, sz.value - 1, None) == L.ERR_ARG
+    assert lib.plhr_cholqr_c128(1000, Z, 8, C.c_void_p(4096 + 16), None, W, sz.value,
+                                None) == L.ERR_ARG                            # overlap
+    assert lib.plhr_cholqr_c128(1000, None, 8, Q, None, W, sz.value, None) == L.ERR_ARG
