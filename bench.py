@@ -33,8 +33,8 @@ the timed region), the same figures for every kernel, the HBM rate of the
 sparse-times-block product (the benchmark operator as a CSR matrix, and
 the same product through the grid stencil) in `spmm`, that of the complex
 Bloch-periodic product (96^3, 32 columns), of one V-cycle of its
-Laplacian part and the FP64 matrix-core rate of the complex Gram of a
-128-column basis in `bloch`, and the CPU oracle
+Laplacian part, the FP64 matrix-core rate of the complex Gram of a
+128-column basis and a complex Cholesky-QR in `bloch`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -283,6 +283,23 @@ def bloch_leg(N=96, ncols=32, reps=20):
                    "bound": "mfma", "peak": 78.6, "us_per_launch": usg,
                    "achieved": fl / (usg * 1e-6) / 1e12,
                    "frac": fl / (usg * 1e-6) / 1e12 / 78.6, "algorithmic_flops": fl}
+    # Cholesky-QR of a 64-column complex block (one synchronising call):
+    # Z read twice (Gram, transform) and Q written: 3 n m 16 bytes
+    from paper_1408_0042_amd.plhr import cholqr_c128
+    del G
+    Zq = Z[:, :64].contiguous()
+    del Z
+    cholqr_c128(Zq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        cholqr_c128(Zq)
+    torch.cuda.synchronize()
+    usq = 1e6 * (time.perf_counter() - t0) / 5
+    bq = 3.0 * n * 64 * 16
+    out["cholqr"] = {"workload": f"Q R = Z, Z n x 64 complex128 (n {n}), host clock per call",
+                     "us_per_call": usq, "achieved": bq / (usq * 1e-6) / 1e9,
+                     "frac": bq / (usq * 1e-6) / 1e9 / HBM_PEAK_GBS, "algorithmic_per_call": bq}
     return out
 
 

@@ -3,8 +3,8 @@
 // upper triangular with a real positive diagonal), Q = Z R^-1.
 //
 //   k_cchol_inv  one workgroup: R and R^-1 from G, in LDS (m <= 64)
-//   k_cright     Q = Z R^-1, rows of the block spread over workgroups,
-//                R^-1 in LDS; Q[p, b] sums Z[p, a] R^-1[a, b] over a <= b
+//   k_cright     Q = Z R^-1, tiles of rows spread over workgroups, R^-1
+//                and the tile in LDS; Q[p, b] sums Z[p, a] R^-1[a, b], a <= b
 #include <cmath>
 
 #include "common.cuh"
@@ -80,20 +80,40 @@ __global__ __launch_bounds__(256) void k_cchol_inv(int m, const double2* __restr
   if (t == 0) *fail = failed;
 }
 
+// Q = Z R^-1 by tiles of 16 rows staged in LDS next to R^-1: lane (b, g)
+// (b = column, g = row group) accumulates the rows g, g + 4, g + 8, g + 12
+// of the tile; the row values are LDS broadcasts within a wavefront.
+constexpr int kCrTile = 16;
+
 __global__ __launch_bounds__(256) void k_cright(size_t n, int m, const double2* __restrict__ Z,
                                                 const double2* __restrict__ Rinv,
                                                 double2* __restrict__ Q) {
   extern __shared__ double2 ri[];
+  double2* zt = ri + m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) ri[e] = Rinv[e];
-  __syncthreads();
-  const int rpb = blockDim.x / m;  // rows per pass of the workgroup
-  const int lr = threadIdx.x / m, b = threadIdx.x - lr * m;
-  if (lr >= rpb) return;
-  for (size_t p = (size_t)blockIdx.x * rpb + lr; p < n; p += (size_t)gridDim.x * rpb) {
-    const double2* z = Z + p * m;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int a = 0; a <= b; ++a) acc = cmac(acc, z[a], ri[a * m + b]);
-    Q[p * m + b] = acc;
+  const int b = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const size_t ntiles = (n + kCrTile - 1) / kCrTile;
+  for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const size_t p0 = tile * kCrTile;
+    const int rows = (n - p0 < (size_t)kCrTile) ? (int)(n - p0) : kCrTile;
+    __syncthreads();  // R^-1 loaded; the previous tile's rows consumed
+    for (int e = threadIdx.x; e < rows * m; e += blockDim.x) zt[e] = Z[p0 * m + e];
+    __syncthreads();
+    if (b < m) {
+      double2 acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+      for (int a = 0; a <= b; ++a) {
+        const double2 r = ri[a * m + b];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = cmac(acc[q], zt[(g + 4 * q) * m + a], r);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = g + 4 * q;
+        if (row < rows) Q[(p0 + row) * m + b] = acc[q];
+      }
+    }
   }
 }
 
@@ -103,21 +123,24 @@ hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G,
                               double* Rinv, int* fail, double* Q, hipStream_t s) {
   const size_t lds = (size_t)2 * m * m * sizeof(double2);
   if (!cchol_attr_done) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_cchol_inv,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(2 * 64 * 64 * sizeof(double2)));
+    hipError_t e = hipFuncSetAttribute((const void*)k_cchol_inv,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(2 * 64 * 64 * sizeof(double2)));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cright, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((64 * 64 + kCrTile * 64) * sizeof(double2)));
     if (e != hipSuccess) return e;
     cchol_attr_done = true;
   }
   hipLaunchKernelGGL(k_cchol_inv, dim3(1), dim3(256), lds, s, m,
                      reinterpret_cast<const double2*>(G), reinterpret_cast<double2*>(R),
                      reinterpret_cast<double2*>(Rinv), fail);
-  const int rpb = 256 / m;
-  size_t nb = (n + rpb - 1) / rpb;
-  if (nb > 4096) nb = 4096;
+  size_t nb = (n + kCrTile - 1) / kCrTile;
+  if (nb > 2048) nb = 2048;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_cright, dim3((unsigned)nb), dim3(256), (size_t)m * m * sizeof(double2), s,
-                     n, m, reinterpret_cast<const double2*>(Z),
+  hipLaunchKernelGGL(k_cright, dim3((unsigned)nb), dim3(256),
+                     (size_t)(m * m + kCrTile * m) * sizeof(double2), s, n, m,
+                     reinterpret_cast<const double2*>(Z),
                      reinterpret_cast<const double2*>(Rinv), reinterpret_cast<double2*>(Q));
   return hipGetLastError();
 }
