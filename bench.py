@@ -34,7 +34,8 @@ sparse-times-block product (the benchmark operator as a CSR matrix, and
 the same product through the grid stencil) in `spmm`, that of the complex
 Bloch-periodic product (96^3, 32 columns), of one V-cycle of its
 Laplacian part, the FP64 matrix-core rate of the complex Gram of a
-128-column basis and a complex Cholesky-QR in `bloch`, and the CPU oracle
+128-column basis, a complex Cholesky-QR and a complex block update in
+`bloch`, and the CPU oracle
 timed on a bounded sample.
 """
 from __future__ import annotations
@@ -300,6 +301,21 @@ def bloch_leg(N=96, ncols=32, reps=20):
     out["cholqr"] = {"workload": f"Q R = Z, Z n x 64 complex128 (n {n}), host clock per call",
                      "us_per_call": usq, "achieved": bq / (usq * 1e-6) / 1e9,
                      "frac": bq / (usq * 1e-6) / 1e9 / HBM_PEAK_GBS, "algorithmic_per_call": bq}
+    # block update Y = Z M, M 64 x 32: Z read and Y written once
+    from paper_1408_0042_amd.plhr import rowmul_c128
+    Mq = torch.from_numpy(wl.start_block(64, 32, (3, 7), dtype=np.complex128)).cuda()
+    rowmul_c128(Zq, Mq)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        rowmul_c128(Zq, Mq)
+    e1.record()
+    torch.cuda.synchronize()
+    usr = 1e3 * e0.elapsed_time(e1) / 5
+    br = n * (64 + 32) * 16.0
+    out["rowmul"] = {"workload": f"Y = Z M, Z n x 64, M 64 x 32 complex128 (n {n})",
+                     "us_per_launch": usr, "achieved": br / (usr * 1e-6) / 1e9,
+                     "frac": br / (usr * 1e-6) / 1e9 / HBM_PEAK_GBS, "algorithmic_per_launch": br}
     return out
 
 

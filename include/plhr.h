@@ -374,6 +374,19 @@ plhr_status plhr_cholqr_c128_workspace(int64_t n, int32_t m, size_t* bytes);
 plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void* R,
                              void* workspace, size_t ws_bytes, void* stream);
 
+/* Complex block product Y = Z M: the block updates of the complex
+ * iteration (Algorithm 2, the new V and P as combinations of the trial
+ * basis with the coefficients of the projected eigenvectors).
+ *   n        rows, >= 0 (0: nothing is done)
+ *   Z        device, n x m complex128 (interleaved), point-major
+ *   M        device, m x k complex128, row-major
+ *   Y        device, n x k complex128, written; must not overlap Z
+ *   1 <= m, k <= 64
+ *   stream   hipStream_t (NULL: the null stream); asynchronous
+ * PLHR_ERR_ARG for a NULL, overlapping or out-of-range argument.        */
+plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M, int32_t k,
+                             void* Y, void* stream);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

@@ -338,6 +338,30 @@ plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, 
   return PLHR_OK;
 }
 
+plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M, int32_t k,
+                             void* Y, void* stream) {
+  if (n < 0 || m < 1 || m > 64 || k < 1 || k > 64) {
+    set_error("plhr_rowmul_c128: need n >= 0, 1 <= m, k <= 64");
+    return PLHR_ERR_ARG;
+  }
+  if (n == 0) return PLHR_OK;
+  if (!Z || !M || !Y) {
+    set_error("plhr_rowmul_c128: NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  const size_t zb = (size_t)n * m * 16, yb = (size_t)n * k * 16;
+  const char* z = static_cast<const char*>(Z);
+  const char* y = static_cast<const char*>(Y);
+  if (z < y + yb && y < z + zb) {
+    set_error("plhr_rowmul_c128: Z and Y overlap");
+    return PLHR_ERR_ARG;
+  }
+  PLHR_HIP_CHECK(launch_crowmul((size_t)n, m, k, static_cast<const double*>(Z),
+                                static_cast<const double*>(M), static_cast<double*>(Y),
+                                static_cast<hipStream_t>(stream)));
+  return PLHR_OK;
+}
+
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 plhr_status plhr_cholqr_c128_workspace(int64_t n, int32_t m, size_t* bytes) {

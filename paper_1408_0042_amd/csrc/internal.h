@@ -282,6 +282,9 @@ void launch_cgram(size_t n, const double* X, int mx, const double* Y, int my, do
 // m <= 64; *fail = 1 if G is not positive definite), then Q = Z R^-1.
 hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G, double* R,
                               double* Rinv, int* fail, double* Q, hipStream_t s);
+// Y = Z M for complex128 blocks (Z n x m, M m x k row-major, m, k <= 64).
+hipError_t launch_crowmul(size_t n, int m, int k, const double* Z, const double* M, double* Y,
+                          hipStream_t s);
 void launch_gram_mfma(size_t n, const double* X, int ldx, int mx, const double* Y1, int ldy1,
                       int my1, const double* Y2, int ldy2, int my, double* part, int nblk,
                       double* out, const DevStatus* st, hipStream_t s);

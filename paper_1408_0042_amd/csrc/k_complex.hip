@@ -3,8 +3,9 @@
 // upper triangular with a real positive diagonal), Q = Z R^-1.
 //
 //   k_cchol_inv  one workgroup: R and R^-1 from G, in LDS (m <= 64)
-//   k_cright     Q = Z R^-1, tiles of rows spread over workgroups, R^-1
-//                and the tile in LDS; Q[p, b] sums Z[p, a] R^-1[a, b], a <= b
+//   k_cright     Q = Z R^-1 (and the general product Y = Z M of the block
+//                updates), tiles of rows spread over workgroups, the small
+//                matrix and the tile in LDS
 #include <cmath>
 
 #include "common.cuh"
@@ -80,38 +81,42 @@ __global__ __launch_bounds__(256) void k_cchol_inv(int m, const double2* __restr
   if (t == 0) *fail = failed;
 }
 
-// Q = Z R^-1 by tiles of 16 rows staged in LDS next to R^-1: lane (b, g)
-// (b = column, g = row group) accumulates the rows g, g + 4, g + 8, g + 12
-// of the tile; the row values are LDS broadcasts within a wavefront.
+// Y = Z M (Z n x m, M m x k, k <= 64) by tiles of 16 rows staged in LDS
+// next to M: lane (b, g) (b = column, g = row group) accumulates the rows
+// g, g + 4, g + 8, g + 12 of the tile; the row values are LDS broadcasts
+// within a wavefront.  tri: M upper triangular (R^-1 of the Cholesky-QR),
+// the sum for column b stops at a = b.
 constexpr int kCrTile = 16;
 
-__global__ __launch_bounds__(256) void k_cright(size_t n, int m, const double2* __restrict__ Z,
-                                                const double2* __restrict__ Rinv,
+__global__ __launch_bounds__(256) void k_cright(size_t n, int m, int k, int tri,
+                                                const double2* __restrict__ Z,
+                                                const double2* __restrict__ M,
                                                 double2* __restrict__ Q) {
   extern __shared__ double2 ri[];
-  double2* zt = ri + m * m;
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) ri[e] = Rinv[e];
+  double2* zt = ri + m * k;
+  for (int e = threadIdx.x; e < m * k; e += blockDim.x) ri[e] = M[e];
   const int b = threadIdx.x & 63, g = threadIdx.x >> 6;
   const size_t ntiles = (n + kCrTile - 1) / kCrTile;
   for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const size_t p0 = tile * kCrTile;
     const int rows = (n - p0 < (size_t)kCrTile) ? (int)(n - p0) : kCrTile;
-    __syncthreads();  // R^-1 loaded; the previous tile's rows consumed
+    __syncthreads();  // M loaded; the previous tile's rows consumed
     for (int e = threadIdx.x; e < rows * m; e += blockDim.x) zt[e] = Z[p0 * m + e];
     __syncthreads();
-    if (b < m) {
+    if (b < k) {
       double2 acc[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
-      for (int a = 0; a <= b; ++a) {
-        const double2 r = ri[a * m + b];
+      const int amax = tri ? b : m - 1;
+      for (int a = 0; a <= amax; ++a) {
+        const double2 r = ri[a * k + b];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = cmac(acc[q], zt[(g + 4 * q) * m + a], r);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = g + 4 * q;
-        if (row < rows) Q[(p0 + row) * m + b] = acc[q];
+        if (row < rows) Q[(p0 + row) * k + b] = acc[q];
       }
     }
   }
@@ -119,29 +124,47 @@ __global__ __launch_bounds__(256) void k_cright(size_t n, int m, const double2* 
 
 static bool cchol_attr_done = false;
 
-hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G, double* R,
-                              double* Rinv, int* fail, double* Q, hipStream_t s) {
-  const size_t lds = (size_t)2 * m * m * sizeof(double2);
-  if (!cchol_attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cchol_inv,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(2 * 64 * 64 * sizeof(double2)));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_cright, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((64 * 64 + kCrTile * 64) * sizeof(double2)));
-    if (e != hipSuccess) return e;
-    cchol_attr_done = true;
-  }
-  hipLaunchKernelGGL(k_cchol_inv, dim3(1), dim3(256), lds, s, m,
-                     reinterpret_cast<const double2*>(G), reinterpret_cast<double2*>(R),
-                     reinterpret_cast<double2*>(Rinv), fail);
+static hipError_t cplx_attrs() {
+  if (cchol_attr_done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_cchol_inv,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(2 * 64 * 64 * sizeof(double2)));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_cright, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)((64 * 64 + kCrTile * 64) * sizeof(double2)));
+  if (e != hipSuccess) return e;
+  cchol_attr_done = true;
+  return hipSuccess;
+}
+
+static void launch_cright(size_t n, int m, int k, int tri, const double* Z, const double* M,
+                          double* Y, hipStream_t s) {
   size_t nb = (n + kCrTile - 1) / kCrTile;
   if (nb > 2048) nb = 2048;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_cright, dim3((unsigned)nb), dim3(256),
-                     (size_t)(m * m + kCrTile * m) * sizeof(double2), s, n, m,
-                     reinterpret_cast<const double2*>(Z),
-                     reinterpret_cast<const double2*>(Rinv), reinterpret_cast<double2*>(Q));
+                     (size_t)(m * k + kCrTile * m) * sizeof(double2), s, n, m, k, tri,
+                     reinterpret_cast<const double2*>(Z), reinterpret_cast<const double2*>(M),
+                     reinterpret_cast<double2*>(Y));
+}
+
+hipError_t launch_crowmul(size_t n, int m, int k, const double* Z, const double* M, double* Y,
+                          hipStream_t s) {
+  const hipError_t e = cplx_attrs();
+  if (e != hipSuccess) return e;
+  launch_cright(n, m, k, 0, Z, M, Y, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr_tail(size_t n, int m, const double* Z, const double* G, double* R,
+                              double* Rinv, int* fail, double* Q, hipStream_t s) {
+  const size_t lds = (size_t)2 * m * m * sizeof(double2);
+  const hipError_t e = cplx_attrs();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cchol_inv, dim3(1), dim3(256), lds, s, m,
+                     reinterpret_cast<const double2*>(G), reinterpret_cast<double2*>(R),
+                     reinterpret_cast<double2*>(Rinv), fail);
+  launch_cright(n, m, m, 1, Z, Rinv, Q, s);
   return hipGetLastError();
 }
 

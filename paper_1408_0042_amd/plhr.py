@@ -310,6 +310,22 @@ def gram_c128(X: torch.Tensor, Y: Optional[torch.Tensor] = None,
     return out
 
 
+def rowmul_c128(Z: torch.Tensor, M: torch.Tensor) -> torch.Tensor:
+    """Y = Z M for complex128 device blocks Z (n, m) and M (m, k), m, k <= 64
+    (plhr_rowmul_c128), on torch's current stream."""
+    _require_cuda(Z, "Z", torch.complex128)
+    _require_cuda(M, "M", torch.complex128)
+    if Z.dim() != 2 or M.dim() != 2 or Z.shape[1] != M.shape[0]:
+        raise ValueError("Z must be (n, m) and M (m, k)")
+    n, m = Z.shape
+    k = M.shape[1]
+    Y = torch.empty((n, k), dtype=torch.complex128, device=Z.device)
+    L.check(L.load().plhr_rowmul_c128(n, C.c_void_p(Z.data_ptr()), m, C.c_void_p(M.data_ptr()),
+                                      k, C.c_void_p(Y.data_ptr()),
+                                      C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return Y
+
+
 def cholqr_c128(Z: torch.Tensor):
     """Q, R with Z = Q R, Q^H Q = I, R upper triangular with a real positive
     diagonal (plhr_cholqr_c128), for a complex128 device block (n, m),

@@ -231,3 +231,13 @@ def test_complex_cholqr_arguments_are_validated_on_the_host():
     assert lib.plhr_cholqr_c128(1000, Z, 8, C.c_void_p(4096 + 16), None, W, sz.value,
                                 None) == L.ERR_ARG                            # overlap
     assert lib.plhr_cholqr_c128(1000, None, 8, Q, None, W, sz.value, None) == L.ERR_ARG
+
+
+def test_complex_block_product_arguments_are_validated_on_the_host():
+    lib = L.load()
+    Z, M, Y = C.c_void_p(4096), C.c_void_p(1 << 24), C.c_void_p(1 << 26)
+    assert lib.plhr_rowmul_c128(0, None, 8, None, 4, None, None) == L.OK     # no rows
+    assert lib.plhr_rowmul_c128(100, Z, 65, M, 4, Y, None) == L.ERR_ARG
+    assert lib.plhr_rowmul_c128(100, Z, 8, M, 0, Y, None) == L.ERR_ARG
+    assert lib.plhr_rowmul_c128(100, Z, 8, None, 4, Y, None) == L.ERR_ARG
+    assert lib.plhr_rowmul_c128(100, Z, 8, M, 4, C.c_void_p(4096 + 32), None) == L.ERR_ARG
