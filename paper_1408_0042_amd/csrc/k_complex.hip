@@ -3,9 +3,10 @@
 // upper triangular with a real positive diagonal), Q = Z R^-1.
 //
 //   k_cchol_inv  one workgroup: R and R^-1 from G, in LDS (m <= 64)
-//   k_cright     Q = Z R^-1 (and the general product Y = Z M of the block
-//                updates), tiles of rows spread over workgroups, the small
-//                matrix and the tile in LDS
+//   k_cright     Q = Z R^-1, tiles of rows spread over workgroups, R^-1
+//                and the tile in LDS (the vector form, triangular or full)
+//   k_crowmul_mfma  the general product Y = Z M of the block updates on
+//                the FP64 matrix cores
 #include <cmath>
 
 #include "common.cuh"
@@ -122,6 +123,65 @@ __global__ __launch_bounds__(256) void k_cright(size_t n, int m, int k, int tri,
   }
 }
 
+// Y = Z M on the FP64 matrix cores (v_mfma_f64_16x16x4f64; lane l holds
+// A[l%16][l/16] and B[l/16][l%16], accumulator r of lane l is
+// D[4r + l/16][l%16]).  With Z', Y' the interleaved real views (n x 2m,
+// n x 2k), Y' = Z' M' where M' (2m x 2k) holds each complex entry of M as
+// the real 2 x 2 block [[re, im], [-im, re]]; M' is built in LDS.  Each
+// wavefront takes 16-row tiles of Z' and all 2k columns (up to 8 tiles of
+// 16), stepping the contraction 4 at a time.
+typedef double cd4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_crowmul_mfma(size_t n, int m, int k,
+                                                      const double* __restrict__ Z,
+                                                      const double2* __restrict__ M,
+                                                      double* __restrict__ Y) {
+  extern __shared__ double mp[];  // 2m x 2k, rows padded to an odd stride
+  const int K2 = 2 * m, N2 = 2 * k, NP = N2 + 1;
+  for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+    const int a = e / k, b = e - a * k;
+    const double2 v = M[e];
+    mp[(2 * a) * NP + 2 * b] = v.x;
+    mp[(2 * a) * NP + 2 * b + 1] = v.y;
+    mp[(2 * a + 1) * NP + 2 * b] = -v.y;
+    mp[(2 * a + 1) * NP + 2 * b + 1] = v.x;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int li = l & 15, lk = l >> 4;
+  const int nct = (N2 + 15) / 16;
+  const size_t ntiles = (n + 15) / 16;
+  for (size_t tile = (size_t)blockIdx.x * 4 + w; tile < ntiles; tile += (size_t)gridDim.x * 4) {
+    const size_t row0 = tile * 16;
+    const size_t ra = row0 + li;  // this lane's A row
+    cd4 acc[8];
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) acc[ct] = (cd4){0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < K2; kk += 4) {
+      const int kc = kk + lk;
+      const double a = (ra < n && kc < K2) ? Z[ra * K2 + kc] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct) {
+        if (ct < nct) {
+          const int col = ct * 16 + li;
+          const double b = (kc < K2 && col < N2) ? mp[kc * NP + col] : 0.0;
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      if (ct >= nct) continue;
+      const int col = ct * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t row = row0 + 4 * r + lk;
+        if (row < n && col < N2) Y[row * N2 + col] = acc[ct][r];
+      }
+    }
+  }
+}
+
 static bool cchol_attr_done = false;
 
 static hipError_t cplx_attrs() {
@@ -132,6 +192,9 @@ static hipError_t cplx_attrs() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_cright, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)((64 * 64 + kCrTile * 64) * sizeof(double2)));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_crowmul_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(128 * 129 * sizeof(double)));
   if (e != hipSuccess) return e;
   cchol_attr_done = true;
   return hipSuccess;
@@ -152,7 +215,12 @@ hipError_t launch_crowmul(size_t n, int m, int k, const double* Z, const double*
                           hipStream_t s) {
   const hipError_t e = cplx_attrs();
   if (e != hipSuccess) return e;
-  launch_cright(n, m, k, 0, Z, M, Y, s);
+  size_t nb = (n + 63) / 64;  // four 16-row tiles per workgroup
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_crowmul_mfma, dim3((unsigned)nb), dim3(256),
+                     (size_t)2 * m * (2 * k + 1) * sizeof(double), s, n, m, k, Z,
+                     reinterpret_cast<const double2*>(M), Y);
   return hipGetLastError();
 }
 
