@@ -9,7 +9,9 @@ problems with LAPACK through scipy, in the order and notation of the paper.
 Modules
   operators  sparse assembly of the model operators (FD Dirichlet, Bloch
              periodic, bilinear/trilinear finite elements) and a potential
-  mg         geometric multigrid V-cycle used as the HPD preconditioner T
+  mg         geometric multigrid V-cycle used as the HPD preconditioner T,
+             and the AV-MG / INV-MG preconditioners of Appendix A
+             (Algorithms 4 and 5)
   plhr       Algorithms 1, 2 and 3 of the paper (single-vector PLHR, block
              PLHR in complex arithmetic, block PLHR in real arithmetic), the
              final Rayleigh-Ritz step and the convergence test

@@ -75,3 +75,124 @@ def test_restriction_is_scaled_transpose_of_prolongation():
     assert np.isclose(rows.max(), 1.0)
     # each coarse column's weights sum to 2^d away from the boundary
     assert np.isclose(P.sum(axis=0).max(), 8.0)
+
+
+def test_bloch_vcycle_spectrally_equivalent():
+    """kappa(T A_theta) stays small at nonzero phases: the transfer must
+    pick up exp(-+i theta) across a periodic face in the right direction
+    (the opposite sign keeps T Hermitian positive definite but lets the
+    coarse correction point the wrong way, kappa ~ 10)."""
+    dims, th = (8, 8, 8), (0.6, 1.2, 1.8)
+    V = mg.VCycle("bloch", dims, 1.0, 0.5, 3, thetas=th)
+    A = ops.bloch_periodic(dims, 1.0, th, scale=0.5).toarray()
+    T = _dense_T(V, 512, np.complex128)
+    ev = np.linalg.eigvals(T @ A).real
+    assert ev.min() > 0.0
+    assert ev.max() / ev.min() < 3.0
+
+
+# -------------------------------------------------------------- AV-MG
+def test_abs_polynomial_positive_and_convergent():
+    """The damped Chebyshev series of |x| on [a, b] (a < 0 < b) is positive
+    on the whole interval (so p(L - sigma I) is SPD) and its error shrinks
+    with the degree."""
+    a, b = -3.0, 9.0
+    x = np.linspace(a, b, 40001)
+    errs = []
+    for deg in (4, 10, 20, 40):
+        c = mg.abs_polynomial(a, b, deg)
+        p = mg.cheb_eval(c, a, b, x)
+        assert p.min() > 0.0
+        errs.append(np.abs(p - np.abs(x)).max())
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 0.35 * (b - a) / 40 * 4
+
+
+def test_chebyshev_recurrence_matches_spectral_evaluation():
+    """p(S) X by the three-term recurrence equals U p(Lambda) U^T X from
+    the eigendecomposition of S."""
+    dims, h = (6, 5), 0.1
+    L = ops.fd_dirichlet(dims, h)
+    sigma = 300.0
+    S = L.toarray() - sigma * np.eye(30)
+    ev, U = np.linalg.eigh(S)
+    a, b = -sigma, 8.0 / h**2 - sigma
+    c = mg.abs_polynomial(a, b, 9)
+    X = np.random.default_rng(30).standard_normal((30, 3))
+    got = mg.cheb_apply(c, a, b, S, X)
+    want = U @ (mg.cheb_eval(c, a, b, ev)[:, None] * (U.T @ X))
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+def test_avmg_without_shift_is_the_plain_vcycle():
+    """sigma = 0: every level takes B_l = L_l (sqrt(sigma) h_l < delta),
+    Richardson with alpha = omega / diag is weighted Jacobi and the
+    coarsest |L_0|^-1 = L_0^-1, so Algorithm 4 is the V-cycle."""
+    dims, h = (16, 8), 1 / 17
+    V = mg.VCycle("fd", dims, h, 1.0, 3)
+    W = mg.AVMG(dims, h, 1.0, 3, 0.0)
+    X = np.random.default_rng(31).standard_normal((128, 4))
+    assert W.kind == ["laplacian", "laplacian", "laplacian"]
+    assert np.allclose(W.apply(X), V.apply(X), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("mode,absval", [("av", True), ("inv", False)])
+def test_single_level_is_the_exact_coarse_solve(mode, absval):
+    """One level: Algorithm 4 is |L - sigma I|^-1 and Algorithm 5 is
+    (L - sigma I)^-1; |S| is computed here as the square root of S^2."""
+    import scipy.linalg as sla
+    dims, h = (7, 6), 0.1
+    L = ops.fd_dirichlet(dims, h).toarray()
+    sigma = 401.0
+    S = L - sigma * np.eye(42)
+    W = mg.AVMG(dims, h, 1.0, 1, sigma, mode=mode)
+    T = W.apply(np.eye(42))
+    ref = np.linalg.inv(np.real(sla.sqrtm(S @ S)) if absval else S)
+    assert np.allclose(T, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_avmg_two_level_closed_form():
+    """One V-cycle of Algorithm 4 over two levels is
+    T = (I - E^2) B^-1 + E P |L_c - sigma|^-1 P^T E / 2^d,  E = (I - alpha B)^nu,
+    with B = p_m(L - sigma I) here (a deep shift)."""
+    dims, h = (8, 8), 1 / 9
+    L = ops.fd_dirichlet(dims, h)
+    sigma = 0.3 * 8 / h**2
+    W = mg.AVMG(dims, h, 1.0, 2, sigma, nu=2)
+    assert W.kind[0] == "poly"
+    n = 64
+    B = W.level_op(0, np.eye(n))
+    ev, U = np.linalg.eigh(L.toarray() - sigma * np.eye(n))
+    c, a, b = W.poly[0]
+    assert np.allclose(B, U @ np.diag(mg.cheb_eval(c, a, b, ev)) @ U.T, atol=1e-10 * np.abs(B).max())
+    E = np.linalg.matrix_power(np.eye(n) - W.alpha[0] * B, 2)
+    Lc = W.L[1].toarray()
+    evc, Uc = np.linalg.eigh(Lc - sigma * np.eye(Lc.shape[0]))
+    Tc = Uc @ np.diag(1.0 / np.abs(evc)) @ Uc.T
+    P = W.P[0].toarray()
+    ref = (np.eye(n) - E @ E) @ np.linalg.inv(B) + E @ P @ Tc @ P.T @ E / 4.0
+    T = W.apply(np.eye(n))
+    assert np.allclose(T, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("d,N,frac,levels", [(2, 32, 0.05, 4), (2, 32, 0.2, 4), (3, 8, 0.25, 3)])
+def test_avmg_spd_and_better_than_vcycle_at_deep_shifts(d, N, frac, levels):
+    """Algorithm 4 is SPD and approximates |L - sigma I|^-1 far better than
+    the V-cycle of L does: kappa(T |L - sigma I|) drops by >= 8x."""
+    h = 1.0 / (N + 1)
+    dims = (N,) * d
+    Ld = ops.fd_dirichlet(dims, h).toarray()
+    n = Ld.shape[0]
+    ev, U = np.linalg.eigh(Ld)
+    sigma = frac * ev.max()
+    absS = (U * np.abs(ev - sigma)) @ U.T
+    kap = {}
+    for name, T in (("vc", mg.VCycle("fd", dims, h, 1.0, levels)),
+                    ("av", mg.AVMG(dims, h, 1.0, levels, sigma))):
+        Tm = T.apply(np.eye(n))
+        if name == "av":
+            assert np.linalg.norm(Tm - Tm.T) <= 1e-12 * np.linalg.norm(Tm)
+            assert np.linalg.eigvalsh(0.5 * (Tm + Tm.T)).min() > 0.0
+        e = np.linalg.eigvals(Tm @ absS).real
+        kap[name] = e.max() / e.min()
+    assert kap["av"] * 8.0 < kap["vc"]
