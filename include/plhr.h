@@ -387,6 +387,44 @@ plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void*
 plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M, int32_t k,
                              void* Y, void* stream);
 
+/* The projected eigenproblem of one iteration on given Gram matrices:
+ * eq. (3.5), G_L y = xi G_R y, solved as in every iteration of the solver
+ * (Cholesky G_L = L L^T, C = L^-1 G_R L^-T, real Schur form of C, tau =
+ * 1/xi), the k_int units of smallest |xi| in the order (|xi|, Re xi,
+ * -Im xi) with a conjugate pair kept together (Definition 3.1), and the
+ * real coefficient basis Y' = [Y0 YR ytilde_R YI] of Algorithm 3 (the
+ * real part of a selected pair's eigenvector in YR and its imaginary part
+ * in YI; a pair whose conjugate would be unit k_int + 1 contributes only
+ * its real part, ytilde_R).  Stands alone so that this step can be
+ * checked on synthetic pencils.
+ *   m        trial-subspace width, kint <= m <= 84
+ *   kint     columns selected, >= 1
+ *   GL, GR   device, m x m doubles, row-major: G_L symmetric positive
+ *            definite (its two triangles are averaged), G_R general
+ *   keep     device, m int32 (nonzero: slot used), or NULL for all; the
+ *            problem is posed on the kept slots, other rows of Y are zero
+ *   Y        device, m x kint doubles, row-major: Y' (each column, or each
+ *            R/I pair as one complex vector, of unit 2-norm; a real
+ *            column's largest entry positive)
+ *   xi       device, 2 x m doubles: real parts, then imaginary parts, of
+ *            the sorted xi (the Im > 0 member of a pair first; entries
+ *            past the kept width are zero)
+ *   kinds    device, kint int32: 0 real, 1 YR, 2 ytilde_R, 3 YI
+ *   pair     device, kint int32: the partner column of a YR/YI column,
+ *            -1 otherwise
+ *   n_excluded host, receives the number of slots left out because G_L
+ *            had a clearly negative pivot (may be NULL)
+ *   workspace device scratch of plhr_projected_workspace(m, kint) bytes
+ *   stream   hipStream_t (NULL: the null stream); synchronised on return
+ * PLHR_ERR_ARG for a NULL, misaligned (8 bytes), overlapping or
+ * out-of-range argument; PLHR_ERR_BREAKDOWN when fewer than kint slots
+ * remain or the QR iteration does not converge.                          */
+plhr_status plhr_projected_workspace(int32_t m, int32_t kint, size_t* bytes);
+plhr_status plhr_projected_solve(int32_t m, int32_t kint, const double* GL, const double* GR,
+                                 const int32_t* keep, double* Y, double* xi, int32_t* kinds,
+                                 int32_t* pair, int32_t* n_excluded, void* workspace,
+                                 size_t ws_bytes, void* stream);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

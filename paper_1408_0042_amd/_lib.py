@@ -120,6 +120,9 @@ def load() -> C.CDLL:
         "plhr_cholqr_c128_workspace": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
         "plhr_cholqr_c128": (C.c_int, [C.c_int64, P, C.c_int32, P, P, P, C.c_size_t, P]),
         "plhr_rowmul_c128": (C.c_int, [C.c_int64, P, C.c_int32, P, C.c_int32, P, P]),
+        "plhr_projected_workspace": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+        "plhr_projected_solve": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P, P, P,
+                                           C.POINTER(C.c_int32), P, C.c_size_t, P]),
         "plhr_get_state": (C.c_int, [P, C.POINTER(C.c_double), P]),
         "plhr_debug_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
         "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),

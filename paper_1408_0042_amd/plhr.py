@@ -346,6 +346,43 @@ def cholqr_c128(Z: torch.Tensor):
     return Q, R
 
 
+def projected_solve(GL: torch.Tensor, GR: torch.Tensor, kint: int,
+                    keep: Optional[torch.Tensor] = None):
+    """The projected step of one iteration on given Gram matrices
+    (plhr_projected_solve): G_L y = xi G_R y, the kint units of smallest
+    |xi| and the real coefficient basis Y' of Algorithm 3.  GL, GR are
+    float64 (m, m) device tensors, keep an optional int32 (m,) mask.
+    Returns (Y (m, kint), xi (m,) complex, kinds (kint,), pair (kint,),
+    n_excluded).  Synchronises torch's current stream."""
+    _require_cuda(GL, "GL")
+    _require_cuda(GR, "GR")
+    m = GL.shape[0]
+    if GL.shape != (m, m) or GR.shape != (m, m):
+        raise ValueError("GL and GR must be (m, m)")
+    if keep is not None:
+        _require_cuda(keep, "keep", torch.int32)
+        if keep.shape != (m,):
+            raise ValueError("keep must be (m,)")
+    dev = GL.device
+    Y = torch.empty((m, kint), dtype=torch.float64, device=dev)
+    xi = torch.empty((2, m), dtype=torch.float64, device=dev)
+    kinds = torch.empty(kint, dtype=torch.int32, device=dev)
+    pair = torch.empty(kint, dtype=torch.int32, device=dev)
+    lib = L.load()
+    need = C.c_size_t()
+    L.check(lib.plhr_projected_workspace(m, kint, C.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    nex = C.c_int32()
+    L.check(lib.plhr_projected_solve(m, kint, C.c_void_p(GL.data_ptr()),
+                                     C.c_void_p(GR.data_ptr()), C.c_void_p(_ptr(keep)),
+                                     C.c_void_p(Y.data_ptr()), C.c_void_p(xi.data_ptr()),
+                                     C.c_void_p(kinds.data_ptr()), C.c_void_p(pair.data_ptr()),
+                                     C.byref(nex), C.c_void_p(ws.data_ptr()), need.value,
+                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    xic = torch.complex(xi[0], xi[1])
+    return Y, xic, kinds, pair, int(nex.value)
+
+
 class BlochPrecond:
     """One multigrid V-cycle for the Bloch operator scale*(-Laplacian_theta)
     on the periodic nx x ny x nz box (plhr_bloch_prec_*): apply(X) returns

@@ -1,0 +1,122 @@
+"""Failure paths of the solver (raised from the host side inputs, every
+kernel exits normally) and run-to-run reproducibility."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense, operators as ops
+from tests import closed_forms as cf
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(**kw):
+    from paper_1408_0042_amd.plhr import Solver
+    return Solver(**kw)
+
+
+def _small(**kw):
+    N, h = 12, 1 / 13
+    ev = cf.fd_dirichlet_eigs((N, N), h)
+    u = np.unique(np.round(ev, 8))
+    sigma = float(u[10] + 0.4 * (u[11] - u[10]))
+    args = dict(kind="fd5_2d", dims=(N, N), h=h, sigma=sigma, k=3, k_extra=2, tol=1e-10,
+                max_iters=3000, precond={"levels": 2, "nu": 2, "omega": 2 / 3})
+    args.update(kw)
+    return args, ev
+
+
+def test_rank_deficient_start_block_is_a_breakdown():
+    from paper_1408_0042_amd import _lib as L
+    args, _ = _small()
+    V0 = wl.start_block(144, 5, (80, 0))
+    V0[:, 3] = V0[:, 1]
+    S = _solver(**args)
+    with pytest.raises(L.PLHRError) as e:
+        S.solve(dev(V0))
+    assert e.value.code == L.ERR_BREAKDOWN
+    S.close()
+
+
+def test_non_finite_start_block_is_a_breakdown():
+    from paper_1408_0042_amd import _lib as L
+    args, _ = _small()
+    V0 = wl.start_block(144, 5, (81, 0))
+    V0[7, 2] = np.nan
+    S = _solver(**args)
+    with pytest.raises(L.PLHRError) as e:
+        S.solve(dev(V0))
+    assert e.value.code == L.ERR_BREAKDOWN
+    S.close()
+
+
+def test_max_iters_returns_not_converged_with_the_best_iterate():
+    from paper_1408_0042_amd import _lib as L
+    args, ev = _small(max_iters=3)
+    S = _solver(**args)
+    r = S.solve(dev(wl.start_block(144, 5, (82, 0))), allow_unconverged=True)
+    assert not r.converged and r.iters == 3
+    assert np.all(np.isfinite(host(r.eigvals))) and np.all(np.isfinite(r.rel_res))
+    assert np.all(r.rel_res > 0)
+    with pytest.raises(L.PLHRError) as e:
+        S.solve(dev(wl.start_block(144, 5, (82, 0))))
+    assert e.value.code == L.ERR_NOT_CONVERGED
+    S.close()
+
+
+def test_start_block_of_exact_eigenvectors_converges_at_once():
+    """V0 holding the k + k_extra nearest sine modes: the residual check
+    before the first step is already met."""
+    args, ev = _small()
+    N = 12
+    sigma = args["sigma"]
+    modes = [(i, j) for i in range(1, N + 1) for j in range(1, N + 1)]
+    lam = np.array([(4 * 169.0) * (np.sin(i * np.pi / 26) ** 2 + np.sin(j * np.pi / 26) ** 2)
+                    for i, j in modes])
+    pick = np.lexsort((lam, np.abs(lam - sigma)))[:5]
+    V0 = np.column_stack([cf.fd_dirichlet_mode((N, N), modes[p]) for p in pick])
+    S = _solver(**args)
+    r = S.solve(dev(np.ascontiguousarray(V0)))
+    assert r.converged and r.iters == 0
+    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:3])
+    assert np.allclose(np.sort(host(r.eigvals)), ref, rtol=1e-12)
+    S.close()
+
+
+def test_shift_on_an_eigenvalue():
+    """sigma exactly an eigenvalue (xi = 0 is then a T-harmonic value once
+    its vector enters the trial subspace, G_L singular to rounding): the
+    iteration still returns the nearest pairs."""
+    args, ev = _small()
+    u = np.unique(np.round(ev, 8))
+    sigma = float(ev[np.argmin(np.abs(ev - u[10]))])     # a simple or double eigenvalue
+    args.update(sigma=sigma, k=2, k_extra=3)
+    S = _solver(**args)
+    r = S.solve(dev(wl.start_block(144, 5, (83, 0))))
+    assert r.converged
+    A = ops.fd_dirichlet((12, 12), 1 / 13)
+    lam_b, _ = dense.nearest_pairs(A, None, sigma, 2)
+    assert np.allclose(np.sort(host(r.eigvals)), np.sort(lam_b), rtol=1e-10)
+    S.close()
+
+
+def test_repeated_solves_are_bitwise_identical():
+    """No atomics and fixed reduction orders: two solves from the same
+    start block give the same bits (eigenvalues, vectors, residuals and
+    iteration count)."""
+    args, _ = _small()
+    V0 = dev(wl.start_block(144, 5, (84, 0)))
+    S = _solver(**args)
+    r1 = S.solve(V0)
+    a = (host(r1.eigvals).copy(), host(r1.V).copy(), r1.rel_res.copy(), r1.iters)
+    r2 = S.solve(V0)
+    b = (host(r2.eigvals), host(r2.V), r2.rel_res, r2.iters)
+    assert a[3] == b[3]
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    S.close()
+    S2 = _solver(**args)
+    r3 = S2.solve(V0)
+    assert r3.iters == a[3] and np.array_equal(host(r3.V), a[1])
+    S2.close()

@@ -108,23 +108,29 @@ def test_3d_multigrid_mixed_precision_matches_brute_force():
 
 def test_largest_trial_subspace_m84_matches_closed_form():
     """k + k_extra = 21, the largest block the on-chip projected solver
-    takes (m = 84): every small kernel at its LDS and thread limits."""
+    takes (m = 84): every small kernel at its LDS and thread limits.  The
+    stopping tolerance is set from the gap so that the residual meets
+    ||r|| <= 1e-8 gap, where the subspace sine is bounded by ~1e-8."""
     from tests.gpu_util import dev, host
     N, h, k, kx = 32, 1 / 33, 16, 5
     ev = cf.fd_dirichlet_eigs((N, N), h)
     u = np.unique(np.round(ev, 8))
     sigma = float(u[32] + 0.4 * (u[33] - u[32]))
-    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:k])
-    S = _solver(kind="fd5_2d", dims=(N, N), h=h, sigma=sigma, k=k, k_extra=kx, tol=1e-10,
-                max_iters=3000, precond={"levels": 3, "nu": 2, "omega": 2 / 3})
+    order = np.lexsort((ev, np.abs(ev - sigma)))
+    ref = np.sort(ev[order][:k])
+    # gap between the wanted set and the rest of the spectrum
+    rest = ev[order][k:]
+    rest = rest[np.abs(rest - ref[:, None]).min(axis=0) > 1e-8 * ev.max()]
+    gap = np.abs(rest[None, :] - ref[:, None]).min()
+    norm = 8.0 / h**2 + abs(sigma)
+    tol = 1e-8 * gap / norm
+    S = _solver(kind="fd5_2d", dims=(N, N), h=h, sigma=sigma, k=k, k_extra=kx, tol=tol,
+                max_iters=4000, precond={"levels": 3, "nu": 2, "omega": 2 / 3})
     r = S.solve(dev(wl.start_block(N * N, k + kx, (118, 0))))
     assert r.converged
     assert np.allclose(np.sort(host(r.eigvals)), ref, rtol=1e-10)
     A = ops.fd_dirichlet((N, N), h)
     _, U = dense.cluster_basis(A, None, sigma, k)
-    # the sine is bounded by residual * ||A|| / gap: ||A||_1 ~ 8.7e3 and
-    # the final Rayleigh-Ritz on span(V) (with the unconverged guard
-    # columns) leaves the edge pair at ~1e-9
-    assert dense.subspace_sine(U, host(r.V)) < 1e-6
-    assert np.all(r.rel_res <= 1e-8)
+    assert dense.subspace_sine(U, host(r.V)) < 1e-7
+    assert np.all(r.rel_res <= 10 * tol)
     S.close()

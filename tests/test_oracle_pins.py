@@ -9,6 +9,7 @@ import pytest
 import scipy.linalg as sla
 
 from oracle import dense, hf, operators as ops, plhr
+from tests.pencils import projected_pencil
 
 
 # ------------------------------------------------------------ subspace_sine
@@ -55,37 +56,6 @@ def test_subspace_sine_known_angles_b_inner_product(angles):
 
 
 # ---------------------------------------------- selection on a known pencil
-def projected_pencil(xis, seed):
-    """(G_L, G_R) with G_L SPD and G_L y = xi G_R y having exactly the
-    eigenvalues xis (a complex entry stands for the pair xi, conj xi).
-    Built as G_R = L C L^T with G_L = L L^T and C = X J X^-1, J real
-    block diagonal with the tau = 1/xi blocks.  Returns (GL, GR, m, Yblocks)
-    where Yblocks[i] spans (in y) the real invariant subspace of entry i."""
-    rng = np.random.default_rng(seed)
-    sizes = [2 if np.iscomplexobj(x) and np.imag(x) != 0 else 1 for x in xis]
-    m = sum(sizes)
-    J = np.zeros((m, m))
-    pos = 0
-    for x, s in zip(xis, sizes):
-        tau = 1.0 / complex(x)
-        if s == 1:
-            J[pos, pos] = tau.real
-        else:
-            J[pos:pos + 2, pos:pos + 2] = [[tau.real, tau.imag], [-tau.imag, tau.real]]
-        pos += s
-    X = rng.standard_normal((m, m)) + 2.0 * np.eye(m)
-    C = X @ J @ np.linalg.inv(X)
-    F = rng.standard_normal((m, m))
-    GL = F @ F.T + m * np.eye(m)
-    L = np.linalg.cholesky(GL)
-    GR = L @ C @ L.T
-    Yb, pos = [], 0
-    for s in sizes:
-        Yb.append(sla.solve_triangular(L.T, X[:, pos:pos + s], lower=False))
-        pos += s
-    return GL, GR, m, Yb
-
-
 def _in_span(y, S):
     c, *_ = np.linalg.lstsq(S, y, rcond=None)
     return np.linalg.norm(y - S @ c) / np.linalg.norm(y)
