@@ -363,7 +363,8 @@ plhr_status plhr_gram_c128(int64_t n, const void* X, int32_t mx, const void* Y, 
  *   Z        device, n x m complex128 (interleaved), point-major; read only
  *   m        columns, 1 <= m <= 64
  *   Q        device, n x m complex128, written; must not overlap Z
- *   R        device, m x m complex128 row-major (lower part zero), or NULL
+ *   R        device, m x m complex128 row-major (lower part zero), or NULL;
+ *            must not overlap Z, Q or the workspace
  *   workspace device scratch of plhr_cholqr_c128_workspace(n, m) bytes
  *   stream   hipStream_t (NULL: the null stream)
  * Synchronises the stream to report a breakdown: PLHR_ERR_NOT_HPD when
@@ -380,10 +381,11 @@ plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void*
  *   n        rows, >= 0 (0: nothing is done)
  *   Z        device, n x m complex128 (interleaved), point-major
  *   M        device, m x k complex128, row-major
- *   Y        device, n x k complex128, written; must not overlap Z
+ *   Y        device, n x k complex128, written; must not overlap Z or M
  *   1 <= m, k <= 64
  *   stream   hipStream_t (NULL: the null stream); asynchronous
- * PLHR_ERR_ARG for a NULL, overlapping or out-of-range argument.        */
+ * Z, M and Y 16-byte aligned.  PLHR_ERR_ARG for a NULL, misaligned,
+ * overlapping or out-of-range argument.                                  */
 plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M, int32_t k,
                              void* Y, void* stream);
 
@@ -407,8 +409,9 @@ plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M,
  *            R/I pair as one complex vector, of unit 2-norm; a real
  *            column's largest entry positive)
  *   xi       device, 2 x m doubles: real parts, then imaginary parts, of
- *            the sorted xi (the Im > 0 member of a pair first; entries
- *            past the kept width are zero)
+ *            the xi of the sorted units, one entry per unit (a conjugate
+ *            pair by its Im > 0 member); entries past the number of
+ *            units are zero
  *   kinds    device, kint int32: 0 real, 1 YR, 2 ytilde_R, 3 YI
  *   pair     device, kint int32: the partner column of a YR/YI column,
  *            -1 otherwise

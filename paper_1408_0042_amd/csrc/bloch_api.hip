@@ -349,11 +349,22 @@ plhr_status plhr_rowmul_c128(int64_t n, const void* Z, int32_t m, const void* M,
     set_error("plhr_rowmul_c128: NULL argument");
     return PLHR_ERR_ARG;
   }
-  const size_t zb = (size_t)n * m * 16, yb = (size_t)n * k * 16;
+  if (((uintptr_t)Z | (uintptr_t)M | (uintptr_t)Y) & 15) {
+    set_error("plhr_rowmul_c128: Z, M and Y must be 16-byte aligned");
+    return PLHR_ERR_ARG;
+  }
+  // every workgroup stages M while others already store Y: M must not
+  // overlap Y either
+  const size_t zb = (size_t)n * m * 16, yb = (size_t)n * k * 16, mb = (size_t)m * k * 16;
   const char* z = static_cast<const char*>(Z);
   const char* y = static_cast<const char*>(Y);
+  const char* mm = static_cast<const char*>(M);
   if (z < y + yb && y < z + zb) {
     set_error("plhr_rowmul_c128: Z and Y overlap");
+    return PLHR_ERR_ARG;
+  }
+  if (mm < y + yb && y < mm + mb) {
+    set_error("plhr_rowmul_c128: M and Y overlap");
     return PLHR_ERR_ARG;
   }
   PLHR_HIP_CHECK(launch_crowmul((size_t)n, m, k, static_cast<const double*>(Z),
@@ -396,6 +407,16 @@ plhr_status plhr_cholqr_c128(int64_t n, const void* Z, int32_t m, void* Q, void*
   if (zb < qb + bytes && qb < zb + bytes) {
     set_error("plhr_cholqr_c128: Z and Q overlap");
     return PLHR_ERR_ARG;
+  }
+  if (R) {  // R is written by the factor kernel while Z, Q and the workspace are in use
+    const char* rb = static_cast<const char*>(R);
+    const size_t rbytes = (size_t)m * m * 16;
+    const char* wb = static_cast<const char*>(workspace);
+    if ((rb < zb + bytes && zb < rb + rbytes) || (rb < qb + bytes && qb < rb + rbytes) ||
+        (rb < wb + need && wb < rb + rbytes)) {
+      set_error("plhr_cholqr_c128: R overlaps Z, Q or the workspace");
+      return PLHR_ERR_ARG;
+    }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(workspace);

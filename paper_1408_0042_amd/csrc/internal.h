@@ -432,5 +432,12 @@ void launch_final_res(const SmallParams& p, const double* part, int nblk, SmallB
 void launch_colsum_first(const double* part, int nblk, int k, double* out, hipStream_t s);
 hipError_t small_set_attributes(int m, int kint);
 hipError_t tharm_set_attributes(int m, int kint);
+// Raise a kernel's dynamic-LDS limit to the device's per-workgroup maximum.
+// Limits are per function and process-wide, so they are never set to a
+// size of one context (a later, smaller context would lower the limit
+// under an earlier, larger one); the size a launch uses is its own.
+hipError_t set_lds_limit(const void* kernel);
+// Largest dynamic LDS the projected-solver kernels use at (m, kint).
+size_t tharm_lds_bytes(int m, int kint);
 
 }  // namespace plhr

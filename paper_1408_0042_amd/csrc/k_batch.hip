@@ -505,10 +505,10 @@ void launch_hf_b(const Chunk* ch, int nch, const BProb* pr, const double* V, int
                      accumulate);
 }
 hipError_t batch_set_attributes(int m) {
+  (void)m;
   hipError_t e = hipSuccess;
-#define SETB(T)                                                                              \
-  e = hipFuncSetAttribute((const void*)k_rowmul_b<T>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                          (int)((size_t)m * (T * 16 + 4) * sizeof(double)));                   \
+#define SETB(T)                                  \
+  e = set_lds_limit((const void*)k_rowmul_b<T>); \
   if (e != hipSuccess) return e;
   SETB(1) SETB(2) SETB(3) SETB(4) SETB(5) SETB(6)
 #undef SETB

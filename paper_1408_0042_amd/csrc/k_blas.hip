@@ -206,6 +206,25 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   out[e] = s;
 }
 
+hipError_t set_lds_limit(const void* kernel) {
+  int dev = 0, lim = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
+          hipSuccess &&
+      optin > lim)
+    lim = optin;
+  // the limit covers the kernel's static LDS as well
+  hipFuncAttributes fa{};
+  e = hipFuncGetAttributes(&fa, kernel);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             lim - (int)fa.sharedSizeBytes);
+}
+
 int gram_blocks(size_t n) {
   size_t nb = (n + 511) / 512;
   if (nb > 512) nb = 512;

@@ -172,13 +172,11 @@ void launch_rowmul_mfma(size_t n, double* const* X, int narr, int ld, int m, con
 }
 
 hipError_t mfma_set_attributes(int m, int kint) {
-  // largest dynamic LDS each row-product instance can ask for
+  (void)m;
   (void)kint;
   hipError_t e = hipSuccess;
-#define SET_ROW(T)                                                                         \
-  e = hipFuncSetAttribute((const void*)k_rowmul_mfma<T>,                                   \
-                          hipFuncAttributeMaxDynamicSharedMemorySize,                      \
-                          (int)rowmul_mfma_shm(m, T * 16, 0));                             \
+#define SET_ROW(T)                                          \
+  e = set_lds_limit((const void*)k_rowmul_mfma<T>);         \
   if (e != hipSuccess) return e;
   SET_ROW(1) SET_ROW(2) SET_ROW(3) SET_ROW(4) SET_ROW(5) SET_ROW(6)
 #undef SET_ROW

@@ -705,12 +705,9 @@ void launch_final_res_b(const BatchSmall* bs, int nb, hipStream_t s) {
 hipError_t small_set_attributes(int m, int kint) {
   hipError_t e = tharm_set_attributes(m, kint);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_ortho_small_b, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(((size_t)2 * m * m + m) * sizeof(double)));
+  e = set_lds_limit((const void*)k_ortho_small_b);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_ortho_small,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(((size_t)2 * m * m + m) * sizeof(double)));
+  return set_lds_limit((const void*)k_ortho_small);
 }
 
 }  // namespace plhr

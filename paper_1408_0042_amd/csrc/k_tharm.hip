@@ -21,6 +21,7 @@
 //                   together, selection, eigenvectors of T by back
 //                   substitution (16 lanes per eigenvector), y = L^-T Q x,
 //                   normalisation and scatter into Y'.
+#include <algorithm>
 #include <cmath>
 
 #include "common.cuh"
@@ -1140,20 +1141,21 @@ static size_t vectors_lds(int m, int kint) {
 }
 
 hipError_t tharm_set_attributes(int m, int kint) {
-  const void* fr[2] = {(const void*)k_tharm_reduce, (const void*)k_tharm_reduce_b};
-  const void* fq[2] = {(const void*)k_tharm_qr, (const void*)k_tharm_qr_b};
-  const void* fv[2] = {(const void*)k_tharm_vectors, (const void*)k_tharm_vectors_b};
-  for (int i = 0; i < 2; ++i) {
-    hipError_t e = hipFuncSetAttribute(fr[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)reduce_lds(m));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(fq[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_lds(m));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(fv[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)vectors_lds(m, kint));
+  (void)m;
+  (void)kint;
+  const void* f[6] = {(const void*)k_tharm_reduce,  (const void*)k_tharm_reduce_b,
+                      (const void*)k_tharm_qr,      (const void*)k_tharm_qr_b,
+                      (const void*)k_tharm_vectors, (const void*)k_tharm_vectors_b};
+  for (const void* k : f) {
+    const hipError_t e = set_lds_limit(k);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Largest dynamic LDS the three kernels ask for at (m, kint).
+size_t tharm_lds_bytes(int m, int kint) {
+  return std::max(reduce_lds(m), std::max(qr_lds(m), vectors_lds(m, kint)));
 }
 
 void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {

@@ -7,20 +7,19 @@
 // singular G_R) independently of the rest of the iteration.
 #include <cstdint>
 #include <string>
-#include <vector>
 
 #include "internal.h"
 
 using namespace plhr;
 
 namespace {
-size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct ProjLayout {
   size_t glr, keep, work, st, total;
 };
 
-ProjLayout proj_layout(int m) {
+constexpr ProjLayout proj_layout(int m) {
   ProjLayout L{};
   size_t o = 0;
   L.glr = o;
@@ -34,6 +33,125 @@ ProjLayout proj_layout(int m) {
   L.total = o;
   return L;
 }
+
+// Stage the inputs for the projected-solver kernels: [G_L | G_R] side by
+// side (m x 2m), the slot mask (all slots when keep is null) and a
+// cleared status block.  One kernel instead of copies and fills, so that
+// the sequence holds kernel launches only.
+__global__ __launch_bounds__(256) void k_proj_stage(int m, const double* __restrict__ GL,
+                                                    const double* __restrict__ GR,
+                                                    const int* __restrict__ keep,
+                                                    double* __restrict__ GLR, int* __restrict__ kp,
+                                                    DevStatus* st) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+  const int tot = 2 * m * m;
+  for (int e = tid; e < tot; e += nt) {
+    const int i = e / (2 * m), j = e - i * 2 * m;
+    GLR[e] = (j < m) ? GL[i * m + j] : GR[i * m + (j - m)];
+  }
+  for (int e = tid; e < m; e += nt) kp[e] = keep ? keep[e] : 1;
+  if (tid == 0) {
+    DevStatus z{};
+    *st = z;
+  }
+}
+
+// The device status of the projected step as two int32: the raised
+// plhr_status (0: none) and the number of slots left out.
+__global__ void k_proj_status(const DevStatus* st, int32_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = st->error;
+    out[1] = st->n_excluded;
+  }
+}
+
+// Checks shared by both entry points (workspace excluded).
+plhr_status proj_check(const char* name, int m, int kint, const double* GL, const double* GR,
+                       const int32_t* keep, const double* Y, const double* xi,
+                       const int32_t* kinds, const int32_t* pair, const void* extra,
+                       size_t extra_bytes) {
+  if (kint < 1 || m < kint || m > kMaxM) {
+    set_error(std::string(name) + ": need 1 <= kint <= m <= " + std::to_string(kMaxM));
+    return PLHR_ERR_ARG;
+  }
+  if (!GL || !GR || !Y || !xi || !kinds || !pair) {
+    set_error(std::string(name) + ": NULL argument");
+    return PLHR_ERR_ARG;
+  }
+  if (((uintptr_t)GL | (uintptr_t)GR | (uintptr_t)Y | (uintptr_t)xi) & 7 ||
+      ((uintptr_t)keep | (uintptr_t)kinds | (uintptr_t)pair) & 3) {
+    set_error(std::string(name) + ": misaligned argument (8 bytes for doubles, 4 for int32)");
+    return PLHR_ERR_ARG;
+  }
+  struct Span {
+    const char* p;
+    size_t b;
+  };
+  const size_t mm = (size_t)m * m * sizeof(double);
+  const Span in[3] = {{(const char*)GL, mm}, {(const char*)GR, mm},
+                      {(const char*)keep, keep ? (size_t)m * 4 : 0}};
+  const Span out[5] = {{(const char*)Y, (size_t)m * kint * sizeof(double)},
+                       {(const char*)xi, (size_t)2 * m * sizeof(double)},
+                       {(const char*)kinds, (size_t)kint * 4},
+                       {(const char*)pair, (size_t)kint * 4},
+                       {(const char*)extra, extra ? extra_bytes : 0}};
+  for (const Span& a : in)
+    for (const Span& b : out)
+      if (a.b && b.b && a.p < b.p + b.b && b.p < a.p + a.b) {
+        set_error(std::string(name) + ": an input overlaps an output");
+        return PLHR_ERR_ARG;
+      }
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j)
+      if (out[i].b && out[j].b && out[i].p < out[j].p + out[j].b &&
+          out[j].p < out[i].p + out[i].b) {
+        set_error(std::string(name) + ": outputs overlap each other");
+        return PLHR_ERR_ARG;
+      }
+  int dev = 0, lim = 0;
+  PLHR_HIP_CHECK(hipGetDevice(&dev));
+  PLHR_HIP_CHECK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
+          hipSuccess &&
+      optin > lim)
+    lim = optin;
+  // headroom for the kernels' static LDS (index lists, reduction slots)
+  if (tharm_lds_bytes(m, kint) + 8192 > (size_t)lim) {
+    set_error(std::string(name) + ": kint too large for m (the selected vectors do not fit "
+              "one workgroup's LDS)");
+    return PLHR_ERR_ARG;
+  }
+  return PLHR_OK;
+}
+
+// Enqueue staging and the three projected-solver kernels on s, with the
+// scratch area at w (proj_layout(m).total bytes).
+plhr_status proj_enqueue(int m, int kint, const double* GL, const double* GR,
+                         const int32_t* keep, double* Y, double* xi, int32_t* kinds,
+                         int32_t* pair, char* w, hipStream_t s, DevStatus** st_out) {
+  const ProjLayout L = proj_layout(m);
+  SmallBufs sb{};
+  sb.GLR = (double*)(w + L.glr);
+  sb.keep = (int*)(w + L.keep);
+  sb.work = (double*)(w + L.work);
+  sb.Y = Y;
+  sb.xi = xi;
+  sb.kinds = kinds;
+  sb.pair = pair;
+  DevStatus* st = (DevStatus*)(w + L.st);
+  SmallParams sp{};
+  sp.m = m;
+  sp.kint = kint;
+  const int blocks = (2 * m * m + 255) / 256;
+  hipLaunchKernelGGL(k_proj_stage, dim3(blocks), dim3(256), 0, s, m, GL, GR, keep, sb.GLR,
+                     sb.keep, st);
+  launch_tharm_small(sp, sb, st, s);
+  PLHR_HIP_CHECK(hipGetLastError());
+  *st_out = st;
+  return PLHR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -55,71 +173,27 @@ plhr_status plhr_projected_solve(int32_t m, int32_t kint, const double* GL, cons
   size_t need = 0;
   const plhr_status s0 = plhr_projected_workspace(m, kint, &need);
   if (s0 != PLHR_OK) return s0;
-  if (!GL || !GR || !Y || !xi || !kinds || !pair || !workspace) {
-    set_error("plhr_projected_solve: NULL argument");
+  if (!workspace) {
+    set_error("plhr_projected_solve: NULL workspace");
     return PLHR_ERR_ARG;
   }
   if (ws_bytes < need) {
     set_error("plhr_projected_solve: workspace smaller than plhr_projected_workspace");
     return PLHR_ERR_ARG;
   }
-  if (((uintptr_t)GL | (uintptr_t)GR | (uintptr_t)Y | (uintptr_t)xi | (uintptr_t)workspace) & 7) {
-    set_error("plhr_projected_solve: matrices and workspace must be 8-byte aligned");
+  if ((uintptr_t)workspace & 255) {
+    set_error("plhr_projected_solve: workspace must be 256-byte aligned");
     return PLHR_ERR_ARG;
   }
-  // inputs must not overlap the outputs or the workspace
-  struct Span {
-    const char* p;
-    size_t b;
-  };
-  const size_t mm = (size_t)m * m * sizeof(double);
-  const Span in[3] = {{(const char*)GL, mm}, {(const char*)GR, mm},
-                      {(const char*)keep, keep ? (size_t)m * 4 : 0}};
-  const Span out[5] = {{(const char*)Y, (size_t)m * kint * sizeof(double)},
-                       {(const char*)xi, (size_t)2 * m * sizeof(double)},
-                       {(const char*)kinds, (size_t)kint * 4},
-                       {(const char*)pair, (size_t)kint * 4},
-                       {(const char*)workspace, need}};
-  for (const Span& a : in)
-    for (const Span& b : out)
-      if (a.b && b.b && a.p < b.p + b.b && b.p < a.p + a.b) {
-        set_error("plhr_projected_solve: an input overlaps an output or the workspace");
-        return PLHR_ERR_ARG;
-      }
-  for (int i = 0; i < 5; ++i)
-    for (int j = i + 1; j < 5; ++j)
-      if (out[i].p < out[j].p + out[j].b && out[j].p < out[i].p + out[i].b) {
-        set_error("plhr_projected_solve: outputs overlap each other or the workspace");
-        return PLHR_ERR_ARG;
-      }
+  plhr_status c = proj_check("plhr_projected_solve", m, kint, GL, GR, keep, Y, xi, kinds, pair,
+                             workspace, need);
+  if (c != PLHR_OK) return c;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const ProjLayout L = proj_layout(m);
-  char* w = static_cast<char*>(workspace);
-  SmallBufs sb{};
-  sb.GLR = (double*)(w + L.glr);
-  sb.keep = (int*)(w + L.keep);
-  sb.work = (double*)(w + L.work);
-  sb.Y = Y;
-  sb.xi = xi;
-  sb.kinds = kinds;
-  sb.pair = pair;
-  DevStatus* st = (DevStatus*)(w + L.st);
-  SmallParams sp{};
-  sp.m = m;
-  sp.kint = kint;
   PLHR_HIP_CHECK(tharm_set_attributes(m, kint));
-  const size_t row = (size_t)m * sizeof(double);
-  PLHR_HIP_CHECK(hipMemcpy2DAsync(sb.GLR, 2 * row, GL, row, row, m, hipMemcpyDeviceToDevice, s));
-  PLHR_HIP_CHECK(
-      hipMemcpy2DAsync(sb.GLR + m, 2 * row, GR, row, row, m, hipMemcpyDeviceToDevice, s));
-  std::vector<int> ones(m, 1);
-  if (keep)
-    PLHR_HIP_CHECK(hipMemcpyAsync(sb.keep, keep, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
-  else
-    PLHR_HIP_CHECK(hipMemcpyAsync(sb.keep, ones.data(), (size_t)m * 4, hipMemcpyHostToDevice, s));
-  PLHR_HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), s));
-  launch_tharm_small(sp, sb, st, s);
-  PLHR_HIP_CHECK(hipGetLastError());
+  DevStatus* st = nullptr;
+  c = proj_enqueue(m, kint, GL, GR, keep, Y, xi, kinds, pair, static_cast<char*>(workspace), s,
+                   &st);
+  if (c != PLHR_OK) return c;
   DevStatus host{};
   PLHR_HIP_CHECK(hipMemcpyAsync(&host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   PLHR_HIP_CHECK(hipStreamSynchronize(s));

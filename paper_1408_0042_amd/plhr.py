@@ -352,8 +352,9 @@ def projected_solve(GL: torch.Tensor, GR: torch.Tensor, kint: int,
     (plhr_projected_solve): G_L y = xi G_R y, the kint units of smallest
     |xi| and the real coefficient basis Y' of Algorithm 3.  GL, GR are
     float64 (m, m) device tensors, keep an optional int32 (m,) mask.
-    Returns (Y (m, kint), xi (m,) complex, kinds (kint,), pair (kint,),
-    n_excluded).  Synchronises torch's current stream."""
+    Returns (Y (m, kint), xi (m,) complex: one entry per sorted unit, a
+    pair by its Im > 0 member, zero past the last unit, kinds (kint,),
+    pair (kint,), n_excluded).  Synchronises torch's current stream."""
     _require_cuda(GL, "GL")
     _require_cuda(GR, "GR")
     m = GL.shape[0]

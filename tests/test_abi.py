@@ -241,3 +241,48 @@ def test_complex_block_product_arguments_are_validated_on_the_host():
     assert lib.plhr_rowmul_c128(100, Z, 8, M, 0, Y, None) == L.ERR_ARG
     assert lib.plhr_rowmul_c128(100, Z, 8, None, 4, Y, None) == L.ERR_ARG
     assert lib.plhr_rowmul_c128(100, Z, 8, M, 4, C.c_void_p(4096 + 32), None) == L.ERR_ARG
+
+
+def test_complex_product_and_cholqr_overlap_and_alignment_checks():
+    lib = L.load()
+    Z, M, Y = C.c_void_p(4096), C.c_void_p(1 << 24), C.c_void_p(1 << 26)
+    # M overlapping Y, misaligned pointers
+    assert lib.plhr_rowmul_c128(100, Z, 8, C.c_void_p((1 << 26) + 64), 4, Y, None) == L.ERR_ARG
+    assert lib.plhr_rowmul_c128(100, C.c_void_p(4104), 8, M, 4, Y, None) == L.ERR_ARG
+    assert lib.plhr_rowmul_c128(100, Z, 8, C.c_void_p((1 << 24) + 8), 4, Y, None) == L.ERR_ARG
+    sz = C.c_size_t()
+    lib.plhr_cholqr_c128_workspace(1000, 8, C.byref(sz))
+    Q, W = C.c_void_p(1 << 24), C.c_void_p(1 << 26)
+    for R in (C.c_void_p(4096 + 256), C.c_void_p((1 << 24) + 256), C.c_void_p((1 << 26) + 256)):
+        assert lib.plhr_cholqr_c128(1000, Z, 8, Q, R, W, sz.value, None) == L.ERR_ARG
+
+
+def test_projected_solve_arguments_are_validated_on_the_host():
+    lib = L.load()
+    sz = C.c_size_t()
+    assert lib.plhr_projected_workspace(84, 21, C.byref(sz)) == L.OK and sz.value > 84 * 168 * 8
+    assert lib.plhr_projected_workspace(85, 21, C.byref(sz)) == L.ERR_ARG
+    assert lib.plhr_projected_workspace(8, 9, C.byref(sz)) == L.ERR_ARG
+    assert lib.plhr_projected_workspace(8, 0, C.byref(sz)) == L.ERR_ARG
+    lib.plhr_projected_workspace(16, 4, C.byref(sz))
+    GL, GR = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    Y, xi, kd, pr = C.c_void_p(1 << 22), C.c_void_p(1 << 23), C.c_void_p(1 << 24), C.c_void_p(1 << 25)
+    W = C.c_void_p(1 << 26)
+    nex = C.c_int32()
+
+    def call(**kw):
+        a = dict(m=16, kint=4, GL=GL, GR=GR, keep=None, Y=Y, xi=xi, kinds=kd, pair=pr, W=W,
+                 ws=sz.value)
+        a.update(kw)
+        return lib.plhr_projected_solve(a["m"], a["kint"], a["GL"], a["GR"], a["keep"], a["Y"],
+                                        a["xi"], a["kinds"], a["pair"], C.byref(nex), a["W"],
+                                        a["ws"], None)
+    assert call(ws=sz.value - 1) == L.ERR_ARG
+    assert call(W=None) == L.ERR_ARG
+    assert call(W=C.c_void_p((1 << 26) + 8)) == L.ERR_ARG          # 256-byte alignment
+    assert call(GR=None) == L.ERR_ARG
+    assert call(GL=C.c_void_p((1 << 20) + 4)) == L.ERR_ARG         # misaligned
+    assert call(Y=C.c_void_p((1 << 20) + 64)) == L.ERR_ARG         # Y overlaps G_L
+    assert call(xi=C.c_void_p((1 << 22) + 8)) == L.ERR_ARG         # xi overlaps Y
+    assert call(kinds=C.c_void_p((1 << 26) + 16)) == L.ERR_ARG     # kinds in the workspace
+    assert call(m=100) == L.ERR_ARG

@@ -43,23 +43,31 @@ def _check(GL, GR, kint, ties, keep=None):
     if keep is not None:
         assert np.all(Yg[np.flatnonzero(np.asarray(keep) == 0)] == 0.0)
     Yg = Yg[sel]
-    # the sorted xi of the selection (finite ones) agree with the oracle's
-    fin = np.isfinite(xo)
-    assert np.all(np.isfinite(xg[:kint]))
-    scale = np.abs(xo[fin]).max()
+    # the sorted xi of the selected units agree with the oracle's (the GPU
+    # lists one entry per unit: a pair by its Im xi > 0 member)
+    xo_u = xo[unit == np.arange(len(unit))]
+    nsel = sum(1 for k in ko if k != "I")
+    fin = np.isfinite(xo_u)
+    assert np.all(np.isfinite(xg[:nsel]))
+    scale = np.abs(xo_u[fin]).max()
     if ties:
         key = lambda z: np.lexsort((np.round(z.imag, 9), np.round(z.real, 9)))
-        a, b = xg[:kint], xo[:kint]
+        a, b = xg[:nsel], xo_u[:nsel]
         assert np.allclose(a[key(a)], b[key(b)], rtol=1e-10, atol=1e-12 * scale)
     else:
-        assert np.allclose(xg[:kint], xo[:kint], rtol=1e-10, atol=1e-12 * scale)
+        assert np.allclose(xg[:nsel], xo_u[:nsel], rtol=1e-10, atol=1e-12 * scale)
     # the same column layout (kinds, partners)
     assert sorted(kg.tolist()) == sorted(KIND[k] for k in ko)
     if not ties:
         assert kg.tolist() == [KIND[k] for k in ko]
         assert pg.tolist() == po
-    # span of Y' agrees with the oracle's
-    assert dense.subspace_sine(Ypo, Yg) < 1e-9
+    # span of Y' agrees with the oracle's, leaving out the ytilde_R column:
+    # the real part of a complex eigenvector depends on its phase, so any
+    # vector of the pair's real invariant subspace is a correct ytilde_R
+    # (checked below)
+    cg = [c for c in range(kint) if kg[c] != 2]
+    co = [c for c in range(kint) if ko[c] != "tilde"]
+    assert dense.subspace_sine(Ypo[:, co], Yg[:, cg]) < 1e-9
     # column by column: eigenvectors of their own xi; ytilde in the pair's
     # real invariant subspace
     nrm = np.linalg.norm(GLk)
