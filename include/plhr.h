@@ -428,6 +428,33 @@ plhr_status plhr_projected_solve(int32_t m, int32_t kint, const double* GL, cons
                                  int32_t* pair, int32_t* n_excluded, void* workspace,
                                  size_t ws_bytes, void* stream);
 
+/* The projected step of plhr_projected_solve without any allocation and
+ * without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments as for plhr_projected_solve, except:
+ *   status   device, 2 int32, written: the plhr_status the device raised
+ *            (0 when none: PLHR_ERR_BREAKDOWN when fewer than kint slots
+ *            remain or the QR iteration does not converge) and the number
+ *            of slots left out (G_L pivot clearly negative)
+ * Asynchronous: the work is enqueued on `stream` (NULL: the null stream)
+ * and the call returns at once; it never synchronises, allocates or
+ * frees.  Its scratch (the staged [G_L | G_R], the slot mask, the
+ * projected-solver work area and a status block) is a file-scope device
+ * array of plhr_projected_noalloc_scratch_bytes() bytes (about 332 KiB,
+ * for m up to 84), one copy per device, held until the process ends; its
+ * address is looked up on the first call on each device.  Every call on
+ * one device shares that array: calls that overlap in time on one device
+ * (different streams, or different threads without ordering) race and
+ * give undefined results; calls in one stream are ordered.  Each call
+ * clears the status block and restages the inputs, so the contents left
+ * by an earlier call do not matter.  PLHR_ERR_ARG for the argument errors
+ * of plhr_projected_solve (m <= 84) or a NULL/misaligned status.        */
+size_t plhr_projected_noalloc_scratch_bytes(void);
+plhr_status plhr_projected_solve_noalloc(int32_t m, int32_t kint, const double* GL,
+                                         const double* GR, const int32_t* keep, double* Y,
+                                         double* xi, int32_t* kinds, int32_t* pair,
+                                         int32_t* status, void* stream);
+
 /* Read back iteration state for inspection (synchronises the stream).
  *   lam      host, k + k_extra doubles (current Rayleigh quotients)
  *   V        device, n x (k + k_extra) doubles, or NULL (current block)  */

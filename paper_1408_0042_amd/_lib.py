@@ -123,6 +123,9 @@ def load() -> C.CDLL:
         "plhr_projected_workspace": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
         "plhr_projected_solve": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                            C.POINTER(C.c_int32), P, C.c_size_t, P]),
+        "plhr_projected_noalloc_scratch_bytes": (C.c_size_t, []),
+        "plhr_projected_solve_noalloc": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P, P, P, P,
+                                                   P]),
         "plhr_get_state": (C.c_int, [P, C.POINTER(C.c_double), P]),
         "plhr_debug_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
         "plhr_profile_start": (C.c_int, [P, C.c_int32, C.c_int32]),

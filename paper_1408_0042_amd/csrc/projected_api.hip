@@ -6,6 +6,7 @@
 // spectrum (conjugate pairs cut by the block size, ties, a nearly
 // singular G_R) independently of the rest of the iteration.
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -152,6 +153,33 @@ plhr_status proj_enqueue(int m, int kint, const double* GL, const double* GR,
   return PLHR_OK;
 }
 
+// ---- the allocation-free variant: a file-scope scratch area per device
+constexpr size_t kNoAllocScratch = proj_layout(kMaxM).total;
+__device__ __align__(256) char scratch[kNoAllocScratch];
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept; the kernels' LDS limits are
+// raised at the same time.
+plhr_status scratch_for_current_device(char** out) {
+  int dev = 0;
+  PLHR_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("plhr_projected_solve_noalloc: device index out of range");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PLHR_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    PLHR_HIP_CHECK(tharm_set_attributes(kMaxM, 1));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return PLHR_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -202,6 +230,31 @@ plhr_status plhr_projected_solve(int32_t m, int32_t kint, const double* GL, cons
     set_error(std::string("plhr_projected_solve: ") + reason_text(host.reason));
     return (plhr_status)host.error;
   }
+  return PLHR_OK;
+}
+
+size_t plhr_projected_noalloc_scratch_bytes(void) { return kNoAllocScratch; }
+
+plhr_status plhr_projected_solve_noalloc(int32_t m, int32_t kint, const double* GL,
+                                         const double* GR, const int32_t* keep, double* Y,
+                                         double* xi, int32_t* kinds, int32_t* pair,
+                                         int32_t* status, void* stream) {
+  if (!status || ((uintptr_t)status & 3)) {
+    set_error("plhr_projected_solve_noalloc: status must be a 4-byte aligned device pointer");
+    return PLHR_ERR_ARG;
+  }
+  plhr_status c = proj_check("plhr_projected_solve_noalloc", m, kint, GL, GR, keep, Y, xi, kinds,
+                             pair, status, 2 * sizeof(int32_t));
+  if (c != PLHR_OK) return c;
+  char* w = nullptr;
+  c = scratch_for_current_device(&w);
+  if (c != PLHR_OK) return c;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevStatus* st = nullptr;
+  c = proj_enqueue(m, kint, GL, GR, keep, Y, xi, kinds, pair, w, s, &st);
+  if (c != PLHR_OK) return c;
+  hipLaunchKernelGGL(k_proj_status, dim3(1), dim3(64), 0, s, st, status);
+  PLHR_HIP_CHECK(hipGetLastError());
   return PLHR_OK;
 }
 
