@@ -6,14 +6,17 @@ with B_l = L_l on the fine levels).  This module builds the plain V-cycle on
 the Laplacian part of the operator:
 
 * levels: the finest grid has N points per dimension; each coarser level
-  pairs neighbouring points (N -> N/2), cell-centred, down to the coarsest
-  level, which is solved exactly with a dense inverse;
+  pairs neighbouring points (N -> N/2, cell-centred) when N is even, or
+  keeps every other point (N -> (N-1)/2, vertex-centred) when N is odd,
+  down to the coarsest level, which is solved exactly with a dense inverse;
 * level operators: the same stencil re-discretised with spacing 2^l h
   (no potential);
-* prolongation: d-linear interpolation, 3/4 from the parent and 1/4 from the
-  parent's neighbour in each direction; a neighbour outside a Dirichlet box
-  is zero, a neighbour across a Bloch-periodic face is the wrapped value
-  times the phase;
+* prolongation: d-linear interpolation; cell-centred, 3/4 from the parent
+  and 1/4 from the parent's neighbour in each direction; vertex-centred,
+  the coarse value on the points the grids share and the mean of the two
+  coarse neighbours halfway between them; a neighbour outside a Dirichlet
+  box is zero, a neighbour across a Bloch-periodic face is the wrapped
+  value times the phase;
 * restriction: R = P^H / 2^d;
 * smoothing: nu_pre and nu_post sweeps of weighted Jacobi,
   w <- w + omega * D^-1 (r - A_l w), starting from w = 0.
@@ -55,6 +58,30 @@ def _prolong1d(Nc: int, bc: str, theta: float = 0.0) -> sp.csr_matrix:
     return P.tocsr()
 
 
+def _prolong1d_vertex(Nc: int) -> sp.csr_matrix:
+    """Vertex-centred linear interpolation, Nc coarse points to 2 Nc + 1
+    fine points (Dirichlet): fine point 2c+1 sits on coarse point c, fine
+    point 2c halfway between coarse points c-1 and c (zero outside)."""
+    Nf = 2 * Nc + 1
+    P = sp.lil_matrix((Nf, Nc))
+    for c in range(Nc):
+        P[2 * c + 1, c] = 1.0
+        P[2 * c, c] += 0.5
+        P[2 * c + 2, c] += 0.5
+    return P.tocsr()
+
+
+def coarsen(dims):
+    """Coarse grid and transfer kind of one level: every dimension even
+    pairs neighbouring points (cell-centred, N -> N/2); every dimension
+    odd keeps every other point (vertex-centred, N -> (N-1)/2)."""
+    if all(N % 2 == 0 for N in dims):
+        return tuple(N // 2 for N in dims), "cell"
+    if all(N % 2 == 1 and N >= 3 for N in dims):
+        return tuple((N - 1) // 2 for N in dims), "vertex"
+    raise ValueError(f"grid {dims} cannot be coarsened")
+
+
 def _kron_x_fastest(mats):
     out = None
     for m in reversed(mats):
@@ -83,12 +110,15 @@ class VCycle:
             self.Dinv.append(1.0 / A.diagonal())
             if lev == levels - 1:
                 break
-            if any(N % 2 for N in dims):
-                raise ValueError(f"grid {dims} cannot be coarsened")
-            cdims = tuple(N // 2 for N in dims)
-            mats = [_prolong1d(Nc, "bloch" if kind == "bloch" else "dirichlet",
-                               0.0 if thetas is None else thetas[a])
-                    for a, Nc in enumerate(cdims)]
+            cdims, how = coarsen(dims)
+            if how == "vertex":
+                if kind == "bloch":
+                    raise ValueError("a periodic grid needs an even number of points")
+                mats = [_prolong1d_vertex(Nc) for Nc in cdims]
+            else:
+                mats = [_prolong1d(Nc, "bloch" if kind == "bloch" else "dirichlet",
+                                   0.0 if thetas is None else thetas[a])
+                        for a, Nc in enumerate(cdims)]
             self.P.append(_kron_x_fastest(mats))
             dims = cdims
             hl = 2.0 * hl
@@ -241,10 +271,9 @@ class AVMG:
                 self.poly.append((c, a, b))
             if lev == levels - 1:
                 break
-            if any(N % 2 for N in dims):
-                raise ValueError(f"grid {dims} cannot be coarsened")
-            cdims = tuple(N // 2 for N in dims)
-            self.P.append(_kron_x_fastest([_prolong1d(Nc, "dirichlet") for Nc in cdims]))
+            cdims, how = coarsen(dims)
+            self.P.append(_kron_x_fastest([_prolong1d_vertex(Nc) if how == "vertex"
+                                           else _prolong1d(Nc, "dirichlet") for Nc in cdims]))
             dims = cdims
             hl = 2.0 * hl
         S = self.L[-1].toarray() - self.sigma * np.eye(self.L[-1].shape[0])

@@ -72,6 +72,10 @@ class Problem:
     sigma: float = 0.0
     normA1: Optional[float] = None
     normB1: Optional[float] = None
+    # "tharmonic": eq. (3.5); "harmonic": the same with T replaced by I
+    # inside the projection only (the search directions still use T), the
+    # "harm." variant of the experiments in Section 6.2
+    extraction: str = "tharmonic"
 
     def __post_init__(self):
         if self.normA1 is None:
@@ -134,9 +138,15 @@ def b_orthonormalize(blocks, B, drop_tol: float = 1e-10):
 
 
 def tharmonic_matrices(prob: Problem, Zh: np.ndarray):
-    """Left and right matrices of eq. (3.5) for the basis Zh."""
+    """Left and right matrices of eq. (3.5) for the basis Zh (with T = I
+    when prob.extraction is "harmonic")."""
     Q = prob.A @ Zh - prob.sigma * _mul(prob.B, Zh)      # (A - sigma B) Z
-    TQ = _prec(prob.T, Q)                               # T (A - sigma B) Z
+    if prob.extraction == "harmonic":
+        TQ = Q                                          # T -> I in the projection
+    elif prob.extraction == "tharmonic":
+        TQ = _prec(prob.T, Q)                           # T (A - sigma B) Z
+    else:
+        raise ValueError(prob.extraction)
     GL = Q.conj().T @ TQ                                # Z^*(A-sB) T (A-sB) Z
     GR = TQ.conj().T @ _mul(prob.B, Zh)                 # Z^*(A-sB) T B Z  (T = T^*)
     return GL, GR

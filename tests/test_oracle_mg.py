@@ -175,7 +175,8 @@ def test_avmg_two_level_closed_form():
     assert np.allclose(T, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("d,N,frac,levels", [(2, 32, 0.05, 4), (2, 32, 0.2, 4), (3, 8, 0.25, 3)])
+@pytest.mark.parametrize("d,N,frac,levels", [(2, 32, 0.05, 4), (2, 32, 0.2, 4), (3, 8, 0.25, 3),
+                                             (2, 31, 0.05, 3)])
 def test_avmg_spd_and_better_than_vcycle_at_deep_shifts(d, N, frac, levels):
     """Algorithm 4 is SPD and approximates |L - sigma I|^-1 far better than
     the V-cycle of L does: kappa(T |L - sigma I|) drops by >= 8x."""
@@ -196,3 +197,34 @@ def test_avmg_spd_and_better_than_vcycle_at_deep_shifts(d, N, frac, levels):
         e = np.linalg.eigvals(Tm @ absS).real
         kap[name] = e.max() / e.min()
     assert kap["av"] * 8.0 < kap["vc"]
+
+
+@pytest.mark.parametrize("dims,levels", [((15, 15), 3), ((31, 31), 4), ((7, 7, 7), 2),
+                                         ((15, 15, 15), 3)])
+def test_vertex_centred_vcycle_spd_and_spectrally_equivalent(dims, levels):
+    """Odd grids coarsen vertex-centred (N -> (N-1)/2, linear interpolation,
+    full weighting R = P^T / 2^d): T stays SPD and kappa(T A) small."""
+    h = 1.0 / (dims[0] + 1)
+    V = mg.VCycle("fd", dims, h, 1.0, levels)
+    A = ops.fd_dirichlet(dims, h).toarray()
+    T = _dense_T(V, A.shape[0])
+    assert np.linalg.norm(T - T.T) <= 1e-12 * np.linalg.norm(T)
+    ev = np.linalg.eigvals(T @ A).real
+    assert ev.min() > 0.0
+    assert ev.max() / ev.min() < 3.0
+
+
+def test_vertex_centred_transfer_is_exact_on_linear_functions():
+    """Linear interpolation reproduces a linear function on the shared and
+    the halfway points; the coarse grid of 2^j - 1 points has spacing 2h."""
+    cd, how = mg.coarsen((15, 7))
+    assert cd == (7, 3) and how == "vertex"
+    P = mg._prolong1d_vertex(7).toarray()
+    xc = np.arange(1, 8) * 2.0          # coarse points at fine positions 2, 4, .., 14
+    xf = np.arange(1, 16) * 1.0
+    f = P @ (3.0 * xc)
+    # exact inside; the first and last fine points see the zero boundary
+    assert np.allclose(f[1:-1], 3.0 * xf[1:-1])
+    assert np.isclose(f[0], 0.5 * 3.0 * 2.0) and np.isclose(f[-1], 0.5 * 3.0 * 14.0)
+    with pytest.raises(ValueError):
+        mg.coarsen((15, 8))

@@ -324,3 +324,46 @@ def test_hf_gradient_matches_finite_differences_and_sum_rule():
         fd = (hf.loss_and_grad_targets(lams(pp)[0], targets)[0]
               - hf.loss_and_grad_targets(lams(pm)[0], targets)[0]) / (2 * eps)
         assert abs(fd - g[x]) <= 1e-7 * max(1.0, abs(g[x]))
+
+
+# ------------------------------------------------- harmonic extraction
+def test_harmonic_extraction_ignores_T_in_the_projection():
+    """extraction="harmonic": eq. (3.5) with T -> I inside the projection
+    (Section 6.2, "harm."): with B = I the values are the standard harmonic
+    Ritz values 1/eig(Z^T S, S^T S), S = (A - sigma) Z, whatever T is."""
+    A = _small_problem(seed=7)
+    n = A.shape[0]
+    sigma = 700.0
+    V = mg.VCycle("fd", (10, 10), 1 / 11, 1.0, 2)
+    prob = plhr.Problem(A=A, T=V.apply, sigma=sigma, extraction="harmonic")
+    Z = np.random.default_rng(14).standard_normal((n, 10))
+    S = A @ Z - sigma * Z
+    xi_ref = 1.0 / sla.eigh(Z.T @ S, S.T @ S, eigvals_only=True)
+    GL, GR = plhr.tharmonic_matrices(prob, Z)
+    xi, _, _ = plhr.sorted_tharmonic(GL, GR, real_pairs=True)
+    assert np.all(xi.imag == 0.0)
+    assert np.allclose(np.sort(xi.real), np.sort(xi_ref), rtol=1e-8)
+    # the T-harmonic values of the same basis differ
+    prob.extraction = "tharmonic"
+    GL2, GR2 = plhr.tharmonic_matrices(prob, Z)
+    xi2, _, _ = plhr.sorted_tharmonic(GL2, GR2, real_pairs=True)
+    assert not np.allclose(np.sort(np.abs(xi2)), np.sort(np.abs(xi_ref)), rtol=1e-3)
+
+
+def test_bplhr_with_avmg_and_both_extractions_converges():
+    """Block PLHR with the AV-MG preconditioner (Algorithm 4), T-harmonic
+    and harmonic extraction, on a 2-D Laplacian (vertex-centred 31 x 31
+    grid, 3 levels) at an interior shift: both reach the brute-force
+    nearest pairs."""
+    N = 31
+    h = 1.0 / (N + 1)
+    A = ops.fd_dirichlet((N, N), h)
+    ev = cf.fd_dirichlet_eigs((N, N), h)
+    sigma = wl.shift_between(ev, 30)
+    T = mg.AVMG((N, N), h, 1.0, 3, sigma)
+    lam_ref, _ = dense.nearest_pairs(A, None, sigma, 4)
+    for ex in ("tharmonic", "harmonic"):
+        prob = plhr.Problem(A=A, T=T.apply, sigma=sigma, extraction=ex)
+        res = plhr.bplhr(prob, wl.start_block(N * N, 6, (27, 0)), 4, tol=1e-10, maxit=600)
+        assert res.converged, ex
+        assert np.allclose(np.sort(res.lam), np.sort(lam_ref), rtol=1e-10), ex
