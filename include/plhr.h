@@ -118,23 +118,47 @@ typedef struct {
 /* Preconditioner kinds (Section 5: T must be Hermitian positive definite). */
 typedef enum {
   PLHR_PREC_IDENTITY = 0,
-  PLHR_PREC_MG_VCYCLE = 1 /* one V-cycle on the Laplacian part of A */
+  PLHR_PREC_MG_VCYCLE = 1, /* one V-cycle on the Laplacian part of A            */
+  PLHR_PREC_AV_MG = 2,     /* AV-MG, T ~ |L - sigma I|^-1 (Appendix A, Alg. 4)  */
+  PLHR_PREC_INV_MG = 3     /* INV-MG, T ~ (L - sigma I)^-1, indefinite (Alg. 5) */
 } plhr_prec_kind;
 
 /* Preconditioner descriptor.
  *   kind     one of plhr_prec_kind
- *   levels   number of grid levels including the finest (>= 1); each level
- *            halves every grid dimension (which must stay even); the
- *            coarsest level is solved with a dense inverse (at most 4096
- *            points)
- *   nu_pre, nu_post  weighted-Jacobi sweeps before / after the coarse
- *            correction (must be equal so that T is Hermitian)
- *   omega    Jacobi weight, 0 < omega <= 2/3 keeps T positive definite   */
+ *   levels   number of grid levels including the finest (>= 1).  A level
+ *            whose dimensions are all even pairs neighbouring points for
+ *            the next one (n -> n/2, cell-centred, trilinear interpolation
+ *            3/4-1/4); one whose dimensions are all odd (>= 3) keeps every
+ *            other point (n -> (n - 1)/2, vertex-centred, linear
+ *            interpolation and full weighting); the coarsest level (at
+ *            most 1024 points) is solved densely
+ *   nu_pre, nu_post  smoothing steps before / after the coarse correction
+ *            (must be equal so that T is Hermitian)
+ *   omega    Jacobi weight, 0 < omega <= 2/3 keeps T positive definite
+ *   delta    AV-MG only (> 0): a level of spacing h_l uses the Laplacian
+ *            L_l as its operator B_l when sqrt(sigma / scale) h_l < delta
+ *            and the polynomial p_m(L_l - sigma I) otherwise (default 0.6)
+ *   degree   AV-MG only (1 .. 64): degree m of p_m, the Jackson-damped
+ *            Chebyshev series of |x| on [-sigma, 4 d scale / h_l^2 - sigma]
+ *            (default 10)
+ * PLHR_PREC_MG_VCYCLE: every level the re-discretised Laplacian, weighted
+ * Jacobi, the coarsest L_0^-1.  PLHR_PREC_AV_MG (Appendix A, Algorithm 4):
+ * Richardson smoothing w <- w + alpha_l (r - B_l w) with alpha_l =
+ * omega / diag(L_l) on the Laplacian levels and 1 / max p_m on the
+ * polynomial ones, the coarsest |L_0 - sigma I_0|^-1 (a host
+ * eigendecomposition at create); T is symmetric positive definite.
+ * PLHR_PREC_INV_MG (Algorithm 5, the indefinite comparison of Section
+ * 6.2): B_l = L_l - sigma I_l on every level, alpha_l = omega / diag(L_l),
+ * the coarsest (L_0 - sigma I_0)^-1.  sigma on an eigenvalue of the
+ * coarsest operator gives PLHR_ERR_ARG at create.                         */
 typedef struct {
   int32_t kind;
   int32_t levels;
   int32_t nu_pre, nu_post;
   double omega;
+  double delta;
+  int32_t degree;
+  int32_t reserved0;
 } plhr_prec_desc;
 
 /* Arithmetic of the preconditioner.  PLHR_PREC_MIXED runs the multigrid
@@ -147,6 +171,12 @@ typedef struct {
  * block updates, convergence test) stays in FP64, so the converged pairs
  * meet the same FP64 tolerance.  No effect when T is the identity.      */
 typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
+
+/* Extraction of the projected problem.  PLHR_EXTRACT_T_HARMONIC is the
+ * method's eq. (3.5).  PLHR_EXTRACT_HARMONIC replaces T by the identity
+ * inside the projection only (the search directions still use T): the
+ * standard harmonic Rayleigh-Ritz of the "harm." rows of Section 6.2.    */
+typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_extraction;
 
 /* Solver options (plhr_options_default fills the defaults shown).
  *   tol          relative residual ||A v - lam B v|| /
@@ -165,7 +195,12 @@ typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
  *                ill-conditioned (converged columns without locking) at
  *                the price of one more Gram and transform       (1)
  *   drop_tol     squared relative norm below which a W/S/P column is
- *                dropped during B-orthonormalisation          (1e-12) */
+ *                dropped during B-orthonormalisation          (1e-12)
+ *   extraction   a plhr_extraction value                      [T_HARMONIC]
+ *   use_graph    1: each iteration's launches are captured once in a HIP
+ *                graph (on a stream of the library's own) and replayed on
+ *                the context's stream; 0: launched one by one.  Launch
+ *                profiling bypasses the graphs                [0]       */
 typedef struct {
   double tol;
   int32_t max_iters;
@@ -175,6 +210,8 @@ typedef struct {
   int32_t check_every;
   int32_t ortho_passes;
   double drop_tol;
+  int32_t extraction;
+  int32_t use_graph;
 } plhr_options;
 
 typedef struct plhr_ctx_s* plhr_ctx;

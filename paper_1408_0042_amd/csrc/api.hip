@@ -265,6 +265,11 @@ struct plhr_ctx_s {
   long host_iter = 0;  // iterations enqueued since plhr_start
   bool use_mfma = true;
   Prof prof;
+  // use_graph: the captured iteration (index 1: with the refresh of the
+  // carried products) and the stream it was recorded on
+  hipStream_t cap = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -285,6 +290,12 @@ struct Layout {
     return off;
   }
 };
+
+// 0 the plain V-cycle (or none), 1 AV-MG, 2 INV-MG
+int mg_mode(const plhr_prec_desc* T) {
+  if (!T) return 0;
+  return T->kind == PLHR_PREC_AV_MG ? 1 : (T->kind == PLHR_PREC_INV_MG ? 2 : 0);
+}
 
 plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
                      double sigma, int32_t k, const plhr_options* opt) {
@@ -376,15 +387,20 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
   if (opt) {
     if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
         !(opt->drop_tol > 0.0) || opt->ortho_passes < 0 || opt->ortho_passes > 2 ||
-        (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED)) {
+        (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED) ||
+        (opt->extraction != PLHR_EXTRACT_T_HARMONIC &&
+         opt->extraction != PLHR_EXTRACT_HARMONIC) ||
+        (opt->use_graph != 0 && opt->use_graph != 1)) {
       set_error(
           "invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, "
-          "ortho_passes 0..2, precision FP64 or MIXED)");
+          "ortho_passes 0..2, precision FP64 or MIXED, extraction T_HARMONIC or HARMONIC, "
+          "use_graph 0 or 1)");
       return PLHR_ERR_ARG;
     }
   }
   if (T && T->kind != PLHR_PREC_IDENTITY) {
-    if (T->kind != PLHR_PREC_MG_VCYCLE) {
+    if (T->kind != PLHR_PREC_MG_VCYCLE && T->kind != PLHR_PREC_AV_MG &&
+        T->kind != PLHR_PREC_INV_MG) {
       set_error("T: unknown preconditioner kind");
       return PLHR_ERR_ARG;
     }
@@ -397,14 +413,21 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
       set_error("T: need levels >= 1, nu_pre == nu_post >= 1, 0 < omega <= 1");
       return PLHR_ERR_ARG;
     }
-    const int f = 1 << (T->levels - 1);
-    const int dim = a2d ? 2 : 3;
-    if (A->nx % f || A->ny % f || (dim == 3 && A->nz % f)) {
-      set_error("T: every grid dimension must be divisible by 2^(levels-1)");
+    if (T->kind == PLHR_PREC_AV_MG &&
+        (!(T->delta > 0.0) || !std::isfinite(T->delta) || T->degree < 1 || T->degree > 64)) {
+      set_error("T: AV-MG needs delta > 0 and 1 <= degree <= 64");
       return PLHR_ERR_ARG;
     }
-    size_t nc = (size_t)(A->nx / f) * (A->ny / f) * (dim == 3 ? A->nz / f : 1);
-    if (nc > 1024) {
+    Grid g = make_grid(A);
+    for (int lv = 0; lv + 1 < T->levels; ++lv) {
+      int vtx = 0;
+      if (!mg_coarsen(g, &vtx)) {
+        set_error("T: level " + std::to_string(lv) +
+                  " cannot be coarsened (its dimensions must be all even, or all odd and >= 3)");
+        return PLHR_ERR_ARG;
+      }
+    }
+    if (g.n() > 1024) {
       set_error("T: coarsest level has more than 1024 points; add levels");
       return PLHR_ERR_ARG;
     }
@@ -414,7 +437,7 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
 
 
 Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag, bool bst,
-              plhr_ctx_s* c) {
+              plhr_ctx_s* c, int mgmode = 0) {
   Layout L;
   const size_t n = g.n();
   const int m = 4 * kint;
@@ -447,7 +470,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
     oBVfin = L.take(n * k * 8);
   }
   size_t omg = L.bytes;
-  if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint);
+  if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint, mgmode);
   if (c) {
     char* b = c->ws;
     c->Z = (double*)(b + oZ);
@@ -576,13 +599,18 @@ int update(plhr_ctx_s* c, double* const* arrs, int narr, const DevStatus* st) {
                        c->stream);
 }
 
-void enqueue_iteration(plhr_ctx_s* c) {
+// One pass through the loop of Algorithm 3; `refresh` recomputes the
+// carried (A - sigma B)V and T(A - sigma B)V slots from V.  With the
+// harmonic extraction the products with T that only enter the projection
+// (T(A - sigma B)Z) are not formed.
+void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   const int kint = c->kint, m = c->m;
   const size_t n = c->n;
   hipStream_t s = c->stream;
   DevStatus* st = c->st;
   double *Z = c->Z, *QZ = c->QZ, *TQZ = c->TQZ, *R = c->R;
   const Blk none{nullptr, 0};
+  const bool tharm = (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC);
   // (A - sigma B)V afresh from V, and the Rayleigh quotients from it: the
   // copy carried by the block updates drifts from the true product by
   // rounding (about 1e-11 relative after a thousand iterations), which
@@ -595,10 +623,10 @@ void enqueue_iteration(plhr_ctx_s* c) {
   // they are refreshed together, every kRefreshT iterations.
   double* BZ = c->BZ;  // null unless B is a stencil
   const bool bst = c->bst;
-  if (c->host_iter % kRefreshT == kRefreshT - 1) {
+  if (refresh) {
     stencil(c, Z, m, Blk{QZ, m}, none, nullptr, none, kint, c->sigma, st,
             bst ? Blk{BZ, m} : none);
-    precond(c, QZ, m, Blk{TQZ, m}, none, kint, kint, st);
+    if (tharm) precond(c, QZ, m, Blk{TQZ, m}, none, kint, kint, st);
   }
   stencil(c, Z, m, Blk{c->QVf, kint}, none, nullptr, none, kint, c->sigma, st,
           bst ? Blk{c->BVf, kint} : none);
@@ -615,7 +643,9 @@ void enqueue_iteration(plhr_ctx_s* c) {
   stencil(c, Z + kint, m, Blk{QZ + kint, m}, Blk{R, 2 * kint}, c->sb.lam, Blk{R + kint, 2 * kint},
           kint, c->sigma, st, bst ? Blk{BZ + kint, m} : none);
   // S = T (A W - B W Lam), TQW = T (A - sigma) W
-  if (c->opt.precision == PLHR_PREC_MIXED) {
+  if (!tharm) {
+    precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
+  } else if (c->opt.precision == PLHR_PREC_MIXED) {
     precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
     precond(c, R + kint, 2 * kint, Blk{TQZ + kint, m}, none, kint, kint, st);
   } else {
@@ -624,22 +654,77 @@ void enqueue_iteration(plhr_ctx_s* c) {
   // QS = (A - sigma) S ; TQS = T QS
   stencil(c, Z + 2 * kint, m, Blk{QZ + 2 * kint, m}, none, nullptr, none, kint, c->sigma, st,
           bst ? Blk{BZ + 2 * kint, m} : none);
-  precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
+  if (tharm) precond(c, QZ + 2 * kint, m, Blk{TQZ + 2 * kint, m}, none, kint, kint, st);
   // B-orthonormalise Z = [V W S P] (Cholesky-QR in slot order)
-  double* arrs[4] = {Z, QZ, TQZ, BZ};
-  const int narr = bst ? 4 : 3;
+  double* arrs[4];
+  int narr = 0;
+  arrs[narr++] = Z;
+  arrs[narr++] = QZ;
+  if (tharm) arrs[narr++] = TQZ;
+  if (bst) arrs[narr++] = BZ;
   for (int pass = 0; pass < std::max(1, c->opt.ortho_passes); ++pass) {
     gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
     launch_ortho_small(c->sp, c->sb, st, s);
     transform(c, arrs, narr, st);
   }
-  // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]
-  gram(c, TQZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
+  // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]  (Q Zhat for the harmonic
+  // extraction)
+  gram(c, tharm ? TQZ : QZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
   launch_tharm_small(c->sp, c->sb, st, s);
   // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
   nb = update(c, arrs, narr, st);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
+}
+
+void destroy_graphs(plhr_ctx_s* c) {
+  for (int i = 0; i < 2; ++i) {
+    if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+    if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+    c->gexec[i] = nullptr;
+    c->graph[i] = nullptr;
+  }
+}
+
+// Record one iteration (and one with the refresh) into HIP graphs, on a
+// stream of the library's own (capture is not allowed on the null
+// stream); they are replayed on the context's stream.  Every captured
+// node is a kernel launch.
+plhr_status capture_graphs(plhr_ctx_s* c) {
+  destroy_graphs(c);
+  if (!c->cap) PLHR_HIP_CHECK(hipStreamCreate(&c->cap));
+  PLHR_HIP_CHECK(hipStreamSynchronize(c->stream));
+  hipStream_t user = c->stream;
+  c->stream = c->cap;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) break;
+    enqueue_iteration_body(c, i == 1);
+    e = hipStreamEndCapture(c->cap, &c->graph[i]);
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec[i], c->graph[i], nullptr, nullptr, 0);
+  }
+  c->stream = user;
+  if (e != hipSuccess) {
+    set_error(std::string("graph capture: ") + hipGetErrorString(e));
+    destroy_graphs(c);
+    return PLHR_ERR_HIP;
+  }
+  return PLHR_OK;
+}
+
+plhr_status enqueue_iteration(plhr_ctx_s* c) {
+  const bool refresh = (c->host_iter % kRefreshT == kRefreshT - 1);
+  if (c->opt.use_graph && c->prof.cat == -2) {
+    if (!c->gexec[0]) {
+      const plhr_status s = capture_graphs(c);
+      if (s != PLHR_OK) return s;
+    }
+    PLHR_HIP_CHECK(hipGraphLaunch(c->gexec[refresh ? 1 : 0], c->stream));
+  } else {
+    enqueue_iteration_body(c, refresh);
+  }
   ++c->host_iter;
+  return PLHR_OK;
 }
 
 plhr_status read_status(plhr_ctx_s* c) {
@@ -703,10 +788,11 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
     set_error("ws_bytes is NULL");
     return PLHR_ERR_ARG;
   }
-  const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
+  const bool mgp = T && T->kind != PLHR_PREC_IDENTITY;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   const bool bs = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
-  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, bs, nullptr);
+  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, bs, nullptr,
+                    mg_mode(T));
   *ws_bytes = L.bytes;
   return PLHR_OK;
 }
@@ -735,7 +821,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->m = 4 * c->kint;
   c->opt = o;
   c->n = c->grid.n();
-  const bool mgp = T && T->kind == PLHR_PREC_MG_VCYCLE;
+  const bool mgp = T && T->kind != PLHR_PREC_IDENTITY;
   c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   if (bd) c->bdiag = B->potential;
@@ -744,7 +830,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   if (c->csr) c->Acsr = CsrMat{A->row_ptr, A->col_idx, A->values, (long long)A->nnz};
   if (B && B->kind == PLHR_OP_CSR)
     c->Bcsr = CsrMat{B->row_ptr, B->col_idx, B->values, (long long)B->nnz};
-  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr);
+  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr,
+                    mg_mode(T));
   if (workspace) {
     if (ws_bytes < L.bytes) {
       set_error("workspace smaller than plhr_workspace_size");
@@ -768,7 +855,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     c->own_ws = true;
   }
   c->ws_bytes = L.bytes;
-  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, c);
+  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, c, mg_mode(T));
   // norms for the relative residual
   std::vector<double> pot;
   if (c->pot) {
@@ -830,9 +917,14 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     }
   }
   if (mgp) {
-    char* wp = c->ws + L.bytes - mg_workspace_bytes(c->grid, T->levels, 2 * c->kint);
+    char* wp = c->ws + L.bytes - mg_workspace_bytes(c->grid, T->levels, 2 * c->kint, mg_mode(T));
+    MGOpts av;
+    av.mode = mg_mode(T);
+    av.sigma = sigma;
+    av.delta = T->delta;
+    av.degree = T->degree;
     s = mg_setup(c->mg, c->grid, T->levels, T->nu_pre, T->nu_post, T->omega, 2 * c->kint, wp,
-                 c->stream);
+                 c->stream, av);
     if (s != PLHR_OK) {
       plhr_destroy(c);
       return s;
@@ -888,7 +980,8 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   const Blk none{nullptr, 0};
   stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr,
           c->bst ? Blk{c->BZ, m} : none);
-  precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
+  if (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC)
+    precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
   const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s, c->bst ? c->BZ : nullptr, m);
   launch_init_lam(c->sp, c->part, nb, c->sb, c->st, s);
   gram(c, c->Z, m, kint, c->bst ? c->BZ : c->Z, m, kint, nullptr, 0, kint, c->sb.G, nullptr);
@@ -919,7 +1012,10 @@ plhr_status plhr_iterate(plhr_ctx c, int32_t n_steps, plhr_iter_info* info) {
   int done_steps = 0;
   while (done_steps < n_steps) {
     const int chunk = std::min(c->opt.check_every, n_steps - done_steps);
-    for (int i = 0; i < chunk; ++i) enqueue_iteration(c);
+    for (int i = 0; i < chunk; ++i) {
+      const plhr_status e = enqueue_iteration(c);
+      if (e != PLHR_OK) return e;
+    }
     PLHR_HIP_CHECK(hipGetLastError());
     done_steps += chunk;
     plhr_status s = read_status(c);
@@ -1203,6 +1299,8 @@ void plhr_destroy(plhr_ctx c) {
   if (!c) return;
   prof_release(c->prof);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;

@@ -186,19 +186,47 @@ struct MGLevel {
   double* x = nullptr;   // n_l x cmax
   double* t = nullptr;   // n_l x cmax
   double* r = nullptr;   // n_l x cmax (levels > 0)
+  // three more blocks on every level of AV-MG / INV-MG (the Chebyshev
+  // recurrence of a polynomial level: two terms and the sum)
+  double* u0 = nullptr;
+  double* u1 = nullptr;
+  double* u2 = nullptr;
+  // level operator B_l: 0 the Laplacian L_l, 1 L_l - sigma I, 2 the
+  // polynomial p_m(L_l - sigma I); shift is subtracted from the stencil's
+  // diagonal (kinds 1 and 2); w is the Richardson weight of the smoother
+  int kind = 0;
+  double shift = 0.0;
+  double w = 0.0;
+  int vtx = 0;  // the transfer to the next coarser level is vertex-centred
+  std::vector<double> cheb;   // kind 2: Chebyshev coefficients c_0 .. c_m
+  double ca = 0.0, cb = 0.0;  // kind 2: X = ca (L_l - sigma I) + cb I
+};
+// Appendix A variants: mode 0 the plain V-cycle, 1 AV-MG (Algorithm 4),
+// 2 INV-MG (Algorithm 5).
+struct MGOpts {
+  int mode = 0;
+  double sigma = 0.0;
+  double delta = 0.6;
+  int degree = 10;
 };
 struct MG {
   int levels = 0, nu_pre = 2, nu_post = 2;
   double omega = 2.0 / 3.0;
   int cmax = 0;
+  MGOpts av;
   std::vector<MGLevel> lv;
   double* coarse_inv = nullptr;  // nc x nc, row-major
   float* coarse_inv32 = nullptr;  // the same in FP32
   int nc = 0;
 };
-size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax);
+// The next coarser grid of a hierarchy: all (active) dimensions even pair
+// neighbouring points (cell-centred, n -> n/2); all odd and >= 3 keep every
+// other point (vertex-centred, n -> (n - 1)/2, *vtx = 1); h doubles.
+// False when neither applies.
+bool mg_coarsen(Grid& g, int* vtx);
+size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax, int mode = 0);
 plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_post, double omega,
-                     int cmax, char*& ws, hipStream_t s);
+                     int cmax, char*& ws, hipStream_t s, const MGOpts& av = MGOpts{});
 // X_out = T R (ncols columns).  Output may be split over two blocks:
 // columns [0, split) go to out0, [split, ncols) to out1.  f32: level
 // storage and arithmetic in FP32 (FP64 input and output).

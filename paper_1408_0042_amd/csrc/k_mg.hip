@@ -14,8 +14,24 @@
 // T is symmetric; omega = 2/3 makes the smoother convergent, so T is
 // positive definite.
 //
+// Appendix A's AV-MG (Algorithm 4) and INV-MG (Algorithm 5) reuse the
+// same hierarchy with other level operators B_l and Richardson smoothing
+// w <- w + alpha_l (r - B_l w):
+//   * B_l = L_l (the plain Laplacian; alpha_l = omega / diag makes this
+//     weighted Jacobi) where sqrt(sigma / scale) h_l < delta,
+//   * B_l = p_m(L_l - sigma I), the Jackson-damped Chebyshev series of |x|
+//     of degree m on [-sigma, lambda_max(L_l) - sigma], applied by the
+//     three-term recurrence (one stencil pass per degree), on the other
+//     levels of AV-MG, alpha_l = 1 / max p_m,
+//   * B_l = L_l - sigma I on every level of INV-MG (alpha_l = omega/diag),
+// and the coarsest level solved with |L_0 - sigma I_0|^-1 (AV-MG) or
+// (L_0 - sigma I_0)^-1 (INV-MG) from a host eigendecomposition.
+// A level whose dimensions are all odd coarsens vertex-centred
+// (N -> (N - 1)/2, linear interpolation, full weighting R = P^T / 2^d).
+//
 // Every level works on point-major blocks of ncols columns; kernels assign
 // one workgroup per grid row so accesses stay contiguous.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -86,12 +102,14 @@ __device__ __forceinline__ vec<S, W> nb_sum(const T* xp, int i, int j, int l, in
   return nb;
 }
 
-// x_out = x_in + omega * (r - A x_in) / diag; x_in == nullptr means zero.
+// x_out = x_in + w (r - A x_in), A = diag I + off (neighbour sum) (diag
+// includes a shift of the level operator; w = omega / diag of the
+// Laplacian is weighted Jacobi); x_in == nullptr means zero.
 // Level storage and arithmetic in S; r is read as RT (the FP64 input block
 // at level 0), the output written as OT; columns [0, split) go to o0, the
 // rest to o1 (split is a multiple of W).
 template <int DIM, int W, typename S, typename RT, typename OT>
-__global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, S off, S omega,
+__global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, S off, S w,
                                                 const S* __restrict__ xin,
                                                 const RT* __restrict__ r, int ldr,
                                                 OT* __restrict__ o0, int ld0,
@@ -103,7 +121,6 @@ __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, 
   const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
-  const S w = omega / diag;
   const int c = ln.c;
   OT* const ob = (c < split) ? o0 + c : o1 + (c - split);
   const int ldo = (c < split) ? ld0 : ld1;
@@ -124,10 +141,10 @@ __global__ __launch_bounds__(256) void k_jacobi(int nx, int ny, int nz, S diag, 
 }
 
 // The first two sweeps from a zero guess in one pass over r:
-//   x1 = w r,  x2 = x1 + w (r - A x1) = w (2 r - w A r),  w = omega / diag
+//   x1 = w r,  x2 = x1 + w (r - A x1) = w (2 r - w A r)
 // (A x1 = w A r because w is a constant).
 template <int DIM, int W, typename S, typename RT>
-__global__ __launch_bounds__(256) void k_jacobi2z(int nx, int ny, int nz, S diag, S off, S omega,
+__global__ __launch_bounds__(256) void k_jacobi2z(int nx, int ny, int nz, S diag, S off, S w,
                                                   const RT* __restrict__ r, int ldr,
                                                   S* __restrict__ o, int ncols,
                                                   const DevStatus* st) {
@@ -137,7 +154,6 @@ __global__ __launch_bounds__(256) void k_jacobi2z(int nx, int ny, int nz, S diag
   const RowLanes ln = row_lanes<W>(ncols);
   if (!ln.on) return;
   const size_t rowp = (size_t)row * nx;
-  const S w = omega / diag;
   const int c = ln.c;
   for (int i = ln.i0; i < nx; i += ln.P) {
     const size_t p = rowp + i;
@@ -278,6 +294,166 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nx, int ny, int nz,
   }
 }
 
+// Vertex-centred transfers (all fine dimensions odd, coarse point c on
+// fine point 2c + 1).  Restriction: coarse r = P^T res / 2^d, i.e. full
+// weighting with the 1-D weights (1/4, 1/2, 1/4) on fine points 2c, 2c + 1,
+// 2c + 2; one workgroup per coarse row, the 3^d fine values read directly.
+template <int DIM, int W, typename S>
+__global__ __launch_bounds__(256) void k_restrict_v(int cnx, int cny, int cnz,
+                                                    const S* __restrict__ res,
+                                                    S* __restrict__ rc, int ncols,
+                                                    const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int cj = row % cny, cl = row / cny;
+  const int fnx = 2 * cnx + 1, fny = 2 * cny + 1;
+  const RowLanes ln = row_lanes<W>(ncols);
+  if (!ln.on) return;
+  const int c = ln.c;
+  const S w1[3] = {(S)0.25, (S)0.5, (S)0.25};
+  for (int ci = ln.i0; ci < cnx; ci += ln.P) {
+    vec<S, W> acc = (S)0;
+#pragma unroll
+    for (int dz = 0; dz < ((DIM == 3) ? 3 : 1); ++dz) {
+      const int fl = (DIM == 3) ? 2 * cl + dz : 0;
+      const S wz = (DIM == 3) ? w1[dz] : (S)1;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int fj = 2 * cj + dy;
+        const S wy = wz * w1[dy];
+        const S* rp = res + (((size_t)fl * fny + fj) * fnx + 2 * ci) * ncols + c;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) acc += (wy * w1[dx]) * vload<W, S>(rp + (size_t)dx * ncols);
+      }
+    }
+    const size_t cp = ((size_t)cl * cny + cj) * cnx + ci;
+    vstore<W, S>(rc + cp * ncols + c, acc);
+  }
+}
+
+// x += P e, vertex-centred (fine dims nx, ny, nz odd; coarse (n - 1)/2):
+// per direction an odd fine index i takes coarse (i - 1)/2, an even one
+// the mean of coarse i/2 - 1 and i/2 (zero outside the box).
+template <int DIM, int W, typename S>
+__global__ __launch_bounds__(256) void k_prolong_add_v(int nx, int ny, int nz,
+                                                       const S* __restrict__ ec,
+                                                       S* __restrict__ x, int ncols,
+                                                       const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny, l = row / ny;
+  const int cnx = (nx - 1) / 2, cny = (ny - 1) / 2, cnz = (DIM == 3) ? (nz - 1) / 2 : 1;
+  const RowLanes ln = row_lanes<W>(ncols);
+  if (!ln.on) return;
+  const int c = ln.c;
+  // coarse rows (y, z) and their weights
+  int cjs[2], cls[2];
+  S wjs[2], wls[2];
+  auto one = [](int f, int nc, int* cs, S* ws) {
+    if (f & 1) {
+      cs[0] = (f - 1) >> 1, ws[0] = (S)1;
+      cs[1] = 0, ws[1] = (S)0;
+    } else {
+      const int a = (f >> 1) - 1, b = f >> 1;
+      cs[0] = (a >= 0) ? a : 0, ws[0] = (a >= 0) ? (S)0.5 : (S)0;
+      cs[1] = (b < nc) ? b : 0, ws[1] = (b < nc) ? (S)0.5 : (S)0;
+    }
+  };
+  one(j, cny, cjs, wjs);
+  if (DIM == 3) {
+    one(l, cnz, cls, wls);
+  } else {
+    cls[0] = 0, wls[0] = (S)1, cls[1] = 0, wls[1] = (S)0;
+  }
+  const size_t rowp = (size_t)row * nx;
+  for (int i = ln.i0; i < nx; i += ln.P) {
+    int cis[2];
+    S wis[2];
+    one(i, cnx, cis, wis);
+    vec<S, W> acc = (S)0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const S wzy = wls[a] * wjs[b];
+        const S* ep = ec + ((size_t)cls[a] * cny + cjs[b]) * cnx * ncols + c;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc += (wzy * wis[q]) * vload<W, S>(ep + (size_t)cis[q] * ncols);
+      }
+    S* xp = x + (rowp + i) * ncols + c;
+    vstore<W, S>(xp, vload<W, S>(xp) + acc);
+  }
+}
+
+// One step of the Chebyshev recurrence for y = p(L - sigma I) x, with
+// X = ca (L - sigma I) + cb I (the interval mapped to [-1, 1]) and
+// L - sigma I = adiag I + off (neighbour sum):
+//   first step:  t_1 = X t_0,                y = c_0 t_0 + c_1 t_1
+//   later steps: t_{j+1} = 2 X t_j - t_{j-1}, y = y + c_{j+1} t_{j+1}
+// tc is t_j (read with its neighbours), tp is t_{j-1} (point-wise, may be
+// the output buffer tn), tn receives t_{j+1} (null on the last step), yin
+// may be yout.
+template <int DIM, int W, typename S>
+__global__ __launch_bounds__(256) void k_cheb_step(int nx, int ny, int nz, S adiag, S off, S ca,
+                                                   S cb, const S* __restrict__ tc, const S* tp,
+                                                   S* tn, const S* yin, S* yout, S c0, S cj,
+                                                   int first, int ncols, const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = row % ny, l = row / ny;
+  const RowLanes ln = row_lanes<W>(ncols);
+  if (!ln.on) return;
+  const size_t rowp = (size_t)row * nx;
+  const int c = ln.c;
+  for (int i = ln.i0; i < nx; i += ln.P) {
+    const size_t e = (rowp + i) * ncols + c;
+    const S* xp = tc + e;
+    const vec<S, W> xv = vload<W, S>(xp);
+    const vec<S, W> sx = adiag * xv + off * nb_sum<DIM, W, S>(xp, i, j, l, nx, ny, nz, ncols);
+    const vec<S, W> xt = ca * sx + cb * xv;
+    vec<S, W> t, y;
+    if (first) {
+      t = xt;
+      y = c0 * xv + cj * xt;
+    } else {
+      t = (S)2 * xt - vload<W, S>(tp + e);
+      y = vload<W, S>(yin + e) + cj * t;
+    }
+    if (tn) vstore<W, S>(tn + e, t);
+    vstore<W, S>(yout + e, y);
+  }
+}
+
+// out = x + w (r - y), x and y null meaning zero (the Richardson step of a
+// polynomial level, or its residual with x = null and w = 1); r read as RT
+// with leading dimension ldr, the output as OT split at `split` like the
+// Jacobi sweep.
+template <int W, typename S, typename RT, typename OT>
+__global__ __launch_bounds__(256) void k_lincomb(int nx, const S* __restrict__ x,
+                                                 const RT* __restrict__ r, int ldr,
+                                                 const S* __restrict__ y, S w,
+                                                 OT* __restrict__ o0, int ld0,
+                                                 OT* __restrict__ o1, int ld1, int split,
+                                                 int ncols, const DevStatus* st) {
+  if (halted(st)) return;
+  const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+  const RowLanes ln = row_lanes<W>(ncols);
+  if (!ln.on) return;
+  const size_t rowp = (size_t)row * nx;
+  const int c = ln.c;
+  OT* const ob = (c < split) ? o0 + c : o1 + (c - split);
+  const int ldo = (c < split) ? ld0 : ld1;
+  for (int i = ln.i0; i < nx; i += ln.P) {
+    const size_t p = rowp + i;
+    vec<S, W> v = vload<W, S>(r + p * ldr + c);
+    if (y) v -= vload<W, S>(y + p * ncols + c);
+    v = w * v;
+    if (x) v += vload<W, S>(x + p * ncols + c);
+    vstore<W, S>(ob + p * ldo, v);
+  }
+}
+
 // x = Ainv r on the coarsest level (nc points).
 template <typename S>
 __global__ __launch_bounds__(256) void k_dense_apply(int nc, const S* __restrict__ Ainv,
@@ -313,13 +489,14 @@ constexpr int kCoarseMaxLev = 4;
 struct CoarseLev {
   int nx, ny, nz, n;
   float inx, inxy;  // 1/nx and 1/(nx ny) for the index arithmetic
-  double diag, off;
+  double diag, off;  // level operator (diag includes a shift)
+  double w;          // Richardson weight of the sweeps
+  int vtx;           // the transfer to the next level is vertex-centred
 };
 struct CoarseArgs {
   CoarseLev lv[kCoarseMaxLev];
   int nlev;  // levels handled; the last one is solved densely
   int nu_pre, nu_post;
-  double omega;
   const void* Ainv;  // nc x nc
   int nc;
   int ncols, cc;
@@ -362,9 +539,9 @@ __device__ __forceinline__ S cc_nb(const S* xp, const CIdx& q, const CoarseLev& 
 // mode 0: out = xin + w (r - A xin), xin == nullptr meaning zero;
 // mode 1: out = w (2 r - w A r) (two sweeps from zero); mode 2: out = r - A xin
 template <int DIM, typename S>
-__device__ void cc_sweep(const CoarseLev& L, const S* xin, const S* r, S* out, int mode, S omega,
-                         int cc, float icc) {
-  const S diag = (S)L.diag, off = (S)L.off, w = omega / diag;
+__device__ void cc_sweep(const CoarseLev& L, const S* xin, const S* r, S* out, int mode, int cc,
+                         float icc) {
+  const S diag = (S)L.diag, off = (S)L.off, w = (S)L.w;
   for (int e = threadIdx.x; e < L.n * cc; e += kCoarseNT) {
     const CIdx q = cidx<DIM>(e, cc, icc, L);
     const S rv = r[e];
@@ -386,6 +563,30 @@ template <int DIM, typename S>
 __device__ void cc_restrict(const CoarseLev& F, const CoarseLev& C, const S* res, S* rc, int cc,
                             float icc) {
   const S norm = (DIM == 3) ? (S)0.125 : (S)0.25;
+  if (F.vtx) {  // full weighting on fine points 2c, 2c + 1, 2c + 2
+    for (int e = threadIdx.x; e < C.n * cc; e += kCoarseNT) {
+      const CIdx q = cidx<DIM>(e, cc, icc, C);
+      S acc = 0;
+#pragma unroll
+      for (int dz = 0; dz < ((DIM == 3) ? 3 : 1); ++dz) {
+        const int fl = (DIM == 3) ? 2 * q.l + dz : 0;
+        const S wz = (DIM == 3) ? ((dz == 1) ? (S)0.5 : (S)0.25) : (S)1;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int fj = 2 * q.j + dy;
+          const S wy = wz * ((dy == 1) ? (S)0.5 : (S)0.25);
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const int fi = 2 * q.i + dx;
+            const S wx = (dx == 1) ? (S)0.5 : (S)0.25;
+            acc += (wy * wx) * res[(((size_t)fl * F.ny + fj) * F.nx + fi) * cc + q.c];
+          }
+        }
+      }
+      rc[e] = acc;
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < C.n * cc; e += kCoarseNT) {
     const CIdx q = cidx<DIM>(e, cc, icc, C);
     S acc = 0;
@@ -412,10 +613,45 @@ __device__ void cc_restrict(const CoarseLev& F, const CoarseLev& C, const S* res
   }
 }
 
+// the coarse neighbours of fine index f (vertex-centred) and weights
+__device__ __forceinline__ void vtx_parents(int f, int nc, int* cs, float* ws) {
+  if (f & 1) {
+    cs[0] = (f - 1) >> 1, ws[0] = 1.0f, cs[1] = 0, ws[1] = 0.0f;
+  } else {
+    const int a = (f >> 1) - 1, b = f >> 1;
+    cs[0] = (a >= 0) ? a : 0, ws[0] = (a >= 0) ? 0.5f : 0.0f;
+    cs[1] = (b < nc) ? b : 0, ws[1] = (b < nc) ? 0.5f : 0.0f;
+  }
+}
+
 // x (level F) += P e (level C)
 template <int DIM, typename S>
 __device__ void cc_prolong(const CoarseLev& F, const CoarseLev& C, const S* ec, S* x, int cc,
                            float icc) {
+  if (F.vtx) {
+    for (int e = threadIdx.x; e < F.n * cc; e += kCoarseNT) {
+      const CIdx q = cidx<DIM>(e, cc, icc, F);
+      int ci[2], cj[2], cl[2];
+      float wi[2], wj[2], wl[2];
+      vtx_parents(q.i, C.nx, ci, wi);
+      vtx_parents(q.j, C.ny, cj, wj);
+      if (DIM == 3)
+        vtx_parents(q.l, C.nz, cl, wl);
+      else
+        cl[0] = cl[1] = 0, wl[0] = 1.0f, wl[1] = 0.0f;
+      S acc = 0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            acc += (S)(wl[a] * wj[b] * wi[d]) *
+                   ec[(((size_t)cl[a] * C.ny + cj[b]) * C.nx + ci[d]) * cc + q.c];
+      x[e] += acc;
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < F.n * cc; e += kCoarseNT) {
     const CIdx q = cidx<DIM>(e, cc, icc, F);
     const int pi = q.i >> 1, qi = (q.i & 1) ? pi + 1 : pi - 1;
@@ -453,7 +689,6 @@ __global__ __launch_bounds__(kCoarseNT) void k_coarse_cycle(CoarseArgs a, const 
   S* lds = reinterpret_cast<S*>(smem_c);
   const int cc = a.cc, c0 = blockIdx.x * cc, ncols = a.ncols;
   const float icc = 1.0f / (float)cc;
-  const S om = (S)a.omega;
   S* X[kCoarseMaxLev];
   S* T[kCoarseMaxLev];
   S* R[kCoarseMaxLev];
@@ -487,21 +722,21 @@ __global__ __launch_bounds__(kCoarseNT) void k_coarse_cycle(CoarseArgs a, const 
     S* oth = T[l];
     int it;
     if (a.nu_pre >= 2) {
-      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 1, om, cc, icc);
+      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 1, cc, icc);
       it = 2;
     } else {
-      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 0, om, cc, icc);
+      cc_sweep<DIM, S>(L, nullptr, R[l], cur, 0, cc, icc);
       it = 1;
     }
     __syncthreads();
     for (; it < a.nu_pre; ++it) {
-      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, om, cc, icc);
+      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, cc, icc);
       __syncthreads();
       S* tmp = cur;
       cur = oth;
       oth = tmp;
     }
-    cc_sweep<DIM, S>(L, cur, R[l], oth, 2, om, cc, icc);  // residual
+    cc_sweep<DIM, S>(L, cur, R[l], oth, 2, cc, icc);  // residual
     __syncthreads();
     cc_restrict<DIM, S>(L, a.lv[l + 1], oth, R[l + 1], cc, icc);
     __syncthreads();
@@ -540,7 +775,7 @@ __global__ __launch_bounds__(kCoarseNT) void k_coarse_cycle(CoarseArgs a, const 
     cc_prolong<DIM, S>(L, a.lv[l + 1], ec, cur, cc, icc);
     __syncthreads();
     for (int it = 0; it < a.nu_post; ++it) {
-      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, om, cc, icc);
+      cc_sweep<DIM, S>(L, cur, R[l], oth, 0, cc, icc);
       __syncthreads();
       S* tmp = cur;
       cur = oth;
@@ -628,18 +863,33 @@ bool coarse_inverse(const Grid& g, std::vector<double>& inv) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax) {
+bool mg_coarsen(Grid& g, int* vtx) {
+  const int d[3] = {g.nx, g.ny, g.nz};
+  const int nd = g.dim;
+  bool even = true, odd = true;
+  for (int q = 0; q < nd; ++q) {
+    even = even && (d[q] % 2 == 0);
+    odd = odd && (d[q] % 2 == 1 && d[q] >= 3);
+  }
+  if (!even && !odd) return false;
+  *vtx = odd ? 1 : 0;
+  g.nx = even ? g.nx / 2 : (g.nx - 1) / 2;
+  g.ny = even ? g.ny / 2 : (g.ny - 1) / 2;
+  if (nd == 3) g.nz = even ? g.nz / 2 : (g.nz - 1) / 2;
+  g.h *= 2.0;
+  return true;
+}
+
+size_t mg_workspace_bytes(const Grid& fine, int levels, int cmax, int mode) {
   size_t bytes = 0;
   Grid g = fine;
   for (int lv = 0; lv < levels; ++lv) {
     const size_t blk = align256(g.n() * cmax * sizeof(double));
-    bytes += (lv == 0 ? 2 : 3) * blk;
+    bytes += (lv == 0 ? 2 : 3) * blk + (mode ? 3 * blk : 0);
     if (lv == levels - 1)
       bytes += align256(g.n() * g.n() * sizeof(double)) + align256(g.n() * g.n() * sizeof(float));
-    g.nx /= 2;
-    g.ny /= 2;
-    if (g.dim == 3) g.nz /= 2;
-    g.h *= 2.0;
+    int vtx = 0;
+    if (lv + 1 < levels && !mg_coarsen(g, &vtx)) break;
   }
   return bytes;
 }
@@ -655,17 +905,176 @@ static hipError_t coarse_set_attributes() {
   return hipSuccess;
 }
 
+// Eigendecomposition of a symmetric n x n matrix (row-major, host, FP64):
+// on return A holds the eigenvectors as columns and d the eigenvalues.
+// Householder reduction to tridiagonal form with the transformations
+// accumulated, then the implicit symmetric QR iteration with Wilkinson
+// shifts on the tridiagonal matrix, the Givens rotations applied to the
+// accumulated basis (Golub & Van Loan, Sec. 8.3).
+static void sym_eig(std::vector<double>& A, int n, std::vector<double>& d) {
+  std::vector<double> Q((size_t)n * n, 0.0), v(n), p(n), w(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int k = 0; k + 2 < n; ++k) {
+    double nrm = 0.0;
+    for (int i = k + 1; i < n; ++i) nrm += at(i, k) * at(i, k);
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double x0 = at(k + 1, k);
+    const double alpha = (x0 >= 0.0) ? -nrm : nrm;  // new subdiagonal entry
+    for (int i = 0; i < n; ++i) v[i] = 0.0;
+    v[k + 1] = x0 - alpha;
+    for (int i = k + 2; i < n; ++i) v[i] = at(i, k);
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // A <- H A H on rows/columns k.. with H = I - beta v v^T (v zero above k+1)
+    for (int i = k; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += at(i, j) * v[j];
+      p[i] = beta * acc;
+    }
+    double kk = 0.0;
+    for (int i = k + 1; i < n; ++i) kk += v[i] * p[i];
+    kk *= 0.5 * beta;
+    for (int i = k; i < n; ++i) w[i] = p[i] - kk * v[i];
+    for (int i = k; i < n; ++i)
+      for (int j = k; j < n; ++j) at(i, j) -= v[i] * w[j] + w[i] * v[j];
+    // Q <- Q H
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += Q[(size_t)i * n + j] * v[j];
+      acc *= beta;
+      for (int j = k + 1; j < n; ++j) Q[(size_t)i * n + j] -= acc * v[j];
+    }
+  }
+  d.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = at(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(i + 1, i);
+  // implicit QR on the tridiagonal (d, e): deflate from the bottom
+  int hi = n - 1;
+  int guard = 0;
+  while (hi > 0 && guard < 60 * n) {
+    const double tiny = 1e-15 * (std::fabs(d[hi - 1]) + std::fabs(d[hi]));
+    if (std::fabs(e[hi - 1]) <= tiny || std::fabs(e[hi - 1]) < 1e-300) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > 1e-15 * (std::fabs(d[lo - 1]) + std::fabs(d[lo])))
+      --lo;
+    ++guard;
+    // Wilkinson shift from the trailing 2 x 2 block
+    const double dd = 0.5 * (d[hi - 1] - d[hi]);
+    const double ee = e[hi - 1];
+    const double den = dd + ((dd >= 0.0) ? 1.0 : -1.0) * std::hypot(dd, ee);
+    const double mu = d[hi] - ((den != 0.0) ? ee * ee / den : 0.0);
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double c = (r == 0.0) ? 1.0 : x / r, sn = (r == 0.0) ? 0.0 : -z / r;
+      // rotate rows/columns k, k+1 of the tridiagonal
+      if (k > lo) e[k - 1] = r;
+      const double a11 = d[k], a22 = d[k + 1], a12 = e[k];
+      d[k] = c * c * a11 - 2.0 * c * sn * a12 + sn * sn * a22;
+      d[k + 1] = sn * sn * a11 + 2.0 * c * sn * a12 + c * c * a22;
+      e[k] = c * sn * (a11 - a22) + (c * c - sn * sn) * a12;
+      if (k + 1 < hi) {
+        x = e[k];
+        z = -sn * e[k + 1];
+        e[k + 1] *= c;
+      }
+      for (int i = 0; i < n; ++i) {
+        const double qa = Q[(size_t)i * n + k], qb = Q[(size_t)i * n + k + 1];
+        Q[(size_t)i * n + k] = c * qa - sn * qb;
+        Q[(size_t)i * n + k + 1] = sn * qa + c * qb;
+      }
+    }
+  }
+  A.swap(Q);
+}
+
+// f(L_0 - sigma I) for the coarsest level from its eigendecomposition:
+// f(x) = 1/|x| (AV-MG) or 1/x (INV-MG).  False when an eigenvalue of the
+// shifted operator vanishes to rounding (sigma on a coarse eigenvalue).
+static bool coarse_function(const Grid& g, double sigma, bool absval, std::vector<double>& out) {
+  const int n = (int)g.n();
+  std::vector<double> A, d;
+  coarse_dense(g, A);
+  for (int i = 0; i < n; ++i) A[(size_t)i * n + i] -= sigma;
+  sym_eig(A, n, d);
+  double big = 0.0;
+  for (double x : d) big = std::max(big, std::fabs(x));
+  std::vector<double> f(n);
+  for (int i = 0; i < n; ++i) {
+    if (!(std::fabs(d[i]) > 1e-13 * big)) return false;
+    f[i] = absval ? 1.0 / std::fabs(d[i]) : 1.0 / d[i];
+  }
+  out.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += A[(size_t)i * n + q] * f[q] * A[(size_t)j * n + q];
+      out[(size_t)i * n + j] = acc;
+    }
+  return true;
+}
+
+// Jackson-damped Chebyshev series of |x| of degree m on [a, b]: the
+// coefficients of the series (discrete cosine sums over 8192 Chebyshev
+// points) times the Jackson factors, which make the truncated series a
+// convolution of |x| with a nonnegative kernel (so the polynomial stays
+// positive on [a, b]).
+static std::vector<double> abs_cheb(double a, double b, int m) {
+  const int N = 8192;
+  std::vector<double> f(N), c(m + 1, 0.0);
+  for (int j = 0; j < N; ++j) {
+    const double th = M_PI * (j + 0.5) / N;
+    f[j] = std::fabs(0.5 * (b - a) * std::cos(th) + 0.5 * (a + b));
+  }
+  for (int i = 0; i <= m; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < N; ++j) acc += f[j] * std::cos(i * M_PI * (j + 0.5) / N);
+    c[i] = 2.0 * acc / N;
+  }
+  c[0] *= 0.5;
+  const int K = m + 1;
+  const double q = M_PI / (K + 1);
+  for (int i = 0; i <= m; ++i)
+    c[i] *= ((K - i + 1) * std::cos(i * q) + std::sin(i * q) / std::tan(q)) / (K + 1);
+  return c;
+}
+
+static double cheb_value(const std::vector<double>& c, double t) {
+  double t0 = 1.0, t1 = t, y = c[0] + (c.size() > 1 ? c[1] * t : 0.0);
+  for (size_t i = 2; i < c.size(); ++i) {
+    const double t2 = 2.0 * t * t1 - t0;
+    y += c[i] * t2;
+    t0 = t1;
+    t1 = t2;
+  }
+  return y;
+}
+
 plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_post, double omega,
-                     int cmax, char*& ws, hipStream_t s) {
+                     int cmax, char*& ws, hipStream_t s, const MGOpts& av) {
   PLHR_HIP_CHECK(coarse_set_attributes());
-  {  // the restriction stages one fine row of cmax FP64 columns in LDS
+  {  // the cell-centred restriction stages one fine row of cmax FP64 columns in LDS
     Grid g = fine;
     for (int lv = 0; lv + 1 < levels; ++lv) {
-      if ((size_t)g.nx * cmax * sizeof(double) > 65536) {
+      int vtx = 0;
+      Grid f = g;
+      if (!mg_coarsen(g, &vtx)) {
+        set_error("multigrid: a level cannot be coarsened (dimensions must be all even or all "
+                  "odd and >= 3)");
+        return PLHR_ERR_ARG;
+      }
+      if (!vtx && (size_t)f.nx * cmax * sizeof(double) > 65536) {
         set_error("multigrid: a fine grid row of the block exceeds 64 KiB");
         return PLHR_ERR_UNSUPPORTED;
       }
-      g.nx /= 2;
     }
   }
   mg.levels = levels;
@@ -673,6 +1082,7 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
   mg.nu_post = nu_post;
   mg.omega = omega;
   mg.cmax = cmax;
+  mg.av = av;
   mg.lv.clear();
   Grid g = fine;
   for (int lv = 0; lv < levels; ++lv) {
@@ -687,20 +1097,51 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
       L.r = (double*)ws;
       ws += blk;
     }
+    if (av.mode) {
+      L.u0 = (double*)ws;
+      ws += blk;
+      L.u1 = (double*)ws;
+      ws += blk;
+      L.u2 = (double*)ws;
+      ws += blk;
+    }
+    // the level operator and its smoother
+    L.w = omega / g.diag();
+    if (av.mode == 2) {
+      L.kind = 1;
+      L.shift = av.sigma;
+    } else if (av.mode == 1 && !(std::sqrt(std::max(av.sigma, 0.0) / g.scale) * g.h < av.delta)) {
+      L.kind = 2;
+      L.shift = av.sigma;
+      const double a = -av.sigma, b = 2.0 * g.diag() - av.sigma;  // Gershgorin bound
+      L.cheb = abs_cheb(a, b, av.degree);
+      double pmax = 0.0;
+      for (int q = 0; q <= 20000; ++q) pmax = std::max(pmax, cheb_value(L.cheb, -1.0 + q / 1e4));
+      L.w = 1.0 / pmax;
+      L.ca = 2.0 / (b - a);
+      L.cb = -(a + b) / (b - a);
+    }
+    if (lv == levels - 1) {
+      mg.lv.push_back(L);
+      break;
+    }
+    int vtx = 0;
+    mg_coarsen(g, &vtx);
+    L.vtx = vtx;
     mg.lv.push_back(L);
-    if (lv == levels - 1) break;
-    g.nx /= 2;
-    g.ny /= 2;
-    if (g.dim == 3) g.nz /= 2;
-    g.h *= 2.0;
   }
   const Grid& gc = mg.lv.back().g;
   mg.nc = (int)gc.n();
   std::vector<double> A;
-  coarse_dense(gc, A);
-  if (!spd_inverse(A, mg.nc)) {
-    set_error("coarsest multigrid operator is not positive definite");
-    return PLHR_ERR_NOT_HPD;
+  if (av.mode == 0) {
+    coarse_dense(gc, A);
+    if (!spd_inverse(A, mg.nc)) {
+      set_error("coarsest multigrid operator is not positive definite");
+      return PLHR_ERR_NOT_HPD;
+    }
+  } else if (!coarse_function(gc, av.sigma, av.mode == 1, A)) {
+    set_error("sigma is an eigenvalue of the coarsest multigrid operator (to rounding)");
+    return PLHR_ERR_ARG;
   }
   mg.coarse_inv = (double*)ws;
   ws += align256((size_t)mg.nc * mg.nc * sizeof(double));
@@ -723,6 +1164,35 @@ plhr_status mg_setup(MG& mg, const Grid& fine, int levels, int nu_pre, int nu_po
     prof_end(cat, s);                         \
   } while (0)
 
+// y = p(L_l - sigma I) x on a polynomial level, by the three-term
+// recurrence (L.u0, L.u1 hold the terms, y is L.u2).
+template <int DIM, int W, typename S>
+static S* cheb_apply(MGLevel& L, const S* x, int ncols, const DevStatus* st, hipStream_t s) {
+  const Grid& g = L.g;
+  const int rows = g.ny * g.nz;
+  const double nb = (double)g.n() * ncols * sizeof(S);
+  const double fl = (double)g.n() * ncols;
+  const S adiag = (S)(g.diag() - L.shift), off = (S)g.off(), ca = (S)L.ca, cb = (S)L.cb;
+  S* tb[2] = {reinterpret_cast<S*>(L.u0), reinterpret_cast<S*>(L.u1)};
+  S* y = reinterpret_cast<S*>(L.u2);
+  const int m = (int)L.cheb.size() - 1;
+  // t_1 = X x, y = c_0 x + c_1 t_1
+  PROF_LAUNCH(KC_JACOBI, 3.0 * nb, (2.0 * DIM + 6.0) * fl, (k_cheb_step<DIM, W, S>), dim3(rows),
+              dim3(256), 0, s, g.nx, g.ny, g.nz, adiag, off, ca, cb, x, (const S*)nullptr,
+              m > 1 ? tb[0] : (S*)nullptr, (const S*)nullptr, y, (S)L.cheb[0], (S)L.cheb[1], 1,
+              ncols, st);
+  for (int j = 1; j < m; ++j) {
+    // t_{j+1} = 2 X t_j - t_{j-1}, y += c_{j+1} t_{j+1}
+    const S* tc = tb[(j - 1) & 1];
+    const S* tp = (j == 1) ? x : tb[j & 1];
+    S* tn = (j + 1 < m) ? tb[j & 1] : nullptr;
+    PROF_LAUNCH(KC_JACOBI, 5.0 * nb, (2.0 * DIM + 8.0) * fl, (k_cheb_step<DIM, W, S>), dim3(rows),
+                dim3(256), 0, s, g.nx, g.ny, g.nz, adiag, off, ca, cb, tc, tp, tn, (const S*)y, y,
+                (S)0, (S)L.cheb[j + 1], 0, ncols, st);
+  }
+  return y;
+}
+
 // One V-cycle at level `lev` on input r (ld ldr, element type RT).  Level
 // storage and arithmetic in S.  At level 0 the result goes to out0/out1
 // (FP64, split by column); at coarser levels it is left in one of the
@@ -741,13 +1211,14 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
   S* Lt = reinterpret_cast<S*>(L.t);
   const S* Ainv = (sizeof(S) == 4) ? reinterpret_cast<const S*>(mg.coarse_inv32)
                                    : reinterpret_cast<const S*>(mg.coarse_inv);
-  // every level from here down is small: one launch runs the rest of the
-  // cycle, one workgroup per column chunk, in LDS
+  // every level from here down is small (and none is a polynomial level):
+  // one launch runs the rest of the cycle, one workgroup per column chunk,
+  // in LDS
   {
     const int nl_tot = (int)mg.lv.size() - lev;
     bool small = lev > 0 && nl_tot >= 2 && nl_tot <= kCoarseMaxLev;
     for (int q = lev; small && q < (int)mg.lv.size(); ++q)
-      small = mg.lv[q].g.n() <= (size_t)kCoarseMaxPts;
+      small = mg.lv[q].g.n() <= (size_t)kCoarseMaxPts && mg.lv[q].kind != 2;
     int cc = 0;
     for (int w : {2, 1})
       if (small && cc == 0 && ncols % w == 0 && coarse_lds(mg, lev, w, sizeof(S)) <= kCoarseMaxLds)
@@ -757,7 +1228,6 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
       a.nlev = nl_tot;
       a.nu_pre = mg.nu_pre;
       a.nu_post = mg.nu_post;
-      a.omega = mg.omega;
       a.Ainv = Ainv;
       a.nc = mg.nc;
       a.ncols = ncols;
@@ -775,8 +1245,10 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
         c.n = (int)M.g.n();
         c.inx = 1.0f / (float)M.g.nx;
         c.inxy = 1.0f / (float)(M.g.nx * M.g.ny);
-        c.diag = M.g.diag();
+        c.diag = M.g.diag() - M.shift;
         c.off = M.g.off();
+        c.w = M.w;
+        c.vtx = M.vtx;
         flops += 40.0 * (double)M.g.n() * ncols;
       }
       PROF_LAUNCH(KC_COARSE, bytes, flops, (k_coarse_cycle<DIM, S>), dim3(ncols / cc),
@@ -792,52 +1264,101 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
                 reinterpret_cast<const S*>(r), Lx, ncols, st);
     return Lx;
   }
-  const S diag = (S)g.diag(), off = (S)g.off(), om = (S)mg.omega;
+  const S diag = (S)(g.diag() - L.shift), off = (S)g.off(), wr = (S)L.w;
   const double rb = sizeof(RT) / (double)sizeof(S);  // input pass relative to a level pass
+  const bool poly = (L.kind == 2);
   S* cur = Lx;
   S* oth = Lt;
-  // pre-smoothing from a zero guess (nu_pre >= 1); the first two sweeps
-  // in one kernel
+  // pre-smoothing from a zero guess (nu_pre >= 1)
   int it0 = 0;
-  if (mg.nu_pre >= 2) {
-    PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb, (2.0 * DIM + 6.0) * fl, (k_jacobi2z<DIM, W, S, RT>),
-                dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om, r, ldr, oth, ncols, st);
-    std::swap(cur, oth);
-    it0 = 2;
-  }
-  for (int it = it0; it < mg.nu_pre; ++it) {
-    PROF_LAUNCH(KC_JACOBI, (it == 0 ? 1.0 + rb : 2.0 + rb) * nb,
-                (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>), dim3(rows),
-                blk, 0, s, g.nx, g.ny, g.nz, diag, off, om,
-                it == 0 ? (const S*)nullptr : (const S*)cur, r, ldr, oth, ncols, oth, ncols,
+  if (poly) {
+    // w_1 = alpha r, then w <- w + alpha (r - B w)
+    PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb, fl, (k_lincomb<W, S, RT, S>), dim3(rows), blk, 0, s,
+                g.nx, (const S*)nullptr, r, ldr, (const S*)nullptr, wr, cur, ncols, cur, ncols,
                 ncols, ncols, st);
-    std::swap(cur, oth);
+    for (int it = 1; it < mg.nu_pre; ++it) {
+      const S* y = cheb_apply<DIM, W, S>(L, cur, ncols, st, s);
+      PROF_LAUNCH(KC_JACOBI, (3.0 + rb) * nb, 3.0 * fl, (k_lincomb<W, S, RT, S>), dim3(rows), blk,
+                  0, s, g.nx, (const S*)cur, r, ldr, y, wr, oth, ncols, oth, ncols, ncols, ncols,
+                  st);
+      std::swap(cur, oth);
+    }
+  } else {
+    // the first two sweeps in one kernel
+    if (mg.nu_pre >= 2) {
+      PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb, (2.0 * DIM + 6.0) * fl,
+                  (k_jacobi2z<DIM, W, S, RT>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off,
+                  wr, r, ldr, oth, ncols, st);
+      std::swap(cur, oth);
+      it0 = 2;
+    }
+    for (int it = it0; it < mg.nu_pre; ++it) {
+      PROF_LAUNCH(KC_JACOBI, (it == 0 ? 1.0 + rb : 2.0 + rb) * nb,
+                  (it == 0 ? 1.0 : 2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>),
+                  dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, wr,
+                  it == 0 ? (const S*)nullptr : (const S*)cur, r, ldr, oth, ncols, oth, ncols,
+                  ncols, ncols, st);
+      std::swap(cur, oth);
+    }
   }
   // residual -> oth, restrict -> coarse r, coarse cycle, prolongate into cur
-  PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, (2.0 * DIM + 3.0) * fl, (k_residual<DIM, W, S, RT>),
-              dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, cur, r, ldr, oth, ncols, st);
+  if (poly) {
+    const S* y = cheb_apply<DIM, W, S>(L, cur, ncols, st, s);
+    PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, 2.0 * fl, (k_lincomb<W, S, RT, S>), dim3(rows), blk,
+                0, s, g.nx, (const S*)nullptr, r, ldr, y, (S)1, oth, ncols, oth, ncols, ncols,
+                ncols, st);
+  } else {
+    PROF_LAUNCH(KC_RESIDUAL, (2.0 + rb) * nb, (2.0 * DIM + 3.0) * fl,
+                (k_residual<DIM, W, S, RT>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off,
+                cur, r, ldr, oth, ncols, st);
+  }
   MGLevel& C = mg.lv[lev + 1];
   const int crows = C.g.ny * C.g.nz;
   S* Cr = reinterpret_cast<S*>(C.r);
-  PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              (k_restrict<DIM, W, S>), dim3(crows), blk, (size_t)g.nx * ncols * sizeof(S), s,
-              C.g.nx, C.g.ny, C.g.nz, oth, Cr, ncols, st);
+  if (L.vtx)
+    PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+                (k_restrict_v<DIM, W, S>), dim3(crows), blk, 0, s, C.g.nx, C.g.ny, C.g.nz, oth,
+                Cr, ncols, st);
+  else
+    PROF_LAUNCH(KC_RESTRICT, nb * (1.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+                (k_restrict<DIM, W, S>), dim3(crows), blk, (size_t)g.nx * ncols * sizeof(S), s,
+                C.g.nx, C.g.ny, C.g.nz, oth, Cr, ncols, st);
   S* ec = cycle<DIM, W, S, S>(mg, lev + 1, Cr, ncols, Blk{nullptr, 0}, Blk{nullptr, 0}, ncols,
                            ncols, st, s);
-  PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
-              (k_prolong_add<DIM, W, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur, ncols,
-              st);
+  if (L.vtx)
+    PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+                (k_prolong_add_v<DIM, W, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur,
+                ncols, st);
+  else
+    PROF_LAUNCH(KC_PROLONG, nb * (2.0 + 1.0 / (1 << DIM)), 2.0 * (1 << DIM) * fl,
+                (k_prolong_add<DIM, W, S>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, ec, cur,
+                ncols, st);
   // post-smoothing (nu_post >= 1); at level 0 the last sweep writes the
   // FP64 output
   for (int it = 0; it < mg.nu_post; ++it) {
-    if (it == mg.nu_post - 1 && lev == 0) {
+    const bool last0 = (it == mg.nu_post - 1 && lev == 0);
+    if (poly) {
+      const S* y = cheb_apply<DIM, W, S>(L, cur, ncols, st, s);
+      if (last0) {
+        PROF_LAUNCH(KC_JACOBI, (2.0 + rb) * nb + fl * 8.0, 3.0 * fl,
+                    (k_lincomb<W, S, RT, double>), dim3(rows), blk, 0, s, g.nx, (const S*)cur, r,
+                    ldr, y, wr, out0.ptr, out0.ld, out1.ptr, out1.ld, split, ncols, st);
+        return nullptr;
+      }
+      PROF_LAUNCH(KC_JACOBI, (3.0 + rb) * nb, 3.0 * fl, (k_lincomb<W, S, RT, S>), dim3(rows), blk,
+                  0, s, g.nx, (const S*)cur, r, ldr, y, wr, oth, ncols, oth, ncols, ncols, ncols,
+                  st);
+      std::swap(cur, oth);
+      continue;
+    }
+    if (last0) {
       PROF_LAUNCH(KC_JACOBI, (1.0 + rb) * nb + fl * 8.0, (2.0 * DIM + 5.0) * fl,
                   (k_jacobi<DIM, W, S, RT, double>), dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag,
-                  off, om, cur, r, ldr, out0.ptr, out0.ld, out1.ptr, out1.ld, split, ncols, st);
+                  off, wr, cur, r, ldr, out0.ptr, out0.ld, out1.ptr, out1.ld, split, ncols, st);
       return nullptr;
     }
     PROF_LAUNCH(KC_JACOBI, (2.0 + rb) * nb, (2.0 * DIM + 5.0) * fl, (k_jacobi<DIM, W, S, RT, S>),
-                dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, om, cur, r, ldr, oth, ncols,
+                dim3(rows), blk, 0, s, g.nx, g.ny, g.nz, diag, off, wr, cur, r, ldr, oth, ncols,
                 oth, ncols, ncols, ncols, st);
     std::swap(cur, oth);
   }

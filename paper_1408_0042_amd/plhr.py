@@ -61,7 +61,11 @@ class Solver:
     device tensor added to the diagonal; mass: None (B = I), an (n,)
     float64 positive device tensor (B = diag(mass), finite differences),
     or "q1" (B = the consistent finite-element mass); precond: None (T = I)
-    or a dict {"levels", "nu", "omega"} for the multigrid V-cycle.
+    or a dict {"levels", "nu", "omega"} for the multigrid V-cycle, with
+    "kind": "av" (AV-MG, Appendix A Algorithm 4; "delta", "degree") or
+    "inv" (INV-MG, Algorithm 5) for the preconditioners of Section 6.2;
+    extraction: "tharmonic" (eq. 3.5) or "harmonic" (T -> I in the
+    projection); use_graph: replay each iteration from a captured HIP graph.
     kind "csr": a general sparse symmetric A given as csr = (row_ptr int32,
     col_idx int32, values float64) device tensors, dims = (n,); mass may
     then be a CSR triple for B; T must be the identity.
@@ -73,6 +77,7 @@ class Solver:
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
                  drop_tol: float = 1e-12, precision: str = "fp64", ortho_passes: int = 1,
+                 extraction: str = "tharmonic", use_graph: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
         if not torch.cuda.is_available():
@@ -135,14 +140,19 @@ class Solver:
         t = None
         if precond is not None:
             t = L.PrecDesc()
-            t.kind = L.PREC_MG_VCYCLE
+            kinds = {"vcycle": L.PREC_MG_VCYCLE, "av": L.PREC_AV_MG, "inv": L.PREC_INV_MG}
+            t.kind = kinds[precond.get("kind", "vcycle")]
             t.levels = int(precond.get("levels", 5))
             t.nu_pre = t.nu_post = int(precond.get("nu", 2))
             t.omega = float(precond.get("omega", 2.0 / 3.0))
+            t.delta = float(precond.get("delta", 0.6))
+            t.degree = int(precond.get("degree", 10))
         o = L.default_options()
         o.tol, o.max_iters, o.k_extra = float(tol), int(max_iters), int(k_extra)
         o.lock, o.check_every, o.drop_tol = int(bool(lock)), int(check_every), float(drop_tol)
         o.ortho_passes = int(ortho_passes)
+        o.extraction = {"tharmonic": L.EXTRACT_T_HARMONIC, "harmonic": L.EXTRACT_HARMONIC}[extraction]
+        o.use_graph = int(bool(use_graph))
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         o.precision = L.PRECISION_MIXED if precision == "mixed" else L.PRECISION_FP64
@@ -506,10 +516,13 @@ class BatchSolver:
         t = None
         if precond is not None:
             t = L.PrecDesc()
-            t.kind = L.PREC_MG_VCYCLE
+            kinds = {"vcycle": L.PREC_MG_VCYCLE, "av": L.PREC_AV_MG, "inv": L.PREC_INV_MG}
+            t.kind = kinds[precond.get("kind", "vcycle")]
             t.levels = int(precond.get("levels", 5))
             t.nu_pre = t.nu_post = int(precond.get("nu", 2))
             t.omega = float(precond.get("omega", 2.0 / 3.0))
+            t.delta = float(precond.get("delta", 0.6))
+            t.degree = int(precond.get("degree", 10))
         o = L.default_options()
         o.tol, o.max_iters, o.k_extra = float(tol), int(max_iters), int(k_extra)
         o.lock, o.check_every, o.drop_tol = int(bool(lock)), int(check_every), float(drop_tol)

@@ -1,0 +1,133 @@
+"""GPU parity of the Appendix A preconditioners (AV-MG, Algorithm 4;
+INV-MG, Algorithm 5), the vertex-centred hierarchy of odd grids and the
+harmonic extraction variant of Section 6.2 against the oracle, and
+graph replays against eager launches."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense, mg, operators as ops, plhr
+from tests import closed_forms as cf
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(**kw):
+    from paper_1408_0042_amd.plhr import Solver
+    return Solver(**kw)
+
+
+CASES = [
+    # kind, dims, levels, frac of lambda_max (sigma), oracle preconditioner
+    ("av", (32, 32), 4, 0.05),     # every level polynomial (deep shift)
+    ("av", (64, 64), 4, 0.004),    # Laplacian fine levels, polynomial coarse ones
+    ("av", (31, 31), 3, 0.01),     # vertex-centred
+    ("av", (16, 16, 16), 3, 0.02),
+    ("av", (15, 15, 15), 3, 0.02),  # vertex-centred 3-D
+    ("inv", (32, 32), 4, 0.01),
+    ("inv", (31, 31), 3, 0.01),
+    ("vcycle", (31, 31), 4, 0.01),
+    ("vcycle", (15, 15, 15), 3, 0.01),
+]
+
+
+@pytest.mark.parametrize("kind,dims,levels,frac", CASES)
+def test_preconditioner_apply_matches_oracle(kind, dims, levels, frac):
+    d = len(dims)
+    N = dims[0]
+    h = 1.0 / (N + 1)
+    lmax = wl.fd_lambda_max(N, h, d)
+    ev = (cf.fd_dirichlet_eigs(dims, h) if np.prod(dims) <= 40000 else None)
+    sigma = wl.shift_between(ev, int(frac * len(ev))) if ev is not None else frac * lmax
+    print(f"T parity {kind} dims={dims} levels={levels} sigma={sigma:.3f}", flush=True)
+    if kind == "vcycle":
+        T = mg.VCycle("fd", dims, h, 1.0, levels)
+    else:
+        T = mg.AVMG(dims, h, 1.0, levels, sigma, mode=kind)
+    k, kx = 3, 2
+    n = int(np.prod(dims))
+    S = _solver(kind="fd5_2d" if d == 2 else "fd7_3d", dims=dims, h=h, sigma=sigma, k=k,
+                k_extra=kx, precond={"kind": kind, "levels": levels, "nu": 2, "omega": 2 / 3})
+    for ncols in (2 * (k + kx), 3):
+        X = wl.start_block(n, ncols, (50, ncols))
+        got = host(S.apply("T", dev(X)))
+        want = T.apply(X)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        assert err < 1e-11, (kind, dims, ncols, err)
+    S.close()
+
+
+@pytest.mark.parametrize("extraction", ["tharmonic", "harmonic"])
+def test_first_steps_with_avmg_match_oracle(extraction):
+    """Three iterations of Algorithm 3 with AV-MG, both extractions: the
+    Rayleigh quotients equal the oracle's."""
+    dims, h = (31, 31), 1 / 32
+    N = 31
+    ev = cf.fd_dirichlet_eigs(dims, h)
+    sigma = wl.shift_between(ev, 40)
+    A = ops.fd_dirichlet(dims, h)
+    T = mg.AVMG(dims, h, 1.0, 3, sigma)
+    k, kx = 4, 2
+    V0 = wl.start_block(N * N, k + kx, (51, 0))
+    prob = plhr.Problem(A=A, T=T.apply, sigma=sigma, extraction=extraction)
+    o = plhr.BPLHR(prob, V0, k, real=True, lock=False)
+    S = _solver(kind="fd5_2d", dims=dims, h=h, sigma=sigma, k=k, k_extra=kx, lock=False,
+                extraction=extraction, precond={"kind": "av", "levels": 3, "nu": 2})
+    S.start(dev(V0))
+    for it in range(3):
+        o.step()
+        S.iterate(1)
+        lam_g, _ = S.state()
+        assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-8), (it, lam_g, o.lam)
+    S.close()
+
+
+@pytest.mark.parametrize("dims,levels,nbelow,extraction",
+                         [((31, 31), 3, 40, "tharmonic"), ((31, 31), 3, 40, "harmonic"),
+                          ((16, 16, 16), 3, 60, "tharmonic")])
+def test_avmg_solve_matches_brute_force(dims, levels, nbelow, extraction):
+    d = len(dims)
+    N = dims[0]
+    h = 1.0 / (N + 1)
+    ev = cf.fd_dirichlet_eigs(dims, h)
+    sigma = wl.shift_between(ev, nbelow)
+    A = ops.fd_dirichlet(dims, h)
+    k, kx = 4, 3
+    order = np.lexsort((ev, np.abs(ev - sigma)))
+    ref = np.sort(ev[order][:k])
+    rest = ev[order][k:]
+    rest = rest[np.abs(rest - ref[:, None]).min(axis=0) > 1e-8 * ev.max()]
+    gap = np.abs(rest[None, :] - ref[:, None]).min()
+    tol = 1e-8 * gap / (4 * d / h**2 + abs(sigma))
+    print(f"AV-MG solve dims={dims} sigma={sigma:.3f} tol={tol:.2e} {extraction}", flush=True)
+    S = _solver(kind="fd5_2d" if d == 2 else "fd7_3d", dims=dims, h=h, sigma=sigma, k=k,
+                k_extra=kx, tol=tol, max_iters=3000, extraction=extraction,
+                precond={"kind": "av", "levels": levels, "nu": 2})
+    r = S.solve(dev(wl.start_block(int(np.prod(dims)), k + kx, (52, 0))))
+    print(f"  iterations {r.iters}", flush=True)
+    assert r.converged
+    assert np.allclose(np.sort(host(r.eigvals)), ref, rtol=1e-10)
+    _, U = dense.cluster_basis(A, None, sigma, k)
+    assert dense.subspace_sine(U, host(r.V)) < 1e-7
+    S.close()
+
+
+def test_graph_replay_is_bitwise_identical_to_eager_launches():
+    dims, h = (32, 32), 1 / 33
+    ev = cf.fd_dirichlet_eigs(dims, h)
+    sigma = wl.shift_between(ev, 30)
+    V0 = dev(wl.start_block(1024, 6, (53, 0)))
+    out = []
+    for g in (False, True):
+        S = _solver(kind="fd5_2d", dims=dims, h=h, sigma=sigma, k=4, k_extra=2, tol=1e-10,
+                    max_iters=2000, use_graph=g, precond={"levels": 3, "nu": 2})
+        r = S.solve(V0)
+        out.append((r.iters, host(r.eigvals).copy(), host(r.V).copy(), r.rel_res.copy()))
+        if g:  # a second solve replays the graphs captured by the first
+            r2 = S.solve(V0)
+            assert r2.iters == r.iters and np.array_equal(host(r2.V), out[-1][2])
+        S.close()
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert np.array_equal(a, b)
