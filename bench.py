@@ -380,6 +380,76 @@ def run_batched(nb, steps, warmup):
                                     if c != "truncated" and v["launches"] > 0}}
 
 
+# Iteration counts the paper prints for the 2-D Laplacian experiments
+# (Section 6.2): Table 1 (k = 10, h = 2^-7, residual 1e-6), Table 2 (k = 20),
+# Table 3 (k = 4, sigma = 400, residual 1e-4, h = 1/(2^w + 1)); None is a
+# run that did not converge within 1000 iterations.
+PAPER_T1 = {"shifts": [400, 450, 500, 550, 600, 650, 700],
+            "av_tharm": [57, 81, 68, 133, 117, 190, 278],
+            "av_harm": [563, None, 493, 635, None, None, None],
+            "inv_harm": [30, 40, 45, None, 59, 338, 424]}
+PAPER_T2 = {"shifts": [800, 900, 1000, 1100, 1200, 1300, 1400],
+            "av_tharm": [270, 168, 177, 344, 365, 363, 192],
+            "av_harm": [590, 417, 377, 625, 437, 217, 287],
+            "inv_harm": [None] * 7}
+PAPER_T3 = {"omega": [6, 7, 8, 9], "iters": [41, 42, 43, 42]}
+
+
+def paper_tables(which=("t1", "t2", "t3"), max_iters=1000, nu=1):
+    """The iteration-count experiments of Section 6.2 on the GPU: block
+    PLHR on the 2-D 5-point Laplacian with the AV-MG preconditioner
+    (Algorithm 4: delta 0.6, degree 10, nu Richardson steps per level) and
+    T-harmonic or harmonic extraction, and with INV-MG (Algorithm 5) and
+    harmonic extraction.  The coarsest level has spacing 1/32 in every run
+    (31 x 31 points for h = 2^-7, reached vertex-centred 127 -> 63 -> 31;
+    32 x 32 for h = 1/(2^w + 1), cell-centred), fine enough for the
+    eigenvectors near these shifts; all finer levels then take B_l = L_l.
+    The paper's absolute residual tolerances are turned into the relative
+    one of the library with ||A||_1 + sigma.  Prints one JSON object per
+    run and returns all."""
+    import torch
+    import workloads as wl
+    from paper_1408_0042_amd.plhr import Solver
+    runs = []
+    variants = [("av_tharm", "av", "tharmonic"), ("av_harm", "av", "harmonic"),
+                ("inv_harm", "inv", "harmonic")]
+
+    def one(table, N, levels, sigma, k, tol_abs, kind, extraction, seed):
+        h = 1.0 / (N + 1)
+        tol = tol_abs / (8.0 / h**2 + sigma)
+        S = Solver(kind="fd5_2d", dims=(N, N), h=h, sigma=float(sigma), k=k, k_extra=1, tol=tol,
+                   max_iters=max_iters, check_every=10, extraction=extraction, use_graph=True,
+                   precond={"kind": kind, "levels": levels, "nu": nu, "omega": 2.0 / 3.0,
+                            "delta": 0.6, "degree": 10})
+        V0 = torch.from_numpy(wl.start_block(N * N, k + 1, seed)).cuda()
+        t0 = time.perf_counter()
+        try:
+            r = S.solve(V0, allow_unconverged=True)
+            its, conv = r.iters, bool(r.converged)
+        except Exception as e:          # a breakdown counts as no convergence
+            its, conv = max_iters, False
+            print(json.dumps({"table": table, "error": str(e)[:200]}), flush=True)
+        el = time.perf_counter() - t0
+        S.close()
+        rec = {"table": table, "N": N, "levels": levels, "nu": nu, "sigma": sigma, "k": k,
+               "prec": kind, "extraction": extraction, "iters": its if conv else None,
+               "seconds": round(el, 3)}
+        print(json.dumps(rec), flush=True)
+        runs.append(rec)
+
+    if "t3" in which:
+        for om in PAPER_T3["omega"]:
+            N = 2 ** om
+            one("t3", N, om - 4, 400.0, 4, 1e-4, "av", "tharmonic", (62, om))
+    for tname, tab, k in (("t1", PAPER_T1, 10), ("t2", PAPER_T2, 20)):
+        if tname not in which:
+            continue
+        for sig in tab["shifts"]:
+            for name, kind, ex in variants:
+                one(tname, 127, 3, float(sig), k, 1e-6, kind, ex, (61, sig))
+    return runs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +470,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--ortho-passes", type=int, default=1,
                     help="Cholesky-QR passes of the B-orthonormalisation per iteration (2: CholQR2)")
+    ap.add_argument("--paper-tables", default="",
+                    help="comma list of t1,t2,t3: run the iteration-count experiments of "
+                         "Section 6.2 instead of the benchmark")
+    ap.add_argument("--tables-nu", type=int, default=1,
+                    help="Richardson steps per level of AV-MG / INV-MG in --paper-tables")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first fill and copy this many MiB on the device: kernels of known "
                          "traffic that calibrate the HBM byte counters of a profiler run")
@@ -410,6 +485,9 @@ def main():
               "over several GPUs is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.paper_tables:
+        paper_tables(tuple(args.paper_tables.split(",")), nu=args.tables_nu)
+        return
 
     import torch
     import workloads as wl

@@ -225,8 +225,11 @@ hipError_t set_lds_limit(const void* kernel) {
                              lim - (int)fa.sharedSizeBytes);
 }
 
+// Split-K blocks of the Gram products: 64 rows per block at least, at
+// most 512 blocks (two per compute unit), so that a small basis still
+// spreads over many compute units instead of walking its rows in a few.
 int gram_blocks(size_t n) {
-  size_t nb = (n + 511) / 512;
+  size_t nb = (n + 63) / 64;
   if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   return (int)nb;
