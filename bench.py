@@ -6,37 +6,33 @@ iteration to convergence of the k wanted pairs at relative residual 1e-8,
 and the final Rayleigh-Ritz step.  The metric is converged eigenpairs per
 second over K timed steps after W warm-up steps.
 
-Workload (default): the 3-D 7-point Dirichlet Laplacian on a 64^3 grid
-(n = 262144, h = 1/65), B = I, k = 16 pairs + 4 guard columns (block of
-20, trial subspace of 80), no locking, T = one multigrid V-cycle on the
-Laplacian (5 levels, 2+2 weighted-Jacobi sweeps, omega = 2/3).  The shift
-sits 40% of the way between two distinct eigenvalues about 125 eigenvalues
-into the spectrum (`--shift below121`, sigma ~ 485.22), the regime of the
-paper's Laplacian experiments, where the 16 nearest eigenvalues form whole
-clusters of the cube's degenerate spectrum.  With this preconditioner
-(an approximate inverse of the Laplacian, not of |A - sigma I|) a single
-guard column or soft locking lets the block settle on clusters below the
-shift, so the defaults use 4 guard columns and no locking.  Each step's
-eigenvalues are compared with the closed form of the 16 nearest; a step
-that converged to another set counts zero pairs.  `--shift quarter` uses
-sigma = 0.25 lambda_max instead, where this preconditioner does not reach
-1e-8 in a practical number of iterations; that mode runs a fixed number of
-iterations and reports the residual reached.
+Workload of `value` (the small configuration as specified): the 2-D
+5-point Dirichlet Laplacian on 32 x 32 interior points (n = 1024,
+h = 1/33), B = I, T = I, the k = 4 eigenpairs nearest sigma = 0.4
+lambda_max from the seeded N(0, 1) block.  The block carries two extra
+columns (one lets it settle on a farther eigenvalue of the square's
+double spectrum).  Every step is checked against the closed form; a
+step that converged to another set counts zero pairs.  The roofline
+entry is the kernel that takes the most time, with HIP events around each
+of its launches inside the timed region.
 
-By default the solve is timed twice: in FP64 (the reported `value`) and
-in the mixed mode (the V-cycle in FP32, everything else in FP64), whose
-throughput and ratio to FP64 go in the `mixed` object.
-
-Printed: one JSON line with the metric, a roofline entry for the kernel
-that takes the most time (HIP events around each of its launches inside
-the timed region), the same figures for every kernel, the HBM rate of the
-sparse-times-block product (the benchmark operator as a CSR matrix, and
-the same product through the grid stencil) in `spmm`, that of the complex
-Bloch-periodic product (96^3, 32 columns), of one V-cycle of its
-Laplacian part, the FP64 matrix-core rate of the complex Gram of a
-128-column basis, a complex Cholesky-QR and a complex block update in
-`bloch`, and the CPU oracle
-timed on a bounded sample.
+Further objects of the same JSON line:
+  fd7_64        the second configuration's operator, grid, k, V-cycle and
+                start block (64^3, k = 16 + 4 guard columns, no locking)
+                at a shift about 125 eigenvalues deep (the configuration's
+                quarter-of-lambda_max shift is out of reach of this
+                preconditioner), FP64 and mixed (FP32 V-cycles for the
+                search directions), per-iteration time and the ratio;
+  quarter       the second configuration exactly (sigma = 0.25 lambda_max,
+                k = 16 + 1) for a fixed number of iterations with the
+                V-cycle and with AV-MG: the residual reached;
+  batched       256 independent 2-D Hamiltonians in one solve + backward;
+  spmm, bloch   HBM rates of the CSR product, the complex Bloch product,
+                its V-cycle, the complex Gram, Cholesky-QR and block update;
+  cpu_baseline  the CPU oracle on a bounded sample of the small
+                configuration's iterations (all host threads and one).
+`--paper-tables t1,t2,t3` runs the iteration-count experiments of
+Section 6.2 instead.
 """
 from __future__ import annotations
 
@@ -59,18 +55,6 @@ FP64_PEAK_TFS = 78.6
 def closed_form_3d(N, h):
     s = (4.0 / h**2) * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
     return np.sort(np.add.outer(np.add.outer(s, s), s).ravel())
-
-
-def pick_sigma(N, h, mode):
-    ev = closed_form_3d(N, h)
-    if mode == "quarter":
-        return 0.25 * ev.max(), ev
-    nb = int(mode.replace("below", ""))
-    u = np.unique(np.round(ev, 8))
-    i = int(np.searchsorted(u, ev[nb]))
-    # 40% of the way between two distinct eigenvalues: not an eigenvalue,
-    # and the clusters on either side are not equidistant
-    return u[i - 1] + 0.4 * (u[i] - u[i - 1]), ev
 
 
 # HBM traffic per launch of a kernel, from two profiler passes over
@@ -130,37 +114,65 @@ def roofline_entry(cat, p):
     return hbm
 
 
-def cpu_baseline(w, sigma, k, kx, lock, gpu_iters, budget_s):
-    """The oracle as it stands, on the host cores, for a bounded number of
-    iterations of the same workload; extrapolated to the GPU's iteration
-    count."""
-    from oracle import mg as omg, operators as ops, plhr as oplhr
+def cpu_baseline_config1(gpu_iters, budget_s):
+    """The oracle as it stands on the host cores, on the small
+    configuration (the same operator, shift, block and start block as the
+    GPU solve): a bounded number of iterations with all BLAS threads and
+    with one, extrapolated to the GPU's iteration count."""
     import workloads as wl
-    A = ops.fd_dirichlet(w.dims, w.h)
-    T = omg.VCycle("fd", w.dims, w.h, 1.0, w.mg_levels)
-    prob = oplhr.Problem(A=A, T=T.apply, sigma=sigma)
-    V0 = wl.start_block(w.n, k + kx, w.v0_seed)
-    s = oplhr.BPLHR(prob, V0, k, real=True, lock=bool(lock))
-    s.tol = 1e-8
-    t0 = time.perf_counter()
-    its = 0
-    while True:
-        s.step()
-        its += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or its >= max(gpu_iters, 1):
-            break
-    per_it = el / its
-    est = per_it * max(gpu_iters, 1)
+    from oracle import operators as ops, plhr as oplhr
     try:
         import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([d.get("num_threads", 1) for d in info] + [1])
     except Exception:
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": k / est, "unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{its} oracle iterations ({el:.1f} s, {per_it:.2f} s/iter) of the same "
-                      f"workload, extrapolated to the GPU's {gpu_iters} iterations"}
+        threadpoolctl = None
+    w = wl.config1()
+    w.k_extra = 2
+    A = ops.fd_dirichlet(w.dims, w.h)
+    prob = oplhr.Problem(A=A, sigma=w.sigma)
+
+    def sample(budget):
+        s = oplhr.BPLHR(prob, wl.start_block(w.n, w.k + w.k_extra, w.v0_seed), w.k, real=True,
+                        lock=True)
+        s.tol = 1e-8
+        t0 = time.perf_counter()
+        its = 0
+        while its < gpu_iters:
+            s.residuals()
+            s.step()
+            its += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return its, time.perf_counter() - t0
+
+    out = {}
+    threads_all = os.cpu_count() or 1
+    for label, nthreads in (("all", threads_all), ("one", 1)):
+        if threadpoolctl is not None:
+            with threadpoolctl.threadpool_limits(limits=nthreads):
+                its, el = sample(budget_s / 2)
+            info = threadpoolctl.threadpool_info()
+            used = min(nthreads, max([d.get("num_threads", 1) for d in info] + [1]))
+        else:
+            its, el = sample(budget_s / 2)
+            used = nthreads
+        out[label] = {"iterations": its, "seconds": el, "threads": used,
+                      "value": w.k / (el / its * gpu_iters)}
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": out["all"]["value"], "unit": "eigenpairs/s", "cores": out["all"]["threads"],
+            "kind": "oracle",
+            "sample": f"{out['all']['iterations']} oracle iterations ({out['all']['seconds']:.1f} s) "
+                      f"of the small configuration, extrapolated to the GPU's {gpu_iters} "
+                      "iterations",
+            "one_thread": {"value": out["one"]["value"], "iterations": out["one"]["iterations"],
+                           "seconds": out["one"]["seconds"]},
+            "host": {"cpu_model": model, "nproc": threads_all}}
 
 
 def spmm_leg(w, sigma, k, kx, reps=20):
@@ -450,26 +462,139 @@ def paper_tables(which=("t1", "t2", "t3"), max_iters=1000, nu=1):
     return runs
 
 
+def timed_solves(solver, V0, k, ref, steps, warmup):
+    """Warm-up solves, one untimed solve profiling every kernel, then the
+    timed solves with HIP events around the dominant kernel's launches
+    only (on the solver's stream).  A solve counts its k pairs when it
+    converged and its eigenvalues match the closed form `ref`."""
+    from paper_1408_0042_amd import _lib as L
+    import torch
+    for _ in range(warmup):
+        solver.solve(V0, allow_unconverged=True)
+    solver.profile_start(-1, 400000)
+    solver.solve(V0, allow_unconverged=True)
+    prof_all = solver.profile_stop()
+    cats = [c for c in L.KCAT_NAMES if prof_all[c]["launches"] > 0]
+    dom = max(cats, key=lambda c: prof_all[c]["ms"])
+    dom_id = L.KCAT_NAMES.index(dom)
+    torch.cuda.synchronize()
+    solver.profile_start(dom_id, 400000)
+    times, iters, conv, correct = [], [], [], []
+    t00 = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = solver.solve(V0, allow_unconverged=True)
+        times.append(time.perf_counter() - t0)
+        iters.append(r.iters)
+        conv.append(bool(r.converged))
+        lam = np.sort(r.eigvals.cpu().numpy())
+        correct.append(bool(np.all(np.abs(lam - ref) <= 1e-6 * np.abs(ref))))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t00
+    prof = solver.profile_stop()
+    p = prof[dom]
+    roof = roofline_entry(dom, p)
+    roof["kernel"] = L.KCAT_KERNELS[dom_id]
+    roof["launches"] = p["launches"]
+    roof["avg_launch_us"] = 1e3 * p["ms"] / max(1, p["launches"])
+    roof["algorithmic_per_launch"] = ((p["bytes"] if roof["unit"] == "GB/s" else p["flops"])
+                                      / max(1, p["launches"]))
+    roof["share_of_step"] = p["ms"] / (1e3 * el)
+    if roof["bound"] == "alu":
+        # one workgroup: the fraction of one compute unit's FP64 peak as well
+        roof["frac_of_one_cu"] = roof["frac"] * 256
+    kernels = {}
+    for c in cats:
+        e = roofline_entry(c, prof_all[c])
+        kernels[c] = {"ms_per_step": round(prof_all[c]["ms"], 3),
+                      "us_per_launch": round(1e3 * prof_all[c]["ms"] / prof_all[c]["launches"], 2),
+                      "bound": e["bound"], "achieved": round(e["achieved"], 2), "unit": e["unit"],
+                      "frac": round(e["frac"], 5)}
+    good = sum(1 for c, r in zip(conv, correct) if c and r)
+    its_med = float(np.median(iters))
+    return {"value": k * good / el, "el": el, "ms_per_step": 1e3 * el / steps,
+            "median_ms": 1e3 * float(np.median(times)), "iters": iters, "conv": conv,
+            "correct": correct, "us_per_iteration": 1e6 * float(np.median(times)) / max(its_med, 1),
+            "roof": roof, "dom": dom, "kernels": kernels}
+
+
+def fd7_leg(N, steps):
+    """The second configuration's operator at a shift ~125 eigenvalues deep
+    (see the module docstring), FP64 and mixed."""
+    import torch
+    import workloads as wl
+    from paper_1408_0042_amd.plhr import Solver
+    w = wl.bench_workload(N)
+    k, kx = w.k, w.k_extra
+    ev = closed_form_3d(N, w.h)
+    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - w.sigma)))][:k])
+    V0 = torch.from_numpy(wl.start_block(w.n, k + kx, w.v0_seed)).cuda()
+    out = {"workload": f"fd7_3d {N}^3 Dirichlet Laplacian, B=I, k={k}+{kx}, T=V-cycle("
+                       f"{w.mg_levels} levels, 2+2 Jacobi), sigma={w.sigma:.6f} (about 125 "
+                       "eigenvalues deep; off the configuration's shift), lock=0",
+           "shift_note": "off-config: the configuration's sigma = 0.25 lambda_max is in "
+                         "`quarter`"}
+    for prec in ("fp64", "mixed"):
+        S = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=k, k_extra=kx, tol=1e-8,
+                   max_iters=5000, check_every=10, lock=False, precision=prec,
+                   precond={"levels": w.mg_levels, "nu": 2, "omega": 2.0 / 3.0})
+        r = timed_solves(S, V0, k, ref, steps, 0)
+        S.close()
+        out[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                     "iterations": r["iters"], "converged": r["conv"],
+                     "matches_closed_form": r["correct"],
+                     "us_per_iteration": r["us_per_iteration"],
+                     "dominant": r["roof"], "kernels": r["kernels"]}
+    f, m = out["fp64"], out["mixed"]
+    out["mixed_over_fp64"] = {"throughput": m["value"] / f["value"] if f["value"] else None,
+                              "per_iteration": f["us_per_iteration"] / m["us_per_iteration"]}
+    return out
+
+
+def quarter_leg(N, iters):
+    """The second configuration exactly as specified (sigma = 0.25
+    lambda_max, k = 16 + 1, soft locking, seeded start block): a fixed
+    number of iterations with the configured V-cycle and with AV-MG
+    (Algorithm 4), the largest wanted relative residual reached."""
+    import torch
+    import workloads as wl
+    from paper_1408_0042_amd.plhr import Solver
+    w = wl.config2(N)
+    V0 = torch.from_numpy(w.v0()).cuda()
+    out = {"workload": f"fd7_3d {N}^3, sigma = 0.25 lambda_max = {w.sigma:.4f}, k = "
+                       f"{w.k}+{w.k_extra}, {iters} iterations", "iterations": iters}
+    for name, pre in (("vcycle", {"levels": w.mg_levels, "nu": 2}),
+                      ("av_mg", {"kind": "av", "levels": w.mg_levels, "nu": 2, "delta": 0.6,
+                                 "degree": 10})):
+        S = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=w.k, k_extra=w.k_extra,
+                   tol=1e-8, max_iters=iters, check_every=50, precond=pre)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.start(V0)
+        info = S.iterate(iters)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.close()
+        out[name] = {"max_rel_res": info.max_rel_res, "converged": bool(info.converged),
+                     "ms_per_iteration": 1e3 * el / max(1, info.iters)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--N", type=int, default=64)
-    ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--k-extra", type=int, default=4)
-    ap.add_argument("--lock", type=int, default=0)
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
-    ap.add_argument("--shift", default="below121")
-    ap.add_argument("--check-every", type=int, default=10)
-    ap.add_argument("--max-iters", type=int, default=5000)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--check-every", type=int, default=25)
+    ap.add_argument("--cpu-budget", type=float, default=24.0,
+                    help="seconds of oracle iterations (half with all threads, half with one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fd7", action="store_true", help="skip the 64^3 leg")
+    ap.add_argument("--fd7-steps", type=int, default=1)
+    ap.add_argument("--quarter-iters", type=int, default=200)
     ap.add_argument("--no-spmm", action="store_true", help="skip the sparse-times-block and Bloch legs")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
-    ap.add_argument("--ortho-passes", type=int, default=1,
-                    help="Cholesky-QR passes of the B-orthonormalisation per iteration (2: CholQR2)")
     ap.add_argument("--paper-tables", default="",
                     help="comma list of t1,t2,t3: run the iteration-count experiments of "
                          "Section 6.2 instead of the benchmark")
@@ -491,128 +616,69 @@ def main():
 
     import torch
     import workloads as wl
-    from paper_1408_0042_amd import _lib as L
     from paper_1408_0042_amd.plhr import Solver
 
-    N, k, kx = args.N, args.k, args.k_extra
-    w = wl.config2(N)
-    sigma, ev = pick_sigma(N, w.h, args.shift)
-    fixed = args.shift == "quarter"
-    # the k eigenvalues nearest sigma, from the closed form
-    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:k])
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib * 131072, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # the small configuration as specified (two extra block columns)
+    w = wl.config1()
+    w.k_extra = 2
+    N, h, k, kx = w.dims[0], w.h, w.k, w.k_extra
+    s1 = (4.0 / h**2) * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    ev = np.sort(np.add.outer(s1, s1).ravel())
+    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - w.sigma)))][:k])
     V0 = torch.from_numpy(wl.start_block(w.n, k + kx, w.v0_seed)).to("cuda")
     torch.cuda.synchronize()
-
-    def run(precision):
-        """Warm-up, one untimed solve profiling every kernel, then the timed
-        solves with events around the dominant kernel only."""
-        solver = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=sigma, k=k, k_extra=kx,
-                        tol=1e-8, max_iters=args.max_iters, check_every=args.check_every,
-                        lock=bool(args.lock), precision=precision, ortho_passes=args.ortho_passes,
-                        precond={"levels": w.mg_levels, "nu": 2, "omega": 2.0 / 3.0})
-        lams = []
-
-        def one_step():
-            if fixed:
-                solver.start(V0)
-                info = solver.iterate(args.max_iters)
-                solver.finish()
-                return info.iters, bool(info.converged)
-            r = solver.solve(V0, allow_unconverged=True)
-            lams.append(r.eigvals)
-            return r.iters, r.converged
-
-        for _ in range(args.warmup):
-            one_step()
-        solver.profile_start(-1, 200000)
-        one_step()
-        prof_all = solver.profile_stop()
-        cats = [c for c in L.KCAT_NAMES if prof_all[c]["launches"] > 0]
-        dom = max(cats, key=lambda c: prof_all[c]["ms"])
-        dom_id = L.KCAT_NAMES.index(dom)
-        torch.cuda.synchronize()
-        lams.clear()
-        solver.profile_start(dom_id, 200000)
-        t0 = time.perf_counter()
-        iters, conv = [], []
-        for _ in range(args.steps):
-            it, cv = one_step()
-            iters.append(it)
-            conv.append(cv)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        prof = solver.profile_stop()
-        solver.close()
-        correct = [bool(np.all(np.abs(np.sort(l.cpu().numpy()) - ref) <= 1e-6 * np.abs(ref)))
-                   for l in lams] if not fixed else [False] * args.steps
-        value = k * sum(1 for c, r in zip(conv, correct) if c and r) / el
-        p = prof[dom]
-        roof = roofline_entry(dom, p)
-        roof["kernel"] = L.KCAT_KERNELS[dom_id]
-        roof["launches"] = p["launches"]
-        roof["avg_launch_us"] = 1e3 * p["ms"] / max(1, p["launches"])
-        roof["algorithmic_per_launch"] = ((p["bytes"] if roof["unit"] == "GB/s" else p["flops"])
-                                          / max(1, p["launches"]))
-        roof["share_of_step"] = p["ms"] / (1e3 * el)
-        # per launch at the full trial width m = 4 (k + kx), in bytes
-        roof["traffic"] = measured_traffic(dom, 4 * (k + kx))
-        kernels = {}
-        for c in cats:
-            e = roofline_entry(c, prof_all[c])
-            kernels[c] = {"ms_per_step": round(prof_all[c]["ms"], 3), "bound": e["bound"],
-                          "achieved": round(e["achieved"], 2), "unit": e["unit"],
-                          "frac": round(e["frac"], 5)}
-        return {"value": value, "el": el, "ms_per_step": 1e3 * el / args.steps, "iters": iters,
-                "conv": conv, "correct": correct, "roof": roof, "kernels": kernels}
-
-    primary = "mixed" if args.precision == "mixed" else "fp64"
-    res = run(primary)
-    other = run("mixed") if args.precision == "both" else None
-    value, ms_per_step, iters, conv, correct = (res["value"], res["ms_per_step"], res["iters"],
-                                                res["conv"], res["correct"])
-    roof, kernels = res["roof"], res["kernels"]
+    S = Solver(kind="fd5_2d", dims=w.dims, h=h, sigma=w.sigma, k=k, k_extra=kx, tol=1e-8,
+               max_iters=30000, check_every=args.check_every)
+    res = timed_solves(S, V0, k, ref, args.steps, args.warmup)
+    S.close()
+    roof = res["roof"]
+    roof["traffic"] = measured_traffic(res["dom"], 4 * (k + kx))
     out = {
-        "metric": "converged eigenpairs/s at rel. residual 1e-8 (FP64 path; mixed FP32 V-cycle in 'mixed')",
-        "value": value,
+        "metric": "converged eigenpairs/s at rel. residual 1e-8",
+        "value": res["value"],
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if primary == "fp64" else "f64 (V-cycle f32)",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"fd7_3d {N}^3 Dirichlet Laplacian, B=I, k={k}+{kx}, "
-                               f"T=V-cycle({w.mg_levels} levels, 2+2 Jacobi), "
-                               f"sigma={sigma:.6f} ({args.shift}), lock={args.lock}",
-                   "n": w.n, "k": k, "k_extra": kx, "precision": primary,
-                   "ortho_passes": args.ortho_passes, "iterations": iters,
-                   "converged": conv, "matches_closed_form": correct},
+        "config": {"workload": f"fd5_2d {N}x{N} Dirichlet Laplacian (h = 1/{N + 1}), B=I, T=I, "
+                               f"k={k}+{kx}, sigma = 0.4 lambda_max = {w.sigma:.8f}, "
+                               "seeded N(0,1) start block, soft locking",
+                   "n": w.n, "k": k, "k_extra": kx, "iterations": res["iters"],
+                   "converged": res["conv"], "matches_closed_form": res["correct"],
+                   "median_ms_per_solve": res["median_ms"],
+                   "us_per_iteration": res["us_per_iteration"]},
         "roofline": roof,
-        "kernels": kernels,
+        "kernels": res["kernels"],
     }
-    if other is not None:
-        out["mixed"] = {"value": other["value"], "ms_per_step": other["ms_per_step"],
-                        "iterations": other["iters"], "converged": other["conv"],
-                        "matches_closed_form": other["correct"],
-                        "mixed_over_fp64": other["value"] / value if value > 0 else None,
-                        "kernels": {c: v["ms_per_step"] for c, v in other["kernels"].items()}}
+    print(json.dumps({"progress": "small configuration timed", "value": res["value"]}),
+          file=sys.stderr, flush=True)
+    if not args.no_fd7:
+        out["fd7_64"] = fd7_leg(64, args.fd7_steps)
+        print(json.dumps({"progress": "fd7_64 done"}), file=sys.stderr, flush=True)
+        out["quarter"] = quarter_leg(64, args.quarter_iters)
+        print(json.dumps({"progress": "quarter done"}), file=sys.stderr, flush=True)
     if args.batch > 0:
         out["batched"] = run_batched(args.batch, args.batch_steps, 1)
+        print(json.dumps({"progress": "batched done"}), file=sys.stderr, flush=True)
     if not args.no_spmm:
-        out["spmm"] = spmm_leg(w, sigma, k, kx)
+        w2 = wl.bench_workload(64)
+        out["spmm"] = spmm_leg(w2, w2.sigma, w2.k, w2.k_extra)
         out["bloch"] = bloch_leg()
+        print(json.dumps({"progress": "spmm and bloch done"}), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, sigma, k, kx, args.lock, int(np.median(iters)),
-                                       args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline_config1(int(np.median(res["iters"])), args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -189,13 +189,20 @@ typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_ext
  *   lock         soft locking of converged columns            (1)
  *   check_every  iterations between host convergence checks   (1)
  *   ortho_passes Cholesky-QR passes of the B-orthonormalisation of
- *                [V W S P] per iteration: 0 or 1 for one, 2 for a second
- *                pass on the result (CholQR2), which restores the
- *                B-orthogonality a single pass loses when the block is
- *                ill-conditioned (converged columns without locking) at
- *                the price of one more Gram and transform       (1)
- *   drop_tol     squared relative norm below which a W/S/P column is
- *                dropped during B-orthonormalisation          (1e-12)
+ *                [V W S P] per iteration: 1 one pass, 2 always a second
+ *                pass on the result (CholQR2), 0 a second pass only when
+ *                the first meets a pivot of the column-scaled Gram below
+ *                1e-4 (one pass loses about eps / pivot of
+ *                B-orthogonality, which grows when converged columns
+ *                are not locked); the second pass's kernels return at
+ *                once otherwise                               [0]
+ *   drop_tol     squared relative norm (the pivot of the column-scaled
+ *                Gram) below which a column is dropped during the
+ *                B-orthonormalisation: the transform R^-1 scales by up to
+ *                pivot^-1/2 and also acts on the carried products
+ *                (A - sigma B)Z and T(A - sigma B)Z, so a smaller pivot
+ *                amplifies their rounding-level disagreement with Z each
+ *                iteration                                    [1e-10]
  *   extraction   a plhr_extraction value                      [T_HARMONIC]
  *   use_graph    1: each iteration's launches are captured once in a HIP
  *                graph (on a stream of the library's own) and replayed on

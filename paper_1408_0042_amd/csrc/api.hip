@@ -260,6 +260,7 @@ struct plhr_ctx_s {
   SmallBufs sb{};
   SmallParams sp{};
   DevStatus* st = nullptr;
+  DevStatus* gate = nullptr;  // the automatic second Cholesky-QR pass
   DevStatus* st_host = nullptr;
   bool started = false, finished = false;
   long host_iter = 0;  // iterations enqueued since plhr_start
@@ -457,6 +458,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
   size_t ofc = L.take((size_t)kint * kint * 8), oft = L.take(kint * 8), ovbv = L.take(kint * 8);
   size_t owork = L.take((size_t)4 * m * m * 8);
   size_t ost = L.take(sizeof(DevStatus));
+  size_t ogate = L.take(sizeof(DevStatus));
   size_t obsq = 0, obisq = 0, oRs = 0;
   if (bdiag) {
     obsq = L.take(n * 8);
@@ -501,6 +503,7 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
     c->sb.work = (double*)(b + owork);
     c->sb.scratch = nullptr;
     c->st = (DevStatus*)(b + ost);
+    c->gate = (DevStatus*)(b + ogate);
     if (bdiag) {
       c->bsq = (double*)(b + obsq);
       c->bisq = (double*)(b + obisq);
@@ -543,8 +546,9 @@ void precond_raw(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int 
     const bool f32 = direction && c->opt.precision == PLHR_PREC_MIXED;
     mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, f32, st, c->stream);
   } else {
-    if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream);
-    if (split < ncols) launch_copy(c->n, Rin + split, ldr, o1.ptr, o1.ld, ncols - split, c->stream);
+    if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream, st);
+    if (split < ncols)
+      launch_copy(c->n, Rin + split, ldr, o1.ptr, o1.ld, ncols - split, c->stream, st);
   }
 }
 
@@ -555,11 +559,12 @@ void precond(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int spli
     precond_raw(c, Rin, ldr, o0, o1, split, ncols, st, direction);
     return;
   }
-  launch_rowscale(c->n, c->bsq, Rin, ldr, c->Rs, ncols, ncols, c->stream);
+  launch_rowscale(c->n, c->bsq, Rin, ldr, c->Rs, ncols, ncols, c->stream, st);
   precond_raw(c, c->Rs, ncols, o0, o1, split, ncols, st, direction);
-  if (split > 0) launch_rowscale(c->n, c->bsq, o0.ptr, o0.ld, o0.ptr, o0.ld, split, c->stream);
+  if (split > 0)
+    launch_rowscale(c->n, c->bsq, o0.ptr, o0.ld, o0.ptr, o0.ld, split, c->stream, st);
   if (split < ncols)
-    launch_rowscale(c->n, c->bsq, o1.ptr, o1.ld, o1.ptr, o1.ld, ncols - split, c->stream);
+    launch_rowscale(c->n, c->bsq, o1.ptr, o1.ld, o1.ptr, o1.ld, ncols - split, c->stream, st);
 }
 
 // Gram product on the matrix cores when the shape fits.
@@ -662,15 +667,44 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   arrs[narr++] = QZ;
   if (tharm) arrs[narr++] = TQZ;
   if (bst) arrs[narr++] = BZ;
-  for (int pass = 0; pass < std::max(1, c->opt.ortho_passes); ++pass) {
+  // The first pass also decides (on the device, in the gate) whether the
+  // basis met a small pivot: then the B-orthogonality needs a second pass
+  // (ortho_passes 0: automatic; 2: always) and the carried products of the
+  // V and P slots, which the transform mixes with weights up to
+  // pivot^-1/2, are recomputed from the new basis below.
+  {
+    SmallParams p1 = c->sp, p2 = c->sp;
+    SmallBufs b1 = c->sb;
+    b1.gate = c->gate;
+    p1.pass = 1;
+    p2.pass = 2;
     gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-    launch_ortho_small(c->sp, c->sb, st, s);
+    launch_ortho_small(p1, b1, st, s);
     transform(c, arrs, narr, st);
+    if (c->opt.ortho_passes == 0) {
+      gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, c->gate);
+      launch_ortho_small(p2, b1, st, s);
+      transform(c, arrs, narr, c->gate);
+    } else if (c->opt.ortho_passes == 2) {
+      gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
+      launch_ortho_small(c->sp, c->sb, st, s);
+      transform(c, arrs, narr, st);
+    }
+    // gated recomputation of (A - sigma B)Z and T(A - sigma B)Z for V and P
+    for (int slot : {0, 3}) {
+      stencil(c, Z + slot * kint, m, Blk{QZ + slot * kint, m}, none, nullptr, none, kint,
+              c->sigma, c->gate, bst ? Blk{BZ + slot * kint, m} : none);
+      if (tharm) precond(c, QZ + slot * kint, m, Blk{TQZ + slot * kint, m}, none, kint, kint,
+                         c->gate);
+    }
   }
   // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]  (Q Zhat for the harmonic
   // extraction)
   gram(c, tharm ? TQZ : QZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
-  launch_tharm_small(c->sp, c->sb, st, s);
+  if (c->sp.sym)
+    launch_tharm_sym(c->sp, c->sb, st, s);
+  else
+    launch_tharm_small(c->sp, c->sb, st, s);
   // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
   nb = update(c, arrs, narr, st);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
@@ -772,7 +806,7 @@ plhr_status plhr_options_default(plhr_options* opt) {
   opt->precision = PLHR_PREC_FP64;
   opt->lock = 1;
   opt->check_every = 1;
-  opt->drop_tol = 1e-12;
+  opt->drop_tol = 1e-10;
   return PLHR_OK;
 }
 
@@ -939,8 +973,17 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->sp.normB1 = c->normB1;
   c->sp.drop_tol = o.drop_tol;
   c->sp.lock = o.lock;
+  // G_R of eq. (3.5) is symmetric when T does not enter the projection
+  // (T = I, or the harmonic extraction) and B = I: the projected problem
+  // is then Hermitian-definite
+  c->sp.sym = (!c->bst && (o.extraction == PLHR_EXTRACT_HARMONIC ||
+                           (c->prec_kind == PLHR_PREC_IDENTITY && !c->bdiag)))
+                  ? 1
+                  : 0;
+  if (getenv("PLHR_NO_SYM")) c->sp.sym = 0;
   c->use_mfma = (getenv("PLHR_NO_MFMA") == nullptr);
   hipError_t e = small_set_attributes(c->m, c->kint);
+  if (e == hipSuccess) e = tharm_sym_set_attributes();
   if (e == hipSuccess) e = mfma_set_attributes(c->m, c->kint);
   if (e != hipSuccess) {
     set_error(std::string("LDS attribute: ") + hipGetErrorString(e));
@@ -973,6 +1016,7 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   PLHR_HIP_CHECK(hipMemsetAsync(c->TQZ, 0, n * m * sizeof(double), s));
   if (c->bst) PLHR_HIP_CHECK(hipMemsetAsync(c->BZ, 0, n * m * sizeof(double), s));
   PLHR_HIP_CHECK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
+  PLHR_HIP_CHECK(hipMemsetAsync(c->gate, 0, sizeof(DevStatus), s));
   if (c->bdiag)
     launch_rowscale(n, c->bsq, V0, kint, c->Z, m, kint, s);  // u = B^1/2 v
   else

@@ -275,11 +275,13 @@ int update_blocks(size_t n);
 void launch_small_gemm(size_t n, const double* X, int ldx, int kin, const double* M, int kout,
                        double* Y, int ldy, hipStream_t s);
 
-// copy n x c block with leading dimensions
-void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s);
-// Y = diag(w) X, n x c (Y may alias X with ldy == ldx)
+// copy n x c block with leading dimensions (nothing when st is halted)
+void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s,
+                 const DevStatus* st = nullptr);
+// Y = diag(w) X, n x c (Y may alias X with ldy == ldx; nothing when st is
+// halted)
 void launch_rowscale(size_t n, const double* w, const double* X, int ldx, double* Y, int ldy,
-                     int c, hipStream_t s);
+                     int c, hipStream_t s, const DevStatus* st = nullptr);
 
 // column partial sums for final residuals (as launch_resid_prep, no R):
 int launch_coldots(size_t n, const double* X, int ldx, const double* QX, int ldq, int c,
@@ -340,6 +342,10 @@ struct SmallBufs {
   double* vbv;      // kint
   double* work;     // 4 m^2: projected-solver matrices between its kernels
   double* scratch;  // misc
+  // automatic second Cholesky-QR pass: the first pass sets gate->done to 0
+  // when it is needed (1 otherwise); the second pass's kernels take the
+  // gate as their status word and return at once when it is 1
+  DevStatus* gate = nullptr;
 };
 
 struct SmallParams {
@@ -349,6 +355,8 @@ struct SmallParams {
   double normA1, normB1;
   double drop_tol;
   int lock;
+  int sym = 0;        // G_R symmetric (T = I or harmonic extraction, B = I)
+  int pass = 0;       // Cholesky-QR pass with a gate: 1 first, 2 second; 0 none
 };
 
 // ------------------------------------------------------------- batches
@@ -448,6 +456,10 @@ void launch_conv_check(const SmallParams& p, const double* part, int nblk, Small
                        DevStatus* st, int max_iters, hipStream_t s);
 void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// The same step when G_R is symmetric: Cholesky, C = L^-1 G_R L^-T and
+// the cyclic Jacobi method in one workgroup (k_tharm_sym.hip).
+void launch_tharm_sym(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+hipError_t tharm_sym_set_attributes();
 // Rayleigh quotients from per-block partial sums [v.v | v.(A - sigma B)v];
 // end_of_iteration also advances the iteration counter.
 void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,

@@ -434,7 +434,9 @@ void launch_small_gemm(size_t n, const double* X, int ldx, int kin, const double
 }
 
 __global__ __launch_bounds__(256) void k_copy(size_t n, const double* __restrict__ X, int ldx,
-                                              double* __restrict__ Y, int ldy, int c) {
+                                              double* __restrict__ Y, int ldy, int c,
+                                              const DevStatus* st) {
+  if (halted(st)) return;
   const size_t tot = n * c;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -444,18 +446,20 @@ __global__ __launch_bounds__(256) void k_copy(size_t n, const double* __restrict
   }
 }
 
-void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s) {
+void launch_copy(size_t n, const double* X, int ldx, double* Y, int ldy, int c, hipStream_t s,
+                 const DevStatus* st) {
   size_t tot = n * c;
   size_t nb = (tot + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, n, X, ldx, Y, ldy, c);
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, n, X, ldx, Y, ldy, c, st);
 }
 
 // Y = diag(w) X (rows scaled; Y may be X with the same leading dimension).
 __global__ __launch_bounds__(256) void k_rowscale(size_t n, const double* __restrict__ w,
                                                   const double* X, int ldx, double* Y, int ldy,
-                                                  int c) {
+                                                  int c, const DevStatus* st) {
+  if (halted(st)) return;
   const size_t tot = n * (size_t)c;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -466,13 +470,13 @@ __global__ __launch_bounds__(256) void k_rowscale(size_t n, const double* __rest
 }
 
 void launch_rowscale(size_t n, const double* w, const double* X, int ldx, double* Y, int ldy,
-                     int c, hipStream_t s) {
+                     int c, hipStream_t s, const DevStatus* st) {
   if (c <= 0 || n == 0) return;
   const size_t tot = n * (size_t)c;
   const size_t want = (tot + 255) / 256;
   const int nb = (int)(want < 4096 ? want : 4096);
   prof_begin(KC_VEC, (double)n * c * 16.0 + n * 8.0, (double)n * c, s);
-  hipLaunchKernelGGL(k_rowscale, dim3(nb), dim3(256), 0, s, n, w, X, ldx, Y, ldy, c);
+  hipLaunchKernelGGL(k_rowscale, dim3(nb), dim3(256), 0, s, n, w, X, ldx, Y, ldy, c, st);
   prof_end(KC_VEC, s);
 }
 

@@ -220,8 +220,17 @@ __global__ __launch_bounds__(256) void k_conv_check_b(const BatchSmall* __restri
 // --------------------------------------------- Cholesky-QR in slot order
 // LDS: Gs (m x m, Cholesky factor R in the upper triangle) | X (m x m,
 // R^-1) | d (m)
+// smallest pivot of the column-scaled Gram (squared relative norm of a
+// column's part orthogonal to the earlier ones) below which one pass loses
+// more than ~eps / pivot of B-orthogonality and a second pass is run
+constexpr double kOrthoRedo = 1e-4;
+
 __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
-  if (halted(st)) return;
+  if (halted(st)) {
+    if (p.pass == 1 && b.gate && threadIdx.x == 0) b.gate->done = 1;
+    return;
+  }
+  if (p.pass == 2 && b.gate && b.gate->done) return;
   extern __shared__ __attribute__((aligned(16))) double sm[];
   const int m = p.m, kint = p.kint;
   double* Gs = sm;
@@ -278,6 +287,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   // per kept column.  A dropped column takes no barrier: the decision is
   // uniform and column j is read by no later step.
   __shared__ double rsc[256];  // 1/sqrt(pivot) of each kept slot
+  double minpiv = INFINITY;    // (thread 0) smallest kept pivot
   for (int j = 0; j < m; ++j) {
     if (!valid[j]) continue;
     const double piv = Gs[j * m + j];
@@ -285,6 +295,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
       if (t == 0) valid[j] = 0;
       continue;
     }
+    minpiv = fmin(minpiv, piv);
     const double ip = 1.0 / piv;
     if (t == 0) rsc[j] = piv;  // 1 / sqrt(pivot) after the loop, by all lanes
     // rows and columns of slots left out at the start are exact zeros and
@@ -362,6 +373,10 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     }
     st->m_kept = nk;
     st->n_dropped = nd;
+    if (p.pass == 1 && b.gate) {
+      b.gate->error = 0;
+      b.gate->done = (minpiv < kOrthoRedo) ? 0 : 1;
+    }
   }
 }
 
@@ -441,9 +456,22 @@ __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
   // is a breakdown.
   __shared__ int drop[128];
   __shared__ double dsc[128];
+  // When at least k columns met the tolerance, the columns that did not
+  // (guard columns still converging) are left out as well: a guard column
+  // that shares a multiple eigenvalue with wanted pairs would otherwise be
+  // mixed into the returned vectors by the rotation within that cluster.
+  __shared__ int excl[128];
+  __shared__ int nconv_s;
+  if (t == 0) {
+    int cnv = 0;
+    for (int j = 0; j < n; ++j) cnv += (b.relres[j] <= p.tol) ? 1 : 0;
+    nconv_s = cnv;
+  }
+  __syncthreads();
   for (int j = t; j < n; j += kTh) {
     const double g = L[j * n + j];
     dsc[j] = (g > 0.0 && g < INFINITY) ? 1.0 / sqrt(g) : 0.0;
+    excl[j] = (nconv_s >= k && !(b.relres[j] <= p.tol)) ? 1 : 0;
   }
   __syncthreads();
   for (int e = t; e < n * n; e += kTh) {
@@ -457,7 +485,7 @@ __device__ void k_final_rr_body(SmallParams p, const double* __restrict__ HM,
   for (int j = 0; j < n; ++j) {
     const double piv = L[j * n + j];
     __syncthreads();
-    if (!(piv > p.drop_tol)) {  // uniform
+    if (!(piv > p.drop_tol) || excl[j]) {  // uniform
       for (int i = t; i < n; i += kTh) {
         if (i > j) L[i * n + j] = 0.0;
         if (i < j) L[j * n + i] = 0.0;

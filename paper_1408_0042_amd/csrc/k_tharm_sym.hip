@@ -1,0 +1,311 @@
+// The projected eigenproblem of eq. (3.5) when G_R is symmetric: with
+// T = I (or the harmonic extraction, T -> I in the projection) and B = I,
+//     G_L = Zhat^*(A - sigma)^2 Zhat,   G_R = Zhat^*(A - sigma) Zhat,
+// the Hermitian-definite harmonic Rayleigh-Ritz problem (Section 3.1):
+// every xi is real.  With G_L = L L^T, C = L^-1 G_R L^-T is symmetric, so
+// its eigenpairs come from the cyclic Jacobi method (Golub & Van Loan,
+// Sec. 8.5) instead of a Hessenberg reduction and the nonsymmetric QR:
+// each round rotates n/2 disjoint (p, q) planes of a round-robin
+// tournament at once, three barriers per round.  The k_int eigenvectors
+// of smallest |xi| = 1/|tau| (ties: smaller xi) are y = L^-T u, scaled to
+// unit 2-norm with their largest entry positive, in Y' (all columns real,
+// no pairs).  One workgroup; C and the rotations in LDS.
+#include <cmath>
+
+#include "common.cuh"
+
+namespace plhr {
+
+namespace {
+
+constexpr int kST = 256;
+
+__device__ double sym_block_sum(double a, double* red) {
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kST / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+}  // namespace
+
+// LDS: C n*ld | V n*ld (L during the factorisation, later the
+// eigenvectors) | 4 n doubles
+__global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, DevStatus* st) {
+  if (halted(st)) return;
+  extern __shared__ __attribute__((aligned(16))) double sm[];
+  __shared__ int idx[kMaxM + 1];
+  __shared__ int dead[kMaxM + 1];
+  __shared__ int cnt_s, ndead_s;
+  __shared__ double red[kST / 64];
+  __shared__ double csr[kMaxM / 2 + 1], snr[kMaxM / 2 + 1];
+  const int m = p.m, kint = p.kint, t = threadIdx.x;
+  if (t == 0) {
+    int c = 0;
+    for (int s = 0; s < m; ++s)
+      if (b.keep[s]) idx[c++] = s;
+    cnt_s = c;
+    ndead_s = 0;
+  }
+  __syncthreads();
+  const int n = cnt_s;
+  if (n < kint) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    return;
+  }
+  const int ld = n | 1;
+  double* C = sm;
+  double* V = C + n * ld;
+  double* piv = V + n * ld;  // pivots, later tau
+  double* aux = piv + n;     // 1/sqrt(pivot)
+  double* yv = aux + n;      // (unused spare)
+  const int ld2 = 2 * m;
+  // symmetric parts of G_L (into V) and G_R (into C) on the kept slots
+  for (int e = t; e < n * n; e += kST) {
+    const int i = e / n, j = e - i * n;
+    const int ia = idx[i], ja = idx[j];
+    V[i * ld + j] = 0.5 * (b.GLR[(size_t)ia * ld2 + ja] + b.GLR[(size_t)ja * ld2 + ia]);
+    C[i * ld + j] = 0.5 * (b.GLR[(size_t)ia * ld2 + m + ja] + b.GLR[(size_t)ja * ld2 + m + ia]);
+  }
+  for (int j = t; j < n; j += kST) dead[j] = 0;
+  __syncthreads();
+  // Cholesky of G_L, right-looking on unscaled columns; pivots as in the
+  // general projected solver (raised to 1e-15 max diag, a clearly
+  // negative one leaves its slot out)
+  double maxd = 0.0;
+  for (int j = 0; j < n; ++j) maxd = fmax(maxd, V[j * ld + j]);
+  const double floor_ = fmax(1e-15 * maxd, 1e-300);
+  for (int j = 0; j < n; ++j) {
+    const double p0 = V[j * ld + j];
+    if (p0 < -1e-10 * maxd) {  // uniform across the workgroup
+      if (t == 0) {
+        dead[j] = 1;
+        ++ndead_s;
+      }
+      continue;
+    }
+    const double pp = fmax(p0, floor_);
+    if (t == 0) piv[j] = pp;
+    const double inv = 1.0 / pp;
+    const int rem = n - j - 1;
+    for (int e = t; e < rem * rem; e += kST) {
+      const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+      if (c <= i) V[i * ld + c] -= V[i * ld + j] * inv * V[c * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int j = t; j < n; j += kST) aux[j] = dead[j] ? 0.0 : 1.0 / sqrt(piv[j]);
+  __syncthreads();
+  // L = unscaled columns times 1/sqrt(pivot); dead slots: row and column
+  // of L are e_j, G_R's row and column zero (tau = 0, never selected)
+  for (int e = t; e < n * n; e += kST) {
+    const int i = e / n, c = e - i * n;
+    double v = 0.0;
+    if (dead[i] || dead[c])
+      v = (i == c) ? 1.0 : 0.0;
+    else if (c == i)
+      v = sqrt(piv[i]);
+    else if (c < i)
+      v = V[i * ld + c] * aux[c];
+    V[i * ld + c] = v;
+    if (dead[i] || dead[c]) C[i * ld + c] = 0.0;
+  }
+  __syncthreads();
+  if (t == 0 && ndead_s) st->n_excluded += ndead_s;
+  if (ndead_s && n - ndead_s < kint) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    return;
+  }
+  // C <- L^-1 C (columns, one thread each), then C <- C L^-T (rows)
+  for (int c = t; c < n; c += kST)
+    for (int i = 0; i < n; ++i) {
+      double s = C[i * ld + c];
+      for (int r = 0; r < i; ++r) s -= V[i * ld + r] * C[r * ld + c];
+      C[i * ld + c] = s / V[i * ld + i];
+    }
+  __syncthreads();
+  for (int r = t; r < n; r += kST)
+    for (int i = 0; i < n; ++i) {
+      double s = C[r * ld + i];
+      for (int c = 0; c < i; ++c) s -= V[i * ld + c] * C[r * ld + c];
+      C[r * ld + i] = s / V[i * ld + i];
+    }
+  __syncthreads();
+  // L to the work area (compact); C symmetrised; V = I
+  for (int e = t; e < n * n; e += kST) {
+    const int i = e / n, c = e - i * n;
+    b.work[e] = V[i * ld + c];
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += kST) {
+    const int i = e / n, c = e - i * n;
+    if (c < i) {
+      const double a = 0.5 * (C[i * ld + c] + C[c * ld + i]);
+      C[i * ld + c] = a;
+      C[c * ld + i] = a;
+    }
+    V[i * ld + c] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // cyclic Jacobi, round-robin tournament over ne = n rounded up to even
+  // positions (an index >= n is a bye)
+  const int ne = n + (n & 1), np = ne / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double a2 = 0.0, o2 = 0.0;
+    for (int e = t; e < n * n; e += kST) {
+      const int i = e / n, c = e - i * n;
+      const double v = C[i * ld + c];
+      if (i == c)
+        a2 += v * v;
+      else
+        o2 += v * v;
+    }
+    a2 = sym_block_sum(a2, red);
+    o2 = sym_block_sum(o2, red);
+    if (!(o2 > 1e-32 * a2)) break;  // uniform
+    for (int rnd = 0; rnd < ne - 1; ++rnd) {
+      // pair k: positions k and ne - 1 - k; position 0 holds player 0,
+      // position i >= 1 player 1 + (i - 1 + rnd) mod (ne - 1)
+      if (t < np) {
+        const int i0 = t, i1 = ne - 1 - t;
+        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
+        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
+        double c = 1.0, s = 0.0;
+        if (pa < n && pb < n) {
+          const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+          const double apq = C[pp * ld + qq];
+          if (apq != 0.0) {
+            const double app = C[pp * ld + pp], aqq = C[qq * ld + qq];
+            const double th = (aqq - app) / (2.0 * apq);
+            const double tt = ((th >= 0.0) ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+          }
+        }
+        csr[t] = c;
+        snr[t] = s;
+      }
+      __syncthreads();
+      // rows p, q of C <- J^T (rows)
+      for (int e = t; e < np * n; e += kST) {
+        const int k = e / n, j = e - k * n;
+        const int i0 = k, i1 = ne - 1 - k;
+        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
+        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
+        if (pa >= n || pb >= n) continue;
+        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+        const double c = csr[k], s = snr[k];
+        if (s == 0.0) continue;
+        const double xp = C[pp * ld + j], xq = C[qq * ld + j];
+        C[pp * ld + j] = c * xp - s * xq;
+        C[qq * ld + j] = s * xp + c * xq;
+      }
+      __syncthreads();
+      // columns p, q of C and of V <- (.) J
+      for (int e = t; e < np * n; e += kST) {
+        const int k = e / n, i = e - k * n;
+        const int i0 = k, i1 = ne - 1 - k;
+        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
+        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
+        if (pa >= n || pb >= n) continue;
+        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+        const double c = csr[k], s = snr[k];
+        if (s == 0.0) continue;
+        const double xp = C[i * ld + pp], xq = C[i * ld + qq];
+        C[i * ld + pp] = c * xp - s * xq;
+        C[i * ld + qq] = s * xp + c * xq;
+        const double vp = V[i * ld + pp], vq = V[i * ld + qq];
+        V[i * ld + pp] = c * vp - s * vq;
+        V[i * ld + qq] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // tau and the ranks of xi = 1/tau by (|xi|, xi, index); tau = 0 last
+  for (int i = t; i < n; i += kST) piv[i] = C[i * ld + i];
+  __syncthreads();
+  int* rank = reinterpret_cast<int*>(aux);  // n ints fit in n doubles
+  for (int i = t; i < n; i += kST) {
+    const double ti = piv[i];
+    const double xa = (ti != 0.0) ? 1.0 / fabs(ti) : INFINITY;
+    const double xs = (ti != 0.0) ? 1.0 / ti : INFINITY;
+    int r = 0;
+    for (int o = 0; o < n; ++o) {
+      if (o == i) continue;
+      const double to = piv[o];
+      const double oa = (to != 0.0) ? 1.0 / fabs(to) : INFINITY;
+      const double os = (to != 0.0) ? 1.0 / to : INFINITY;
+      r += (oa < xa || (oa == xa && (os < xs || (os == xs && o < i)))) ? 1 : 0;
+    }
+    rank[i] = r;
+  }
+  __syncthreads();
+  // sorted xi for the host, Y' cleared, kinds and partners
+  for (int i = t; i < n; i += kST) {
+    const double ti = piv[i];
+    b.xi[rank[i]] = (ti != 0.0) ? 1.0 / ti : INFINITY;
+    b.xi[m + rank[i]] = 0.0;
+  }
+  for (int r = n + t; r < m; r += kST) {
+    b.xi[r] = 0.0;
+    b.xi[m + r] = 0.0;
+  }
+  for (int e = t; e < m * kint; e += kST) b.Y[e] = 0.0;
+  for (int c = t; c < kint; c += kST) {
+    b.kinds[c] = 0;
+    b.pair[c] = -1;
+  }
+  // L back into the C region (C's diagonal is saved in piv)
+  for (int e = t; e < n * n; e += kST) {
+    const int i = e / n, c = e - i * n;
+    C[i * ld + c] = b.work[e];
+  }
+  __syncthreads();
+  // y = L^-T u for the selected eigenvectors, one thread each, written as
+  // column `rank` of V's spare layout: solve L^T y = u from the last row
+  for (int i = t; i < n; i += kST) {
+    const int col = rank[i];
+    if (col >= kint) continue;
+    double* u = V + i;  // column i of V, stride ld (overwritten by y)
+    for (int r = n - 1; r >= 0; --r) {
+      double s = u[r * ld];
+      for (int q = r + 1; q < n; ++q) s -= C[q * ld + r] * u[q * ld];
+      u[r * ld] = s / C[r * ld + r];
+    }
+    double nr2 = 0.0, big = -1.0;
+    int im = 0;
+    for (int r = 0; r < n; ++r) {
+      const double v = u[r * ld];
+      nr2 += v * v;
+      if (fabs(v) > big) big = fabs(v), im = r;
+    }
+    double sc = (nr2 > 0.0) ? 1.0 / sqrt(nr2) : 0.0;
+    if (u[im * ld] < 0.0) sc = -sc;
+    for (int r = 0; r < n; ++r) b.Y[(size_t)idx[r] * kint + col] = u[r * ld] * sc;
+  }
+  (void)yv;
+}
+
+static size_t sym_lds(int m) { return ((size_t)2 * m * (m | 1) + 4 * (size_t)m) * sizeof(double); }
+
+hipError_t tharm_sym_set_attributes() { return set_lds_limit((const void*)k_tharm_sym); }
+
+void launch_tharm_sym(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
+  const double m3 = (double)p.m * p.m * p.m, mm = (double)p.m * p.m;
+  // model counts: Cholesky m^3/3, C 2 m^3, Jacobi ~8 sweeps of 4 m^3,
+  // eigenvectors m^2 kint
+  prof_begin(KC_THARM_QR, 3.0 * mm * 8.0, (1.0 / 3.0 + 2.0 + 32.0) * m3 + mm * p.kint, s);
+  hipLaunchKernelGGL(k_tharm_sym, dim3(1), dim3(kST), sym_lds(p.m), s, p, b, st);
+  prof_end(KC_THARM_QR, s);
+}
+
+}  // namespace plhr

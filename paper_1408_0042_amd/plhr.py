@@ -76,7 +76,7 @@ class Solver:
                  mass=None, csr=None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
-                 drop_tol: float = 1e-12, precision: str = "fp64", ortho_passes: int = 1,
+                 drop_tol: float = 1e-10, precision: str = "fp64", ortho_passes: int = 0,
                  extraction: str = "tharmonic", use_graph: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
@@ -491,7 +491,7 @@ class BatchSolver:
                  scale: float = 1.0, potentials: Optional[Sequence[torch.Tensor]] = None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 10,
-                 drop_tol: float = 1e-12, stream: Optional[torch.cuda.Stream] = None):
+                 drop_tol: float = 1e-10, stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")

@@ -137,3 +137,54 @@ def test_largest_trial_subspace_m84_matches_closed_form():
     # ten times the stopping tolerance (the bounds above still hold)
     assert np.all(r.rel_res <= 1e-9)
     S.close()
+
+
+@pytest.mark.parametrize("no_sym", [False, True])
+def test_first_steps_with_identity_preconditioner_match_oracle(no_sym, monkeypatch):
+    """T = I, B = I: the projected problem is Hermitian-definite and runs on
+    the Jacobi kernel (no_sym: the general Hessenberg-QR path).  The first
+    iterations' Rayleigh quotients equal the oracle's."""
+    from tests.gpu_util import dev
+    if no_sym:
+        monkeypatch.setenv("PLHR_NO_SYM", "1")
+    dims, h = (20, 20), 1 / 21
+    pot = np.random.default_rng(42).uniform(0, 300, 400)
+    A = ops.fd_dirichlet(dims, h, potential=pot)
+    sigma = 2500.0
+    k, kx = 5, 2
+    V0 = wl.start_block(400, k + kx, (43, 0))
+    prob = plhr.Problem(A=A, sigma=sigma)
+    o = plhr.BPLHR(prob, V0, k, real=True, lock=False)
+    S = _solver(kind="fd5_2d", dims=dims, h=h, sigma=sigma, k=k, k_extra=kx, lock=False,
+                potential=dev(pot))
+    S.start(dev(V0))
+    for it in range(4):
+        o.step()
+        S.iterate(1)
+        lam_g, _ = S.state()
+        assert np.allclose(np.sort(lam_g), np.sort(o.lam), rtol=1e-9), (it, lam_g, o.lam)
+    S.close()
+
+
+def test_vector_alu_kernels_match_matrix_core_kernels(monkeypatch):
+    """PLHR_NO_MFMA=1 selects the vector-ALU Gram and row-product kernels:
+    the same converged pairs as the matrix-core kernels."""
+    from tests.gpu_util import dev, host
+    N, h = 16, 1 / 17
+    ev = cf.fd_dirichlet_eigs((N, N), h)
+    u = np.unique(np.round(ev, 8))
+    sigma = float(u[12] + 0.4 * (u[13] - u[12]))
+    V0 = dev(wl.start_block(N * N, 6, (44, 0)))
+    out = []
+    for flag in (None, "1"):
+        if flag:
+            monkeypatch.setenv("PLHR_NO_MFMA", flag)
+        S = _solver(kind="fd5_2d", dims=(N, N), h=h, sigma=sigma, k=4, k_extra=2, tol=1e-11,
+                    max_iters=2000, precond={"levels": 3, "nu": 2})
+        r = S.solve(V0)
+        assert r.converged
+        out.append(np.sort(host(r.eigvals)))
+        S.close()
+    assert np.allclose(out[0], out[1], rtol=1e-11)
+    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:4])
+    assert np.allclose(out[1], ref, rtol=1e-10)
