@@ -20,6 +20,14 @@ namespace {
 
 constexpr int kST = 256;
 
+// 1/d from the hardware estimate and two Newton steps
+__device__ __forceinline__ double sym_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
 __device__ double sym_block_sum(double a, double* red) {
   for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
@@ -42,7 +50,9 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   __shared__ int cnt_s, ndead_s;
   __shared__ double red[kST / 64];
   __shared__ double csr[kMaxM / 2 + 1], snr[kMaxM / 2 + 1];
+  __shared__ int prs[kMaxM / 2 + 1], qrs[kMaxM / 2 + 1];
   const int m = p.m, kint = p.kint, t = threadIdx.x;
+  if (t == 0) st->tphase[0] = clock64();
   if (t == 0) {
     int c = 0;
     for (int s = 0; s < m; ++s)
@@ -75,6 +85,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   }
   for (int j = t; j < n; j += kST) dead[j] = 0;
   __syncthreads();
+  if (t == 0) st->tphase[1] = clock64();
   // Cholesky of G_L, right-looking on unscaled columns; pivots as in the
   // general projected solver (raised to 1e-15 max diag, a clearly
   // negative one leaves its slot out)
@@ -125,6 +136,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     }
     return;
   }
+  if (t == 0) st->tphase[2] = clock64();
   // C <- L^-1 C (columns, one thread each), then C <- C L^-T (rows)
   for (int c = t; c < n; c += kST)
     for (int i = 0; i < n; ++i) {
@@ -157,9 +169,16 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   }
   __syncthreads();
   // cyclic Jacobi, round-robin tournament over ne = n rounded up to even
-  // positions (an index >= n is a bye)
+  // positions (an index >= n is a bye).  The pair table of a round is
+  // written by its first np threads with the rotations; the two-sided
+  // update acts on the disjoint 2 x 2 blocks (pair k's rows, pair l's
+  // columns) in one phase, so a round takes two barriers.
+  if (t == 0) st->tphase[3] = clock64();
   const int ne = n + (n & 1), np = ne / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  // exact float reciprocals for the block and row indices (e < 2^12)
+  const float inp = 1.0f / (float)np, inn = 1.0f / (float)n;
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
     double a2 = 0.0, o2 = 0.0;
     for (int e = t; e < n * n; e += kST) {
       const int i = e / n, c = e - i * n;
@@ -171,64 +190,80 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     }
     a2 = sym_block_sum(a2, red);
     o2 = sym_block_sum(o2, red);
-    if (!(o2 > 1e-32 * a2)) break;  // uniform
+    // off(C) at the rounding level of ||C|| (a rotation leaves about
+    // eps max(|a_pp|, |a_qq|) behind)
+    if (!(o2 > 1e-28 * a2)) break;  // uniform
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
-      // pair k: positions k and ne - 1 - k; position 0 holds player 0,
-      // position i >= 1 player 1 + (i - 1 + rnd) mod (ne - 1)
       if (t < np) {
-        const int i0 = t, i1 = ne - 1 - t;
-        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
-        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
-        double c = 1.0, s = 0.0;
-        if (pa < n && pb < n) {
-          const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+        // position 0 holds player 0; position i >= 1 player 1 + (i - 1 + rnd) mod (ne - 1)
+        const int i1 = ne - 1 - t;
+        int pa = 0;
+        if (t > 0) {
+          pa = t - 1 + rnd;
+          if (pa >= ne - 1) pa -= ne - 1;
+          ++pa;
+        }
+        int pb = i1 - 1 + rnd;
+        if (pb >= ne - 1) pb -= ne - 1;
+        ++pb;
+        double c = 1.0, sn = 0.0;
+        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+        if (qq < n) {
           const double apq = C[pp * ld + qq];
-          if (apq != 0.0) {
-            const double app = C[pp * ld + pp], aqq = C[qq * ld + qq];
-            const double th = (aqq - app) / (2.0 * apq);
-            const double tt = ((th >= 0.0) ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
-            s = tt * c;
+          const double app = C[pp * ld + pp], aqq = C[qq * ld + qq];
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+            const double th = (aqq - app) * sym_rcp(2.0 * apq);
+            const double tt = copysign(sym_rcp(fabs(th) + sqrt(th * th + 1.0)), th);
+            c = sym_rcp(sqrt(tt * tt + 1.0));
+            sn = tt * c;
           }
         }
         csr[t] = c;
-        snr[t] = s;
+        snr[t] = sn;
+        prs[t] = pp;
+        qrs[t] = (qq < n) ? qq : -1;
       }
       __syncthreads();
-      // rows p, q of C <- J^T (rows)
-      for (int e = t; e < np * n; e += kST) {
-        const int k = e / n, j = e - k * n;
-        const int i0 = k, i1 = ne - 1 - k;
-        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
-        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
-        if (pa >= n || pb >= n) continue;
-        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
-        const double c = csr[k], s = snr[k];
-        if (s == 0.0) continue;
-        const double xp = C[pp * ld + j], xq = C[qq * ld + j];
-        C[pp * ld + j] = c * xp - s * xq;
-        C[qq * ld + j] = s * xp + c * xq;
-      }
-      __syncthreads();
-      // columns p, q of C and of V <- (.) J
-      for (int e = t; e < np * n; e += kST) {
-        const int k = e / n, i = e - k * n;
-        const int i0 = k, i1 = ne - 1 - k;
-        const int pa = (i0 == 0) ? 0 : 1 + (i0 - 1 + rnd) % (ne - 1);
-        const int pb = 1 + (i1 - 1 + rnd) % (ne - 1);
-        if (pa >= n || pb >= n) continue;
-        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
-        const double c = csr[k], s = snr[k];
-        if (s == 0.0) continue;
-        const double xp = C[i * ld + pp], xq = C[i * ld + qq];
-        C[i * ld + pp] = c * xp - s * xq;
-        C[i * ld + qq] = s * xp + c * xq;
-        const double vp = V[i * ld + pp], vq = V[i * ld + qq];
-        V[i * ld + pp] = c * vp - s * vq;
-        V[i * ld + qq] = s * vp + c * vq;
+      // C <- J^T C J on the 2 x 2 blocks (rows of pair k, columns of pair
+      // l), which are disjoint, and V <- V J; one phase.  Every load of a
+      // thread's items is issued before the first store.
+      {
+        double* __restrict__ Cw = C;
+        double* __restrict__ Vw = V;
+        for (int e = t; e < np * np; e += kST) {
+          const int k = (int)(((float)e + 0.5f) * inp), l = e - k * np;
+          const int pr = prs[k], qr = qrs[k], pc = prs[l], qc = qrs[l];
+          const double ck = csr[k], sk = snr[k], cl = csr[l], sl = snr[l];
+          const int qrr = (qr >= 0) ? qr : pr, qcc = (qc >= 0) ? qc : pc;
+          const double a = Cw[pr * ld + pc], bb = Cw[pr * ld + qcc];
+          const double cc = Cw[qrr * ld + pc], dd = Cw[qrr * ld + qcc];
+          const double a1 = ck * a - sk * cc, b1 = ck * bb - sk * dd;
+          const double c1 = sk * a + ck * cc, d1 = sk * bb + ck * dd;
+          // a bye (q < 0) has c = 1, s = 0, so its row or column is copied
+          // through unchanged and only the existing entries are stored
+          Cw[pr * ld + pc] = cl * a1 - sl * b1;
+          if (qc >= 0) Cw[pr * ld + qc] = sl * a1 + cl * b1;
+          if (qr >= 0) Cw[qr * ld + pc] = cl * c1 - sl * d1;
+          if (qr >= 0 && qc >= 0) Cw[qr * ld + qc] = sl * c1 + cl * d1;
+        }
+        for (int e = t; e < np * n; e += kST) {
+          const int l = (int)(((float)e + 0.5f) * inn), i = e - l * n;
+          const int pc = prs[l], qc = qrs[l];
+          const double cl = csr[l], sl = snr[l];
+          const int qcc = (qc >= 0) ? qc : pc;
+          const double vp = Vw[i * ld + pc], vq = Vw[i * ld + qcc];
+          if (qc >= 0) {
+            Vw[i * ld + pc] = cl * vp - sl * vq;
+            Vw[i * ld + qc] = sl * vp + cl * vq;
+          }
+        }
       }
       __syncthreads();
     }
+  }
+  if (t == 0) {
+    st->tphase[4] = clock64();
+    st->tphase[10] = sweep;
   }
   // tau and the ranks of xi = 1/tau by (|xi|, xi, index); tau = 0 last
   for (int i = t; i < n; i += kST) piv[i] = C[i * ld + i];
@@ -264,6 +299,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     b.kinds[c] = 0;
     b.pair[c] = -1;
   }
+  if (t == 0) st->tphase[5] = clock64();
   // L back into the C region (C's diagonal is saved in piv)
   for (int e = t; e < n * n; e += kST) {
     const int i = e / n, c = e - i * n;
@@ -292,6 +328,8 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     if (u[im * ld] < 0.0) sc = -sc;
     for (int r = 0; r < n; ++r) b.Y[(size_t)idx[r] * kint + col] = u[r * ld] * sc;
   }
+  __syncthreads();
+  if (t == 0) st->tphase[6] = clock64();
   (void)yv;
 }
 
