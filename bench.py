@@ -58,8 +58,8 @@ def closed_form_3d(N, h):
 
 
 # HBM traffic per launch of a kernel, from two profiler passes over
-# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --precision fp64 --batch 0
-# --max-iters 20 --copy-mib 256`: FETCH_SIZE, then WRITE_SIZE (KiB per
+# `bench.py --steps 1 --warmup 0 --no-fd7 --batch 0 --no-spmm
+# --no-cpu-baseline --copy-mib 256`: FETCH_SIZE, then WRITE_SIZE (KiB per
 # dispatch).  Each counter is scaled by what it reads for kernels of known
 # traffic in the same run: a 256 MiB device copy reads 131089 KiB of
 # FETCH_SIZE for 262144 KiB fetched (factor 2.0), a 256 MiB fill 262144 KiB
@@ -69,9 +69,9 @@ def closed_form_3d(N, h):
 FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
-    ("tharm_qr", 80): {"source": "paper_1408_0042_amd/csrc/k_tharm.hip",
-                       "sha256": "4e1d7bb777cec5f93ff941eda4e87384f4ba6ca9961334946cd5ec779ff8972f",
-                       "fetch_kib": 61.9375, "write_kib": 101.09375},
+    ("tharm_qr", 24): {"source": "paper_1408_0042_amd/csrc/k_tharm_sym.hip",
+                       "sha256": "6ab973a20e4175125e28e1d0c4eb9d8f40cca61a70fb4adcea71e1f8be83c1a5",
+                       "fetch_kib": 18.79, "write_kib": 5.55},
 }
 
 
