@@ -311,10 +311,15 @@ class AVMG:
         return w
 
     def apply(self, R: np.ndarray) -> np.ndarray:
-        R = np.asarray(R, dtype=np.float64)
+        R = np.asarray(R)
         one = R.ndim == 1
         Rb = R[:, None] if one else R
-        out = self._cycle(0, Rb)
+        if np.iscomplexobj(Rb):
+            # a real operator: applied to the real and imaginary parts
+            out = (self._cycle(0, np.ascontiguousarray(Rb.real, dtype=np.float64))
+                   + 1j * self._cycle(0, np.ascontiguousarray(Rb.imag, dtype=np.float64)))
+        else:
+            out = self._cycle(0, Rb.astype(np.float64))
         return out[:, 0] if one else out
 
     __call__ = apply

@@ -228,3 +228,17 @@ def test_vertex_centred_transfer_is_exact_on_linear_functions():
     assert np.isclose(f[0], 0.5 * 3.0 * 2.0) and np.isclose(f[-1], 0.5 * 3.0 * 14.0)
     with pytest.raises(ValueError):
         mg.coarsen((15, 8))
+
+
+def test_avmg_acts_on_complex_vectors_as_a_real_operator():
+    """Algorithm 1 runs in complex arithmetic with a real T: applied to a
+    complex block, AV-MG must equal its dense matrix (assembled from real
+    unit vectors) times that block."""
+    dims, h = (15, 15), 1 / 16
+    T = mg.AVMG(dims, h, 1.0, 3, 300.0)
+    n = 225
+    Td = mg.dense_matrix(T.apply, n)
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    assert np.allclose(T.apply(Z), Td @ Z, rtol=1e-12, atol=1e-12 * np.abs(Td @ Z).max())
+    assert np.abs((T.apply(Z)).imag).max() > 0.0
