@@ -120,7 +120,8 @@ typedef enum {
   PLHR_PREC_IDENTITY = 0,
   PLHR_PREC_MG_VCYCLE = 1, /* one V-cycle on the Laplacian part of A            */
   PLHR_PREC_AV_MG = 2,     /* AV-MG, T ~ |L - sigma I|^-1 (Appendix A, Alg. 4)  */
-  PLHR_PREC_INV_MG = 3     /* INV-MG, T ~ (L - sigma I)^-1, indefinite (Alg. 5) */
+  PLHR_PREC_INV_MG = 3,    /* INV-MG, T ~ (L - sigma I)^-1, indefinite (Alg. 5) */
+  PLHR_PREC_DENSE = 4      /* a dense n x n matrix given by the caller        */
 } plhr_prec_kind;
 
 /* Preconditioner descriptor.
@@ -150,7 +151,14 @@ typedef enum {
  * PLHR_PREC_INV_MG (Algorithm 5, the indefinite comparison of Section
  * 6.2): B_l = L_l - sigma I_l on every level, alpha_l = omega / diag(L_l),
  * the coarsest (L_0 - sigma I_0)^-1.  sigma on an eigenvalue of the
- * coarsest operator gives PLHR_ERR_ARG at create.                         */
+ * coarsest operator gives PLHR_ERR_ARG at create.
+ * PLHR_PREC_DENSE: T is the dense symmetric positive definite matrix at
+ * `matrix` (device, n x n doubles, row i at matrix + i n; caller-owned,
+ * read by every application, so it must stay allocated while the context
+ * is used; symmetry and definiteness are not checked).  This is the form
+ * of the preconditioners of the small finite-element experiment of
+ * Section 6.1, perturbations of |A - sigma B|^-1 that the caller builds.
+ * levels, nu_pre, nu_post, omega, delta and degree are ignored.          */
 typedef struct {
   int32_t kind;
   int32_t levels;
@@ -159,6 +167,7 @@ typedef struct {
   double delta;
   int32_t degree;
   int32_t reserved0;
+  const double* matrix;
 } plhr_prec_desc;
 
 /* Arithmetic of the preconditioner.  PLHR_PREC_MIXED runs the multigrid
@@ -177,6 +186,17 @@ typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
  * inside the projection only (the search directions still use T): the
  * standard harmonic Rayleigh-Ritz of the "harm." rows of Section 6.2.    */
 typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_extraction;
+
+/* Iteration.  PLHR_ALG_BLOCK is the block method in real arithmetic
+ * (Algorithm 3).  PLHR_ALG_SINGLE is the single-vector method (Algorithm
+ * 1, k = 1) in complex arithmetic, as Section 3.2 prescribes even for real
+ * A and B since the projected problem can have complex eigenpairs: the
+ * iterate v, the directions w, s, p and their products are complex
+ * vectors stored as two real columns each (real and imaginary parts, i.e.
+ * the interleaved layout of a complex128 vector), every basis is
+ * orthonormalised in the complex B-inner product, and the 4 x 4 (3 x 3 on
+ * the first step) projected problem is solved in complex arithmetic.    */
+typedef enum { PLHR_ALG_BLOCK = 0, PLHR_ALG_SINGLE = 1 } plhr_algorithm;
 
 /* Solver options (plhr_options_default fills the defaults shown).
  *   tol          relative residual ||A v - lam B v|| /
@@ -207,7 +227,14 @@ typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_ext
  *   use_graph    1: each iteration's launches are captured once in a HIP
  *                graph (on a stream of the library's own) and replayed on
  *                the context's stream; 0: launched one by one.  Launch
- *                profiling bypasses the graphs                [0]       */
+ *                profiling bypasses the graphs                [0]
+ *   algorithm    a plhr_algorithm value.  PLHR_ALG_SINGLE needs k = 1;
+ *                k_extra and lock are then ignored, the start block is
+ *                n x 2 doubles (the real and imaginary parts of the start
+ *                vector), the convergence test uses the residual of the
+ *                complex vector, and the returned eigenvector is real
+ *                (the final Rayleigh-Ritz on the span of the two parts)
+ *                                                             [BLOCK]   */
 typedef struct {
   double tol;
   int32_t max_iters;
@@ -219,6 +246,8 @@ typedef struct {
   double drop_tol;
   int32_t extraction;
   int32_t use_graph;
+  int32_t algorithm;
+  int32_t reserved0;
 } plhr_options;
 
 typedef struct plhr_ctx_s* plhr_ctx;
@@ -252,8 +281,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
                                 const plhr_options* opt, size_t* ws_bytes);
 
 /* Create a solver for the k eigenpairs of A v = lambda B v nearest sigma
- * (Algorithm 3 for these real operators).
- *   A          host descriptor of A (FD5_2D or FD7_3D)
+ * (Algorithm 3 for these real operators; Algorithm 1 with
+ * PLHR_ALG_SINGLE).
+ *   A          host descriptor of A (FD5_2D, FD7_3D, Q1_2D, Q1_3D or CSR)
  *   B          host descriptor of B: NULL or PLHR_OP_IDENTITY for the
  *              identity, PLHR_OP_DIAG for a positive diagonal B with a
  *              finite-difference A (the diagonal is read once at create
@@ -262,7 +292,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
  *   sigma      finite real shift
  *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n; a trial
  *              subspace wider than 84 (4*(k + k_extra) > 84) gives
- *              PLHR_ERR_UNSUPPORTED
+ *              PLHR_ERR_UNSUPPORTED; PLHR_ALG_SINGLE needs k = 1 (its
+ *              basis takes 8 real columns) and gives PLHR_ERR_ARG
+ *              otherwise
  *   opt        host options, or NULL for defaults
  *   stream     HIP stream (hipStream_t) all work is enqueued on; NULL is
  *              the null stream
@@ -276,7 +308,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B,
                         size_t ws_bytes, plhr_ctx* out);
 
 /* Algorithm 3, steps 1-2: load the start block and B-normalise it.
- *   V0   device, n x (k + k_extra) doubles, point-major; copied.          */
+ *   V0   device, n x (k + k_extra) doubles, point-major (n x 2 with
+ *        PLHR_ALG_SINGLE: real and imaginary parts); copied.             */
 plhr_status plhr_start(plhr_ctx ctx, const double* V0);
 
 /* Run up to n_steps iterations of the while-loop of Algorithm 3, stopping

@@ -20,8 +20,9 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 OP_IDENTITY, OP_FD5_2D, OP_FD7_3D, OP_DIAG, OP_Q1_2D, OP_Q1_3D, OP_Q1_MASS, OP_CSR = 0, 1, 2, 3, 4, 5, 6, 7
 OP_BLOCH7_3D = 8
 F64, C128 = 0, 1
-PREC_IDENTITY, PREC_MG_VCYCLE, PREC_AV_MG, PREC_INV_MG = 0, 1, 2, 3
+PREC_IDENTITY, PREC_MG_VCYCLE, PREC_AV_MG, PREC_INV_MG, PREC_DENSE = 0, 1, 2, 3, 4
 EXTRACT_T_HARMONIC, EXTRACT_HARMONIC = 0, 1
+ALG_BLOCK, ALG_SINGLE = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 
 
@@ -36,14 +37,15 @@ class OpDesc(C.Structure):
 class PrecDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("levels", C.c_int32), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("omega", C.c_double), ("delta", C.c_double),
-                ("degree", C.c_int32), ("reserved0", C.c_int32)]
+                ("degree", C.c_int32), ("reserved0", C.c_int32), ("matrix", C.c_void_p)]
 
 
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("k_extra", C.c_int32),
                 ("precision", C.c_int32), ("lock", C.c_int32), ("check_every", C.c_int32),
                 ("ortho_passes", C.c_int32), ("drop_tol", C.c_double),
-                ("extraction", C.c_int32), ("use_graph", C.c_int32)]
+                ("extraction", C.c_int32), ("use_graph", C.c_int32),
+                ("algorithm", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class IterInfo(C.Structure):

@@ -244,6 +244,7 @@ struct plhr_ctx_s {
   CsrMat Acsr{}, Bcsr{};
   int prec_kind = PLHR_PREC_IDENTITY;
   MG mg;
+  const double* Tdense = nullptr;  // PLHR_PREC_DENSE: caller's n x n matrix
   double sigma = 0.0;
   int k = 0, kint = 0, m = 0;
   plhr_options opt{};
@@ -296,6 +297,18 @@ struct Layout {
 int mg_mode(const plhr_prec_desc* T) {
   if (!T) return 0;
   return T->kind == PLHR_PREC_AV_MG ? 1 : (T->kind == PLHR_PREC_INV_MG ? 2 : 0);
+}
+
+// T is one of the multigrid preconditioners (needs a hierarchy)
+bool uses_mg(const plhr_prec_desc* T) {
+  return T && (T->kind == PLHR_PREC_MG_VCYCLE || T->kind == PLHR_PREC_AV_MG ||
+               T->kind == PLHR_PREC_INV_MG);
+}
+
+// block columns: k + k_extra, or the two real columns of the complex
+// vector of the single-vector iteration
+int block_cols(int32_t k, const plhr_options& o) {
+  return o.algorithm == PLHR_ALG_SINGLE ? 2 : k + o.k_extra;
 }
 
 plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
@@ -375,8 +388,17 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("k must be >= 1 and k_extra >= 0");
     return PLHR_ERR_ARG;
   }
+  const bool single = opt && opt->algorithm == PLHR_ALG_SINGLE;
+  if (opt && opt->algorithm != PLHR_ALG_BLOCK && !single) {
+    set_error("invalid options (algorithm PLHR_ALG_BLOCK or PLHR_ALG_SINGLE)");
+    return PLHR_ERR_ARG;
+  }
+  if (single && k != 1) {
+    set_error("PLHR_ALG_SINGLE computes one pair: k must be 1");
+    return PLHR_ERR_ARG;
+  }
   const size_t n = (size_t)A->nx * A->ny * A->nz;
-  const int kint = k + kextra;
+  const int kint = single ? 2 : k + kextra;
   if ((size_t)4 * kint > n) {
     set_error("4*(k + k_extra) must not exceed n");
     return PLHR_ERR_ARG;
@@ -399,7 +421,16 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
       return PLHR_ERR_ARG;
     }
   }
-  if (T && T->kind != PLHR_PREC_IDENTITY) {
+  if (T && T->kind == PLHR_PREC_DENSE) {
+    if (!T->matrix || ((uintptr_t)T->matrix & 7)) {
+      set_error("T: PLHR_PREC_DENSE needs `matrix`, an 8-byte aligned n x n device array");
+      return PLHR_ERR_ARG;
+    }
+    if (n > ((size_t)1 << 31)) {
+      set_error("T: PLHR_PREC_DENSE needs n <= 2^31");
+      return PLHR_ERR_ARG;
+    }
+  } else if (T && T->kind != PLHR_PREC_IDENTITY) {
     if (T->kind != PLHR_PREC_MG_VCYCLE && T->kind != PLHR_PREC_AV_MG &&
         T->kind != PLHR_PREC_INV_MG) {
       set_error("T: unknown preconditioner kind");
@@ -545,6 +576,8 @@ void precond_raw(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int 
   if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
     const bool f32 = direction && c->opt.precision == PLHR_PREC_MIXED;
     mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, f32, st, c->stream);
+  } else if (c->prec_kind == PLHR_PREC_DENSE) {
+    launch_dense_prec(c->n, c->Tdense, Rin, ldr, o0, o1, split, ncols, st, c->stream);
   } else {
     if (split > 0) launch_copy(c->n, Rin, ldr, o0.ptr, o0.ld, split, c->stream, st);
     if (split < ncols)
@@ -678,16 +711,19 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
     b1.gate = c->gate;
     p1.pass = 1;
     p2.pass = 2;
+    // the single-vector iteration orthonormalises in the complex inner
+    // product of its interleaved columns
+    auto ortho = c->sp.cplx ? launch_single_ortho : launch_ortho_small;
     gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-    launch_ortho_small(p1, b1, st, s);
+    ortho(p1, b1, st, s);
     transform(c, arrs, narr, st);
     if (c->opt.ortho_passes == 0) {
       gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, c->gate);
-      launch_ortho_small(p2, b1, st, s);
+      ortho(p2, b1, st, s);
       transform(c, arrs, narr, c->gate);
     } else if (c->opt.ortho_passes == 2) {
       gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-      launch_ortho_small(c->sp, c->sb, st, s);
+      ortho(c->sp, c->sb, st, s);
       transform(c, arrs, narr, st);
     }
     // gated recomputation of (A - sigma B)Z and T(A - sigma B)Z for V and P
@@ -701,7 +737,9 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]  (Q Zhat for the harmonic
   // extraction)
   gram(c, tharm ? TQZ : QZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
-  if (c->sp.sym)
+  if (c->sp.cplx)
+    launch_single_tharm(c->sp, c->sb, st, s);
+  else if (c->sp.sym)
     launch_tharm_sym(c->sp, c->sb, st, s);
   else
     launch_tharm_small(c->sp, c->sb, st, s);
@@ -822,10 +860,10 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
     set_error("ws_bytes is NULL");
     return PLHR_ERR_ARG;
   }
-  const bool mgp = T && T->kind != PLHR_PREC_IDENTITY;
+  const bool mgp = uses_mg(T);
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   const bool bs = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
-  Layout L = layout(make_grid(A), k, k + o.k_extra, mgp, mgp ? T->levels : 0, bd, bs, nullptr,
+  Layout L = layout(make_grid(A), k, block_cols(k, o), mgp, mgp ? T->levels : 0, bd, bs, nullptr,
                     mg_mode(T));
   *ws_bytes = L.bytes;
   return PLHR_OK;
@@ -851,12 +889,16 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->pot = A->potential;
   c->sigma = sigma;
   c->k = k;
-  c->kint = k + o.k_extra;
+  c->kint = block_cols(k, o);
   c->m = 4 * c->kint;
   c->opt = o;
   c->n = c->grid.n();
-  const bool mgp = T && T->kind != PLHR_PREC_IDENTITY;
+  const bool mgp = uses_mg(T);
   c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
+  if (T && T->kind == PLHR_PREC_DENSE) {
+    c->prec_kind = PLHR_PREC_DENSE;
+    c->Tdense = T->matrix;
+  }
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   if (bd) c->bdiag = B->potential;
   c->bst = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
@@ -972,7 +1014,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->sp.normA1 = c->normA1;
   c->sp.normB1 = c->normB1;
   c->sp.drop_tol = o.drop_tol;
-  c->sp.lock = o.lock;
+  c->sp.cplx = (o.algorithm == PLHR_ALG_SINGLE) ? 1 : 0;
+  c->sp.lock = c->sp.cplx ? 0 : o.lock;
   // G_R of eq. (3.5) is symmetric when T does not enter the projection
   // (T = I, or the harmonic extraction) and B = I: the projected problem
   // is then Hermitian-definite
@@ -980,7 +1023,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
                            (c->prec_kind == PLHR_PREC_IDENTITY && !c->bdiag)))
                   ? 1
                   : 0;
-  if (getenv("PLHR_NO_SYM")) c->sp.sym = 0;
+  if (getenv("PLHR_NO_SYM") || c->sp.cplx) c->sp.sym = 0;
   c->use_mfma = (getenv("PLHR_NO_MFMA") == nullptr);
   hipError_t e = small_set_attributes(c->m, c->kint);
   if (e == hipSuccess) e = tharm_sym_set_attributes();

@@ -357,6 +357,8 @@ struct SmallParams {
   int lock;
   int sym = 0;        // G_R symmetric (T = I or harmonic extraction, B = I)
   int pass = 0;       // Cholesky-QR pass with a gate: 1 first, 2 second; 0 none
+  int cplx = 0;       // single-vector complex iteration (Algorithm 1): kint = 2
+                      // real columns hold one complex vector (re, im)
 };
 
 // ------------------------------------------------------------- batches
@@ -460,6 +462,16 @@ void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStr
 // the cyclic Jacobi method in one workgroup (k_tharm_sym.hip).
 void launch_tharm_sym(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 hipError_t tharm_sym_set_attributes();
+// Single-vector complex iteration (Algorithm 1, k_single.hip): the complex
+// Cholesky-QR of Z = [v w s p] from the real Gram of its 8 real columns
+// (same gating as launch_ortho_small), and the complex 4 x 4 projected
+// problem of eq. (3.5) with the selection of the smallest |xi|.
+void launch_single_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+void launch_single_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// Y = T X for a dense n x n T (row-major); columns [0, split) of Y go to
+// o0, the rest to o1 (nothing when st is halted).
+void launch_dense_prec(size_t n, const double* T, const double* X, int ldx, Blk o0, Blk o1,
+                       int split, int ncols, const DevStatus* st, hipStream_t s);
 // Rayleigh quotients from per-block partial sums [v.v | v.(A - sigma B)v];
 // end_of_iteration also advances the iteration counter.
 void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,

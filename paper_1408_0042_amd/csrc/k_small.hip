@@ -1,5 +1,5 @@
 // Small dense kernels of the PLHR iteration, each one workgroup with all
-// operands in LDS (m = 4 (k + k_extra) slots, m <= 100).
+// operands in LDS (m = 4 (k + k_extra) slots, m <= kMaxM = 84).
 //
 //   k_init_lam     Rayleigh quotients of the start block (Algorithm 3, step 2)
 //   k_conv_check   relative residuals, soft locking, stopping test
@@ -9,12 +9,9 @@
 //                  are orthonormalised in this order, which is what a
 //                  Cholesky factorisation of the Gram matrix in slot order
 //                  computes)
-//   k_tharm_small  the projected problem eq. (3.5), G_L y = xi G_R y, via
-//                  G_L = L L^T, C = L^-1 G_R L^-T, Hessenberg reduction,
-//                  Francis double-shift QR (real Schur form), eigenvectors
-//                  by back substitution; selection of the kint smallest
-//                  |xi| with conjugate pairs kept adjacent and the real
-//                  basis Y' = [Y0 YR ytilde_R YI] of Algorithm 3
+//   (the projected problem eq. (3.5) and the selection of Algorithm 3 are
+//   in k_tharm.hip and k_tharm_sym.hip; the complex single-vector steps of
+//   Algorithm 1 in k_single.hip)
 //   k_rq_small     Rayleigh quotients of the new block, eq. (4.1) for pairs
 //   k_final_rr     standard Rayleigh-Ritz on span(V) (the last step of
 //                  Algorithms 2 and 3): Cholesky + cyclic Jacobi
@@ -81,6 +78,11 @@ __device__ void k_init_lam_body(SmallParams p, const double* __restrict__ part, 
     b.kinds[c] = 0;
     b.pair[c] = -1;
     b.active[c] = 1;
+    if (p.cplx) {  // one complex vector in columns 0 (re) and 1 (im)
+      b.lam[c] = p.sigma + (sums[p.kint] + sums[p.kint + 1]) / (sums[0] + sums[1]);
+      b.kinds[c] = c == 0 ? 1 : 3;
+      b.pair[c] = 1 - c;
+    }
   }
   if (c == 0) {
     st->done = 0;
@@ -110,6 +112,14 @@ __global__ __launch_bounds__(256) void k_init_lam_b(const BatchSmall* __restrict
 // kint, in b.G); a pivot below drop_tol means linearly dependent columns.
 __device__ void k_start_check_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (threadIdx.x != 0) return;
+  if (p.cplx) {  // the complex start vector must not vanish
+    const double g = b.G[0] + b.G[p.kint + 1];
+    if (!(g > 0.0 && g < INFINITY)) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonStartRank;
+    }
+    return;
+  }
   const int n = p.kint;  // <= 25 (4 kint <= 100)
   __shared__ double G[25 * 25];
   __shared__ double d[25];
@@ -163,7 +173,11 @@ __device__ void k_conv_check_body(SmallParams p, const double* __restrict__ part
   const int kint = p.kint;
   sum_partials(part, nblk, 2 * kint, sums, red);
   if (c < kint) {
-    const double rr = sums[c], vv = sums[kint + c];
+    double rr = sums[c], vv = sums[kint + c];
+    if (p.cplx) {  // residual and norm of the complex vector
+      rr = sums[0] + sums[1];
+      vv = sums[kint] + sums[kint + 1];
+    }
     const double lam = b.lam[c];
     const double den = (p.normA1 + fabs(lam) * p.normB1) * sqrt(vv);
     const double r = (den > 0.0) ? sqrt(rr) / den : INFINITY;
@@ -181,7 +195,7 @@ __device__ void k_conv_check_body(SmallParams p, const double* __restrict__ part
       const double dq = fabs(lq - p.sigma);
       if (dq < dc || (dq == dc && (lq < lc || (lq == lc && q < c)))) ++rank;
     }
-    rel[64 + c] = (rank < p.k) ? 1.0 : 0.0;  // wanted flag
+    rel[64 + c] = (rank < p.k || p.cplx) ? 1.0 : 0.0;  // wanted flag
     b.active[c] = p.lock ? (rel[c] > p.tol ? 1 : 0) : 1;
   }
   __syncthreads();

@@ -66,6 +66,10 @@ class Solver:
     "inv" (INV-MG, Algorithm 5) for the preconditioners of Section 6.2;
     extraction: "tharmonic" (eq. 3.5) or "harmonic" (T -> I in the
     projection); use_graph: replay each iteration from a captured HIP graph.
+    precond {"kind": "dense", "matrix": T} takes T as an (n, n) float64
+    device tensor (symmetric positive definite, kept referenced).
+    algorithm: "block" (Algorithm 3) or "single" (Algorithm 1 in complex
+    arithmetic, k = 1; the start block is (n, 2): real and imaginary parts).
     kind "csr": a general sparse symmetric A given as csr = (row_ptr int32,
     col_idx int32, values float64) device tensors, dims = (n,); mass may
     then be a CSR triple for B; T must be the identity.
@@ -78,7 +82,7 @@ class Solver:
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
                  drop_tol: float = 1e-10, precision: str = "fp64", ortho_passes: int = 0,
                  extraction: str = "tharmonic", use_graph: bool = False,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 algorithm: str = "block", stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
@@ -135,13 +139,23 @@ class Solver:
             bdesc.h, bdesc.scale = 1.0, 1.0
             bdesc.potential = mass.data_ptr()
         self.k = int(k)
-        self.kint = int(k) + int(k_extra)
+        if algorithm not in ("block", "single"):
+            raise ValueError("algorithm must be 'block' or 'single'")
+        self.kint = 2 if algorithm == "single" else int(k) + int(k_extra)
         self.sigma = float(sigma)
         t = None
         if precond is not None:
             t = L.PrecDesc()
-            kinds = {"vcycle": L.PREC_MG_VCYCLE, "av": L.PREC_AV_MG, "inv": L.PREC_INV_MG}
+            kinds = {"vcycle": L.PREC_MG_VCYCLE, "av": L.PREC_AV_MG, "inv": L.PREC_INV_MG,
+                     "dense": L.PREC_DENSE}
             t.kind = kinds[precond.get("kind", "vcycle")]
+            if t.kind == L.PREC_DENSE:
+                Tm = precond["matrix"]
+                _require_cuda(Tm, "precond matrix")
+                if tuple(Tm.shape) != (self.n, self.n) or not Tm.is_contiguous():
+                    raise ValueError(f"precond matrix must be a contiguous {(self.n, self.n)} tensor")
+                self._tmat = Tm
+                t.matrix = Tm.data_ptr()
             t.levels = int(precond.get("levels", 5))
             t.nu_pre = t.nu_post = int(precond.get("nu", 2))
             t.omega = float(precond.get("omega", 2.0 / 3.0))
@@ -153,6 +167,7 @@ class Solver:
         o.ortho_passes = int(ortho_passes)
         o.extraction = {"tharmonic": L.EXTRACT_T_HARMONIC, "harmonic": L.EXTRACT_HARMONIC}[extraction]
         o.use_graph = int(bool(use_graph))
+        o.algorithm = L.ALG_SINGLE if algorithm == "single" else L.ALG_BLOCK
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         o.precision = L.PRECISION_MIXED if precision == "mixed" else L.PRECISION_FP64

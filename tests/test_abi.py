@@ -286,3 +286,31 @@ def test_projected_solve_arguments_are_validated_on_the_host():
     assert call(xi=C.c_void_p((1 << 22) + 8)) == L.ERR_ARG         # xi overlaps Y
     assert call(kinds=C.c_void_p((1 << 26) + 16)) == L.ERR_ARG     # kinds in the workspace
     assert call(m=100) == L.ERR_ARG
+
+
+def test_single_vector_and_dense_preconditioner_options_are_validated_on_the_host():
+    """PLHR_ALG_SINGLE (Algorithm 1) takes k = 1 and a basis of 8 real
+    columns; PLHR_PREC_DENSE needs its matrix."""
+    a = _fd3(16)
+    n = 16 ** 3
+    o = L.default_options()
+    o.algorithm = L.ALG_SINGLE
+    code, sz = _ws(a, None, 1.0, 1, o)
+    assert code == L.OK and sz >= 3 * n * 8 * 8          # Z, QZ, TQZ of 8 real columns
+    assert _ws(a, None, 1.0, 2, o)[0] == L.ERR_ARG         # one pair only
+    assert b"k must be 1" in L.load().plhr_last_error()
+    o.k_extra = 30                                         # ignored by the single iteration
+    assert _ws(a, None, 1.0, 1, o)[0] == L.OK
+    o.algorithm = 7
+    assert _ws(a, None, 1.0, 1, o)[0] == L.ERR_ARG
+    t = L.PrecDesc()
+    t.kind = L.PREC_DENSE
+    assert _ws(a, t, 1.0, 4)[0] == L.ERR_ARG               # no matrix
+    t.matrix = 4096 + 4
+    assert _ws(a, t, 1.0, 4)[0] == L.ERR_ARG               # misaligned
+    t.matrix = 4096
+    code_d, sz_d = _ws(a, t, 1.0, 4)
+    code_i, sz_i = _ws(a, None, 1.0, 4)
+    assert code_d == L.OK and sz_d == sz_i                 # no multigrid workspace
+    t.kind = 9
+    assert _ws(a, t, 1.0, 4)[0] == L.ERR_ARG

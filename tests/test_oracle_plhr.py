@@ -245,6 +245,24 @@ def test_generalized_fe_reproduces_paper_eigenvalue():
     assert abs(lams[-1] - 497.5521) < 5e-5
 
 
+@pytest.mark.parametrize("sigma,printed", [(497.0, 497.5521), (980.0, 979.7072)])
+def test_single_vector_with_perturbed_av_preconditioner_reproduces_paper(sigma, printed):
+    """Section 6.1: Algorithm 1 on the FE pencil (K, M), 50 x 50 elements,
+    with T = |A - sigma B|^-1 + E, ||E|| = 1e-5 ||(A - sigma B)^-1||,
+    converges to the printed eigenvalue nearest sigma, and to the dense
+    generalized eigenvalue to rounding."""
+    K, M = ops.fe_q1(50, 2)
+    Kd, Md = K.toarray(), M.toarray()
+    T = wl.perturbed_abs_inverse(Kd, Md, sigma, 1e-5, (25, int(sigma)))
+    prob = plhr.Problem(A=K, B=M, T=lambda X: T @ X, sigma=sigma)
+    v0 = wl.start_block(K.shape[0], 1, (22, 0))[:, 0]
+    lams, v = plhr.plhr_single(prob, v0, maxit=30, tol=1e-11)
+    assert len(lams) <= 12                      # a strong preconditioner: a few steps
+    assert abs(lams[-1] - printed) < 5e-5
+    w = sla.eigh(Kd, Md, eigvals_only=True)
+    assert abs(lams[-1] - w[np.argmin(np.abs(w - sigma))]) < 1e-9 * sigma
+
+
 def test_algorithm3_equals_algorithm2_when_all_xi_real():
     """With T = I and B = I every xi is real (harmonic RR), so the real
     version follows the complex one (Section 4.1, last paragraph)."""

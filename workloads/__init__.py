@@ -215,3 +215,19 @@ def batched_problem(b: int, sizes=(64, 96, 128, 160)):
     pot = gaussian_potential(N, 16, (5, 1, b))
     targets = np.sort(rng(5, 3, b).uniform(1.5, 2.5, 8))
     return N, pot, targets
+
+
+def perturbed_abs_inverse(A: np.ndarray, B: np.ndarray, sigma: float, eps: float,
+                          seed: Tuple[int, ...]) -> np.ndarray:
+    """The preconditioners of the small finite-element experiment of
+    Section 6.1: T = |A - sigma B|^-1 + E, with |.| the matrix absolute
+    value of the symmetric matrix A - sigma B (from its eigendecomposition)
+    and E = G G^T (G seeded standard normal) scaled to spectral norm
+    eps ||(A - sigma B)^-1||.  A, B dense; returns a dense SPD matrix."""
+    d, U = np.linalg.eigh(A - sigma * B)
+    T = (U / np.abs(d)) @ U.T
+    G = rng(*seed).standard_normal(A.shape)
+    E = G @ G.T
+    E *= eps / np.abs(d).min() / np.linalg.norm(E, 2)
+    T = T + E
+    return 0.5 * (T + T.T)
