@@ -7,7 +7,10 @@ Follows the paper step by step:
 * Algorithm 2 (Section 4): block PLHR in complex arithmetic;
 * Algorithm 3 (Section 4.1): block PLHR in real arithmetic for real
   symmetric A, B and T, with complex-conjugate T-harmonic Ritz vectors
-  replaced by their real and imaginary parts.
+  replaced by their real and imaginary parts;
+* the PLMR variant (Section 3.3): Algorithm 1's trial subspace with the
+  refinement extraction (minimal T-norm residual at the current Rayleigh
+  quotient).
 
 The projected problem of every iteration is eq. (3.5),
 
@@ -392,6 +395,52 @@ def plhr_single(prob: Problem, v0: np.ndarray, maxit: int = 50, tol: float = 0.0
         v = y[0] * v + p
         v = v / np.sqrt(np.real(np.vdot(v, _mul(prob.B, v))))
         lam = np.real(np.vdot(v, prob.A @ v))
+        lams.append(lam)
+        if tol > 0:
+            rr = np.linalg.norm(prob.A @ v - lam * _mul(prob.B, v)) / (
+                (prob.normA1 + abs(lam) * prob.normB1) * np.linalg.norm(v))
+            if rr <= tol:
+                break
+    return np.array(lams), v
+
+
+def refined_vector(prob: Problem, Zh: np.ndarray, lam_t: float):
+    """The refinement extraction of Section 3.3: over span(Zh) (Zh
+    B-orthonormal), the B-unit vector v = Zh y minimising the T-norm of
+    A v - lam_t B v, i.e. the eigenvector of the smallest eigenvalue of
+    Zh^*(A - lam_t B) T (A - lam_t B) Zh y = theta^2 y.  Returns (theta^2, y)."""
+    Rl = prob.A @ Zh - lam_t * _mul(prob.B, Zh)          # (A - lam_t B) Z
+    F = Rl.conj().T @ _prec(prob.T, Rl)
+    F = 0.5 * (F + F.conj().T)
+    th, Y = np.linalg.eigh(F)
+    return th[0], Y[:, 0]
+
+
+def plmr_single(prob: Problem, v0: np.ndarray, maxit: int = 50, tol: float = 0.0):
+    """The PLMR method of Section 3.3: the trial subspace of Algorithm 1,
+    span{v, w, s, p}, with the refinement extraction at the current Rayleigh
+    quotient (lam_t = lam) in place of the T-harmonic one; the conjugate
+    direction is p = beta w + gamma s + delta p as in Algorithm 1.  The
+    basis is B-orthonormalised in the order v, w, s, p (the same span).
+    Real arithmetic for real A, B, T (the projected problem is Hermitian).
+    Returns the Rayleigh quotients (the initial one first) and v."""
+    v = np.array(v0, dtype=np.float64).ravel()
+    v = v / np.sqrt(np.vdot(v, _mul(prob.B, v)))
+    lam = float(np.vdot(v, prob.A @ v))
+    p = None
+    lams = [lam]
+    for _ in range(maxit):
+        w = _prec(prob.T, prob.A @ v - lam * _mul(prob.B, v))
+        s = _prec(prob.T, prob.A @ w - lam * _mul(prob.B, w))
+        blocks = [("V", v[:, None]), ("W", w[:, None]), ("S", s[:, None]),
+                  ("P", None if p is None else p[:, None])]
+        Zh, labels = b_orthonormalize(blocks, prob.B)
+        _, y = refined_vector(prob, Zh, lam)
+        isV = np.array([lb[0] == "V" for lb in labels])
+        p = Zh[:, ~isV] @ y[~isV]
+        v = Zh[:, isV] @ y[isV] + p
+        v = v / np.sqrt(np.vdot(v, _mul(prob.B, v)))
+        lam = float(np.vdot(v, prob.A @ v))
         lams.append(lam)
         if tol > 0:
             rr = np.linalg.norm(prob.A @ v - lam * _mul(prob.B, v)) / (

@@ -385,3 +385,56 @@ def test_bplhr_with_avmg_and_both_extractions_converges():
         res = plhr.bplhr(prob, wl.start_block(N * N, 6, (27, 0)), 4, tol=1e-10, maxit=600)
         assert res.converged, ex
         assert np.allclose(np.sort(res.lam), np.sort(lam_ref), rtol=1e-10), ex
+
+
+def test_refined_extraction_minimises_the_T_norm_residual():
+    """Section 3.3: the refined vector is the B-unit vector of span(Z) with
+    the smallest ||A v - lam B v||_T.  Checked against an independent route:
+    the smallest singular value of T^{1/2}(A - lam B) Zhat (Zhat
+    B-orthonormal) and its right singular vector, and random trial
+    vectors never doing better."""
+    K, M = ops.fe_q1(8, 2)
+    n = K.shape[0]
+    T = mg.VCycle("fd", (7, 7), 1 / 8, 1.0, 2)
+    prob = plhr.Problem(A=K, B=M, T=T.apply, sigma=300.0)
+    Z = np.random.default_rng(71).standard_normal((n, 4))
+    Zh, _ = plhr.b_orthonormalize([("V", Z)], M)
+    lam_t = 280.0
+    th2, y = plhr.refined_vector(prob, Zh, lam_t)
+    Td = mg.dense_matrix(T.apply, n)
+    d, U = np.linalg.eigh(0.5 * (Td + Td.T))
+    Th = (U * np.sqrt(d)) @ U.T
+    Kmat = Th @ ((K.toarray() - lam_t * M.toarray()) @ Zh)
+    _, sv, Vt = np.linalg.svd(Kmat)
+    assert np.isclose(th2, sv[-1] ** 2, rtol=1e-10)
+    assert abs(abs(np.dot(Vt[-1], y)) - 1.0) < 1e-10
+    R = np.random.default_rng(72).standard_normal((4, 200))
+    vals = np.sum((Kmat @ R) ** 2, axis=0) / np.sum(R ** 2, axis=0)
+    assert vals.min() >= th2 * (1 - 1e-12)
+
+
+def test_plmr_converges_to_the_eigenpair_its_start_approximates():
+    """PLMR refines toward the eigenpair near the current Rayleigh quotient:
+    from a perturbed eigenvector it converges to that eigenpair, quickly
+    with T close to |A - sigma|^-1 and more slowly with a V-cycle; from the
+    exact eigenvector the refined residual is zero and nothing moves."""
+    A = _small_problem(N=12, seed=7)
+    n = A.shape[0]
+    lam, X = np.linalg.eigh(A.toarray())
+    gaps = np.minimum(lam[10:41] - lam[9:40], lam[11:42] - lam[10:41])
+    j = 10 + int(np.argmax(gaps))              # a well separated interior pair
+    r = np.random.default_rng(73).standard_normal(n)
+    v0 = X[:, j] + 0.05 * r / np.linalg.norm(r)
+    Tabs = _abs_inv(A, None, lam[j] - 1.0)
+    prob = plhr.Problem(A=A, T=lambda Y: Tabs @ Y, sigma=lam[j])
+    lams, v = plhr.plmr_single(prob, v0, maxit=20, tol=1e-12)
+    assert len(lams) <= 12
+    assert abs(lams[-1] - lam[j]) <= 1e-12 * abs(lam[j])
+    assert dense.subspace_sine(X[:, [j]], v[:, None]) < 1e-8
+    T = mg.VCycle("fd", (12, 12), 1 / 13, 1.0, 2)
+    prob = plhr.Problem(A=A, T=T.apply, sigma=lam[j])
+    lams, v = plhr.plmr_single(prob, v0, maxit=200)
+    assert abs(lams[-1] - lam[j]) <= 1e-10 * abs(lam[j])
+    lams2, v2 = plhr.plmr_single(prob, X[:, j], maxit=2)
+    assert np.allclose(lams2, lam[j], rtol=1e-12)
+    assert dense.subspace_sine(X[:, [j]], v2[:, None]) < 1e-10
