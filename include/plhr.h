@@ -195,8 +195,16 @@ typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_ext
  * vectors stored as two real columns each (real and imaginary parts, i.e.
  * the interleaved layout of a complex128 vector), every basis is
  * orthonormalised in the complex B-inner product, and the 4 x 4 (3 x 3 on
- * the first step) projected problem is solved in complex arithmetic.    */
-typedef enum { PLHR_ALG_BLOCK = 0, PLHR_ALG_SINGLE = 1 } plhr_algorithm;
+ * the first step) projected problem is solved in complex arithmetic.
+ * PLHR_ALG_PLMR is the PLMR method of Section 3.3 (k = 1, real
+ * arithmetic): the trial subspace of Algorithm 1 with the refinement
+ * extraction, the B-unit vector v of span{v, w, s, p} of least
+ * ||A v - lam B v||_T at the current Rayleigh quotient lam, i.e. the
+ * eigenvector of the smallest eigenvalue of
+ * Z^*(A - lam B)T(A - lam B)Z y = theta^2 Z^*BZ y.  T(A - lam B) of v and
+ * w are w and s themselves, so it costs the same four preconditioner
+ * applications per iteration as the T-harmonic extraction.              */
+typedef enum { PLHR_ALG_BLOCK = 0, PLHR_ALG_SINGLE = 1, PLHR_ALG_PLMR = 2 } plhr_algorithm;
 
 /* Solver options (plhr_options_default fills the defaults shown).
  *   tol          relative residual ||A v - lam B v|| /
@@ -233,8 +241,9 @@ typedef enum { PLHR_ALG_BLOCK = 0, PLHR_ALG_SINGLE = 1 } plhr_algorithm;
  *                n x 2 doubles (the real and imaginary parts of the start
  *                vector), the convergence test uses the residual of the
  *                complex vector, and the returned eigenvector is real
- *                (the final Rayleigh-Ritz on the span of the two parts)
- *                                                             [BLOCK]   */
+ *                (the final Rayleigh-Ritz on the span of the two parts).
+ *                PLHR_ALG_PLMR needs k = 1; k_extra, lock and extraction
+ *                are ignored and the start block is n x 1   [BLOCK]   */
 typedef struct {
   double tol;
   int32_t max_iters;
@@ -292,9 +301,9 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
  *   sigma      finite real shift
  *   k          wanted pairs, 1 <= k and 4*(k + k_extra) <= n; a trial
  *              subspace wider than 84 (4*(k + k_extra) > 84) gives
- *              PLHR_ERR_UNSUPPORTED; PLHR_ALG_SINGLE needs k = 1 (its
- *              basis takes 8 real columns) and gives PLHR_ERR_ARG
- *              otherwise
+ *              PLHR_ERR_UNSUPPORTED; PLHR_ALG_SINGLE (its basis takes 8
+ *              real columns) and PLHR_ALG_PLMR (4 columns) need k = 1 and
+ *              give PLHR_ERR_ARG otherwise
  *   opt        host options, or NULL for defaults
  *   stream     HIP stream (hipStream_t) all work is enqueued on; NULL is
  *              the null stream
@@ -309,7 +318,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B,
 
 /* Algorithm 3, steps 1-2: load the start block and B-normalise it.
  *   V0   device, n x (k + k_extra) doubles, point-major (n x 2 with
- *        PLHR_ALG_SINGLE: real and imaginary parts); copied.             */
+ *        PLHR_ALG_SINGLE: real and imaginary parts; n x 1 with
+ *        PLHR_ALG_PLMR); copied.                                         */
 plhr_status plhr_start(plhr_ctx ctx, const double* V0);
 
 /* Run up to n_steps iterations of the while-loop of Algorithm 3, stopping

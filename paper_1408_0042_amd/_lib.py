@@ -22,7 +22,7 @@ OP_BLOCH7_3D = 8
 F64, C128 = 0, 1
 PREC_IDENTITY, PREC_MG_VCYCLE, PREC_AV_MG, PREC_INV_MG, PREC_DENSE = 0, 1, 2, 3, 4
 EXTRACT_T_HARMONIC, EXTRACT_HARMONIC = 0, 1
-ALG_BLOCK, ALG_SINGLE = 0, 1
+ALG_BLOCK, ALG_SINGLE, ALG_PLMR = 0, 1, 2
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 
 

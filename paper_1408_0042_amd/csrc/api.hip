@@ -305,10 +305,12 @@ bool uses_mg(const plhr_prec_desc* T) {
                T->kind == PLHR_PREC_INV_MG);
 }
 
-// block columns: k + k_extra, or the two real columns of the complex
-// vector of the single-vector iteration
+// block columns: k + k_extra, the two real columns of the complex vector
+// of the single-vector iteration, or PLMR's one real column
 int block_cols(int32_t k, const plhr_options& o) {
-  return o.algorithm == PLHR_ALG_SINGLE ? 2 : k + o.k_extra;
+  if (o.algorithm == PLHR_ALG_SINGLE) return 2;
+  if (o.algorithm == PLHR_ALG_PLMR) return 1;
+  return k + o.k_extra;
 }
 
 plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
@@ -389,16 +391,17 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     return PLHR_ERR_ARG;
   }
   const bool single = opt && opt->algorithm == PLHR_ALG_SINGLE;
-  if (opt && opt->algorithm != PLHR_ALG_BLOCK && !single) {
-    set_error("invalid options (algorithm PLHR_ALG_BLOCK or PLHR_ALG_SINGLE)");
+  const bool plmr = opt && opt->algorithm == PLHR_ALG_PLMR;
+  if (opt && opt->algorithm != PLHR_ALG_BLOCK && !single && !plmr) {
+    set_error("invalid options (algorithm PLHR_ALG_BLOCK, PLHR_ALG_SINGLE or PLHR_ALG_PLMR)");
     return PLHR_ERR_ARG;
   }
-  if (single && k != 1) {
-    set_error("PLHR_ALG_SINGLE computes one pair: k must be 1");
+  if ((single || plmr) && k != 1) {
+    set_error("PLHR_ALG_SINGLE and PLHR_ALG_PLMR compute one pair: k must be 1");
     return PLHR_ERR_ARG;
   }
   const size_t n = (size_t)A->nx * A->ny * A->nz;
-  const int kint = single ? 2 : k + kextra;
+  const int kint = single ? 2 : (plmr ? 1 : k + kextra);
   if ((size_t)4 * kint > n) {
     set_error("4*(k + k_extra) must not exceed n");
     return PLHR_ERR_ARG;
@@ -637,11 +640,60 @@ int update(plhr_ctx_s* c, double* const* arrs, int narr, const DevStatus* st) {
                        c->stream);
 }
 
+// B-orthonormalise Z = [V W S P] and the arrays carried with it (Cholesky-QR
+// in slot order).  The first pass also decides (on the device, in the gate)
+// whether the basis met a small pivot: then the B-orthogonality needs a
+// second pass (ortho_passes 0: automatic; 2: always) and the carried
+// products of the V and P slots, which the transform mixes with weights up
+// to pivot^-1/2, are recomputed from the new basis (T(A - sigma B)Z too
+// when `recompute_tq`).
+void orthonormalise(plhr_ctx_s* c, double* const* arrs, int narr, bool recompute_tq) {
+  const int kint = c->kint, m = c->m;
+  hipStream_t s = c->stream;
+  DevStatus* st = c->st;
+  double *Z = c->Z, *QZ = c->QZ, *TQZ = c->TQZ, *BZ = c->BZ;
+  const bool bst = c->bst;
+  const Blk none{nullptr, 0};
+  SmallParams p1 = c->sp, p2 = c->sp;
+  SmallBufs b1 = c->sb;
+  b1.gate = c->gate;
+  p1.pass = 1;
+  p2.pass = 2;
+  // the single-vector iteration orthonormalises in the complex inner
+  // product of its interleaved columns
+  auto ortho = c->sp.cplx ? launch_single_ortho : launch_ortho_small;
+  gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
+  ortho(p1, b1, st, s);
+  transform(c, arrs, narr, st);
+  if (c->opt.ortho_passes == 0) {
+    gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, c->gate);
+    ortho(p2, b1, st, s);
+    transform(c, arrs, narr, c->gate);
+  } else if (c->opt.ortho_passes == 2) {
+    gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
+    ortho(c->sp, c->sb, st, s);
+    transform(c, arrs, narr, st);
+  }
+  // gated recomputation of (A - sigma B)Z and T(A - sigma B)Z for V and P
+  for (int slot : {0, 3}) {
+    stencil(c, Z + slot * kint, m, Blk{QZ + slot * kint, m}, none, nullptr, none, kint, c->sigma,
+            c->gate, bst ? Blk{BZ + slot * kint, m} : none);
+    if (recompute_tq)
+      precond(c, QZ + slot * kint, m, Blk{TQZ + slot * kint, m}, none, kint, kint, c->gate);
+  }
+}
+
+void enqueue_plmr_body(plhr_ctx_s* c, bool refresh);
+
 // One pass through the loop of Algorithm 3; `refresh` recomputes the
 // carried (A - sigma B)V and T(A - sigma B)V slots from V.  With the
 // harmonic extraction the products with T that only enter the projection
 // (T(A - sigma B)Z) are not formed.
 void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
+  if (c->sp.plmr) {
+    enqueue_plmr_body(c, refresh);
+    return;
+  }
   const int kint = c->kint, m = c->m;
   const size_t n = c->n;
   hipStream_t s = c->stream;
@@ -700,40 +752,7 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   arrs[narr++] = QZ;
   if (tharm) arrs[narr++] = TQZ;
   if (bst) arrs[narr++] = BZ;
-  // The first pass also decides (on the device, in the gate) whether the
-  // basis met a small pivot: then the B-orthogonality needs a second pass
-  // (ortho_passes 0: automatic; 2: always) and the carried products of the
-  // V and P slots, which the transform mixes with weights up to
-  // pivot^-1/2, are recomputed from the new basis below.
-  {
-    SmallParams p1 = c->sp, p2 = c->sp;
-    SmallBufs b1 = c->sb;
-    b1.gate = c->gate;
-    p1.pass = 1;
-    p2.pass = 2;
-    // the single-vector iteration orthonormalises in the complex inner
-    // product of its interleaved columns
-    auto ortho = c->sp.cplx ? launch_single_ortho : launch_ortho_small;
-    gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-    ortho(p1, b1, st, s);
-    transform(c, arrs, narr, st);
-    if (c->opt.ortho_passes == 0) {
-      gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, c->gate);
-      ortho(p2, b1, st, s);
-      transform(c, arrs, narr, c->gate);
-    } else if (c->opt.ortho_passes == 2) {
-      gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
-      ortho(c->sp, c->sb, st, s);
-      transform(c, arrs, narr, st);
-    }
-    // gated recomputation of (A - sigma B)Z and T(A - sigma B)Z for V and P
-    for (int slot : {0, 3}) {
-      stencil(c, Z + slot * kint, m, Blk{QZ + slot * kint, m}, none, nullptr, none, kint,
-              c->sigma, c->gate, bst ? Blk{BZ + slot * kint, m} : none);
-      if (tharm) precond(c, QZ + slot * kint, m, Blk{TQZ + slot * kint, m}, none, kint, kint,
-                         c->gate);
-    }
-  }
+  orthonormalise(c, arrs, narr, tharm);
   // [G_L | G_R] = (T Q Zhat)^T [Q Zhat | B Zhat]  (Q Zhat for the harmonic
   // extraction)
   gram(c, tharm ? TQZ : QZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
@@ -744,6 +763,60 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   else
     launch_tharm_small(c->sp, c->sb, st, s);
   // V <- Zhat Y', P <- [W S P]hat Y'_WSP  (and the same for QZ, TQZ)
+  nb = update(c, arrs, narr, st);
+  launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
+}
+
+// One iteration of PLMR (Section 3.3), one real column per slot: the
+// trial subspace span{v, w, s, p} of Algorithm 1 and the refinement
+// extraction at the current Rayleigh quotient lam.  The T slot carries
+// T(A - lam B) of each basis column: of v it is w = T(A v - lam B v), of w
+// it is s = T(A w - lam B w), and of s and p it is formed here, so an
+// iteration applies T four times, as the T-harmonic one does.
+void enqueue_plmr_body(plhr_ctx_s* c, bool refresh) {
+  const int m = c->m;  // 4
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  DevStatus* st = c->st;
+  double *Z = c->Z, *QZ = c->QZ, *TL = c->TQZ, *R = c->R, *BZ = c->BZ;
+  const bool bst = c->bst;
+  const Blk none{nullptr, 0};
+  if (refresh)
+    stencil(c, Z, m, Blk{QZ, m}, none, nullptr, none, 1, c->sigma, st, bst ? Blk{BZ, m} : none);
+  stencil(c, Z, m, Blk{c->QVf, 1}, none, nullptr, none, 1, c->sigma, st,
+          bst ? Blk{c->BVf, 1} : none);
+  int nb = launch_xdots(n, Z, m, c->QVf, 1, 1, c->part, s, bst ? c->BVf : nullptr, 1);
+  launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
+  nb = launch_resid_prep(n, Z, m, c->QVf, 1, c->sb.lam, c->sigma, R, 1, 1, c->bdiag,
+                         bst ? c->BVf : nullptr, 1, c->part, st, s);
+  launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
+  // w = T(A v - lam B v)
+  precond(c, R, 1, Blk{Z + 1, m}, none, 1, 1, st);
+  // (A - sigma B) w, and R = (A - lam B) w; s = T R
+  stencil(c, Z + 1, m, Blk{QZ + 1, m}, Blk{R, 1}, c->sb.lam, none, 1, c->sigma, st,
+          bst ? Blk{BZ + 1, m} : none);
+  precond(c, R, 1, Blk{Z + 2, m}, none, 1, 1, st);
+  // (A - sigma B) s, and T(A - lam B) s
+  stencil(c, Z + 2, m, Blk{QZ + 2, m}, Blk{R, 1}, c->sb.lam, none, 1, c->sigma, st,
+          bst ? Blk{BZ + 2, m} : none);
+  precond(c, R, 1, Blk{TL + 2, m}, none, 1, 1, st);
+  // T(A - lam B) p from the carried (A - sigma B) p (zero before the first
+  // update, when the P slot is empty)
+  launch_resid_prep(n, Z + 3, m, QZ + 3, m, c->sb.lam, c->sigma, R, 1, 1, c->bdiag,
+                    bst ? BZ + 3 : nullptr, m, c->part, st, s);
+  precond(c, R, 1, Blk{TL + 3, m}, none, 1, 1, st);
+  launch_copy(n, Z + 1, m, TL, m, 1, s, st);
+  launch_copy(n, Z + 2, m, TL + 1, m, 1, s, st);
+  double* arrs[4];
+  int narr = 0;
+  arrs[narr++] = Z;
+  arrs[narr++] = QZ;
+  arrs[narr++] = TL;
+  if (bst) arrs[narr++] = BZ;
+  orthonormalise(c, arrs, narr, false);
+  // [G_1 | G_2] = (T(A - lam B)Zhat)^T [(A - sigma B)Zhat | B Zhat]
+  gram(c, TL, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
+  launch_plmr_small(c->sp, c->sb, st, s);
   nb = update(c, arrs, narr, st);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 1, s);
 }
@@ -1015,7 +1088,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->sp.normB1 = c->normB1;
   c->sp.drop_tol = o.drop_tol;
   c->sp.cplx = (o.algorithm == PLHR_ALG_SINGLE) ? 1 : 0;
-  c->sp.lock = c->sp.cplx ? 0 : o.lock;
+  c->sp.plmr = (o.algorithm == PLHR_ALG_PLMR) ? 1 : 0;
+  c->sp.lock = (c->sp.cplx || c->sp.plmr) ? 0 : o.lock;
   // G_R of eq. (3.5) is symmetric when T does not enter the projection
   // (T = I, or the harmonic extraction) and B = I: the projected problem
   // is then Hermitian-definite
@@ -1023,7 +1097,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
                            (c->prec_kind == PLHR_PREC_IDENTITY && !c->bdiag)))
                   ? 1
                   : 0;
-  if (getenv("PLHR_NO_SYM") || c->sp.cplx) c->sp.sym = 0;
+  if (getenv("PLHR_NO_SYM") || c->sp.cplx || c->sp.plmr) c->sp.sym = 0;
   c->use_mfma = (getenv("PLHR_NO_MFMA") == nullptr);
   hipError_t e = small_set_attributes(c->m, c->kint);
   if (e == hipSuccess) e = tharm_sym_set_attributes();
@@ -1067,7 +1141,7 @@ plhr_status plhr_start(plhr_ctx c, const double* V0) {
   const Blk none{nullptr, 0};
   stencil(c, c->Z, m, Blk{c->QZ, m}, none, nullptr, none, kint, c->sigma, nullptr,
           c->bst ? Blk{c->BZ, m} : none);
-  if (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC)
+  if (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC && !c->sp.plmr)
     precond(c, c->QZ, m, Blk{c->TQZ, m}, none, kint, kint, nullptr);
   const int nb = launch_xdots(n, c->Z, m, c->QZ, m, kint, c->part, s, c->bst ? c->BZ : nullptr, m);
   launch_init_lam(c->sp, c->part, nb, c->sb, c->st, s);

@@ -359,6 +359,7 @@ struct SmallParams {
   int pass = 0;       // Cholesky-QR pass with a gate: 1 first, 2 second; 0 none
   int cplx = 0;       // single-vector complex iteration (Algorithm 1): kint = 2
                       // real columns hold one complex vector (re, im)
+  int plmr = 0;       // PLMR (Section 3.3): kint = 1, refinement extraction
 };
 
 // ------------------------------------------------------------- batches
@@ -468,6 +469,10 @@ hipError_t tharm_sym_set_attributes();
 // problem of eq. (3.5) with the selection of the smallest |xi|.
 void launch_single_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 void launch_single_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// PLMR (Section 3.3): from [G_1 | G_2] = (T(A - lam B)Zhat)^T [(A - sigma B)Zhat | B Zhat]
+// the matrix F = Zhat^T (A - lam B) T (A - lam B) Zhat = G_1^T + (sigma - lam) G_2^T,
+// its smallest eigenpair by cyclic Jacobi, Y' = y (m x 1).
+void launch_plmr_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 // Y = T X for a dense n x n T (row-major); columns [0, split) of Y go to
 // o0, the rest to o1 (nothing when st is halted).
 void launch_dense_prec(size_t n, const double* T, const double* X, int ldx, Blk o0, Blk o1,

@@ -28,7 +28,8 @@
 //                   the coefficients Y' (8 x 2 real) of v <- Z y
 //
 // The projected problems are at most 4 x 4: one thread does the
-// arithmetic.
+// arithmetic.  The refinement step of PLMR (Section 3.3, real arithmetic,
+// one real column) is here too.
 #include <cmath>
 
 #include "common.cuh"
@@ -458,6 +459,93 @@ __global__ __launch_bounds__(64) void k_single_tharm(SmallParams p, SmallBufs b,
   b.kinds[1] = 3;
   b.pair[0] = 1;
   b.pair[1] = 0;
+}
+
+// ------------------------------------------------ PLMR refinement step
+// F = Zhat^T (A - lam B) T (A - lam B) Zhat on the kept slots from the
+// Gram [G_1 | G_2] = (T(A - lam B)Zhat)^T [(A - sigma B)Zhat | B Zhat]:
+// F(i, j) = G_1(j, i) + (sigma - lam) G_2(j, i), symmetrised.  Its
+// eigenpairs by cyclic Jacobi (Golub & Van Loan, Sec. 8.5); the vector of
+// the smallest eigenvalue theta^2 (ties: lower slot) is y, unit 2-norm,
+// largest entry positive (Zhat is B-orthonormal, so v = Zhat y has
+// ||v||_B = 1).
+__global__ __launch_bounds__(64) void k_plmr_small(SmallParams p, SmallBufs b, DevStatus* st) {
+  if (halted(st)) return;
+  if (threadIdx.x != 0) return;
+  const int m = p.m, ld2 = 2 * m;
+  int idx[kN];
+  int n = 0;
+  for (int a = 0; a < m && a < kN; ++a)
+    if (b.keep[a]) idx[n++] = a;
+  if (n < 1) {
+    st->error = PLHR_ERR_BREAKDOWN;
+    st->reason = kReasonVVanished;
+    return;
+  }
+  const double lam = b.lam[0];
+  double F[kN * kN], V[kN * kN];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int a = idx[i], c = idx[j];
+      const double fij = b.GLR[(size_t)c * ld2 + a] + (p.sigma - lam) * b.GLR[(size_t)c * ld2 + m + a];
+      const double fji = b.GLR[(size_t)a * ld2 + c] + (p.sigma - lam) * b.GLR[(size_t)a * ld2 + m + c];
+      F[i * kN + j] = 0.5 * (fij + fji);
+      V[i * kN + j] = (i == j) ? 1.0 : 0.0;
+    }
+  double a2 = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) a2 += F[i * kN + j] * F[i * kN + j];
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += F[i * kN + j] * F[i * kN + j];
+    if (!(off > 1e-30 * a2)) break;
+    for (int pp = 0; pp < n; ++pp)
+      for (int q = pp + 1; q < n; ++q) {
+        const double apq = F[pp * kN + q];
+        if (apq == 0.0) continue;
+        const double th = (F[q * kN + q] - F[pp * kN + pp]) / (2.0 * apq);
+        const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < n; ++r) {  // columns pp, q
+          const double x = F[r * kN + pp], y = F[r * kN + q];
+          F[r * kN + pp] = c * x - sn * y;
+          F[r * kN + q] = sn * x + c * y;
+          const double u = V[r * kN + pp], w = V[r * kN + q];
+          V[r * kN + pp] = c * u - sn * w;
+          V[r * kN + q] = sn * u + c * w;
+        }
+        for (int r = 0; r < n; ++r) {  // rows pp, q
+          const double x = F[pp * kN + r], y = F[q * kN + r];
+          F[pp * kN + r] = c * x - sn * y;
+          F[q * kN + r] = sn * x + c * y;
+        }
+      }
+  }
+  int js = 0;
+  for (int j = 1; j < n; ++j)
+    if (F[j * kN + j] < F[js * kN + js]) js = j;
+  double nr2 = 0.0, big = -1.0;
+  int im = 0;
+  for (int i = 0; i < n; ++i) {
+    const double v = V[i * kN + js];
+    nr2 += v * v;
+    if (fabs(v) > big) big = fabs(v), im = i;
+  }
+  double sc = (nr2 > 0.0) ? 1.0 / sqrt(nr2) : 0.0;
+  if (V[im * kN + js] < 0.0) sc = -sc;
+  for (int e = 0; e < m * p.kint; ++e) b.Y[e] = 0.0;
+  for (int i = 0; i < n; ++i) b.Y[(size_t)idx[i] * p.kint] = V[i * kN + js] * sc;
+  for (int r = 0; r < 2 * m; ++r) b.xi[r] = 0.0;
+  b.xi[0] = F[js * kN + js];  // theta^2, the squared T-norm of the refined residual
+  b.kinds[0] = 0;
+  b.pair[0] = -1;
+}
+
+void launch_plmr_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
+  prof_begin(KC_THARM_QR, 2.0 * p.m * p.m * 8.0, 2000.0, s);
+  hipLaunchKernelGGL(k_plmr_small, dim3(1), dim3(64), 0, s, p, b, st);
+  prof_end(KC_THARM_QR, s);
 }
 
 void launch_single_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {

@@ -68,8 +68,9 @@ class Solver:
     projection); use_graph: replay each iteration from a captured HIP graph.
     precond {"kind": "dense", "matrix": T} takes T as an (n, n) float64
     device tensor (symmetric positive definite, kept referenced).
-    algorithm: "block" (Algorithm 3) or "single" (Algorithm 1 in complex
-    arithmetic, k = 1; the start block is (n, 2): real and imaginary parts).
+    algorithm: "block" (Algorithm 3), "single" (Algorithm 1 in complex
+    arithmetic, k = 1; the start block is (n, 2): real and imaginary parts)
+    or "plmr" (PLMR of Section 3.3, k = 1, start block (n, 1)).
     kind "csr": a general sparse symmetric A given as csr = (row_ptr int32,
     col_idx int32, values float64) device tensors, dims = (n,); mass may
     then be a CSR triple for B; T must be the identity.
@@ -139,9 +140,9 @@ class Solver:
             bdesc.h, bdesc.scale = 1.0, 1.0
             bdesc.potential = mass.data_ptr()
         self.k = int(k)
-        if algorithm not in ("block", "single"):
-            raise ValueError("algorithm must be 'block' or 'single'")
-        self.kint = 2 if algorithm == "single" else int(k) + int(k_extra)
+        if algorithm not in ("block", "single", "plmr"):
+            raise ValueError("algorithm must be 'block', 'single' or 'plmr'")
+        self.kint = {"single": 2, "plmr": 1}.get(algorithm, int(k) + int(k_extra))
         self.sigma = float(sigma)
         t = None
         if precond is not None:
@@ -167,7 +168,7 @@ class Solver:
         o.ortho_passes = int(ortho_passes)
         o.extraction = {"tharmonic": L.EXTRACT_T_HARMONIC, "harmonic": L.EXTRACT_HARMONIC}[extraction]
         o.use_graph = int(bool(use_graph))
-        o.algorithm = L.ALG_SINGLE if algorithm == "single" else L.ALG_BLOCK
+        o.algorithm = {"block": L.ALG_BLOCK, "single": L.ALG_SINGLE, "plmr": L.ALG_PLMR}[algorithm]
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         o.precision = L.PRECISION_MIXED if precision == "mixed" else L.PRECISION_FP64

@@ -314,3 +314,15 @@ def test_single_vector_and_dense_preconditioner_options_are_validated_on_the_hos
     assert code_d == L.OK and sz_d == sz_i                 # no multigrid workspace
     t.kind = 9
     assert _ws(a, t, 1.0, 4)[0] == L.ERR_ARG
+
+
+def test_plmr_option_is_validated_on_the_host():
+    """PLHR_ALG_PLMR (Section 3.3) takes k = 1 and one real column per slot."""
+    a = _fd3(16)
+    n = 16 ** 3
+    o = L.default_options()
+    o.algorithm = L.ALG_PLMR
+    code, sz = _ws(a, None, 1.0, 1, o)
+    assert code == L.OK and sz >= 3 * n * 4 * 8          # Z, QZ, T(A - lam B)Z
+    assert _ws(a, None, 1.0, 3, o)[0] == L.ERR_ARG
+    assert b"k must be 1" in L.load().plhr_last_error()
