@@ -700,7 +700,12 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   DevStatus* st = c->st;
   double *Z = c->Z, *QZ = c->QZ, *TQZ = c->TQZ, *R = c->R;
   const Blk none{nullptr, 0};
-  const bool tharm = (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC);
+  // T = I (with B = I or a stencil B): T(A - sigma B)Z is (A - sigma B)Z
+  // itself, so the T-harmonic extraction is the harmonic one and no
+  // T-products are formed; W = R and S = (A - lam B)W are written straight
+  // into their slots.
+  const bool tid = (c->prec_kind == PLHR_PREC_IDENTITY && !c->bdiag);
+  const bool tharm = (c->opt.extraction == PLHR_EXTRACT_T_HARMONIC) && !tid;
   // (A - sigma B)V afresh from V, and the Rayleigh quotients from it: the
   // copy carried by the block updates drifts from the true product by
   // rounding (about 1e-11 relative after a thousand iterations), which
@@ -723,17 +728,19 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s, bst ? c->BVf : nullptr, kint);
   launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
   // residuals of the current block, convergence and locking
-  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, R, kint, kint, c->bdiag,
-                         bst ? c->BVf : nullptr, kint, c->part, st,
-                         s);
+  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, tid ? Z + kint : R,
+                         tid ? m : kint, kint, c->bdiag, bst ? c->BVf : nullptr, kint, c->part,
+                         st, s);
   launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
   // W = T (A V - B V Lam)
-  precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st, true);
+  if (!tid) precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st, true);
   // QW = (A - sigma) W;  R = [QW - W (Lam - sigma) | QW]
-  stencil(c, Z + kint, m, Blk{QZ + kint, m}, Blk{R, 2 * kint}, c->sb.lam, Blk{R + kint, 2 * kint},
-          kint, c->sigma, st, bst ? Blk{BZ + kint, m} : none);
+  stencil(c, Z + kint, m, Blk{QZ + kint, m}, tid ? Blk{Z + 2 * kint, m} : Blk{R, 2 * kint},
+          c->sb.lam, tharm ? Blk{R + kint, 2 * kint} : none, kint, c->sigma, st,
+          bst ? Blk{BZ + kint, m} : none);
   // S = T (A W - B W Lam), TQW = T (A - sigma) W
-  if (!tharm) {
+  if (tid) {
+  } else if (!tharm) {
     precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
   } else if (c->opt.precision == PLHR_PREC_MIXED) {
     precond(c, R, 2 * kint, Blk{Z + 2 * kint, m}, none, kint, kint, st, true);
