@@ -405,14 +405,27 @@ typedef struct plhr_bloch_prec_s* plhr_bloch_prec;
  *             2^(levels - 1); the coarsest grid at most 1024 points
  *   max_cols  widest block apply will take (1 .. 2^22)
  *   stream    hipStream_t of every apply (NULL: the null stream)
- * Allocates its level buffers (3 blocks per coarse level, 2 on the finest,
- * of n_l x max_cols complex128) and the coarse inverse on the current
- * device; released by plhr_bloch_prec_destroy.
- * PLHR_ERR_ARG / PLHR_ERR_UNSUPPORTED for bad or unsupported descriptors,
- * PLHR_ERR_NOT_HPD if the coarsest operator is not positive definite (all
- * phases zero), PLHR_ERR_HIP if an allocation or copy fails.            */
+ *   workspace device buffer of at least plhr_bloch_prec_workspace_size
+ *             bytes, 256-byte aligned, caller-owned (it must outlive the
+ *             handle), or NULL: the library allocates
+ *   ws_bytes  size of workspace (ignored when it is NULL)
+ * The level buffers (3 blocks per coarse level, 2 on the finest, of
+ * n_l x max_cols complex128) and the coarse inverse live in the workspace
+ * (or in memory the library allocates on the current device and
+ * plhr_bloch_prec_destroy releases).
+ * PLHR_ERR_ARG / PLHR_ERR_UNSUPPORTED for bad or unsupported descriptors
+ * or a workspace that is too small or misaligned, PLHR_ERR_NOT_HPD if the
+ * coarsest operator is not positive definite (all phases zero),
+ * PLHR_ERR_HIP if an allocation or copy fails.                          */
 plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* T,
-                                   int32_t max_cols, void* stream, plhr_bloch_prec* out);
+                                   int32_t max_cols, void* stream, void* workspace,
+                                   size_t ws_bytes, plhr_bloch_prec* out);
+
+/* Device bytes plhr_bloch_prec_create needs in a caller workspace for
+ * these arguments (validated as for create; no device call).
+ *   ws_bytes  host; receives the size                                    */
+plhr_status plhr_bloch_prec_workspace_size(const plhr_op_desc* A, const plhr_prec_desc* T,
+                                           int32_t max_cols, size_t* ws_bytes);
 
 /* Y = T X, one V-cycle per column, enqueued on the stream given at create
  * (asynchronous).  X, Y: device, n x ncols complex128 (interleaved),
@@ -613,12 +626,25 @@ typedef struct plhr_batch_s* plhr_batch;
  *   k       wanted pairs per problem, 4 (k + k_extra) <= min n_b and <= 84
  *   opt     host options (precision FP64), or NULL for defaults
  *   stream  HIP stream for all work (NULL: the null stream)
+ *   workspace  device buffer of at least plhr_batch_workspace_size bytes,
+ *           256-byte aligned, caller-owned (it must outlive the handle), or
+ *           NULL: the library allocates it (and frees it at destroy)
+ *   ws_bytes  size of workspace (ignored when it is NULL)
  *   out     host; receives the handle
- * The library allocates the device memory it needs; the potentials are
- * read at create and must stay valid until destroy.                      */
+ * With a workspace the handle allocates no device memory (its host state,
+ * graphs and a pinned status array are its own).  The potentials are read
+ * at create and must stay valid until destroy.  A workspace that is too
+ * small or misaligned gives PLHR_ERR_ARG.                                */
 plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_prec_desc* T,
                               const double* sigma, int32_t k, const plhr_options* opt,
-                              void* stream, plhr_batch* out);
+                              void* stream, void* workspace, size_t ws_bytes, plhr_batch* out);
+
+/* Device bytes plhr_batch_create needs in a caller workspace for these
+ * arguments (validated as for create; no device call).
+ *   ws_bytes  host; receives the size                                    */
+plhr_status plhr_batch_workspace_size(int32_t nbatch, const plhr_op_desc* A,
+                                      const plhr_prec_desc* T, const double* sigma, int32_t k,
+                                      const plhr_options* opt, size_t* ws_bytes);
 
 /* Solve every problem from its start block.
  *   V0       host array of nbatch device pointers; V0[b] is n_b x (k +

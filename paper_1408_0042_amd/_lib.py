@@ -115,7 +115,9 @@ def load() -> C.CDLL:
         "plhr_apply": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
         "plhr_op_apply": (C.c_int, [C.POINTER(OpDesc), C.c_double, P, P, C.c_int32, P]),
         "plhr_bloch_prec_create": (C.c_int, [C.POINTER(OpDesc), C.POINTER(PrecDesc), C.c_int32,
-                                             P, C.POINTER(P)]),
+                                             P, P, C.c_size_t, C.POINTER(P)]),
+        "plhr_bloch_prec_workspace_size": (C.c_int, [C.POINTER(OpDesc), C.POINTER(PrecDesc),
+                                                     C.c_int32, C.POINTER(C.c_size_t)]),
         "plhr_bloch_prec_apply": (C.c_int, [P, P, P, C.c_int32]),
         "plhr_bloch_prec_destroy": (None, [P]),
         "plhr_gram_c128_workspace": (C.c_int, [C.c_int64, C.c_int32, C.c_int32,
@@ -138,7 +140,11 @@ def load() -> C.CDLL:
         "plhr_destroy": (None, [P]),
         "plhr_batch_create": (C.c_int, [C.c_int32, C.POINTER(OpDesc), C.POINTER(PrecDesc),
                                         C.POINTER(C.c_double), C.c_int32, C.POINTER(Options), P,
-                                        C.POINTER(P)]),
+                                        P, C.c_size_t, C.POINTER(P)]),
+        "plhr_batch_workspace_size": (C.c_int, [C.c_int32, C.POINTER(OpDesc),
+                                                C.POINTER(PrecDesc), C.POINTER(C.c_double),
+                                                C.c_int32, C.POINTER(Options),
+                                                C.POINTER(C.c_size_t)]),
         "plhr_batch_solve": (C.c_int, [P, C.POINTER(P), P, C.POINTER(P), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "plhr_batch_eigvals_backward": (C.c_int, [P, P, C.POINTER(P), C.c_int32]),

@@ -37,6 +37,7 @@ struct plhr_batch_s {
   std::vector<size_t> ntot_l;  // packed points per level
   // device memory (one allocation)
   char* ws = nullptr;
+  bool own_ws = true;  // false: the caller's workspace
   double *Z = nullptr, *QZ = nullptr, *TQZ = nullptr, *R = nullptr, *QVf = nullptr;
   double *Vfin = nullptr, *QVfin = nullptr;
   std::vector<double*> lx, lt, lr;  // per level, packed, ld 2 kint
@@ -373,16 +374,21 @@ plhr_status finish_b(plhr_batch_s* c) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_prec_desc* T,
+// Validation, layout and set-up of a batch.  With `size_only` it stops after
+// the layout and stores the workspace bytes there (no device call); with a
+// caller `workspace` (at least that many bytes, 256-byte aligned) nothing
+// is allocated on the device.
+plhr_status batch_create_impl(int32_t nbatch, const plhr_op_desc* A, const plhr_prec_desc* T,
                               const double* sigma, int32_t k, const plhr_options* opt,
-                              void* stream, plhr_batch* out) {
-  if (!out || !A || !sigma || nbatch < 1) {
+                              void* stream, void* workspace, size_t ws_bytes,
+                              size_t* size_only, plhr_batch* out) {
+  if ((!out && !size_only) || !A || !sigma || nbatch < 1) {
     set_error("plhr_batch_create: NULL argument or nbatch < 1");
     return PLHR_ERR_ARG;
   }
-  *out = nullptr;
+  if (out) *out = nullptr;
   plhr_options o;
   plhr_options_default(&o);
   if (opt) o = *opt;
@@ -507,7 +513,8 @@ plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_
   const size_t obs = take(NB * sizeof(BatchSmall)), obsF = take(NB * sizeof(BatchSmall));
   const size_t oinv = take(NB * sizeof(double*)), osrc = take(NB * sizeof(double*)),
                odst = take(NB * sizeof(double*)), ovbvp = take(NB * sizeof(double*));
-  // coarse inverses, one per distinct coarsest grid
+  // coarse inverses, one per distinct coarsest grid (the size query only
+  // counts their bytes)
   std::map<std::pair<int, int>, std::vector<double>> invs;
   std::map<std::pair<int, int>, size_t> inv_off;
   if (mg) {
@@ -520,7 +527,9 @@ plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_
       gc.ny = key.second;
       gc.nz = 1;
       std::vector<double> inv;
-      if (!coarse_inverse(gc, inv)) {
+      if (size_only) {
+        inv.assign(gc.n() * gc.n(), 0.0);
+      } else if (!coarse_inverse(gc, inv)) {
         set_error("coarsest multigrid operator is not positive definite");
         delete c;
         return PLHR_ERR_NOT_HPD;
@@ -529,11 +538,28 @@ plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_
       invs[key] = std::move(inv);
     }
   }
-  hipError_t e = hipMalloc((void**)&c->ws, bytes);
-  if (e != hipSuccess) {
-    set_error(std::string("plhr_batch_create: hipMalloc failed: ") + hipGetErrorString(e));
+  if (size_only) {
+    *size_only = bytes;
     delete c;
-    return PLHR_ERR_HIP;
+    return PLHR_OK;
+  }
+  hipError_t e = hipSuccess;
+  if (workspace) {
+    if (ws_bytes < bytes || ((uintptr_t)workspace & 255)) {
+      set_error("plhr_batch_create: the workspace must hold plhr_batch_workspace_size bytes "
+                "and be 256-byte aligned");
+      delete c;
+      return PLHR_ERR_ARG;
+    }
+    c->ws = static_cast<char*>(workspace);
+    c->own_ws = false;
+  } else {
+    e = hipMalloc((void**)&c->ws, bytes);
+    if (e != hipSuccess) {
+      set_error(std::string("plhr_batch_create: hipMalloc failed: ") + hipGetErrorString(e));
+      delete c;
+      return PLHR_ERR_HIP;
+    }
   }
   e = hipHostMalloc((void**)&c->st_host, NB * sizeof(DevStatus), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -686,6 +712,27 @@ plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_
   }
   *out = c;
   return PLHR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+plhr_status plhr_batch_workspace_size(int32_t nbatch, const plhr_op_desc* A,
+                                      const plhr_prec_desc* T, const double* sigma, int32_t k,
+                                      const plhr_options* opt, size_t* ws_bytes) {
+  if (!ws_bytes) {
+    set_error("plhr_batch_workspace_size: ws_bytes is NULL");
+    return PLHR_ERR_ARG;
+  }
+  return batch_create_impl(nbatch, A, T, sigma, k, opt, nullptr, nullptr, 0, ws_bytes, nullptr);
+}
+
+plhr_status plhr_batch_create(int32_t nbatch, const plhr_op_desc* A, const plhr_prec_desc* T,
+                              const double* sigma, int32_t k, const plhr_options* opt,
+                              void* stream, void* workspace, size_t ws_bytes, plhr_batch* out) {
+  return batch_create_impl(nbatch, A, T, sigma, k, opt, stream, workspace, ws_bytes, nullptr,
+                           out);
 }
 
 plhr_status plhr_batch_solve(plhr_batch c, const double* const* V0, double* eigvals,
@@ -872,7 +919,7 @@ void plhr_batch_destroy(plhr_batch c) {
   destroy_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   prof_release(c->prof);
-  if (c->ws) (void)hipFree(c->ws);
+  if (c->ws && c->own_ws) (void)hipFree(c->ws);
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;
 }

@@ -160,15 +160,21 @@ struct plhr_bloch_prec_s {
   }
 };
 
-extern "C" {
+namespace {
 
-plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* T,
-                                   int32_t max_cols, void* stream, plhr_bloch_prec* out) {
-  if (!A || !T || !out) {
+// Validation, hierarchy and buffers of a Bloch V-cycle.  With `size_only`
+// it stops after the layout and stores the device bytes there (no device
+// call); with a caller `workspace` (at least that many bytes, 256-byte
+// aligned) the level buffers and the coarse inverse are carved from it and
+// nothing is allocated on the device.
+plhr_status bloch_prec_create_impl(const plhr_op_desc* A, const plhr_prec_desc* T,
+                                   int32_t max_cols, void* stream, void* workspace,
+                                   size_t ws_bytes, size_t* size_only, plhr_bloch_prec* out) {
+  if (!A || !T || (!out && !size_only)) {
     set_error("plhr_bloch_prec_create: NULL argument");
     return PLHR_ERR_ARG;
   }
-  *out = nullptr;
+  if (out) *out = nullptr;
   if (A->kind != PLHR_OP_BLOCH7_3D || A->dtype != PLHR_C128) {
     set_error("plhr_bloch_prec_create: A must be PLHR_OP_BLOCH7_3D with PLHR_C128");
     return PLHR_ERR_UNSUPPORTED;
@@ -235,8 +241,25 @@ plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* 
     nz /= 2;
     h *= 2.0;
   }
-  // the coarse inverse first (host only), then the device buffers
+  // device bytes: per level x, t (and r below the finest), the inverse
   p->nc = (int)p->lv.back().n();
+  auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t total = 0;
+  for (size_t lev = 0; lev < p->lv.size(); ++lev)
+    total += (lev == 0 ? 2 : 3) * al256(p->lv[lev].n() * (size_t)max_cols * 16);
+  total += al256((size_t)p->nc * p->nc * sizeof(cd));
+  if (size_only) {
+    *size_only = total;
+    delete p;
+    return PLHR_OK;
+  }
+  if (workspace && (ws_bytes < total || ((uintptr_t)workspace & 255))) {
+    delete p;
+    set_error("plhr_bloch_prec_create: the workspace must hold "
+              "plhr_bloch_prec_workspace_size bytes and be 256-byte aligned");
+    return PLHR_ERR_ARG;
+  }
+  // the coarse inverse first (host only), then the device buffers
   std::vector<cd> M;
   bloch_dense(p->lv.back(), p->theta, M);
   if (!hpd_inverse(M, p->nc)) {
@@ -245,7 +268,13 @@ plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* 
               "(all phases 0 leaves the constant vector in its null space)");
     return PLHR_ERR_NOT_HPD;
   }
+  char* wsp = static_cast<char*>(workspace);
   auto alloc = [&](size_t bytes) -> double* {
+    if (wsp) {  // carve from the caller's workspace
+      double* q = reinterpret_cast<double*>(wsp);
+      wsp += al256(bytes);
+      return q;
+    }
     void* q = nullptr;
     const hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) {
@@ -279,6 +308,25 @@ plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* 
   }
   *out = p;
   return PLHR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+plhr_status plhr_bloch_prec_workspace_size(const plhr_op_desc* A, const plhr_prec_desc* T,
+                                           int32_t max_cols, size_t* ws_bytes) {
+  if (!ws_bytes) {
+    set_error("plhr_bloch_prec_workspace_size: ws_bytes is NULL");
+    return PLHR_ERR_ARG;
+  }
+  return bloch_prec_create_impl(A, T, max_cols, nullptr, nullptr, 0, ws_bytes, nullptr);
+}
+
+plhr_status plhr_bloch_prec_create(const plhr_op_desc* A, const plhr_prec_desc* T,
+                                   int32_t max_cols, void* stream, void* workspace,
+                                   size_t ws_bytes, plhr_bloch_prec* out) {
+  return bloch_prec_create_impl(A, T, max_cols, stream, workspace, ws_bytes, nullptr, out);
 }
 
 plhr_status plhr_bloch_prec_apply(plhr_bloch_prec p, const void* X, void* Y, int32_t ncols) {

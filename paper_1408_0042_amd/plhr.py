@@ -414,11 +414,30 @@ class BlochPrecond:
     """One multigrid V-cycle for the Bloch operator scale*(-Laplacian_theta)
     on the periodic nx x ny x nz box (plhr_bloch_prec_*): apply(X) returns
     T X for a complex128 device block (n, ncols), ncols <= max_cols, on
-    torch's current stream at construction."""
+    torch's current stream at construction.  workspace: an optional uint8
+    device tensor of at least workspace_bytes(...) bytes (256-byte aligned)
+    that holds every device buffer of the hierarchy."""
+
+    @staticmethod
+    def workspace_bytes(dims: Sequence[int], h: float = 1.0, thetas=(0.0, 0.0, 0.0),
+                        scale: float = 0.5, levels: int = 3, nu: int = 2,
+                        omega: float = 2.0 / 3.0, max_cols: int = 32) -> int:
+        nx, ny, nz = (tuple(dims) + (1, 1))[:3]
+        d = L.OpDesc()
+        d.kind, d.dtype, d.nx, d.ny, d.nz = L.OP_BLOCH7_3D, L.C128, nx, ny, nz
+        d.h, d.scale = float(h), float(scale)
+        d.theta[0], d.theta[1], d.theta[2] = (float(t) for t in thetas)
+        t = L.PrecDesc()
+        t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = (L.PREC_MG_VCYCLE, int(levels), int(nu),
+                                                           int(nu), float(omega))
+        sz = C.c_size_t()
+        L.check(L.load().plhr_bloch_prec_workspace_size(C.byref(d), C.byref(t), int(max_cols),
+                                                        C.byref(sz)))
+        return int(sz.value)
 
     def __init__(self, dims: Sequence[int], h: float = 1.0, thetas=(0.0, 0.0, 0.0),
                  scale: float = 0.5, levels: int = 3, nu: int = 2, omega: float = 2.0 / 3.0,
-                 max_cols: int = 32):
+                 max_cols: int = 32, workspace: Optional[torch.Tensor] = None):
         self.lib = L.load()
         self.handle = None
         nx, ny, nz = (tuple(dims) + (1, 1))[:3]
@@ -433,8 +452,13 @@ class BlochPrecond:
                                                            int(nu), float(omega))
         hdl = C.c_void_p()
         self.stream = torch.cuda.current_stream()
+        ws, wsb = None, 0
+        if workspace is not None:
+            _require_cuda(workspace, "workspace", torch.uint8)
+            ws, wsb = C.c_void_p(workspace.data_ptr()), workspace.numel()
+            self._ws = workspace
         L.check(self.lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), self.max_cols,
-                                                C.c_void_p(self.stream.cuda_stream),
+                                                C.c_void_p(self.stream.cuda_stream), ws, wsb,
                                                 C.byref(hdl)))
         self.handle = hdl
 
@@ -501,13 +525,17 @@ class BatchResult(NamedTuple):
 class BatchSolver:
     """Many independent 2-D problems scale*(-Laplacian) + diag(potential_b)
     (5-point Dirichlet, spacing h) solved together by plhr_batch_*; each
-    problem has its own grid (dims[b]), potential and shift."""
+    problem has its own grid (dims[b]), potential and shift.  workspace: an
+    optional uint8 device tensor of at least workspace_bytes() bytes
+    (256-byte aligned) that holds every device buffer of the batch;
+    workspace_size=True builds only the size query (no device memory)."""
 
     def __init__(self, dims: Sequence[Sequence[int]], h: float, sigma: Sequence[float], k: int,
                  scale: float = 1.0, potentials: Optional[Sequence[torch.Tensor]] = None,
                  precond: Optional[dict] = None, tol: float = 1e-8, max_iters: int = 10000,
                  k_extra: int = 1, lock: bool = True, check_every: int = 10,
-                 drop_tol: float = 1e-10, stream: Optional[torch.cuda.Stream] = None):
+                 drop_tol: float = 1e-10, stream: Optional[torch.cuda.Stream] = None,
+                 workspace: Optional[torch.Tensor] = None, workspace_size: bool = False):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
@@ -543,11 +571,25 @@ class BatchSolver:
         o.tol, o.max_iters, o.k_extra = float(tol), int(max_iters), int(k_extra)
         o.lock, o.check_every, o.drop_tol = int(bool(lock)), int(check_every), float(drop_tol)
         sig = (C.c_double * self.nb)(*[float(x) for x in sigma])
+        if workspace_size:
+            sz = C.c_size_t()
+            L.check(self.lib.plhr_batch_workspace_size(
+                self.nb, descs, C.byref(t) if t is not None else None, sig, self.k, C.byref(o),
+                C.byref(sz)))
+            self.workspace_bytes = int(sz.value)
+            self.ctx = None
+            return
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = C.c_void_p()
+        ws, wsb = None, 0
+        if workspace is not None:
+            _require_cuda(workspace, "workspace", torch.uint8)
+            ws, wsb = C.c_void_p(workspace.data_ptr()), workspace.numel()
+            self._ws = workspace
         L.check(self.lib.plhr_batch_create(self.nb, descs, C.byref(t) if t is not None else None,
                                            sig, self.k, C.byref(o),
-                                           C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+                                           C.c_void_p(self.stream.cuda_stream), ws, wsb,
+                                           C.byref(ctx)))
         self._descs, self._t = descs, t
         self.ctx = ctx
 

@@ -183,7 +183,8 @@ def test_bloch_preconditioner_arguments_are_validated_on_the_host():
     h = C.c_void_p()
 
     def create(cols=8):
-        return lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), cols, None, C.byref(h))
+        return lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), cols, None, None, 0,
+                                          C.byref(h))
     assert create() == L.ERR_NOT_HPD                     # theta = 0: singular
     d.theta[0], d.theta[1], d.theta[2] = 0.6, 1.2, 1.8
     assert create(0) == L.ERR_ARG                        # max_cols
@@ -326,3 +327,49 @@ def test_plmr_option_is_validated_on_the_host():
     assert code == L.OK and sz >= 3 * n * 4 * 8          # Z, QZ, T(A - lam B)Z
     assert _ws(a, None, 1.0, 3, o)[0] == L.ERR_ARG
     assert b"k must be 1" in L.load().plhr_last_error()
+
+
+def test_batch_and_bloch_workspace_queries_and_checks():
+    """The batch and the Bloch V-cycle take caller workspaces: the size
+    queries need no device, and a workspace that is too small or misaligned
+    is refused before any device call."""
+    lib = L.load()
+    # Bloch V-cycle: levels 16^3, 8^3, 4^3 of 8 complex columns + the
+    # 64 x 64 complex coarse inverse
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz, d.h, d.scale = L.OP_BLOCH7_3D, L.C128, 16, 16, 16, 1.0, 0.5
+    d.theta[0], d.theta[1], d.theta[2] = 0.6, 1.2, 1.8
+    t = L.PrecDesc()
+    t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = L.PREC_MG_VCYCLE, 3, 2, 2, 2 / 3
+    sz = C.c_size_t()
+    assert lib.plhr_bloch_prec_workspace_size(C.byref(d), C.byref(t), 8, C.byref(sz)) == L.OK
+    lev = [16 ** 3, 8 ** 3, 4 ** 3]
+    want = 2 * lev[0] * 8 * 16 + 3 * (lev[1] + lev[2]) * 8 * 16 + 64 * 64 * 16
+    assert sz.value == want
+    h = C.c_void_p()
+    assert lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), 8, None, C.c_void_p(4096),
+                                      sz.value - 1, C.byref(h)) == L.ERR_ARG
+    assert lib.plhr_bloch_prec_create(C.byref(d), C.byref(t), 8, None, C.c_void_p(4096 + 8),
+                                      sz.value, C.byref(h)) == L.ERR_ARG
+    assert lib.plhr_bloch_prec_workspace_size(C.byref(d), C.byref(t), 0, C.byref(sz)) == L.ERR_ARG
+    # batch of two 2-D problems with a 3-level V-cycle
+    descs = (L.OpDesc * 2)()
+    for b, N in enumerate((32, 16)):
+        descs[b].kind, descs[b].dtype, descs[b].nx, descs[b].ny, descs[b].nz = (
+            L.OP_FD5_2D, L.F64, N, N, 1)
+        descs[b].h, descs[b].scale = 1.0, 0.5
+    tb = L.PrecDesc()
+    tb.kind, tb.levels, tb.nu_pre, tb.nu_post, tb.omega = L.PREC_MG_VCYCLE, 3, 2, 2, 2 / 3
+    sig = (C.c_double * 2)(0.1, 0.2)
+    o = L.default_options()
+    assert lib.plhr_batch_workspace_size(2, descs, C.byref(tb), sig, 4, C.byref(o),
+                                         C.byref(sz)) == L.OK
+    n, m, kint = 32 * 32 + 16 * 16, 20, 5
+    assert sz.value >= 3 * n * m * 8                       # Z, QZ, TQZ at least
+    hb = C.c_void_p()
+    assert lib.plhr_batch_create(2, descs, C.byref(tb), sig, 4, C.byref(o), None,
+                                 C.c_void_p(4096), sz.value - 8, C.byref(hb)) == L.ERR_ARG
+    assert lib.plhr_batch_create(2, descs, C.byref(tb), sig, 4, C.byref(o), None,
+                                 C.c_void_p(4096 + 64), sz.value, C.byref(hb)) == L.ERR_ARG
+    assert lib.plhr_batch_workspace_size(2, descs, C.byref(tb), sig, 0, C.byref(o),
+                                         C.byref(sz)) == L.ERR_ARG

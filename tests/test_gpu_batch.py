@@ -84,7 +84,41 @@ def test_batch_matches_brute_force_and_graph_replays_match_eager():
     for r in (r2, r3):
         assert np.array_equal(r.iters, r1.iters)
         assert np.max(np.abs(r.eigvals.cpu().numpy() - lam1) / np.abs(lam1)) <= 1e-14
+    # after the tuning of the first solve the launch configuration is
+    # fixed: eager launches and graph replays are the same arithmetic
+    assert np.array_equal(r2.eigvals.cpu().numpy(), r3.eigvals.cpu().numpy())
     S.close()
+
+
+def test_batch_in_a_caller_workspace():
+    """plhr_batch_create with a caller workspace (no device allocation by
+    the handle) solves the same problems as with its own."""
+    import torch
+    from paper_1408_0042_amd.plhr import BatchSolver
+    probs = _problems([16, 24, 32], 6, 84)
+    k, kx = 4, 5
+    kw = dict(dims=[(N, N) for N, *_ in probs], h=1.0, scale=0.5,
+              sigma=[s for *_, s in probs], k=k, k_extra=kx, tol=1e-11, max_iters=4000,
+              lock=False, precond={"levels": 3, "nu": 2, "omega": 2 / 3}, check_every=10)
+    pots = [torch.from_numpy(p).cuda() for _, p, _, _ in probs]
+    q = BatchSolver(potentials=pots, workspace_size=True, **kw)
+    ws = torch.empty(q.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + q.workspace_bytes]
+    V0 = [torch.from_numpy(wl.start_block(N * N, k + kx, (85, b))).cuda()
+          for b, (N, *_) in enumerate(probs)]
+    S = BatchSolver(potentials=pots, workspace=ws, **kw)
+    r = S.solve(V0)
+    S.close()
+    S0 = BatchSolver(potentials=pots, **kw)
+    r0 = S0.solve(V0)
+    S0.close()
+    assert r.converged and r0.converged
+    lam, lam0 = r.eigvals.cpu().numpy(), r0.eigvals.cpu().numpy()
+    assert np.max(np.abs(lam - lam0) / np.abs(lam0)) <= 1e-12
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        lam_b, _ = dense.nearest_pairs(A, None, sigma, k)
+        assert np.allclose(lam[b], lam_b, rtol=1e-10), b
 
 
 def test_batch_problem_equals_single_solver():

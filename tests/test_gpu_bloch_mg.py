@@ -73,3 +73,25 @@ def test_bloch_vcycle_full_grid_matches_oracle():
     ref = V.apply(X)
     Y = _gpu_T(X, dims, 1.0, 0.5, 5, 2, 2 / 3)
     assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_bloch_vcycle_in_a_caller_workspace_is_bitwise_equal():
+    """With a caller workspace (no device allocation by the handle) the
+    V-cycle is the same arithmetic on the same level sizes: bitwise equal
+    to the one in the library's own buffers."""
+    import torch
+    from paper_1408_0042_amd.plhr import BlochPrecond
+    from tests.gpu_util import dev, host
+    dims, cols = (16, 8, 8), 7
+    kw = dict(thetas=THETAS, levels=3, nu=2, max_cols=cols)
+    nbytes = BlochPrecond.workspace_bytes(dims, **kw)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + nbytes]
+    X = dev(wl.start_block(16 * 8 * 8, cols, (142, 0), dtype=np.complex128))
+    T1 = BlochPrecond(dims, workspace=ws, **kw)
+    T0 = BlochPrecond(dims, **kw)
+    Y1, Y0 = host(T1.apply(X)), host(T0.apply(X))
+    T1.close()
+    T0.close()
+    assert np.array_equal(Y1, Y0)
