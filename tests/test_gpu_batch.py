@@ -174,3 +174,39 @@ def test_batch_backward_matches_dense_gradient_and_finite_differences():
                 pm[x] -= eps
                 fd = (loss_b(pp) - loss_b(pm)) / (2 * eps)
                 assert abs(fd - g_gpu[x]) <= 1e-7 * max(1.0, np.max(np.abs(g_ref)))
+
+
+def test_batch_at_the_batched_sizes_with_five_levels():
+    """Grid sizes 64^2 and 96^2 of the batched set with its 5-level V-cycle
+    (64 -> 4, 96 -> 6) and its shift rule (the 8 lowest states,
+    sigma_b = min V_b - 0.05): every problem's pairs against a
+    shift-invert Lanczos reference (the dense solve is too slow at
+    n = 9216), eigenvalues to 1e-10 and eigenspaces to a sine of 1e-7."""
+    import scipy.sparse.linalg as sla
+    import torch
+    from paper_1408_0042_amd.plhr import BatchSolver
+    k, kx = 8, 4
+    probs = []
+    for b, N in enumerate((64, 96)):
+        pot = wl.gaussian_potential(N, 16, (86, b))
+        A = ops.fd_dirichlet((N, N), 1.0, 0.5, potential=pot)
+        probs.append((N, pot, A, float(pot.min() - 0.05)))
+    S = BatchSolver(dims=[(N, N) for N, *_ in probs], h=1.0, scale=0.5,
+                    sigma=[s for *_, s in probs], k=k, k_extra=kx, tol=1e-11, max_iters=4000,
+                    lock=False, potentials=[torch.from_numpy(p).cuda() for _, p, _, _ in probs],
+                    precond={"levels": 5, "nu": 2, "omega": 2 / 3}, check_every=10)
+    V0 = [torch.from_numpy(wl.start_block(N * N, k + kx, (87, b))).cuda()
+          for b, (N, *_) in enumerate(probs)]
+    r = S.solve(V0)
+    S.close()
+    assert r.converged, (r.status, r.iters)
+    for b, (N, pot, A, sigma) in enumerate(probs):
+        w, X = sla.eigsh(A.tocsc(), k=k + 6, sigma=sigma, which="LM", tol=1e-14)
+        order = np.lexsort((w, np.abs(w - sigma)))
+        ref = np.sort(w[order[:k]])
+        lam = np.sort(r.eigvals[b].cpu().numpy())
+        assert np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10, (b, lam, ref)
+        # the eigenspaces of the k wanted values (the 14 computed cover any
+        # cluster that the k-th value belongs to)
+        sel = np.abs(w[:, None] - ref[None, :]).min(axis=1) <= 1e-9 * np.abs(ref).max()
+        assert dense.subspace_sine(X[:, sel], r.V[b].cpu().numpy()) < 1e-7, b

@@ -31,10 +31,14 @@ def _modes(N, h, values, rtol=1e-8):
     return np.column_stack(cols)
 
 
-def test_bench_workload_full_size():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bench_workload_full_size(precision):
+    """FP64, and the mixed mode (FP32 V-cycles for the search directions)
+    to the same tolerances."""
     import torch
     from oracle import dense
     from paper_1408_0042_amd.plhr import Solver
+    print(f"full size 64^3 precision={precision}", flush=True)
     w = wl.bench_workload(64)
     ev = wl.fd7_closed_form(64, w.h)
     k = w.k
@@ -48,7 +52,7 @@ def test_bench_workload_full_size():
     normA = 12.0 / w.h**2
     tol = 1e-8 * gap / (normA + abs(w.sigma))        # ||r|| <= 1e-8 * gap
     S = Solver(kind="fd7_3d", dims=w.dims, h=w.h, sigma=w.sigma, k=k, k_extra=w.k_extra,
-               tol=tol, max_iters=8000, check_every=20, lock=w.lock,
+               tol=tol, max_iters=8000, check_every=20, lock=w.lock, precision=precision,
                precond={"levels": w.mg_levels, "nu": 2, "omega": 2 / 3})
     V0 = torch.from_numpy(w.v0()).to("cuda")
     r = S.solve(V0)
