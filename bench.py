@@ -59,9 +59,10 @@ def closed_form_3d(N, h):
 
 # HBM traffic per launch of a kernel, from two profiler passes over
 # `bench.py --steps 1 --warmup 0 --no-fd7 --batch 0 --no-spmm
-# --no-cpu-baseline --copy-mib 256`: FETCH_SIZE, then WRITE_SIZE (KiB per
-# dispatch).  Each counter is scaled by what it reads for kernels of known
-# traffic in the same run: a 256 MiB device copy reads 131089 KiB of
+# --no-cpu-baseline --quarter-iters 0 --copy-mib 256`: FETCH_SIZE, then
+# WRITE_SIZE (KiB per dispatch).  Each counter is scaled by what it reads
+# for kernels of known traffic in the same run: a 256 MiB device copy reads
+# 131089 KiB of
 # FETCH_SIZE for 262144 KiB fetched (factor 2.0), a 256 MiB fill 262144 KiB
 # of WRITE_SIZE (factor 1.0).  Keyed on the kernel category and the trial
 # subspace width m; the SHA-256 of the kernel's source when the counters
@@ -70,8 +71,8 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 24): {"source": "paper_1408_0042_amd/csrc/k_tharm_sym.hip",
-                       "sha256": "6ab973a20e4175125e28e1d0c4eb9d8f40cca61a70fb4adcea71e1f8be83c1a5",
-                       "fetch_kib": 18.79, "write_kib": 5.55},
+                       "sha256": "5bd7a3f67c50577dd529e986847ecfffa87a20b35b7377a5133c13b36ecc756c",
+                       "fetch_kib": 18.6248, "write_kib": 5.8302},
 }
 
 

@@ -6,10 +6,15 @@
 // its eigenpairs come from the cyclic Jacobi method (Golub & Van Loan,
 // Sec. 8.5) instead of a Hessenberg reduction and the nonsymmetric QR:
 // each round rotates n/2 disjoint (p, q) planes of a round-robin
-// tournament at once, three barriers per round.  The k_int eigenvectors
-// of smallest |xi| = 1/|tau| (ties: smaller xi) are y = L^-T u, scaled to
-// unit 2-norm with their largest entry positive, in Y' (all columns real,
-// no pairs).  One workgroup; C and the rotations in LDS.
+// tournament at once, two barriers per round; while the first wavefront
+// computes a round's rotations, the other wavefronts apply the previous
+// round's rotations to the eigenvector matrix.  The triangular solves (C
+// from G_R, and y = L^-T u) run right-looking, one barrier per row, all
+// columns at once.
+// The k_int eigenvectors of smallest |xi| = 1/|tau| (ties: smaller xi)
+// are y = L^-T u, scaled to unit 2-norm with their largest entry
+// positive, in Y' (all columns real, no pairs).  One workgroup; C and the
+// rotations in LDS.
 #include <cmath>
 
 #include "common.cuh"
@@ -26,6 +31,52 @@ __device__ __forceinline__ double sym_rcp(double d) {
   r = fma(r, fma(-d, r, 1.0), r);
   r = fma(r, fma(-d, r, 1.0), r);
   return r;
+}
+
+// 1/sqrt(x) from the hardware estimate and two Newton steps
+__device__ __forceinline__ double sym_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
+// Jacobi rotation (c, s) that annihilates a_pq of the 2 x 2 block
+// [[a_pp, a_pq], [a_pq, a_qq]]: an entry negligible against its diagonal
+// (|a_pq| below 1e-18 sqrt|a_pp a_qq|) or below 1e-150 (its square would
+// lose digits) is left alone; otherwise t = tan of the angle from
+// d = a_qq - a_pp, e = 2 a_pq: t = sgn(d) e / (|d| + sqrt(d^2 + e^2)), the
+// smaller root, and c = 1/sqrt(1 + t^2), s = t c.
+__device__ __forceinline__ void sym_rotation(double app, double aqq, double apq, double& c,
+                                             double& sn) {
+  c = 1.0;
+  sn = 0.0;
+  if (fabs(apq) > 1e-150 && apq * apq > 1e-36 * fabs(app * aqq)) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double r2 = fma(d, d, e * e);
+    const double r = r2 * sym_rsq(r2);
+    const double tt = ((d >= 0.0) ? e : -e) * sym_rcp(fabs(d) + r);
+    c = sym_rsq(fma(tt, tt, 1.0));
+    sn = tt * c;
+  }
+}
+
+// Players of pair k in round rnd of the round-robin tournament on ne
+// positions: position 0 holds player 0, position i >= 1 holds player
+// 1 + (i - 1 + rnd) mod (ne - 1); pair k is positions k and ne - 1 - k.
+// Returns (p, q) with p < q, q = -1 for a bye (player >= n).
+__device__ __forceinline__ int2 sym_pair(int k, int rnd, int ne, int n) {
+  int pa = 0;
+  if (k > 0) {
+    pa = k - 1 + rnd;
+    if (pa >= ne - 1) pa -= ne - 1;
+    ++pa;
+  }
+  int pb = ne - 1 - k - 1 + rnd;
+  if (pb >= ne - 1) pb -= ne - 1;
+  ++pb;
+  const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
+  return int2{pp, (qq < n) ? qq : -1};
 }
 
 __device__ double sym_block_sum(double a, double* red) {
@@ -49,8 +100,11 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   __shared__ int dead[kMaxM + 1];
   __shared__ int cnt_s, ndead_s;
   __shared__ double red[kST / 64];
-  __shared__ double csr[kMaxM / 2 + 1], snr[kMaxM / 2 + 1];
-  __shared__ int prs[kMaxM / 2 + 1], qrs[kMaxM / 2 + 1];
+  static_assert(kMaxM / 2 < 64 && kST > 64, "the rotations fit the first wavefront");
+  // rotation tables of the current and the previous round: (c, s) and
+  // (p, q) of each pair (q < 0: a bye)
+  __shared__ double2 rcs[2][kMaxM / 2 + 1];
+  __shared__ int2 rpq[2][kMaxM / 2 + 1];
   const int m = p.m, kint = p.kint, t = threadIdx.x;
   if (t == 0) st->tphase[0] = clock64();
   if (t == 0) {
@@ -137,20 +191,40 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     return;
   }
   if (t == 0) st->tphase[2] = clock64();
-  // C <- L^-1 C (columns, one thread each), then C <- C L^-T (rows)
-  for (int c = t; c < n; c += kST)
-    for (int i = 0; i < n; ++i) {
-      double s = C[i * ld + c];
-      for (int r = 0; r < i; ++r) s -= V[i * ld + r] * C[r * ld + c];
-      C[i * ld + c] = s / V[i * ld + i];
+  // C <- L^-1 C: right-looking forward substitution on unscaled rows
+  // (step r subtracts L[i][r] / L[r][r] times row r from the rows below;
+  // row r is final after step r - 1), then every row scaled by 1 / L[r][r];
+  // C <- C L^-T the same way on columns.  One barrier per step.
+  const float inn = 1.0f / (float)n;  // exact float reciprocal: indices < 2^12
+  for (int r = 0; r + 1 < n; ++r) {
+    const double ir = 1.0 / V[r * ld + r];
+    const int rem = n - r - 1;
+    for (int e = t; e < rem * n; e += kST) {
+      const int q = (int)(((float)e + 0.5f) * inn), c = e - q * n;
+      const int i = r + 1 + q;
+      C[i * ld + c] -= (V[i * ld + r] * ir) * C[r * ld + c];
     }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += kST) {
+    const int i = (int)(((float)e + 0.5f) * inn), c = e - i * n;
+    C[i * ld + c] /= V[i * ld + i];
+  }
   __syncthreads();
-  for (int r = t; r < n; r += kST)
-    for (int i = 0; i < n; ++i) {
-      double s = C[r * ld + i];
-      for (int c = 0; c < i; ++c) s -= V[i * ld + c] * C[r * ld + c];
-      C[r * ld + i] = s / V[i * ld + i];
+  for (int r = 0; r + 1 < n; ++r) {
+    const double ir = 1.0 / V[r * ld + r];
+    const int rem = n - r - 1;
+    for (int e = t; e < rem * n; e += kST) {
+      const int q = (int)(((float)e + 0.5f) * inn), i = e - q * n;
+      const int c = r + 1 + q;
+      C[i * ld + c] -= (V[c * ld + r] * ir) * C[i * ld + r];
     }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += kST) {
+    const int i = (int)(((float)e + 0.5f) * inn), c = e - i * n;
+    C[i * ld + c] /= V[c * ld + c];
+  }
   __syncthreads();
   // L to the work area (compact); C symmetrised; V = I
   for (int e = t; e < n * n; e += kST) {
@@ -176,12 +250,29 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   if (t == 0) st->tphase[3] = clock64();
   const int ne = n + (n & 1), np = ne / 2;
   // exact float reciprocals for the block and row indices (e < 2^12)
-  const float inp = 1.0f / (float)np, inn = 1.0f / (float)n;
+  const float inp = 1.0f / (float)np;
+  // the eigenvector columns of a round's rotations (V <- V J), applied by
+  // the threads t >= np while the next round's rotations are computed
+  auto rotate_vectors = [&](int bb, int t0, int nt) {
+    for (int e = t - t0; e < np * n; e += nt) {
+      const int l = (int)(((float)e + 0.5f) * inn), i = e - l * n;
+      const int2 pq = rpq[bb][l];
+      const int pc = pq.x, qc = pq.y;
+      if (qc < 0) continue;
+      const double2 cs = rcs[bb][l];
+      const double cl = cs.x, sl = cs.y;
+      const double vp = V[i * ld + pc], vq = V[i * ld + qc];
+      V[i * ld + pc] = cl * vp - sl * vq;
+      V[i * ld + qc] = sl * vp + cl * vq;
+    }
+  };
+  int pend = -1;  // table whose vector rotations are still to be applied
+  int cur = 0;
   int sweep = 0;
   for (; sweep < 30; ++sweep) {
     double a2 = 0.0, o2 = 0.0;
     for (int e = t; e < n * n; e += kST) {
-      const int i = e / n, c = e - i * n;
+      const int i = (int)(((float)e + 0.5f) * inn), c = e - i * n;
       const double v = C[i * ld + c];
       if (i == c)
         a2 += v * v;
@@ -194,46 +285,30 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     // eps max(|a_pp|, |a_qq|) behind)
     if (!(o2 > 1e-28 * a2)) break;  // uniform
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
+      // wavefront 0 computes the rotations (np <= 42 lanes), the other
+      // wavefronts apply the previous round's to the eigenvectors
       if (t < np) {
-        // position 0 holds player 0; position i >= 1 player 1 + (i - 1 + rnd) mod (ne - 1)
-        const int i1 = ne - 1 - t;
-        int pa = 0;
-        if (t > 0) {
-          pa = t - 1 + rnd;
-          if (pa >= ne - 1) pa -= ne - 1;
-          ++pa;
-        }
-        int pb = i1 - 1 + rnd;
-        if (pb >= ne - 1) pb -= ne - 1;
-        ++pb;
+        const int2 pq = sym_pair(t, rnd, ne, n);
         double c = 1.0, sn = 0.0;
-        const int pp = (pa < pb) ? pa : pb, qq = (pa < pb) ? pb : pa;
-        if (qq < n) {
-          const double apq = C[pp * ld + qq];
-          const double app = C[pp * ld + pp], aqq = C[qq * ld + qq];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
-            const double th = (aqq - app) * sym_rcp(2.0 * apq);
-            const double tt = copysign(sym_rcp(fabs(th) + sqrt(th * th + 1.0)), th);
-            c = sym_rcp(sqrt(tt * tt + 1.0));
-            sn = tt * c;
-          }
-        }
-        csr[t] = c;
-        snr[t] = sn;
-        prs[t] = pp;
-        qrs[t] = (qq < n) ? qq : -1;
+        if (pq.y >= 0)
+          sym_rotation(C[pq.x * ld + pq.x], C[pq.y * ld + pq.y], C[pq.x * ld + pq.y], c, sn);
+        rcs[cur][t] = double2{c, sn};
+        rpq[cur][t] = pq;
+      } else if (t >= 64 && pend >= 0) {
+        rotate_vectors(pend, 64, kST - 64);
       }
       __syncthreads();
       // C <- J^T C J on the 2 x 2 blocks (rows of pair k, columns of pair
-      // l), which are disjoint, and V <- V J; one phase.  Every load of a
-      // thread's items is issued before the first store.
+      // l), which are disjoint; one phase.  Every load of a thread's items
+      // is issued before the first store.
       {
         double* __restrict__ Cw = C;
-        double* __restrict__ Vw = V;
         for (int e = t; e < np * np; e += kST) {
           const int k = (int)(((float)e + 0.5f) * inp), l = e - k * np;
-          const int pr = prs[k], qr = qrs[k], pc = prs[l], qc = qrs[l];
-          const double ck = csr[k], sk = snr[k], cl = csr[l], sl = snr[l];
+          const int2 pqk = rpq[cur][k], pql = rpq[cur][l];
+          const double2 csk = rcs[cur][k], csl = rcs[cur][l];
+          const int pr = pqk.x, qr = pqk.y, pc = pql.x, qc = pql.y;
+          const double ck = csk.x, sk = csk.y, cl = csl.x, sl = csl.y;
           const int qrr = (qr >= 0) ? qr : pr, qcc = (qc >= 0) ? qc : pc;
           const double a = Cw[pr * ld + pc], bb = Cw[pr * ld + qcc];
           const double cc = Cw[qrr * ld + pc], dd = Cw[qrr * ld + qcc];
@@ -246,20 +321,15 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
           if (qr >= 0) Cw[qr * ld + pc] = cl * c1 - sl * d1;
           if (qr >= 0 && qc >= 0) Cw[qr * ld + qc] = sl * c1 + cl * d1;
         }
-        for (int e = t; e < np * n; e += kST) {
-          const int l = (int)(((float)e + 0.5f) * inn), i = e - l * n;
-          const int pc = prs[l], qc = qrs[l];
-          const double cl = csr[l], sl = snr[l];
-          const int qcc = (qc >= 0) ? qc : pc;
-          const double vp = Vw[i * ld + pc], vq = Vw[i * ld + qcc];
-          if (qc >= 0) {
-            Vw[i * ld + pc] = cl * vp - sl * vq;
-            Vw[i * ld + qc] = sl * vp + cl * vq;
-          }
-        }
       }
       __syncthreads();
+      pend = cur;
+      cur ^= 1;
     }
+  }
+  if (pend >= 0) {  // the last round's vector rotations, all threads
+    rotate_vectors(pend, 0, kST);
+    __syncthreads();
   }
   if (t == 0) {
     st->tphase[4] = clock64();
@@ -306,17 +376,29 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     C[i * ld + c] = b.work[e];
   }
   __syncthreads();
-  // y = L^-T u for the selected eigenvectors, one thread each, written as
-  // column `rank` of V's spare layout: solve L^T y = u from the last row
+  // Y = L^-T U for all eigenvector columns at once: right-looking back
+  // substitution on unscaled rows (step r subtracts L[r][q] / L[r][r]
+  // times row r from the rows q < r; row r is final after step r + 1),
+  // then every row scaled by 1 / L[r][r].  One barrier per step.
+  for (int r = n - 1; r > 0; --r) {
+    const double ir = 1.0 / C[r * ld + r];
+    for (int e = t; e < r * n; e += kST) {
+      const int q = (int)(((float)e + 0.5f) * inn), c = e - q * n;
+      V[q * ld + c] -= (C[r * ld + q] * ir) * V[r * ld + c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += kST) {
+    const int i = (int)(((float)e + 0.5f) * inn), c = e - i * n;
+    V[i * ld + c] /= C[i * ld + i];
+  }
+  __syncthreads();
+  // the selected columns, unit 2-norm, largest entry positive, written as
+  // column `rank` of Y', one thread each
   for (int i = t; i < n; i += kST) {
     const int col = rank[i];
     if (col >= kint) continue;
-    double* u = V + i;  // column i of V, stride ld (overwritten by y)
-    for (int r = n - 1; r >= 0; --r) {
-      double s = u[r * ld];
-      for (int q = r + 1; q < n; ++q) s -= C[q * ld + r] * u[q * ld];
-      u[r * ld] = s / C[r * ld + r];
-    }
+    const double* u = V + i;  // column i of V, stride ld
     double nr2 = 0.0, big = -1.0;
     int im = 0;
     for (int r = 0; r < n; ++r) {
