@@ -122,15 +122,20 @@ def test_avmg_solve_matches_brute_force(dims, levels, nbelow, extraction):
 
 
 def test_graph_replay_is_bitwise_identical_to_eager_launches():
+    """A solve with every iteration replayed from captured HIP graphs is
+    the same arithmetic as eager launches, bit for bit (AV-MG, 30
+    eigenvalues below sigma; the pairs are the closed form's)."""
     dims, h = (32, 32), 1 / 33
     ev = cf.fd_dirichlet_eigs(dims, h)
     sigma = wl.shift_between(ev, 30)
+    ref = np.sort(ev[np.lexsort((ev, np.abs(ev - sigma)))][:4])
     V0 = dev(wl.start_block(1024, 6, (53, 0)))
     out = []
     for g in (False, True):
         S = _solver(kind="fd5_2d", dims=dims, h=h, sigma=sigma, k=4, k_extra=2, tol=1e-10,
-                    max_iters=2000, use_graph=g, precond={"levels": 3, "nu": 2})
+                    max_iters=2000, use_graph=g, precond={"kind": "av", "levels": 3, "nu": 2})
         r = S.solve(V0)
+        assert np.allclose(np.sort(host(r.eigvals)), ref, rtol=1e-10)
         out.append((r.iters, host(r.eigvals).copy(), host(r.V).copy(), r.rel_res.copy()))
         if g:  # a second solve replays the graphs captured by the first
             r2 = S.solve(V0)
