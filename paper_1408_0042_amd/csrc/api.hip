@@ -661,7 +661,7 @@ void orthonormalise(plhr_ctx_s* c, double* const* arrs, int narr, bool recompute
   p2.pass = 2;
   // the single-vector iteration orthonormalises in the complex inner
   // product of its interleaved columns
-  auto ortho = c->sp.cplx ? launch_single_ortho : launch_ortho_small;
+  auto ortho = c->sp.cplx ? launch_cplx_ortho : launch_ortho_small;
   gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
   ortho(p1, b1, st, s);
   transform(c, arrs, narr, st);
@@ -764,7 +764,7 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   // extraction)
   gram(c, tharm ? TQZ : QZ, m, m, QZ, m, m, bst ? BZ : Z, m, 2 * m, c->sb.GLR, st);
   if (c->sp.cplx)
-    launch_single_tharm(c->sp, c->sb, st, s);
+    launch_cplx_tharm(c->sp, c->sb, st, s);
   else if (c->sp.sym)
     launch_tharm_sym(c->sp, c->sb, st, s);
   else
@@ -1108,6 +1108,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->use_mfma = (getenv("PLHR_NO_MFMA") == nullptr);
   hipError_t e = small_set_attributes(c->m, c->kint);
   if (e == hipSuccess) e = tharm_sym_set_attributes();
+  if (e == hipSuccess) e = cplx_set_attributes();
   if (e == hipSuccess) e = mfma_set_attributes(c->m, c->kint);
   if (e != hipSuccess) {
     set_error(std::string("LDS attribute: ") + hipGetErrorString(e));

@@ -463,12 +463,14 @@ void launch_tharm_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStr
 // the cyclic Jacobi method in one workgroup (k_tharm_sym.hip).
 void launch_tharm_sym(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 hipError_t tharm_sym_set_attributes();
-// Single-vector complex iteration (Algorithm 1, k_single.hip): the complex
-// Cholesky-QR of Z = [v w s p] from the real Gram of its 8 real columns
-// (same gating as launch_ortho_small), and the complex 4 x 4 projected
-// problem of eq. (3.5) with the selection of the smallest |xi|.
-void launch_single_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
-void launch_single_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// Complex iterations (Algorithm 1, and Algorithm 2 with k_int complex
+// columns per slot; k_complex_small.hip): the complex Cholesky-QR of
+// Z = [V W S P] from the real Gram of its interleaved columns (same gating
+// as launch_ortho_small), and the complex projected problem of eq. (3.5)
+// with the selection of the k_int smallest |xi|.
+void launch_cplx_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+void launch_cplx_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+hipError_t cplx_set_attributes();
 // PLMR (Section 3.3): from [G_1 | G_2] = (T(A - lam B)Zhat)^T [(A - sigma B)Zhat | B Zhat]
 // the matrix F = Zhat^T (A - lam B) T (A - lam B) Zhat = G_1^T + (sigma - lam) G_2^T,
 // its smallest eigenpair by cyclic Jacobi, Y' = y (m x 1).

@@ -1,0 +1,580 @@
+// Small kernels of the iterations in complex arithmetic: Algorithm 1 (one
+// complex vector) and Algorithm 2 (a block of k_int complex vectors).
+//
+// A complex column is stored as two adjacent real columns (real part,
+// imaginary part), the interleaved layout of a complex128 block, so the
+// trial basis Z = [V W S P] of N = 4 k_int complex columns is a real block
+// of m = 2N columns, and the Gram products, block transforms and updates of
+// the real path act on it unchanged.  The complex Gram products follow from
+// the real ones:
+//     z_a^H Y z_b = G(2a,2b) + G(2a+1,2b+1) + i (G(2a,2b+1) - G(2a+1,2b))
+// for G = Z^T [Y Z] of the interleaved real views (Y real symmetric or the
+// Hermitian operator's interleaved product), and a complex matrix M acting
+// on the columns is the real 2N x 2N matrix with the 2 x 2 blocks
+// [[Re, Im], [-Im, Re]].
+//
+//   k_cplx_ortho   Cholesky of the column-scaled complex Gram in slot order
+//                  with the dropping rule of the real path (a column whose
+//                  pivot is at most drop_tol adds nothing and is left out),
+//                  M = D R^-1 as the real matrix of the interleaved columns;
+//                  the same gate as the real Cholesky-QR for the automatic
+//                  second pass
+//   k_cplx_tharm   eq. (3.5) in complex arithmetic: G_L = L L^H, C = L^-1 G_R
+//                  L^-H, the complex Schur form C = Q T Q^H (Hessenberg by
+//                  Givens rotations, then single-shift QR with Wilkinson
+//                  shifts, Golub & Van Loan Sec. 7.5), the k_int eigenvalues
+//                  tau of largest modulus (xi = 1/tau of smallest modulus,
+//                  ties by (Re xi, -Im xi)), their eigenvectors by back
+//                  substitution in T, y = L^-H Q z of unit 2-norm with the
+//                  largest entry real and positive, and the coefficients Y'
+//                  (2N x 2 k_int real)
+//   k_cplx_final   the final Rayleigh-Ritz step on span(V) in complex
+//                  arithmetic: V^H (A - sigma) V x = theta V^H V x with the
+//                  dropping rule, the k pairs nearest sigma
+//
+// One wavefront per kernel: the loops over rows or columns of a matrix
+// step are spread over the lanes, the steps are separated by barriers
+// (free for a single wavefront).  The matrices are held in LDS.
+#include <cmath>
+
+#include "common.cuh"
+
+namespace plhr {
+
+namespace {
+
+struct cd {
+  double re, im;
+};
+__device__ __forceinline__ cd mk(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd operator*(cd a, cd b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cd cj(cd a) { return {a.re, -a.im}; }
+__device__ __forceinline__ double ab(cd a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ cd dv(cd a, cd b) {  // a / b, scaled against overflow
+  const double s = fmax(fabs(b.re), fabs(b.im));
+  const cd bs = {b.re / s, b.im / s};
+  const double d = bs.re * bs.re + bs.im * bs.im;
+  const cd n = a * cj(bs);
+  return {n.re / (d * s), n.im / (d * s)};
+}
+__device__ cd csqrt_(cd z) {
+  const double r = ab(z);
+  if (r == 0.0) return {0.0, 0.0};
+  const double t = sqrt(0.5 * (r + fabs(z.re)));
+  if (z.re >= 0.0) return {t, z.im / (2.0 * t)};
+  return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+constexpr int kW = 64;          // one wavefront
+constexpr int kMaxN = kMaxM / 2;  // complex columns of the widest basis
+
+// Rotation [[c, s], [-conj(s), c]] (c real) with -conj(s) a + c b = 0.
+__device__ void givens(cd a, cd b, double& c, cd& s) {
+  const double aa = ab(a), bb = ab(b);
+  if (bb == 0.0) {
+    c = 1.0;
+    s = {0.0, 0.0};
+    return;
+  }
+  if (aa == 0.0) {
+    c = 0.0;
+    s = (1.0 / bb) * cj(b);
+    return;
+  }
+  const double r = hypot(aa, bb);
+  c = aa / r;
+  s = (1.0 / (aa * r)) * (a * cj(b));
+}
+
+// Rows p, q of the n x n matrix H (stride ld) from column j0 on, by the lanes.
+__device__ void rot_rows(cd* H, int ld, int n, int j0, int p, int q, double c, cd s) {
+  for (int j = j0 + (int)threadIdx.x; j < n; j += kW) {
+    const cd x = H[p * ld + j], y = H[q * ld + j];
+    H[p * ld + j] = c * x + s * y;
+    H[q * ld + j] = c * y - cj(s) * x;
+  }
+}
+
+// Columns p, q of rows 0..r1-1 of H, and of all n rows of Q, by the lanes
+// (the right product with the rotation's conjugate transpose).
+__device__ void rot_cols(cd* H, cd* Q, int ld, int n, int r1, int p, int q, double c, cd s) {
+  for (int r = threadIdx.x; r < r1; r += kW) {
+    const cd x = H[r * ld + p], y = H[r * ld + q];
+    H[r * ld + p] = c * x + cj(s) * y;
+    H[r * ld + q] = c * y - s * x;
+  }
+  for (int r = threadIdx.x; r < n; r += kW) {
+    const cd u = Q[r * ld + p], v = Q[r * ld + q];
+    Q[r * ld + p] = c * u + cj(s) * v;
+    Q[r * ld + q] = c * v - s * u;
+  }
+}
+
+// Complex Schur form H = Q T Q^H of an n x n matrix (stride ld) in place,
+// by the whole wavefront; every lane keeps the same control flow (all its
+// decisions read the matrix after a barrier).  Returns false when the QR
+// iteration does not converge.
+__device__ bool schur_w(cd* H, cd* Q, int ld, int n) {
+  for (int e = threadIdx.x; e < n * n; e += kW) {
+    const int i = e / n, j = e - i * n;
+    Q[i * ld + j] = mk(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // Hessenberg form by rotations, zeroing column j below the subdiagonal
+  for (int j = 0; j + 2 < n; ++j)
+    for (int i = n - 1; i >= j + 2; --i) {
+      double c;
+      cd s;
+      givens(H[(i - 1) * ld + j], H[i * ld + j], c, s);
+      __syncthreads();
+      rot_rows(H, ld, n, 0, i - 1, i, c, s);
+      __syncthreads();
+      rot_cols(H, Q, ld, n, n, i - 1, i, c, s);
+      __syncthreads();
+      if (threadIdx.x == 0) H[i * ld + j] = mk(0.0, 0.0);
+      __syncthreads();
+    }
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1, its = 0, total = 0;
+  double cs[kMaxN];
+  cd sn[kMaxN];
+  while (hi > 0) {
+    int lo = hi;
+    while (lo > 0) {
+      const double sub = ab(H[lo * ld + lo - 1]);
+      const double dia = ab(H[lo * ld + lo]) + ab(H[(lo - 1) * ld + lo - 1]);
+      if (sub <= eps * dia || sub == 0.0) break;
+      --lo;
+    }
+    __syncthreads();
+    if (lo > 0 && threadIdx.x == 0) H[lo * ld + lo - 1] = mk(0.0, 0.0);
+    if (lo == hi) {
+      __syncthreads();
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (++total > 60 * n) return false;
+    const cd a = H[(hi - 1) * ld + hi - 1], b = H[(hi - 1) * ld + hi];
+    const cd c2 = H[hi * ld + hi - 1], d = H[hi * ld + hi];
+    cd mu;
+    if (its == 10 || its == 20) {
+      mu = d + mk(0.75 * ab(c2), 0.0);
+    } else {
+      const cd half = 0.5 * (a - d);
+      const cd disc = csqrt_(half * half + b * c2);
+      const cd m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
+      mu = (ab(m1 - d) <= ab(m2 - d)) ? m1 : m2;
+    }
+    ++its;
+    __syncthreads();
+    // one explicit-shift QR step on the window [lo, hi]: H - mu I = QR by
+    // rotations from the left, then RQ + mu I
+    for (int k = lo + (int)threadIdx.x; k <= hi; k += kW) H[k * ld + k] = H[k * ld + k] - mu;
+    __syncthreads();
+    for (int k = lo; k < hi; ++k) {
+      givens(H[k * ld + k], H[(k + 1) * ld + k], cs[k], sn[k]);
+      __syncthreads();
+      rot_rows(H, ld, n, k, k, k + 1, cs[k], sn[k]);
+      __syncthreads();
+      if (threadIdx.x == 0) H[(k + 1) * ld + k] = mk(0.0, 0.0);
+      __syncthreads();
+    }
+    for (int k = lo; k < hi; ++k) {
+      rot_cols(H, Q, ld, n, hi + 1, k, k + 1, cs[k], sn[k]);
+      __syncthreads();
+    }
+    for (int k = lo + (int)threadIdx.x; k <= hi; k += kW) H[k * ld + k] = H[k * ld + k] + mu;
+    __syncthreads();
+  }
+  return true;
+}
+
+// ordering of xi = 1/tau: (|xi|, Re xi, -Im xi), tau = 0 last
+__device__ bool xi_before(cd ta, cd tb) {
+  const double aa = ab(ta), bb = ab(tb);
+  if (aa == 0.0 || bb == 0.0) return aa > bb;
+  const double ma = 1.0 / aa, mb = 1.0 / bb;
+  if (ma != mb) return ma < mb;
+  const double ra = ta.re / (aa * aa), rb = tb.re / (bb * bb);
+  if (ra != rb) return ra < rb;
+  const double ia = -ta.im / (aa * aa), ib = -tb.im / (bb * bb);
+  return -ia < -ib;
+}
+
+constexpr double kOrthoRedoC = 1e-4;  // as the real path's Cholesky-QR
+
+// complex Gram entry (a, b) of the interleaved real Gram G (row stride ld)
+__device__ __forceinline__ cd cgram(const double* G, int ld, int a, int b) {
+  const double* r0 = G + (size_t)(2 * a) * ld;
+  const double* r1 = G + (size_t)(2 * a + 1) * ld;
+  return mk(r0[2 * b] + r1[2 * b + 1], r0[2 * b + 1] - r1[2 * b]);
+}
+
+}  // namespace
+
+// ----------------------------------------------------- complex Cholesky-QR
+// LDS: G (N x N, R in its upper triangle) | X (N x N, R^-1)
+__global__ __launch_bounds__(kW) void k_cplx_ortho(SmallParams p, SmallBufs b, DevStatus* st) {
+  if (halted(st)) {
+    if (p.pass == 1 && b.gate && threadIdx.x == 0) b.gate->done = 1;
+    return;
+  }
+  if (p.pass == 2 && b.gate && b.gate->done) return;
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  __shared__ int valid[kMaxN];
+  __shared__ double d[kMaxN];
+  const int m = p.m, N = m / 2, kc = p.kint / 2, t = threadIdx.x;
+  const int ld = N;
+  cd* G = reinterpret_cast<cd*>(smem);
+  cd* X = G + N * ld;
+  const int have_p = st->have_p;
+  for (int a = t; a < N; a += kW) {
+    const int slot = a / kc, col = a - slot * kc;
+    int v = (slot == 0) ? 1 : (slot == 3 ? have_p : b.active[2 * col]);
+    const double g = cgram(b.G, m, a, a).re;
+    if (v && !(g > 0.0 && g < INFINITY)) v = 0;
+    valid[a] = v;
+    d[a] = v ? 1.0 / sqrt(g) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < N * N; e += kW) {
+    const int a = e / N, c = e - a * N;
+    G[a * ld + c] = (valid[a] && valid[c]) ? (d[a] * d[c]) * cgram(b.G, m, a, c) : mk(0.0, 0.0);
+    X[a * ld + c] = mk(a == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // right-looking Cholesky G = R^H R in slot order on the upper triangle;
+  // a numerically dependent column is dropped (the decision is uniform)
+  double minpiv = INFINITY;
+  for (int j = 0; j < N; ++j) {
+    if (!valid[j]) continue;
+    const double piv = G[j * ld + j].re;
+    if (!(piv > p.drop_tol)) {
+      __syncthreads();
+      if (t == 0) valid[j] = 0;
+      __syncthreads();
+      continue;
+    }
+    minpiv = fmin(minpiv, piv);
+    const double r = sqrt(piv), ir = 1.0 / r;
+    __syncthreads();
+    for (int l = j + t; l < N; l += kW) G[j * ld + l] = (l == j) ? mk(r, 0.0) : ir * G[j * ld + l];
+    __syncthreads();
+    const int rem = N - j - 1;
+    for (int e = t; e < rem * rem; e += kW) {
+      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+      if (l >= i) G[i * ld + l] = G[i * ld + l] - cj(G[j * ld + i]) * G[j * ld + l];
+    }
+    __syncthreads();
+  }
+  // rows and columns of dropped or absent columns of R are zero
+  for (int e = t; e < N * N; e += kW) {
+    const int a = e / N, c = e - a * N;
+    if (!(valid[a] && valid[c] && c >= a)) G[a * ld + c] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  // X = R^-1 (upper) by right-looking back substitution on the kept columns
+  for (int i = N - 1; i >= 0; --i) {
+    if (!valid[i]) continue;
+    const double ir = 1.0 / G[i * ld + i].re;
+    for (int c = i + t; c < N; c += kW) X[i * ld + c] = ir * X[i * ld + c];
+    __syncthreads();
+    for (int e = t; e < i * (N - i); e += kW) {
+      const int r = e / (N - i), c = i + e % (N - i);
+      X[r * ld + c] = X[r * ld + c] - G[r * ld + i] * X[i * ld + c];
+    }
+    __syncthreads();
+  }
+  // M = D R^-1 as the real matrix of the interleaved columns
+  for (int e = t; e < N * N; e += kW) {
+    const int a = e / N, c = e - a * N;
+    const bool on = valid[a] && valid[c] && c >= a;
+    const cd v = on ? d[a] * X[a * ld + c] : mk(0.0, 0.0);
+    b.M[(size_t)(2 * a) * m + 2 * c] = v.re;
+    b.M[(size_t)(2 * a) * m + 2 * c + 1] = v.im;
+    b.M[(size_t)(2 * a + 1) * m + 2 * c] = -v.im;
+    b.M[(size_t)(2 * a + 1) * m + 2 * c + 1] = v.re;
+  }
+  for (int a = t; a < N; a += kW) b.keep[2 * a] = b.keep[2 * a + 1] = valid[a];
+  if (t == 0) {
+    int nk = 0, nd = 0, anyv = 0;
+    for (int a = 0; a < N; ++a) {
+      const int slot = a / kc, col = a - slot * kc;
+      nk += valid[a];
+      if (slot == 0) anyv |= valid[a];
+      const int wanted = (slot == 0) ? 1 : (slot == 3 ? have_p : b.active[2 * col]);
+      if (!valid[a] && wanted) ++nd;
+    }
+    st->m_kept = 2 * nk;
+    st->n_dropped = 2 * nd;
+    if (!anyv) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    if (p.pass == 1 && b.gate) {
+      b.gate->error = 0;
+      b.gate->done = (minpiv < kOrthoRedoC) ? 0 : 1;
+    }
+  }
+}
+
+// -------------------------------------------- complex projected problem
+// LDS: GL (-> L) | GR (-> C -> T) | Q | Z (n x kc eigenvectors of T, then
+// y) | ord, idx
+__global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, DevStatus* st) {
+  if (halted(st)) return;
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  __shared__ int idx[kMaxN], dead[kMaxN], ord[kMaxN];
+  __shared__ int n_s, ndead_s, ok_s;
+  const int m = p.m, N = m / 2, kc = p.kint / 2, ld2 = 2 * m, t = threadIdx.x;
+  if (t == 0) {
+    int c = 0;
+    for (int a = 0; a < N; ++a)
+      if (b.keep[2 * a]) idx[c++] = a;
+    n_s = c;
+    ndead_s = 0;
+  }
+  __syncthreads();
+  const int n = n_s, ld = N;
+  if (n < kc) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    return;
+  }
+  cd* L = reinterpret_cast<cd*>(smem);
+  cd* C = L + N * ld;
+  cd* Q = C + N * ld;
+  cd* Zv = Q + N * ld;  // n x kc
+  for (int e = t; e < n * n; e += kW) {
+    const int i = e / n, j = e - i * n;
+    const int a = idx[i], c = idx[j];
+    // Hermitian part of G_L (its lower triangle is what the Cholesky reads)
+    const cd gij = cgram(b.GLR, ld2, a, c), gji = cgram(b.GLR, ld2, c, a);
+    L[i * ld + j] = 0.5 * (gij + cj(gji));
+    const double* r0 = b.GLR + (size_t)(2 * a) * ld2 + m;
+    const double* r1 = b.GLR + (size_t)(2 * a + 1) * ld2 + m;
+    C[i * ld + j] = mk(r0[2 * c] + r1[2 * c + 1], r0[2 * c + 1] - r1[2 * c]);
+  }
+  for (int j = t; j < n; j += kW) dead[j] = 0;
+  __syncthreads();
+  double maxd = 0.0;
+  for (int j = 0; j < n; ++j) maxd = fmax(maxd, L[j * ld + j].re);
+  const double floor_ = fmax(1e-15 * maxd, 1e-300);
+  // G_L = L L^H, right-looking on the lower triangle; pivots as in the real
+  // path (raised to 1e-15 max diag; a clearly negative one leaves its
+  // column out: tau = 0, never selected)
+  for (int j = 0; j < n; ++j) {
+    const double p0 = L[j * ld + j].re;
+    __syncthreads();
+    if (p0 < -1e-10 * maxd) {
+      if (t == 0) {
+        dead[j] = 1;
+        ++ndead_s;
+      }
+      for (int i = j + 1 + t; i < n; i += kW) L[i * ld + j] = mk(0.0, 0.0);
+      __syncthreads();
+      continue;
+    }
+    const double r = sqrt(fmax(p0, floor_)), ir = 1.0 / r;
+    for (int i = j + t; i < n; i += kW) L[i * ld + j] = (i == j) ? mk(r, 0.0) : ir * L[i * ld + j];
+    __syncthreads();
+    const int rem = n - j - 1;
+    for (int e = t; e < rem * rem; e += kW) {
+      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+      if (l <= i) L[i * ld + l] = L[i * ld + l] - L[i * ld + j] * cj(L[l * ld + j]);
+    }
+    __syncthreads();
+  }
+  // L: zero above the diagonal, rows and columns of dead columns e_j; G_R
+  // rows and columns of dead columns zero
+  for (int e = t; e < n * n; e += kW) {
+    const int i = e / n, c = e - i * n;
+    if (dead[i] || dead[c]) {
+      L[i * ld + c] = mk(i == c ? 1.0 : 0.0, 0.0);
+      C[i * ld + c] = mk(0.0, 0.0);
+    } else if (c > i) {
+      L[i * ld + c] = mk(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  if (t == 0 && ndead_s) st->n_excluded += ndead_s;
+  if (ndead_s && n - ndead_s < kc) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonVVanished;
+    }
+    return;
+  }
+  // C <- L^-1 C (rows, unscaled right-looking), then C <- C L^-H (columns)
+  for (int r = 0; r + 1 < n; ++r) {
+    const double ir = 1.0 / L[r * ld + r].re;
+    for (int e = t; e < (n - r - 1) * n; e += kW) {
+      const int i = r + 1 + e / n, c = e % n;
+      C[i * ld + c] = C[i * ld + c] - (ir * L[i * ld + r]) * C[r * ld + c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += kW) {
+    const int i = e / n, c = e - i * n;
+    C[i * ld + c] = (1.0 / L[i * ld + i].re) * C[i * ld + c];
+  }
+  __syncthreads();
+  for (int r = 0; r + 1 < n; ++r) {
+    const double ir = 1.0 / L[r * ld + r].re;
+    for (int e = t; e < (n - r - 1) * n; e += kW) {
+      const int c = r + 1 + e / n, i = e % n;
+      C[i * ld + c] = C[i * ld + c] - (ir * cj(L[c * ld + r])) * C[i * ld + r];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += kW) {
+    const int i = e / n, c = e - i * n;
+    C[i * ld + c] = (1.0 / L[c * ld + c].re) * C[i * ld + c];
+  }
+  __syncthreads();
+  const bool ok = schur_w(C, Q, ld, n);
+  __syncthreads();
+  if (!ok) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonQR;
+    }
+    return;
+  }
+  // eigenvalues in xi order (diagnostics) and the selection
+  if (t == 0) {
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    for (int i = 1; i < n; ++i)
+      for (int j = i; j > 0 && xi_before(C[ord[j] * ld + ord[j]], C[ord[j - 1] * ld + ord[j - 1]]);
+           --j) {
+        const int tmp = ord[j];
+        ord[j] = ord[j - 1];
+        ord[j - 1] = tmp;
+      }
+    ok_s = 1;
+    for (int j = 0; j < kc; ++j)
+      if (!(ab(C[ord[j] * ld + ord[j]]) > 0.0)) ok_s = 0;
+  }
+  __syncthreads();
+  for (int r = t; r < m; r += kW) {
+    b.xi[r] = 0.0;
+    b.xi[m + r] = 0.0;
+  }
+  for (int r = t; r < n; r += kW) {
+    const cd tv = C[ord[r] * ld + ord[r]];
+    const double a2 = tv.re * tv.re + tv.im * tv.im;
+    b.xi[r] = (a2 > 0.0) ? tv.re / a2 : INFINITY;
+    b.xi[m + r] = (a2 > 0.0) ? -tv.im / a2 : 0.0;
+  }
+  if (!ok_s) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonQR;
+    }
+    return;
+  }
+  // eigenvector z of T for each selected tau (z_ks = 1, back substitution),
+  // one lane per eigenvector
+  double cn = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) cn = fmax(cn, ab(C[i * ld + j]));
+  const double small = 2.220446049250313e-16 * fmax(cn, 1e-300);
+  for (int j = t; j < kc; j += kW) {
+    const int ks = ord[j];
+    const cd tau = C[ks * ld + ks];
+    for (int i = 0; i < n; ++i) Zv[i * kc + j] = mk(i == ks ? 1.0 : 0.0, 0.0);
+    for (int i = ks - 1; i >= 0; --i) {
+      cd s = mk(0.0, 0.0);
+      for (int q = i + 1; q <= ks; ++q) s = s + C[i * ld + q] * Zv[q * kc + j];
+      cd den = C[i * ld + i] - tau;
+      if (ab(den) < small) den = mk(small, 0.0);
+      Zv[i * kc + j] = dv(mk(-s.re, -s.im), den);
+    }
+  }
+  __syncthreads();
+  // u = Q z into C's upper region is not free: reuse GL's storage above L?
+  // L is needed below; put u in the T matrix (C), which is not needed any
+  // more, as n x kc
+  for (int e = t; e < n * kc; e += kW) {
+    const int i = e / kc, j = e - i * kc;
+    cd s = mk(0.0, 0.0);
+    for (int q = 0; q < n; ++q) s = s + Q[i * ld + q] * Zv[q * kc + j];
+    C[i * kc + j] = s;  // C is read-only in this loop only through Zv and Q
+  }
+  __syncthreads();
+  // y = L^-H u (one lane per vector), unit 2-norm, largest entry real and
+  // positive, scattered into Y' as real 2 x 2 blocks
+  for (int e = t; e < m * p.kint; e += kW) b.Y[e] = 0.0;
+  __syncthreads();
+  for (int j = t; j < kc; j += kW) {
+    for (int i = n - 1; i >= 0; --i) {
+      cd s = C[i * kc + j];
+      for (int q = i + 1; q < n; ++q) s = s - cj(L[q * ld + i]) * Zv[q * kc + j];
+      Zv[i * kc + j] = (1.0 / L[i * ld + i].re) * s;
+    }
+    double nr2 = 0.0, big = -1.0;
+    int im = 0;
+    for (int i = 0; i < n; ++i) {
+      const cd y = Zv[i * kc + j];
+      const double a2 = y.re * y.re + y.im * y.im;
+      nr2 += a2;
+      if (a2 > big) big = a2, im = i;
+    }
+    const cd ym = Zv[im * kc + j];
+    const double ay = ab(ym);
+    const cd ph = (ay > 0.0) ? mk(ym.re / ay, -ym.im / ay) : mk(1.0, 0.0);
+    const double sc = (nr2 > 0.0) ? 1.0 / sqrt(nr2) : 0.0;
+    const int kint = p.kint;
+    for (int i = 0; i < n; ++i) {
+      const cd v = sc * (Zv[i * kc + j] * ph);
+      const int a = idx[i];
+      b.Y[(size_t)(2 * a) * kint + 2 * j] = v.re;
+      b.Y[(size_t)(2 * a) * kint + 2 * j + 1] = v.im;
+      b.Y[(size_t)(2 * a + 1) * kint + 2 * j] = -v.im;
+      b.Y[(size_t)(2 * a + 1) * kint + 2 * j + 1] = v.re;
+    }
+    b.kinds[2 * j] = 1;
+    b.kinds[2 * j + 1] = 3;
+    b.pair[2 * j] = 2 * j + 1;
+    b.pair[2 * j + 1] = 2 * j;
+  }
+}
+
+static size_t cplx_ortho_lds(int m) {
+  const size_t N = (size_t)m / 2;
+  return 2 * N * N * sizeof(cd);
+}
+static size_t cplx_tharm_lds(int m, int kint) {
+  const size_t N = (size_t)m / 2, kc = (size_t)kint / 2;
+  return (3 * N * N + N * kc) * sizeof(cd);
+}
+
+hipError_t cplx_set_attributes() {
+  hipError_t e = set_lds_limit((const void*)k_cplx_ortho);
+  if (e == hipSuccess) e = set_lds_limit((const void*)k_cplx_tharm);
+  return e;
+}
+
+void launch_cplx_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
+  const double N = p.m / 2.0;
+  prof_begin(KC_ORTHO, (double)p.m * p.m * 8.0, 8.0 * N * N * N / 3.0, s);
+  hipLaunchKernelGGL(k_cplx_ortho, dim3(1), dim3(kW), cplx_ortho_lds(p.m), s, p, b, st);
+  prof_end(KC_ORTHO, s);
+}
+
+void launch_cplx_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
+  const double N = p.m / 2.0;
+  prof_begin(KC_THARM_QR, 2.0 * p.m * p.m * 8.0, 4.0 * 25.0 * N * N * N, s);
+  hipLaunchKernelGGL(k_cplx_tharm, dim3(1), dim3(kW), cplx_tharm_lds(p.m, p.kint), s, p, b, st);
+  prof_end(KC_THARM_QR, s);
+}
+
+}  // namespace plhr
