@@ -138,6 +138,28 @@ plhr_status csr_norm1(const plhr_op_desc* M, const std::vector<double>& pot, dou
   return PLHR_OK;
 }
 
+// ||A||_1 of the Bloch operator: per point |diagonal| plus the moduli of
+// the off-diagonal entries.  A direction with one point folds both
+// neighbours into the diagonal (-2 cs cos theta); with two points both
+// neighbours are the same point, an entry of modulus 2 cs |cos(theta/2)|.
+double bloch_norm1(const plhr_op_desc& A, const std::vector<double>& pot) {
+  const double cs = A.scale / (A.h * A.h);
+  const int N[3] = {A.nx, A.ny, A.nz};
+  double dg = 6.0 * cs, off = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (N[d] == 1)
+      dg -= 2.0 * cs * std::cos(A.theta[d]);
+    else if (N[d] == 2)
+      off += 2.0 * cs * std::fabs(std::cos(0.5 * A.theta[d]));
+    else
+      off += 2.0 * cs;
+  }
+  const size_t n = (size_t)A.nx * A.ny * A.nz;
+  double best = 0.0;
+  for (size_t p = 0; p < n; ++p) best = std::max(best, std::fabs(dg + (pot.empty() ? 0.0 : pot[p])));
+  return best + off;
+}
+
 double exact_norm1(const Grid& g, const std::vector<double>& pot) {
   // max over points of |diag + pot| + (#interior neighbours) * scale / h^2
   const double d = g.diag(), o = -g.off();
@@ -272,6 +294,15 @@ struct plhr_ctx_s {
   hipStream_t cap = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // the complex Bloch operator (Algorithm 2): each complex column is an
+  // interleaved pair of real columns (re, im) of the basis blocks; its
+  // product and its V-cycle take contiguous complex blocks, staged through
+  // Xs and Ys (n x 2 kint real each).  k counts real columns (twice the
+  // pairs returned).
+  bool bloch = false;
+  plhr_op_desc bop{};
+  plhr_bloch_prec bprec = nullptr;
+  double *Xs = nullptr, *Ys = nullptr;
 };
 
 namespace {
@@ -306,11 +337,96 @@ bool uses_mg(const plhr_prec_desc* T) {
 }
 
 // block columns: k + k_extra, the two real columns of the complex vector
-// of the single-vector iteration, or PLMR's one real column
-int block_cols(int32_t k, const plhr_options& o) {
+// of the single-vector iteration, PLMR's one real column, or the real
+// column pairs of k + k_extra complex columns (the Bloch operator)
+int block_cols(const plhr_op_desc* A, int32_t k, const plhr_options& o) {
+  if (A->kind == PLHR_OP_BLOCH7_3D) return 2 * (k + o.k_extra);
   if (o.algorithm == PLHR_ALG_SINGLE) return 2;
   if (o.algorithm == PLHR_ALG_PLMR) return 1;
   return k + o.k_extra;
+}
+
+plhr_status check_options(const plhr_options* opt) {
+  if (opt) {
+    if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
+        !(opt->drop_tol > 0.0) || opt->ortho_passes < 0 || opt->ortho_passes > 2 ||
+        (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED) ||
+        (opt->extraction != PLHR_EXTRACT_T_HARMONIC &&
+         opt->extraction != PLHR_EXTRACT_HARMONIC) ||
+        (opt->use_graph != 0 && opt->use_graph != 1)) {
+      set_error(
+          "invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, "
+          "ortho_passes 0..2, precision FP64 or MIXED, extraction T_HARMONIC or HARMONIC, "
+          "use_graph 0 or 1)");
+      return PLHR_ERR_ARG;
+    }
+  }
+  return PLHR_OK;
+}
+
+// The complex Bloch operator runs the block iteration in complex
+// arithmetic (Algorithm 2) with B = I and T the identity or its V-cycle.
+plhr_status validate_bloch(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
+                           double sigma, int32_t k, const plhr_options* opt) {
+  if (A->dtype != PLHR_C128) {
+    set_error("A: PLHR_OP_BLOCH7_3D needs PLHR_C128");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (A->nx < 1 || A->ny < 1 || A->nz < 1 || !(A->h > 0.0) || !(A->scale > 0.0) ||
+      !std::isfinite(A->h) || !std::isfinite(A->scale) || !std::isfinite(A->theta[0]) ||
+      !std::isfinite(A->theta[1]) || !std::isfinite(A->theta[2])) {
+    set_error("A: need nx, ny, nz >= 1, h and scale positive and finite, theta finite");
+    return PLHR_ERR_ARG;
+  }
+  if (B && B->kind != PLHR_OP_IDENTITY) {
+    set_error("B: the Bloch operator is solved with B = I");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (!std::isfinite(sigma)) {
+    set_error("sigma must be finite");
+    return PLHR_ERR_ARG;
+  }
+  const int kextra = opt ? opt->k_extra : 1;
+  if (k < 1 || kextra < 0) {
+    set_error("k must be >= 1 and k_extra >= 0");
+    return PLHR_ERR_ARG;
+  }
+  if (opt && opt->algorithm != PLHR_ALG_BLOCK) {
+    set_error("the Bloch operator runs the block iteration (PLHR_ALG_BLOCK)");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  const int kc = k + kextra;
+  const size_t n = (size_t)A->nx * A->ny * A->nz;
+  if ((size_t)4 * kc > n) {
+    set_error("4*(k + k_extra) must not exceed n");
+    return PLHR_ERR_ARG;
+  }
+  if (8 * kc > kMaxM) {
+    set_error("8*(k + k_extra) > 84 (complex columns count twice) exceeds the on-chip "
+              "projected-problem limit");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if ((int64_t)A->nx * 4 * kc >= (int64_t(1) << 31) ||
+      (int64_t)A->ny * A->nz >= (int64_t(1) << 31)) {
+    set_error("A: nx*4*(k + k_extra) and ny*nz must be below 2^31");
+    return PLHR_ERR_ARG;
+  }
+  plhr_status st = check_options(opt);
+  if (st != PLHR_OK) return st;
+  if (opt && opt->precision != PLHR_PREC_FP64) {
+    set_error("the Bloch operator runs in FP64 only");
+    return PLHR_ERR_UNSUPPORTED;
+  }
+  if (T && T->kind != PLHR_PREC_IDENTITY) {
+    if (T->kind != PLHR_PREC_MG_VCYCLE) {
+      set_error("T: the Bloch operator takes the identity or PLHR_PREC_MG_VCYCLE");
+      return PLHR_ERR_UNSUPPORTED;
+    }
+    size_t b = 0;
+    st = plhr_bloch_prec_workspace_size(A, T, 2 * kc, &b);
+    if (st != PLHR_OK) return st;
+  }
+  return PLHR_OK;
 }
 
 plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_prec_desc* T,
@@ -319,10 +435,11 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("A descriptor is NULL");
     return PLHR_ERR_ARG;
   }
+  if (A->kind == PLHR_OP_BLOCH7_3D) return validate_bloch(A, B, T, sigma, k, opt);
   if (A->kind != PLHR_OP_FD5_2D && A->kind != PLHR_OP_FD7_3D && A->kind != PLHR_OP_Q1_2D &&
       A->kind != PLHR_OP_Q1_3D && A->kind != PLHR_OP_CSR) {
-    set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D, PLHR_OP_Q1_3D and "
-              "PLHR_OP_CSR are supported (PLHR_OP_BLOCH7_3D: plhr_op_apply only)");
+    set_error("A: only PLHR_OP_FD5_2D, PLHR_OP_FD7_3D, PLHR_OP_Q1_2D, PLHR_OP_Q1_3D, "
+              "PLHR_OP_CSR and PLHR_OP_BLOCH7_3D are supported");
     return PLHR_ERR_UNSUPPORTED;
   }
   const bool acsr = (A->kind == PLHR_OP_CSR);
@@ -410,19 +527,9 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
     set_error("4*(k + k_extra) > 84 exceeds the on-chip projected-problem limit");
     return PLHR_ERR_UNSUPPORTED;
   }
-  if (opt) {
-    if (!(opt->tol > 0.0) || opt->max_iters < 0 || opt->check_every < 1 ||
-        !(opt->drop_tol > 0.0) || opt->ortho_passes < 0 || opt->ortho_passes > 2 ||
-        (opt->precision != PLHR_PREC_FP64 && opt->precision != PLHR_PREC_MIXED) ||
-        (opt->extraction != PLHR_EXTRACT_T_HARMONIC &&
-         opt->extraction != PLHR_EXTRACT_HARMONIC) ||
-        (opt->use_graph != 0 && opt->use_graph != 1)) {
-      set_error(
-          "invalid options (tol > 0, max_iters >= 0, check_every >= 1, drop_tol > 0, "
-          "ortho_passes 0..2, precision FP64 or MIXED, extraction T_HARMONIC or HARMONIC, "
-          "use_graph 0 or 1)");
-      return PLHR_ERR_ARG;
-    }
+  {
+    const plhr_status so = check_options(opt);
+    if (so != PLHR_OK) return so;
   }
   if (T && T->kind == PLHR_PREC_DENSE) {
     if (!T->matrix || ((uintptr_t)T->matrix & 7)) {
@@ -471,8 +578,10 @@ plhr_status validate(const plhr_op_desc* A, const plhr_op_desc* B, const plhr_pr
 }
 
 
+// bloch: the staging blocks Xs, Ys and `bprec_bytes` for the Bloch V-cycle
+// (carved last, 256-byte aligned)
 Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag, bool bst,
-              plhr_ctx_s* c, int mgmode = 0) {
+              plhr_ctx_s* c, int mgmode = 0, bool bloch = false, size_t bprec_bytes = 0) {
   Layout L;
   const size_t n = g.n();
   const int m = 4 * kint;
@@ -505,8 +614,14 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
     oBVf = L.take(n * kint * 8);
     oBVfin = L.take(n * k * 8);
   }
+  size_t oXs = 0, oYs = 0;
+  if (bloch) {
+    oXs = L.take(n * 2 * kint * 8);
+    oYs = L.take(n * 2 * kint * 8);
+  }
   size_t omg = L.bytes;
   if (mgpre) L.bytes += mg_workspace_bytes(g, levels, 2 * kint, mgmode);
+  if (bloch) L.bytes += al(bprec_bytes);
   if (c) {
     char* b = c->ws;
     c->Z = (double*)(b + oZ);
@@ -548,6 +663,10 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
       c->BVf = (double*)(b + oBVf);
       c->BVfin = (double*)(b + oBVfin);
     }
+    if (bloch) {
+      c->Xs = (double*)(b + oXs);
+      c->Ys = (double*)(b + oYs);
+    }
     (void)omg;
   }
   return L;
@@ -557,9 +676,30 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
 
 // (A - shift B)X and its fused outputs; outb (B X) exists only when B is
 // a stencil (the finite-element mass).
+// The Bloch product on interleaved real column pairs: X staged into the
+// contiguous complex block Xs, the product into Ys, then the outputs (the
+// shifted residual form from Ys as launch_resid_prep writes it).
+void bloch_stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr,
+                   const double* colshift, Blk outc, int ncols, double shift,
+                   const DevStatus* st) {
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  const plhr_op_desc& A = c->bop;
+  launch_copy(n, X, ldx, c->Xs, ncols, ncols, s, st);
+  launch_bloch_apply(A.nx, A.ny, A.nz, A.h, A.scale, A.theta, c->pot, shift, c->Xs, c->Ys,
+                     ncols / 2, s);
+  launch_copy(n, c->Ys, ncols, out.ptr, out.ld, ncols, s, st);
+  if (outr.ptr)
+    launch_resid_prep(n, X, ldx, c->Ys, ncols, colshift, c->sigma, outr.ptr, outr.ld, ncols,
+                      nullptr, nullptr, 0, c->part, st, s);
+  if (outc.ptr) launch_copy(n, c->Ys, ncols, outc.ptr, outc.ld, ncols, s, st);
+}
+
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,
              Blk outc, int ncols, double shift, const DevStatus* st, Blk outb = Blk{nullptr, 0}) {
-  if (c->csr)
+  if (c->bloch)
+    bloch_stencil(c, X, ldx, out, outr, colshift, outc, ncols, shift, st);
+  else if (c->csr)
     launch_csr_apply((int)c->n, c->Acsr, c->Bcsr, c->pot, shift, X, ldx, out, outr, colshift,
                      c->sigma, outc, outb, ncols, st, c->stream);
   else if (c->grid.q1)
@@ -576,7 +716,13 @@ void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const d
 // T-harmonic Grams (T(A - sigma B)Z) always use the FP64 V-cycle.
 void precond_raw(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split,
                  int ncols, const DevStatus* st, bool direction) {
-  if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
+  if (c->bprec) {  // the Bloch V-cycle on the staged complex block
+    launch_copy(c->n, Rin, ldr, c->Xs, ncols, ncols, c->stream, st);
+    bloch_prec_cycle(c->bprec, c->Xs, c->Ys, ncols / 2, c->stream);
+    if (split > 0) launch_copy(c->n, c->Ys, ncols, o0.ptr, o0.ld, split, c->stream, st);
+    if (split < ncols)
+      launch_copy(c->n, c->Ys + split, ncols, o1.ptr, o1.ld, ncols - split, c->stream, st);
+  } else if (c->prec_kind == PLHR_PREC_MG_VCYCLE) {
     const bool f32 = direction && c->opt.precision == PLHR_PREC_MIXED;
     mg_apply(c->mg, Rin, ldr, o0, o1, split, ncols, f32, st, c->stream);
   } else if (c->prec_kind == PLHR_PREC_DENSE) {
@@ -659,8 +805,8 @@ void orthonormalise(plhr_ctx_s* c, double* const* arrs, int narr, bool recompute
   b1.gate = c->gate;
   p1.pass = 1;
   p2.pass = 2;
-  // the single-vector iteration orthonormalises in the complex inner
-  // product of its interleaved columns
+  // the complex iterations orthonormalise in the complex inner product of
+  // their interleaved columns
   auto ortho = c->sp.cplx ? launch_cplx_ortho : launch_ortho_small;
   gram(c, Z, m, m, bst ? BZ : Z, m, m, nullptr, 0, m, c->sb.G, st);
   ortho(p1, b1, st, s);
@@ -940,11 +1086,18 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
     set_error("ws_bytes is NULL");
     return PLHR_ERR_ARG;
   }
-  const bool mgp = uses_mg(T);
+  const bool bloch = (A->kind == PLHR_OP_BLOCH7_3D);
+  const bool mgp = !bloch && uses_mg(T);
   const bool bd = B && B->kind == PLHR_OP_DIAG;
   const bool bs = B && (B->kind == PLHR_OP_Q1_MASS || B->kind == PLHR_OP_CSR);
-  Layout L = layout(make_grid(A), k, block_cols(k, o), mgp, mgp ? T->levels : 0, bd, bs, nullptr,
-                    mg_mode(T));
+  const int kint = block_cols(A, k, o);
+  size_t bpb = 0;
+  if (bloch && T && T->kind == PLHR_PREC_MG_VCYCLE) {
+    s = plhr_bloch_prec_workspace_size(A, T, kint, &bpb);
+    if (s != PLHR_OK) return s;
+  }
+  Layout L = layout(make_grid(A), bloch ? 2 * k : k, kint, mgp, mgp ? T->levels : 0, bd, bs,
+                    nullptr, mg_mode(T), bloch, bpb);
   *ws_bytes = L.bytes;
   return PLHR_OK;
 }
@@ -968,13 +1121,24 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->grid = make_grid(A);
   c->pot = A->potential;
   c->sigma = sigma;
-  c->k = k;
-  c->kint = block_cols(k, o);
+  c->bloch = (A->kind == PLHR_OP_BLOCH7_3D);
+  c->bop = *A;
+  c->k = c->bloch ? 2 * k : k;
+  c->kint = block_cols(A, k, o);
   c->m = 4 * c->kint;
   c->opt = o;
   c->n = c->grid.n();
-  const bool mgp = uses_mg(T);
-  c->prec_kind = mgp ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
+  const bool mgp = !c->bloch && uses_mg(T);
+  const bool bmg = c->bloch && T && T->kind == PLHR_PREC_MG_VCYCLE;
+  c->prec_kind = (mgp || bmg) ? PLHR_PREC_MG_VCYCLE : PLHR_PREC_IDENTITY;
+  size_t bpb = 0;
+  if (bmg) {
+    const plhr_status sb = plhr_bloch_prec_workspace_size(A, T, c->kint, &bpb);
+    if (sb != PLHR_OK) {
+      delete c;
+      return sb;
+    }
+  }
   if (T && T->kind == PLHR_PREC_DENSE) {
     c->prec_kind = PLHR_PREC_DENSE;
     c->Tdense = T->matrix;
@@ -986,8 +1150,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   if (c->csr) c->Acsr = CsrMat{A->row_ptr, A->col_idx, A->values, (long long)A->nnz};
   if (B && B->kind == PLHR_OP_CSR)
     c->Bcsr = CsrMat{B->row_ptr, B->col_idx, B->values, (long long)B->nnz};
-  Layout L = layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr,
-                    mg_mode(T));
+  Layout L = layout(c->grid, c->k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, nullptr,
+                    mg_mode(T), c->bloch, bpb);
   if (workspace) {
     if (ws_bytes < L.bytes) {
       set_error("workspace smaller than plhr_workspace_size");
@@ -1011,7 +1175,18 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     c->own_ws = true;
   }
   c->ws_bytes = L.bytes;
-  layout(c->grid, k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, c, mg_mode(T));
+  layout(c->grid, c->k, c->kint, mgp, mgp ? T->levels : 0, bd, c->bst, c, mg_mode(T), c->bloch,
+         bpb);
+  if (bmg) {
+    // the V-cycle's levels and coarse inverse are carved from the end of
+    // the workspace
+    const plhr_status sb = plhr_bloch_prec_create(A, T, c->kint, c->stream,
+                                                  c->ws + L.bytes - al(bpb), al(bpb), &c->bprec);
+    if (sb != PLHR_OK) {
+      plhr_destroy(c);
+      return sb;
+    }
+  }
   // norms for the relative residual
   std::vector<double> pot;
   if (c->pot) {
@@ -1023,7 +1198,7 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
       return PLHR_ERR_HIP;
     }
   }
-  c->normA1 = c->csr ? 0.0 : exact_norm1(c->grid, pot);
+  c->normA1 = c->csr ? 0.0 : (c->bloch ? bloch_norm1(*A, pot) : exact_norm1(c->grid, pot));
   c->normB1 = 1.0;
   if (c->csr) {
     plhr_status e1 = csr_norm1(A, pot, &c->normA1);
@@ -1087,14 +1262,14 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
     }
   }
   c->sp.kint = c->kint;
-  c->sp.k = k;
+  c->sp.k = c->k;
   c->sp.m = c->m;
   c->sp.sigma = sigma;
   c->sp.tol = o.tol;
   c->sp.normA1 = c->normA1;
   c->sp.normB1 = c->normB1;
   c->sp.drop_tol = o.drop_tol;
-  c->sp.cplx = (o.algorithm == PLHR_ALG_SINGLE) ? 1 : 0;
+  c->sp.cplx = c->bloch ? 2 : ((o.algorithm == PLHR_ALG_SINGLE) ? 1 : 0);
   c->sp.plmr = (o.algorithm == PLHR_ALG_PLMR) ? 1 : 0;
   c->sp.lock = (c->sp.cplx || c->sp.plmr) ? 0 : o.lock;
   // G_R of eq. (3.5) is symmetric when T does not enter the projection
@@ -1223,7 +1398,10 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
   const int gnb = c->gram_nblk;
   gram(c, c->Z, m, kint, c->QZ, m, kint, c->bst ? c->BZ : c->Z, m, 2 * kint, c->HM, nullptr);
   (void)gnb;
-  launch_final_rr(c->sp, c->HM, c->sb, c->st, s);
+  if (c->sp.cplx == 2)
+    launch_cplx_final(c->sp, c->HM, c->sb, c->st, s);
+  else
+    launch_final_rr(c->sp, c->HM, c->sb, c->st, s);
   launch_small_gemm(n, c->Z, m, kint, c->sb.final_C, k, c->Vfin, k, s);
   const Blk none{nullptr, 0};
   stencil(c, c->Vfin, k, Blk{c->QVfin, k}, none, nullptr, none, k, c->sigma, nullptr,
@@ -1243,9 +1421,13 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
     launch_colsum_first(c->part, nx, k, c->sb.vbv, s);
     launch_rowscale(n, c->bisq, c->Vfin, k, c->Vfin, k, k, s);
   }
+  // the Bloch operator returns k/2 complex pairs: each value twice in
+  // final_theta and relres, the vectors as interleaved columns (complex128)
+  const int kout = c->bloch ? k / 2 : k, es = c->bloch ? 2 : 1;
   if (eigvals)
-    PLHR_HIP_CHECK(hipMemcpyAsync(eigvals, c->sb.final_theta, k * sizeof(double),
-                                  hipMemcpyDeviceToDevice, s));
+    PLHR_HIP_CHECK(hipMemcpy2DAsync(eigvals, sizeof(double), c->sb.final_theta,
+                                    es * sizeof(double), sizeof(double), kout,
+                                    hipMemcpyDeviceToDevice, s));
   if (V)
     PLHR_HIP_CHECK(hipMemcpyAsync(V, c->Vfin, n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
   std::vector<double> rr(k);
@@ -1254,7 +1436,8 @@ plhr_status plhr_finish(plhr_ctx c, double* eigvals, double* V, double* rel_res)
   PLHR_HIP_CHECK(hipGetLastError());
   plhr_status st = read_status(c);
   if (st != PLHR_OK) return st;
-  if (rel_res) std::memcpy(rel_res, rr.data(), k * sizeof(double));
+  if (rel_res)
+    for (int j = 0; j < kout; ++j) rel_res[j] = rr[(size_t)j * es];
   c->finished = true;
   return device_error(c);
 }
@@ -1286,6 +1469,10 @@ plhr_status plhr_eigvals_backward(plhr_ctx c, const double* dL_dlambda, double* 
     set_error("plhr_eigvals_backward before plhr_finish");
     return PLHR_ERR_STATE;
   }
+  if (c->bloch) {
+    set_error("plhr_eigvals_backward: not available for the Bloch operator");
+    return PLHR_ERR_UNSUPPORTED;
+  }
   launch_hf(c->n, c->Vfin, c->k, c->k, dL_dlambda, c->sb.vbv, dL_dpot, accumulate, c->stream);
   PLHR_HIP_CHECK(hipGetLastError());
   return PLHR_OK;
@@ -1299,6 +1486,10 @@ plhr_status plhr_apply(plhr_ctx c, int32_t which, const double* X, double* Y, in
   }
   if (ncols < 1 || ncols > 2 * c->kint) {
     set_error("plhr_apply: need 1 <= ncols <= 2*(k + k_extra)");
+    return PLHR_ERR_ARG;
+  }
+  if (c->bloch && (ncols & 1)) {
+    set_error("plhr_apply: the Bloch operator takes whole complex columns (even ncols)");
     return PLHR_ERR_ARG;
   }
   const Blk none{nullptr, 0};
@@ -1470,6 +1661,7 @@ void plhr_destroy(plhr_ctx c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->bprec) plhr_bloch_prec_destroy(c->bprec);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;

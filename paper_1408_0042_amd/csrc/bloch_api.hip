@@ -312,6 +312,17 @@ plhr_status bloch_prec_create_impl(const plhr_op_desc* A, const plhr_prec_desc* 
 
 }  // namespace
 
+namespace plhr {
+
+// One V-cycle of the handle on `s` (the solver context runs it on its own
+// stream, or on the stream a graph is being recorded on).
+void bloch_prec_cycle(plhr_bloch_prec p, const double* X, double* Y, int ncols, hipStream_t s) {
+  p->stream = s;
+  p->cycle(0, X, ncols, Y);
+}
+
+}  // namespace plhr
+
 extern "C" {
 
 plhr_status plhr_bloch_prec_workspace_size(const plhr_op_desc* A, const plhr_prec_desc* T,

@@ -165,6 +165,9 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
 void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const double* theta,
                         const double* pot, double shift, const double* X, double* Y, int ncols,
                         hipStream_t s);
+// One V-cycle of a Bloch preconditioner handle on stream s: Y = T X for
+// ncols complex columns (X, Y contiguous n x ncols complex128, no overlap).
+void bloch_prec_cycle(plhr_bloch_prec p, const double* X, double* Y, int ncols, hipStream_t s);
 // Bloch V-cycle pieces (complex128 blocks, n_l x ncols point-major):
 // out = alpha w + beta (r - A_l w) with A_l the level's Bloch stencil of
 // coefficient cs = scale/h_l^2 (w = NULL: w = 0); rc = P^H res / 8 onto the
@@ -357,8 +360,9 @@ struct SmallParams {
   int lock;
   int sym = 0;        // G_R symmetric (T = I or harmonic extraction, B = I)
   int pass = 0;       // Cholesky-QR pass with a gate: 1 first, 2 second; 0 none
-  int cplx = 0;       // single-vector complex iteration (Algorithm 1): kint = 2
-                      // real columns hold one complex vector (re, im)
+  int cplx = 0;       // complex vectors as column pairs (re, im): 1 the
+                      // single-vector iteration (Algorithm 1, kint = 2),
+                      // 2 the complex block iteration (Algorithm 2)
   int plmr = 0;       // PLMR (Section 3.3): kint = 1, refinement extraction
 };
 
@@ -471,6 +475,12 @@ hipError_t tharm_sym_set_attributes();
 void launch_cplx_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 void launch_cplx_tharm(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
 hipError_t cplx_set_attributes();
+// Final Rayleigh-Ritz of the complex block iteration from HM = the real
+// Gram [V^T (A - sigma) V | V^T V] of the interleaved columns of V: the k
+// pairs nearest sigma, final_C (kint x 2k real expansion of the complex
+// coefficients), final_theta (2k, each value twice).
+void launch_cplx_final(const SmallParams& p, const double* HM, SmallBufs b, DevStatus* st,
+                       hipStream_t s);
 // PLMR (Section 3.3): from [G_1 | G_2] = (T(A - lam B)Zhat)^T [(A - sigma B)Zhat | B Zhat]
 // the matrix F = Zhat^T (A - lam B) T (A - lam B) Zhat = G_1^T + (sigma - lam) G_2^T,
 // its smallest eigenpair by cyclic Jacobi, Y' = y (m x 1).

@@ -548,6 +548,182 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
   }
 }
 
+// ------------------------------------------------ final Rayleigh-Ritz
+// V^H (A - sigma) V x = theta V^H V x on the kc = kint/2 complex columns of
+// V: V^H V scaled to unit diagonal and factored with the trial-space
+// dropping rule (a dependent column is left out), C = L^-1 H L^-H, its
+// eigenpairs from the Schur form (C is Hermitian: T is diagonal to rounding
+// and the columns of Q are the eigenvectors), the k values nearest sigma
+// (ties: smaller), x = D L^-H q.  LDS: H (-> C -> T) | L | Q.
+__global__ __launch_bounds__(kW) void k_cplx_final(SmallParams p, const double* __restrict__ HM,
+                                                   SmallBufs b, DevStatus* st) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  __shared__ int keep[kMaxN], ord[kMaxN];
+  __shared__ double dsc[kMaxN];
+  __shared__ int nk_s;
+  const int kint = p.kint, kc = kint / 2, k = p.k / 2, t = threadIdx.x, ld = kc;
+  const int ldh = 2 * kint;  // HM row stride
+  cd* H = reinterpret_cast<cd*>(smem);
+  cd* L = H + kc * ld;
+  cd* Q = L + kc * ld;
+  // when at least k columns met the tolerance, the others (guard columns
+  // still converging) are left out too, as in the real final step
+  if (t == 0) {
+    int cnv = 0;
+    for (int a = 0; a < kc; ++a) cnv += (b.relres[2 * a] <= p.tol) ? 1 : 0;
+    nk_s = cnv;
+  }
+  __syncthreads();
+  for (int a = t; a < kc; a += kW) {
+    const double g = cgram(HM + kint, ldh, a, a).re;
+    const bool excl = nk_s >= k && !(b.relres[2 * a] <= p.tol);
+    keep[a] = (g > 0.0 && g < INFINITY && !excl) ? 1 : 0;
+    dsc[a] = (g > 0.0 && g < INFINITY) ? 1.0 / sqrt(g) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < kc * kc; e += kW) {
+    const int i = e / kc, j = e - i * kc;
+    const double s2 = dsc[i] * dsc[j];
+    H[i * ld + j] = s2 * cgram(HM, ldh, i, j);
+    L[i * ld + j] = s2 * cgram(HM + kint, ldh, i, j);
+  }
+  __syncthreads();
+  // scaled V^H V = L L^H with dropping, right-looking on the lower triangle
+  for (int j = 0; j < kc; ++j) {
+    const double piv = L[j * ld + j].re;
+    const bool drop = !(keep[j] && piv > p.drop_tol);
+    __syncthreads();
+    if (drop) {
+      if (t == 0) keep[j] = 0;
+      for (int i = j + t; i < kc; i += kW) L[i * ld + j] = mk(i == j ? 1.0 : 0.0, 0.0);
+      __syncthreads();
+      continue;
+    }
+    const double r = sqrt(piv), ir = 1.0 / r;
+    for (int i = j + t; i < kc; i += kW) L[i * ld + j] = (i == j) ? mk(r, 0.0) : ir * L[i * ld + j];
+    __syncthreads();
+    const int rem = kc - j - 1;
+    for (int e = t; e < rem * rem; e += kW) {
+      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+      if (l <= i) L[i * ld + l] = L[i * ld + l] - L[i * ld + j] * cj(L[l * ld + j]);
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kc * kc; e += kW) {
+    const int i = e / kc, c = e - i * kc;
+    if (c > i || (!keep[i] && i != c) || (!keep[c] && i != c)) L[i * ld + c] = mk(0.0, 0.0);
+    if (!keep[i] || !keep[c]) H[i * ld + c] = mk(0.0, 0.0);
+  }
+  if (t == 0) {
+    int nk = 0;
+    for (int a = 0; a < kc; ++a) nk += keep[a];
+    nk_s = nk;
+  }
+  __syncthreads();
+  if (nk_s < k) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonFinalGram;
+    }
+    return;
+  }
+  // C = L^-1 H L^-H as in the projected problem
+  for (int r = 0; r + 1 < kc; ++r) {
+    const double ir = 1.0 / L[r * ld + r].re;
+    for (int e = t; e < (kc - r - 1) * kc; e += kW) {
+      const int i = r + 1 + e / kc, c = e % kc;
+      H[i * ld + c] = H[i * ld + c] - (ir * L[i * ld + r]) * H[r * ld + c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kc * kc; e += kW) {
+    const int i = e / kc, c = e - i * kc;
+    H[i * ld + c] = (1.0 / L[i * ld + i].re) * H[i * ld + c];
+  }
+  __syncthreads();
+  for (int r = 0; r + 1 < kc; ++r) {
+    const double ir = 1.0 / L[r * ld + r].re;
+    for (int e = t; e < (kc - r - 1) * kc; e += kW) {
+      const int c = r + 1 + e / kc, i = e % kc;
+      H[i * ld + c] = H[i * ld + c] - (ir * cj(L[c * ld + r])) * H[i * ld + r];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kc * kc; e += kW) {
+    const int i = e / kc, c = e - i * kc;
+    H[i * ld + c] = (1.0 / L[c * ld + c].re) * H[i * ld + c];
+  }
+  __syncthreads();
+  // Hermitian part (rounding), then the Schur form
+  for (int e = t; e < kc * kc; e += kW) {
+    const int i = e / kc, c = e - i * kc;
+    if (c < i) {
+      const cd h = 0.5 * (H[i * ld + c] + cj(H[c * ld + i]));
+      H[i * ld + c] = h;
+      H[c * ld + i] = cj(h);
+    } else if (c == i) {
+      H[i * ld + i] = mk(H[i * ld + i].re, 0.0);
+    }
+  }
+  __syncthreads();
+  const bool ok = schur_w(H, Q, ld, kc);
+  __syncthreads();
+  if (!ok) {
+    if (t == 0) {
+      st->error = PLHR_ERR_BREAKDOWN;
+      st->reason = kReasonQR;
+    }
+    return;
+  }
+  // order by |theta| (theta = lambda - sigma), ties smaller theta; the
+  // eigenvalues of dropped columns (their rows and columns are zero) last
+  if (t == 0) {
+    int c = 0;
+    for (int i = 0; i < kc; ++i) ord[c++] = i;
+    for (int i = 1; i < kc; ++i)
+      for (int j = i; j > 0; --j) {
+        const int a = ord[j], bb = ord[j - 1];
+        const double ta = H[a * ld + a].re, tb = H[bb * ld + bb].re;
+        // a column of Q that lies in the span of dropped columns has a zero
+        // eigenvalue that is not a Ritz value: push it last
+        double wa = 0.0, wb = 0.0;
+        for (int r = 0; r < kc; ++r) {
+          if (keep[r]) continue;
+          wa += ab(Q[r * ld + a]);
+          wb += ab(Q[r * ld + bb]);
+        }
+        const bool da = wa > 0.5, db = wb > 0.5;
+        const bool before = (da != db) ? db : (fabs(ta) < fabs(tb) || (fabs(ta) == fabs(tb) && ta < tb));
+        if (!before) break;
+        ord[j] = bb;
+        ord[j - 1] = a;
+      }
+  }
+  __syncthreads();
+  // x = D L^-H q for the k selected, one lane each; final_C expands it
+  for (int e = t; e < kint * 2 * k; e += kW) b.final_C[e] = 0.0;
+  __syncthreads();
+  for (int j = t; j < k; j += kW) {
+    const int col = ord[j];
+    cd x[kMaxN];
+    for (int i = kc - 1; i >= 0; --i) {
+      cd s = Q[i * ld + col];
+      for (int q = i + 1; q < kc; ++q) s = s - cj(L[q * ld + i]) * x[q];
+      x[i] = (1.0 / L[i * ld + i].re) * s;
+    }
+    for (int i = 0; i < kc; ++i) {
+      const cd v = keep[i] ? dsc[i] * x[i] : mk(0.0, 0.0);
+      b.final_C[(size_t)(2 * i) * (2 * k) + 2 * j] = v.re;
+      b.final_C[(size_t)(2 * i) * (2 * k) + 2 * j + 1] = v.im;
+      b.final_C[(size_t)(2 * i + 1) * (2 * k) + 2 * j] = -v.im;
+      b.final_C[(size_t)(2 * i + 1) * (2 * k) + 2 * j + 1] = v.re;
+    }
+    const double th = p.sigma + H[col * ld + col].re;
+    b.final_theta[2 * j] = th;
+    b.final_theta[2 * j + 1] = th;
+  }
+}
+
 static size_t cplx_ortho_lds(int m) {
   const size_t N = (size_t)m / 2;
   return 2 * N * N * sizeof(cd);
@@ -560,7 +736,14 @@ static size_t cplx_tharm_lds(int m, int kint) {
 hipError_t cplx_set_attributes() {
   hipError_t e = set_lds_limit((const void*)k_cplx_ortho);
   if (e == hipSuccess) e = set_lds_limit((const void*)k_cplx_tharm);
+  if (e == hipSuccess) e = set_lds_limit((const void*)k_cplx_final);
   return e;
+}
+
+void launch_cplx_final(const SmallParams& p, const double* HM, SmallBufs b, DevStatus* st,
+                       hipStream_t s) {
+  const size_t kc = (size_t)p.kint / 2;
+  hipLaunchKernelGGL(k_cplx_final, dim3(1), dim3(kW), 3 * kc * kc * sizeof(cd), s, p, HM, b, st);
 }
 
 void launch_cplx_ortho(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {

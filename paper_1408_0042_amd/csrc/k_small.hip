@@ -78,10 +78,11 @@ __device__ void k_init_lam_body(SmallParams p, const double* __restrict__ part, 
     b.kinds[c] = 0;
     b.pair[c] = -1;
     b.active[c] = 1;
-    if (p.cplx) {  // one complex vector in columns 0 (re) and 1 (im)
-      b.lam[c] = p.sigma + (sums[p.kint] + sums[p.kint + 1]) / (sums[0] + sums[1]);
-      b.kinds[c] = c == 0 ? 1 : 3;
-      b.pair[c] = 1 - c;
+    if (p.cplx) {  // complex vectors: columns 2j (re) and 2j + 1 (im)
+      const int o = c ^ 1;
+      b.lam[c] = p.sigma + (vq + sums[p.kint + o]) / (vv + sums[o]);
+      b.kinds[c] = (c & 1) ? 3 : 1;
+      b.pair[c] = o;
     }
   }
   if (c == 0) {
@@ -112,11 +113,14 @@ __global__ __launch_bounds__(256) void k_init_lam_b(const BatchSmall* __restrict
 // kint, in b.G); a pivot below drop_tol means linearly dependent columns.
 __device__ void k_start_check_body(SmallParams p, SmallBufs b, DevStatus* st) {
   if (threadIdx.x != 0) return;
-  if (p.cplx) {  // the complex start vector must not vanish
-    const double g = b.G[0] + b.G[p.kint + 1];
-    if (!(g > 0.0 && g < INFINITY)) {
-      st->error = PLHR_ERR_BREAKDOWN;
-      st->reason = kReasonStartRank;
+  if (p.cplx) {  // no complex start vector may vanish (the complex
+                 // orthonormalisation drops dependent ones later)
+    for (int j = 0; 2 * j < p.kint; ++j) {
+      const double g = b.G[(2 * j) * p.kint + 2 * j] + b.G[(2 * j + 1) * p.kint + 2 * j + 1];
+      if (!(g > 0.0 && g < INFINITY)) {
+        st->error = PLHR_ERR_BREAKDOWN;
+        st->reason = kReasonStartRank;
+      }
     }
     return;
   }
@@ -175,8 +179,8 @@ __device__ void k_conv_check_body(SmallParams p, const double* __restrict__ part
   if (c < kint) {
     double rr = sums[c], vv = sums[kint + c];
     if (p.cplx) {  // residual and norm of the complex vector
-      rr = sums[0] + sums[1];
-      vv = sums[kint] + sums[kint + 1];
+      rr = sums[c] + sums[c ^ 1];
+      vv = sums[kint + c] + sums[kint + (c ^ 1)];
     }
     const double lam = b.lam[c];
     const double den = (p.normA1 + fabs(lam) * p.normB1) * sqrt(vv);
@@ -195,7 +199,7 @@ __device__ void k_conv_check_body(SmallParams p, const double* __restrict__ part
       const double dq = fabs(lq - p.sigma);
       if (dq < dc || (dq == dc && (lq < lc || (lq == lc && q < c)))) ++rank;
     }
-    rel[64 + c] = (rank < p.k || p.cplx) ? 1.0 : 0.0;  // wanted flag
+    rel[64 + c] = (rank < p.k || p.cplx == 1) ? 1.0 : 0.0;  // wanted flag
     b.active[c] = p.lock ? (rel[c] > p.tol ? 1 : 0) : 1;
   }
   __syncthreads();
@@ -642,7 +646,11 @@ __device__ void k_final_res_body(SmallParams p, const double* __restrict__ part,
   const int c = threadIdx.x, k = p.k;
   sum_partials(part, nblk, 2 * k, sums, red);
   if (c < k) {
-    const double rr = sums[c], vv = sums[k + c];
+    double rr = sums[c], vv = sums[k + c];
+    if (p.cplx == 2) {  // complex Ritz vectors: columns 2j, 2j + 1
+      rr += sums[c ^ 1];
+      vv += sums[k + (c ^ 1)];
+    }
     const double lam = b.final_theta[c];
     b.relres[c] = sqrt(rr) / ((p.normA1 + fabs(lam) * p.normB1) * sqrt(vv));
     b.vbv[c] = vv;

@@ -74,6 +74,12 @@ class Solver:
     kind "csr": a general sparse symmetric A given as csr = (row_ptr int32,
     col_idx int32, values float64) device tensors, dims = (n,); mass may
     then be a CSR triple for B; T must be the identity.
+    kind "bloch7_3d": the complex Hermitian Bloch operator
+    scale (-Laplacian_theta) + diag(potential) on a periodic box with phases
+    `thetas`, solved by the block iteration in complex arithmetic
+    (Algorithm 2); B = I, T the identity or {"levels", "nu", "omega"} for
+    its V-cycle; V0 is an (n, k + k_extra) complex128 tensor and the
+    vectors come back as (n, k) complex128.
     """
 
     def __init__(self, kind: str, dims: Sequence[int], h: float, sigma: float, k: int,
@@ -83,7 +89,8 @@ class Solver:
                  k_extra: int = 1, lock: bool = True, check_every: int = 1,
                  drop_tol: float = 1e-10, precision: str = "fp64", ortho_passes: int = 0,
                  extraction: str = "tharmonic", use_graph: bool = False,
-                 algorithm: str = "block", stream: Optional[torch.cuda.Stream] = None):
+                 algorithm: str = "block", stream: Optional[torch.cuda.Stream] = None,
+                 thetas: Sequence[float] = (0.0, 0.0, 0.0)):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
@@ -105,9 +112,15 @@ class Solver:
             assert len(dims) == 1 and csr is not None
             a.kind, a.nx, a.ny, a.nz = L.OP_CSR, dims[0], 1, 1
             self._csr = _csr_fields(a, csr, dims[0], "csr")
+        elif kind == "bloch7_3d":
+            assert len(dims) == 3
+            a.kind, a.nx, a.ny, a.nz = L.OP_BLOCH7_3D, dims[0], dims[1], dims[2]
+            for d in range(3):
+                a.theta[d] = float(thetas[d])
         else:
             raise ValueError(f"unknown operator kind {kind}")
-        a.dtype = L.F64
+        self.cplx = kind == "bloch7_3d"
+        a.dtype = L.C128 if self.cplx else L.F64
         a.h = float(h)
         a.scale = float(scale)
         self.potential = potential
@@ -143,6 +156,8 @@ class Solver:
         if algorithm not in ("block", "single", "plmr"):
             raise ValueError("algorithm must be 'block', 'single' or 'plmr'")
         self.kint = {"single": 2, "plmr": 1}.get(algorithm, int(k) + int(k_extra))
+        # columns of the start block (complex ones for the Bloch operator)
+        self.kcols = self.kint
         self.sigma = float(sigma)
         t = None
         if precond is not None:
@@ -197,9 +212,13 @@ class Solver:
             pass
 
     def _v0(self, V0: torch.Tensor):
-        _require_cuda(V0, "V0")
-        if tuple(V0.shape) != (self.n, self.kint):
-            raise ValueError(f"V0 must have shape {(self.n, self.kint)}")
+        _require_cuda(V0, "V0", torch.complex128 if self.cplx else torch.float64)
+        if tuple(V0.shape) != (self.n, self.kcols):
+            raise ValueError(f"V0 must have shape {(self.n, self.kcols)}")
+
+    def _vout(self):
+        return torch.empty((self.n, self.k), dtype=torch.complex128 if self.cplx else torch.float64,
+                           device="cuda")
 
     # -- the C ABI, one call each
     def start(self, V0: torch.Tensor):
@@ -214,7 +233,7 @@ class Solver:
 
     def finish(self):
         ev = torch.empty(self.k, dtype=torch.float64, device="cuda")
-        V = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+        V = self._vout()
         rr = (C.c_double * self.k)()
         L.check(self.lib.plhr_finish(self.ctx, C.c_void_p(ev.data_ptr()),
                                      C.c_void_p(V.data_ptr()), rr))
@@ -224,7 +243,7 @@ class Solver:
     def solve(self, V0: torch.Tensor, allow_unconverged: bool = False) -> SolveResult:
         self._v0(V0)
         ev = torch.empty(self.k, dtype=torch.float64, device="cuda")
-        V = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+        V = self._vout()
         rr = (C.c_double * self.k)()
         it = C.c_int32()
         code = self.lib.plhr_solve(self.ctx, C.c_void_p(V0.data_ptr()), C.c_void_p(ev.data_ptr()),
@@ -245,9 +264,11 @@ class Solver:
         return out
 
     def apply(self, which: str, X: torch.Tensor) -> torch.Tensor:
-        _require_cuda(X, "X")
+        _require_cuda(X, "X", torch.complex128 if self.cplx else torch.float64)
         w = {"A": 0, "A-sigma": 1, "T": 2}[which]
         ncols = 1 if X.dim() == 1 else X.shape[1]
+        if self.cplx:
+            ncols *= 2  # real columns of the interleaved view
         Y = torch.empty_like(X)
         L.check(self.lib.plhr_apply(self.ctx, w, C.c_void_p(X.data_ptr()),
                                     C.c_void_p(Y.data_ptr()), int(ncols)))
@@ -272,8 +293,12 @@ class Solver:
         return np.array(buf[:])
 
     def state(self):
-        lam = (C.c_double * self.kint)()
-        V = torch.empty((self.n, self.kint), dtype=torch.float64, device="cuda")
+        """Current Rayleigh quotients (one per real column: each twice, for
+        the complex columns of the Bloch operator) and the block V."""
+        nl = 2 * self.kcols if self.cplx else self.kint
+        lam = (C.c_double * nl)()
+        V = torch.empty((self.n, self.kcols), dtype=torch.complex128 if self.cplx else torch.float64,
+                        device="cuda")
         L.check(self.lib.plhr_get_state(self.ctx, lam, C.c_void_p(V.data_ptr())))
         return np.array(lam[:]), V
 

@@ -140,8 +140,7 @@ def test_csr_descriptors_are_validated_on_the_host():
 
 def test_bloch_op_apply_arguments_are_validated_on_the_host():
     """plhr_op_apply rejects bad descriptors before any launch; an empty
-    block (ncols = 0) is a valid no-op; the solver does not take the
-    complex operator."""
+    block (ncols = 0) is a valid no-op."""
     lib = L.load()
     d = L.OpDesc()
     d.kind, d.dtype, d.nx, d.ny, d.nz, d.h, d.scale = L.OP_BLOCH7_3D, L.C128, 8, 8, 8, 1.0, 0.5
@@ -166,7 +165,6 @@ def test_bloch_op_apply_arguments_are_validated_on_the_host():
     d.dtype = L.F64
     assert lib.plhr_op_apply(C.byref(d), 0.0, X, Y, 4, None) == L.ERR_UNSUPPORTED
     d.dtype = L.C128
-    assert _ws_b(d, None)[0] == L.ERR_UNSUPPORTED       # Algorithm 3 is real
     f = _fd3(8)
     assert lib.plhr_op_apply(C.byref(f), 0.0, X, Y, 4, None) == L.ERR_UNSUPPORTED
 
@@ -373,3 +371,41 @@ def test_batch_and_bloch_workspace_queries_and_checks():
                                  C.c_void_p(4096 + 64), sz.value, C.byref(hb)) == L.ERR_ARG
     assert lib.plhr_batch_workspace_size(2, descs, C.byref(tb), sig, 0, C.byref(o),
                                          C.byref(sz)) == L.ERR_ARG
+
+
+def test_bloch_solver_options_are_validated_on_the_host():
+    """The solver takes the Bloch operator (the block iteration in complex
+    arithmetic): B = I, T the identity or its V-cycle, FP64, the block
+    algorithm, 8 (k + k_extra) <= 84; the workspace query makes no device
+    call and grows with the V-cycle's levels."""
+    d = L.OpDesc()
+    d.kind, d.dtype, d.nx, d.ny, d.nz, d.h, d.scale = L.OP_BLOCH7_3D, L.C128, 8, 8, 8, 1.0, 0.5
+    d.theta[0], d.theta[1], d.theta[2] = 0.6, 1.2, 1.8
+    code, sz0 = _ws_b(d, None, k=3)
+    assert code == L.OK
+    n, kint = 512, 2 * 4
+    assert sz0 >= 3 * n * 4 * kint * 8 + 2 * n * 2 * kint * 8   # Z, QZ, TQZ, staging
+    t = L.PrecDesc()
+    t.kind, t.levels, t.nu_pre, t.nu_post, t.omega = L.PREC_MG_VCYCLE, 3, 2, 2, 2 / 3
+    code, sz1 = _ws(d, t, 0.0, 3)
+    assert code == L.OK and sz1 > sz0
+    t.levels = 5                                   # 8 not divisible by 2^4
+    assert _ws(d, t, 0.0, 3)[0] == L.ERR_ARG
+    t.levels, t.kind = 3, L.PREC_AV_MG
+    assert _ws(d, t, 0.0, 3)[0] == L.ERR_UNSUPPORTED
+    assert b"identity or PLHR_PREC_MG_VCYCLE" in L.load().plhr_last_error()
+    assert _ws_b(d, None, k=9)[0] == L.OK              # 8 * 10 = 80
+    assert _ws_b(d, None, k=10)[0] == L.ERR_UNSUPPORTED   # 8 * 11 > 84
+    assert b"8*(k + k_extra)" in L.load().plhr_last_error()
+    o = L.default_options()
+    o.precision = L.PRECISION_MIXED
+    assert _ws_b(d, None, k=3, o=o)[0] == L.ERR_UNSUPPORTED
+    o = L.default_options()
+    o.algorithm = L.ALG_SINGLE
+    assert _ws_b(d, None, k=1, o=o)[0] == L.ERR_UNSUPPORTED
+    b = L.OpDesc()
+    b.kind, b.dtype, b.nx, b.ny, b.nz = L.OP_DIAG, L.F64, 8, 8, 8
+    b.potential = 4096
+    assert _ws_b(d, b, k=3)[0] == L.ERR_UNSUPPORTED
+    d.dtype = L.F64
+    assert _ws_b(d, None, k=3)[0] == L.ERR_UNSUPPORTED
