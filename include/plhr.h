@@ -59,7 +59,8 @@ typedef enum {
   PLHR_OP_Q1_MASS = 6, /* consistent mass M of the Q1 elements of A (B only) */
   PLHR_OP_CSR = 7,     /* general sparse symmetric matrix (CSR), A or B     */
   PLHR_OP_BLOCH7_3D = 8 /* scale*(-Laplacian_theta) 7-point, Bloch-periodic,
-                           complex, + diag(V): plhr_op_apply only          */
+                           complex Hermitian, + diag(V): the solver
+                           (Algorithm 2) and plhr_op_apply                */
 } plhr_op_kind;
 
 typedef enum {
@@ -187,8 +188,9 @@ typedef enum { PLHR_PREC_FP64 = 0, PLHR_PREC_MIXED = 1 } plhr_precision;
  * standard harmonic Rayleigh-Ritz of the "harm." rows of Section 6.2.    */
 typedef enum { PLHR_EXTRACT_T_HARMONIC = 0, PLHR_EXTRACT_HARMONIC = 1 } plhr_extraction;
 
-/* Iteration.  PLHR_ALG_BLOCK is the block method in real arithmetic
- * (Algorithm 3).  PLHR_ALG_SINGLE is the single-vector method (Algorithm
+/* Iteration.  PLHR_ALG_BLOCK is the block method: in real arithmetic
+ * (Algorithm 3) for the real operators, in complex arithmetic (Algorithm
+ * 2) for PLHR_OP_BLOCH7_3D.  PLHR_ALG_SINGLE is the single-vector method (Algorithm
  * 1, k = 1) in complex arithmetic, as Section 3.2 prescribes even for real
  * A and B since the projected problem can have complex eigenpairs: the
  * iterate v, the directions w, s, p and their products are complex
@@ -290,9 +292,10 @@ plhr_status plhr_workspace_size(const plhr_op_desc* A, const plhr_op_desc* B,
                                 const plhr_options* opt, size_t* ws_bytes);
 
 /* Create a solver for the k eigenpairs of A v = lambda B v nearest sigma
- * (Algorithm 3 for these real operators; Algorithm 1 with
- * PLHR_ALG_SINGLE).
- *   A          host descriptor of A (FD5_2D, FD7_3D, Q1_2D, Q1_3D or CSR)
+ * (Algorithm 3 for the real operators; Algorithm 1 with PLHR_ALG_SINGLE;
+ * Algorithm 2 for PLHR_OP_BLOCH7_3D, see above plhr_op_apply's block).
+ *   A          host descriptor of A (FD5_2D, FD7_3D, Q1_2D, Q1_3D, CSR or
+ *              BLOCH7_3D)
  *   B          host descriptor of B: NULL or PLHR_OP_IDENTITY for the
  *              identity, PLHR_OP_DIAG for a positive diagonal B with a
  *              finite-difference A (the diagonal is read once at create
@@ -319,7 +322,8 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B,
 /* Algorithm 3, steps 1-2: load the start block and B-normalise it.
  *   V0   device, n x (k + k_extra) doubles, point-major (n x 2 with
  *        PLHR_ALG_SINGLE: real and imaginary parts; n x 1 with
- *        PLHR_ALG_PLMR); copied.                                         */
+ *        PLHR_ALG_PLMR; n x (k + k_extra) complex128 for the Bloch
+ *        operator); copied.                                              */
 plhr_status plhr_start(plhr_ctx ctx, const double* V0);
 
 /* Run up to n_steps iterations of the while-loop of Algorithm 3, stopping
@@ -379,11 +383,34 @@ plhr_status plhr_apply(plhr_ctx ctx, int32_t which, const double* X, double* Y, 
  *              stream).  Asynchronous: returns after the launch.
  * PLHR_ERR_ARG for a NULL or invalid argument, PLHR_ERR_UNSUPPORTED for
  * any other operator kind or dtype (the real operators are applied
- * through a context, plhr_apply), PLHR_ERR_HIP if the launch fails.
- * plhr_create rejects PLHR_OP_BLOCH7_3D (PLHR_ERR_UNSUPPORTED): the
- * solver runs Algorithm 3, in real arithmetic.                          */
+ * through a context, plhr_apply), PLHR_ERR_HIP if the launch fails.     */
 plhr_status plhr_op_apply(const plhr_op_desc* A, double shift, const void* X, void* Y,
                           int32_t ncols, void* stream);
+
+/* The complex Hermitian Bloch operator in the solver (Algorithm 2, the
+ * block iteration in complex arithmetic).  plhr_workspace_size /
+ * plhr_create take A = PLHR_OP_BLOCH7_3D with dtype PLHR_C128 (phases in
+ * theta, real potential or NULL) with
+ *   B   NULL or PLHR_OP_IDENTITY (otherwise PLHR_ERR_UNSUPPORTED)
+ *   T   NULL, PLHR_PREC_IDENTITY or PLHR_PREC_MG_VCYCLE: the Bloch V-cycle
+ *       of plhr_bloch_prec_create (its rules on levels and the coarsest
+ *       grid apply; its levels and coarse inverse live in the context's
+ *       workspace); any other kind is PLHR_ERR_UNSUPPORTED
+ *   opt algorithm PLHR_ALG_BLOCK, precision PLHR_PREC_FP64; lock is
+ *       ignored (no soft locking); 8 (k + k_extra) <= 84, since each of
+ *       the k + k_extra complex columns of the four slots counts as two
+ *       real columns of the on-chip projected problem.
+ * Blocks are complex128, interleaved, point-major: V0 of plhr_start /
+ * plhr_solve is n x (k + k_extra) complex (2 n (k + k_extra) doubles),
+ * V of plhr_finish / plhr_solve n x k complex; eigvals and rel_res hold
+ * k values.  plhr_get_state returns 2 (k + k_extra) Rayleigh quotients
+ * (each complex column's value twice) and the n x (k + k_extra) complex
+ * block; plhr_apply takes n x ncols/2 complex columns (ncols even).
+ * plhr_eigvals_backward returns PLHR_ERR_UNSUPPORTED.  The complex
+ * columns run through the Gram, Cholesky-QR and update kernels as pairs
+ * of real columns (real, imaginary part); the orthonormalisation, the
+ * projected problem of eq. (3.5) and the final Rayleigh-Ritz step are
+ * solved in complex arithmetic.                                          */
 
 /* Multigrid preconditioner of the complex Bloch operator (Section 5: T
  * Hermitian positive definite; Appendix A's V-cycle on the Laplacian part
