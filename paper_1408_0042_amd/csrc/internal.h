@@ -302,6 +302,11 @@ void launch_hf(size_t n, const double* V, int ldv, int k, const double* dl, cons
 // Up to four arrays processed by one row-product launch.
 struct ArrPtrs {
   double* a[4];
+  // element i by selects, not a dynamic index (which would copy the
+  // by-value struct into scratch memory)
+  __device__ __forceinline__ double* at(int i) const {
+    return (i == 0) ? a[0] : (i == 1) ? a[1] : (i == 2) ? a[2] : a[3];
+  }
 };
 
 // Matrix-core versions (k_mfma.hip); *_ok tells whether the shape fits.

@@ -293,7 +293,7 @@ __global__ void k_rowmul(size_t n, ArrPtrs arrs, int narr, int ld, int m, const 
     const size_t p0 = tile * kRB;
     const int nr = (n - p0 < (size_t)kRB) ? (int)(n - p0) : kRB;
     for (int a = 0; a < narr; ++a) {
-      double* X = arrs.a[a];
+      double* X = arrs.at(a);
       __syncthreads();
       for (int e = threadIdx.x; e < kRB * m; e += nthr) {
         const int r = e / m, c = e - r * m;

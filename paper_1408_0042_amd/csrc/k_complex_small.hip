@@ -73,22 +73,37 @@ __device__ cd csqrt_(cd z) {
 constexpr int kW = 64;          // one wavefront
 constexpr int kMaxN = kMaxM / 2;  // complex columns of the widest basis
 
-// Rotation [[c, s], [-conj(s), c]] (c real) with -conj(s) a + c b = 0.
+// 1/sqrt(x) from the hardware estimate and two Newton steps
+__device__ __forceinline__ double crsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
+// |re| + |im|: the modulus surrogate of the deflation tests
+__device__ __forceinline__ double ab1(cd a) { return fabs(a.re) + fabs(a.im); }
+
+// Rotation [[c, s], [-conj(s), c]] (c real) with -conj(s) a + c b = 0:
+// c = |a| / r, s = (a / |a|) conj(b) / r, r = sqrt(|a|^2 + |b|^2), from
+// squared moduli and reciprocal square roots (the entries are far from
+// the overflow and underflow thresholds of their squares).
 __device__ void givens(cd a, cd b, double& c, cd& s) {
-  const double aa = ab(a), bb = ab(b);
-  if (bb == 0.0) {
+  const double bb2 = b.re * b.re + b.im * b.im;
+  if (bb2 == 0.0) {
     c = 1.0;
     s = {0.0, 0.0};
     return;
   }
-  if (aa == 0.0) {
+  const double aa2 = a.re * a.re + a.im * a.im;
+  if (aa2 == 0.0) {
     c = 0.0;
-    s = (1.0 / bb) * cj(b);
+    s = crsq(bb2) * cj(b);
     return;
   }
-  const double r = hypot(aa, bb);
-  c = aa / r;
-  s = (1.0 / (aa * r)) * (a * cj(b));
+  const double ia = crsq(aa2), ir = crsq(aa2 + bb2);
+  c = aa2 * ia * ir;
+  s = (ia * ir) * (a * cj(b));
 }
 
 // Rows p, q of the n x n matrix H (stride ld) from column j0 on, by the lanes.
@@ -118,8 +133,9 @@ __device__ void rot_cols(cd* H, cd* Q, int ld, int n, int r1, int p, int q, doub
 // Complex Schur form H = Q T Q^H of an n x n matrix (stride ld) in place,
 // by the whole wavefront; every lane keeps the same control flow (all its
 // decisions read the matrix after a barrier).  Returns false when the QR
-// iteration does not converge.
-__device__ bool schur_w(cd* H, cd* Q, int ld, int n) {
+// iteration does not converge.  `stamp` (may be null) takes the shader
+// clock after the Hessenberg reduction.
+__device__ bool schur_w(cd* H, cd* Q, int ld, int n, long long* stamp = nullptr) {
   for (int e = threadIdx.x; e < n * n; e += kW) {
     const int i = e / n, j = e - i * n;
     Q[i * ld + j] = mk(i == j ? 1.0 : 0.0, 0.0);
@@ -139,15 +155,18 @@ __device__ bool schur_w(cd* H, cd* Q, int ld, int n) {
       if (threadIdx.x == 0) H[i * ld + j] = mk(0.0, 0.0);
       __syncthreads();
     }
+  if (stamp && threadIdx.x == 0) *stamp = clock64();
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, its = 0, total = 0;
-  double cs[kMaxN];
-  cd sn[kMaxN];
+  // a step's rotations, kept for its right-hand sweep (LDS, not per-lane
+  // arrays: those would be indexed dynamically and live in scratch)
+  __shared__ double cs[kMaxN];
+  __shared__ cd sn[kMaxN];
   while (hi > 0) {
     int lo = hi;
-    while (lo > 0) {
-      const double sub = ab(H[lo * ld + lo - 1]);
-      const double dia = ab(H[lo * ld + lo]) + ab(H[(lo - 1) * ld + lo - 1]);
+    while (lo > 0) {  // deflation test with |re| + |im| moduli
+      const double sub = ab1(H[lo * ld + lo - 1]);
+      const double dia = ab1(H[lo * ld + lo]) + ab1(H[(lo - 1) * ld + lo - 1]);
       if (sub <= eps * dia || sub == 0.0) break;
       --lo;
     }
@@ -178,9 +197,15 @@ __device__ bool schur_w(cd* H, cd* Q, int ld, int n) {
     for (int k = lo + (int)threadIdx.x; k <= hi; k += kW) H[k * ld + k] = H[k * ld + k] - mu;
     __syncthreads();
     for (int k = lo; k < hi; ++k) {
-      givens(H[k * ld + k], H[(k + 1) * ld + k], cs[k], sn[k]);
+      double c;
+      cd sk;
+      givens(H[k * ld + k], H[(k + 1) * ld + k], c, sk);
+      if (threadIdx.x == 0) {
+        cs[k] = c;
+        sn[k] = sk;
+      }
       __syncthreads();
-      rot_rows(H, ld, n, k, k, k + 1, cs[k], sn[k]);
+      rot_rows(H, ld, n, k, k, k + 1, c, sk);
       __syncthreads();
       if (threadIdx.x == 0) H[(k + 1) * ld + k] = mk(0.0, 0.0);
       __syncthreads();
@@ -329,6 +354,7 @@ __global__ __launch_bounds__(kW) void k_cplx_ortho(SmallParams p, SmallBufs b, D
 // y) | ord, idx
 __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, DevStatus* st) {
   if (halted(st)) return;
+  if (threadIdx.x == 0) st->tphase[0] = clock64();
   extern __shared__ __attribute__((aligned(16))) double smem[];
   __shared__ int idx[kMaxN], dead[kMaxN], ord[kMaxN];
   __shared__ int n_s, ndead_s, ok_s;
@@ -413,6 +439,7 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     }
     return;
   }
+  if (t == 0) st->tphase[1] = clock64();
   // C <- L^-1 C (rows, unscaled right-looking), then C <- C L^-H (columns)
   for (int r = 0; r + 1 < n; ++r) {
     const double ir = 1.0 / L[r * ld + r].re;
@@ -440,7 +467,9 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     C[i * ld + c] = (1.0 / L[c * ld + c].re) * C[i * ld + c];
   }
   __syncthreads();
-  const bool ok = schur_w(C, Q, ld, n);
+  if (t == 0) st->tphase[2] = clock64();
+  const bool ok = schur_w(C, Q, ld, n, &st->tphase[3]);
+  if (t == 0) st->tphase[4] = clock64();
   __syncthreads();
   if (!ok) {
     if (t == 0) {
@@ -500,16 +529,15 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     }
   }
   __syncthreads();
-  // u = Q z into C's upper region is not free: reuse GL's storage above L?
-  // L is needed below; put u in the T matrix (C), which is not needed any
-  // more, as n x kc
+  // u = Q z, n x kc, stored in the region of T (no longer read)
   for (int e = t; e < n * kc; e += kW) {
     const int i = e / kc, j = e - i * kc;
     cd s = mk(0.0, 0.0);
     for (int q = 0; q < n; ++q) s = s + Q[i * ld + q] * Zv[q * kc + j];
-    C[i * kc + j] = s;  // C is read-only in this loop only through Zv and Q
+    C[i * kc + j] = s;
   }
   __syncthreads();
+  if (t == 0) st->tphase[5] = clock64();
   // y = L^-H u (one lane per vector), unit 2-norm, largest entry real and
   // positive, scattered into Y' as real 2 x 2 blocks
   for (int e = t; e < m * p.kint; e += kW) b.Y[e] = 0.0;
@@ -546,6 +574,8 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     b.pair[2 * j] = 2 * j + 1;
     b.pair[2 * j + 1] = 2 * j;
   }
+  __syncthreads();
+  if (t == 0) st->tphase[6] = clock64();
 }
 
 // ------------------------------------------------ final Rayleigh-Ritz

@@ -186,7 +186,7 @@ __device__ __forceinline__ void rowmul_body(size_t pbeg, size_t pend, size_t fir
     const int a = (int)(it % narr);
     const size_t p0 = pbeg + tile * 16;
     const bool rowok = (it < nitems) && (p0 + li < n);
-    const double* Xa = arrs.a[a];
+    const double* Xa = arrs.at(a);
     const double* src = Xa + (rowok ? (p0 + li) * ld + lk * kq : 0);
     if (rowok && vec2 && ((((uintptr_t)Xa) & 15) == 0)) {
 #pragma unroll
@@ -209,7 +209,7 @@ __device__ __forceinline__ void rowmul_body(size_t pbeg, size_t pend, size_t fir
     const size_t tile = first + w + stride * (it / narr);
     const int a = (int)(it % narr);
     const size_t p0 = pbeg + tile * 16;
-    double* Xa = arrs.a[a];
+    double* Xa = arrs.at(a);
     d4 acc[TJ];
 #pragma unroll
     for (int t = 0; t < TJ; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
