@@ -301,9 +301,12 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   // right-looking Cholesky in slot order; a numerically dependent column
   // (V included) adds nothing to span(Z) and is dropped.  Rows of R stay
   // unscaled during the elimination (the update of step j divides by the
-  // pivot) and are scaled by 1/sqrt(pivot) once at the end: one barrier
-  // per kept column.  A dropped column takes no barrier: the decision is
-  // uniform and column j is read by no later step.
+  // pivot): it is Gaussian elimination E G = U = D L^T with E = L^-1 unit
+  // lower triangular, R = D^1/2 L^T, so R^-1 = E^T D^-1/2.  The same row
+  // operations applied to X = I build E alongside (row j of E is final at
+  // step j): one barrier per kept column and no separate inversion.  A
+  // dropped column takes no barrier: the decision is uniform, column j is
+  // read by no later step, and column j of E stays e_j.
   __shared__ double rsc[256];  // 1/sqrt(pivot) of each kept slot
   double minpiv = INFINITY;    // (thread 0) smallest kept pivot
   for (int j = 0; j < m; ++j) {
@@ -320,16 +323,20 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     // stay zero under the update, and a column dropped at step j' is read
     // by no later step: no per-element test of `valid` is needed
     const double* gj = Gs + j * m;
+    const double* ej = X + j * m;
 #pragma unroll
     for (int a = 0; a < kOrthoSpan; ++a) {
       const int i = j + 1 + ty + 16 * a;
       if (i < m) {
         const double gji = gj[i] * ip;
         double* gi = Gs + i * m;
+        double* ei = X + i * m;
 #pragma unroll
         for (int c = 0; c < kOrthoSpan; ++c) {
           const int l = i + tx + 16 * c;
           if (l < m) gi[l] -= gji * gj[l];
+          const int cc = tx + 16 * c;
+          if (cc <= j) ei[cc] -= gji * ej[cc];
         }
       }
     }
@@ -338,50 +345,11 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   for (int j = t; j < m; j += nt)
     if (valid[j]) rsc[j] = 1.0 / sqrt(rsc[j]);
   __syncthreads();
-  // R (upper, kept slots only; zero elsewhere) in place
-  for (int i = ty; i < m; i += 16)
-    for (int l = tx; l < m; l += 16)
-      Gs[i * m + l] = (valid[i] && valid[l] && l >= i) ? Gs[i * m + l] * rsc[i] : 0.0;
-  __syncthreads();
-  // X = R^-1 by right-looking back substitution over the kept slots, rows
-  // unscaled until the end (step i subtracts R[r][i] / R[i][i] times row i
-  // from the rows above): one barrier per kept slot
-  // (R is zero in the rows and columns of slots that are not kept, so
-  // their updates subtract zero)
-  __shared__ double dinv[256];
-  for (int i = t; i < m; i += nt) dinv[i] = valid[i] ? 1.0 / Gs[i * m + i] : 0.0;
-  __syncthreads();
-  for (int i = m - 1; i >= 0; --i) {
-    if (!valid[i]) continue;
-    const double inv = dinv[i];
-    double xi[kOrthoSpan];
-#pragma unroll
-    for (int c = 0; c < kOrthoSpan; ++c) {
-      const int cc = tx + 16 * c;
-      xi[c] = (cc < m) ? X[i * m + cc] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < kOrthoSpan; ++a) {
-      const int r = ty + 16 * a;
-      if (r < i) {
-        const double f = Gs[r * m + i] * inv;
-#pragma unroll
-        for (int c = 0; c < kOrthoSpan; ++c) {
-          const int cc = tx + 16 * c;
-          if (cc < m) X[r * m + cc] -= f * xi[c];
-        }
-      }
-    }
-    __syncthreads();
-  }
+  // M = D R^-1 = D E^T D_piv^-1/2 on the kept slots, zero elsewhere
   for (int i = ty; i < m; i += 16)
     for (int c = tx; c < m; c += 16)
-      if (valid[i]) X[i * m + c] /= Gs[i * m + i];
-  __syncthreads();
-  // M = D R^-1 on the kept slots, zero elsewhere
-  for (int i = ty; i < m; i += 16)
-    for (int c = tx; c < m; c += 16)
-      b.M[(size_t)i * m + c] = (valid[i] && valid[c]) ? d[i] * X[i * m + c] : 0.0;
+      b.M[(size_t)i * m + c] =
+          (valid[i] && valid[c] && c >= i) ? d[i] * X[c * m + i] * rsc[c] : 0.0;
   for (int s = t; s < m; s += nt) b.keep[s] = valid[s];
   if (t == 0) {
     int nk = 0, nd = 0;

@@ -90,7 +90,9 @@ def test_shift_on_an_eigenvalue():
     them and the T-harmonic extraction cannot single them out; the oracle
     stalls near relative residual 1e-3 here as well.  The GPU must come
     back cleanly: converged or PLHR_ERR_NOT_CONVERGED with finite outputs
-    near sigma, never a breakdown or a non-finite value."""
+    no farther from sigma than the nearest other eigenvalue (the pairs the
+    extraction can see; which of these it returns depends on rounding),
+    never a breakdown or a non-finite value."""
     from paper_1408_0042_amd import _lib as L
     args, ev = _small(max_iters=400)
     u = np.unique(np.round(ev, 8))
@@ -101,7 +103,8 @@ def test_shift_on_an_eigenvalue():
     lam = host(r.eigvals)
     assert np.all(np.isfinite(lam)) and np.all(np.isfinite(host(r.V)))
     assert np.all(np.isfinite(r.rel_res))
-    assert np.all(np.abs(lam - sigma) <= 1e-2 * sigma)
+    gap = np.min(np.abs(u[np.abs(u - sigma) > 1e-6 * sigma] - sigma))
+    assert np.all(np.abs(lam - sigma) <= gap * (1.0 + 1e-6)), (lam, sigma, gap)
     S.close()
 
 
