@@ -871,13 +871,20 @@ void enqueue_iteration_body(plhr_ctx_s* c, bool refresh) {
   }
   stencil(c, Z, m, Blk{c->QVf, kint}, none, nullptr, none, kint, c->sigma, st,
           bst ? Blk{c->BVf, kint} : none);
-  int nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s, bst ? c->BVf : nullptr, kint);
-  launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
-  // residuals of the current block, convergence and locking
-  nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, tid ? Z + kint : R,
-                         tid ? m : kint, kint, c->bdiag, bst ? c->BVf : nullptr, kint, c->part,
-                         st, s);
-  launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
+  int nb = 0;
+  if (!bst && !c->bdiag && vstep_small_ok(n, kint)) {
+    // small problem: quotients, residuals and the test in one workgroup
+    launch_vstep_small(c->sp, n, Z, m, c->QVf, kint, tid ? Z + kint : R, tid ? m : kint,
+                       c->part, c->sb, st, s);
+  } else {
+    nb = launch_xdots(n, Z, m, c->QVf, kint, kint, c->part, s, bst ? c->BVf : nullptr, kint);
+    launch_rq_small(c->sp, c->part, nb, c->sb, st, 0, s);
+    // residuals of the current block, convergence and locking
+    nb = launch_resid_prep(n, Z, m, c->QVf, kint, c->sb.lam, c->sigma, tid ? Z + kint : R,
+                           tid ? m : kint, kint, c->bdiag, bst ? c->BVf : nullptr, kint, c->part,
+                           st, s);
+    launch_conv_check(c->sp, c->part, nb, c->sb, st, c->opt.max_iters, s);
+  }
   // W = T (A V - B V Lam)
   if (!tid) precond(c, R, kint, Blk{Z + kint, m}, none, kint, kint, st, true);
   // QW = (A - sigma) W;  R = [QW - W (Lam - sigma) | QW]

@@ -464,6 +464,14 @@ void launch_tharm_small_b(const BatchSmall* bs, int nb, int m, int kint, hipStre
 void launch_init_lam(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                      DevStatus* st, hipStream_t s);
 void launch_start_check(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);
+// For a small problem with B = I (vstep_small_ok): the Rayleigh quotients
+// of V from (A - sigma)V, the residual block R and the convergence test in
+// one single-workgroup launch (as launch_xdots, launch_rq_small,
+// launch_resid_prep and launch_conv_check in sequence).
+bool vstep_small_ok(size_t n, int kint);
+void launch_vstep_small(const SmallParams& p, size_t n, const double* V, int ldv,
+                        const double* QV, int ldq, double* R, int ldr, double* part,
+                        SmallBufs b, DevStatus* st, hipStream_t s);
 void launch_conv_check(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                        DevStatus* st, int max_iters, hipStream_t s);
 void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s);

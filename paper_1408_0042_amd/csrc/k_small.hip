@@ -636,6 +636,75 @@ __global__ __launch_bounds__(256) void k_final_res_b(const BatchSmall* __restric
 }
 
 
+// ------------------------------------------ fused residual step (small n)
+// One workgroup for a small problem with B = I: the column sums v.v and
+// v.(A - sigma)v, the Rayleigh quotients, the residual block
+// R = (A - sigma)V - V (Lam - sigma) with its column sums r.r and v.v, and
+// the convergence test, in one launch instead of four.  Each column's sums
+// are formed by a fixed group of threads in a fixed order and passed to the
+// quotient and test bodies as a single partial block.
+__global__ __launch_bounds__(256) void k_vstep_small(SmallParams p, size_t n,
+                                                     const double* __restrict__ V, int ldv,
+                                                     const double* __restrict__ QV, int ldq,
+                                                     double* R, int ldr, double* part, SmallBufs b,
+                                                     DevStatus* st) {
+  if (halted(st)) return;
+  __shared__ double red2[2][256];
+  const int kint = p.kint, t = threadIdx.x;
+  const int per = 256 / kint, c = t % kint, g = t / kint;
+  auto column_sums = [&](double a0, double a1) {
+    red2[0][t] = a0;
+    red2[1][t] = a1;
+    __syncthreads();
+    if (t < kint) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int q = 0; q < per; ++q) {
+        s0 += red2[0][q * kint + t];
+        s1 += red2[1][q * kint + t];
+      }
+      part[t] = s0;
+      part[kint + t] = s1;
+    }
+    __threadfence_block();
+    __syncthreads();
+  };
+  double a0 = 0.0, a1 = 0.0;
+  if (g < per)
+    for (size_t r = g; r < n; r += per) {
+      const double v = V[r * ldv + c], q = QV[r * ldq + c];
+      a0 += v * v;
+      a1 += v * q;
+    }
+  column_sums(a0, a1);
+  k_rq_small_body(p, part, 1, b, st, 0);
+  __threadfence_block();
+  __syncthreads();
+  const double sh = b.lam[c] - p.sigma;
+  a0 = 0.0;
+  a1 = 0.0;
+  if (g < per)
+    for (size_t r = g; r < n; r += per) {
+      const double v = V[r * ldv + c];
+      const double rr = QV[r * ldq + c] - v * sh;
+      R[r * ldr + c] = rr;
+      a0 += rr * rr;
+      a1 += v * v;
+    }
+  column_sums(a0, a1);
+  k_conv_check_body(p, part, 1, b, st);
+}
+
+bool vstep_small_ok(size_t n, int kint) { return kint <= 64 && n * (size_t)kint <= 32768; }
+
+void launch_vstep_small(const SmallParams& p, size_t n, const double* V, int ldv,
+                        const double* QV, int ldq, double* R, int ldr, double* part,
+                        SmallBufs b, DevStatus* st, hipStream_t s) {
+  prof_begin(KC_SMALL, (double)n * p.kint * 8.0 * 5.0, 0.0, s);
+  hipLaunchKernelGGL(k_vstep_small, dim3(1), dim3(256), 0, s, p, n, V, ldv, QV, ldq, R, ldr, part,
+                     b, st);
+  prof_end(KC_SMALL, s);
+}
+
 // ------------------------------------------------------------ launchers
 void launch_init_lam(const SmallParams& p, const double* part, int nblk, SmallBufs b,
                      DevStatus* st, hipStream_t s) {
