@@ -507,9 +507,13 @@ def timed_solves(solver, V0, k, ref, steps, warmup, sym=False):
     timed solves with HIP events around the dominant kernel's launches
     only (on the solver's stream).  A solve counts its k pairs when it
     converged and its eigenvalues match the closed form `ref`.  `sym`: the
-    projected problem is symmetric (T = I, B = I), solved by k_tharm_sym."""
+    projected problem is symmetric (T = I, B = I), solved by k_tharm_sym.
+    V0 is one start block or a list of them, one per timed step (the
+    warm-up and profiled solves use the first)."""
     from paper_1408_0042_amd import _lib as L
     import torch
+    V0s = list(V0) if isinstance(V0, (list, tuple)) else [V0] * steps
+    V0 = V0s[0]
     for _ in range(warmup):
         solver.solve(V0, allow_unconverged=True)
     solver.profile_start(-1, 400000)
@@ -522,9 +526,9 @@ def timed_solves(solver, V0, k, ref, steps, warmup, sym=False):
     solver.profile_start(dom_id, 400000)
     times, iters, conv, correct = [], [], [], []
     t00 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         t0 = time.perf_counter()
-        r = solver.solve(V0, allow_unconverged=True)
+        r = solver.solve(V0s[i % len(V0s)], allow_unconverged=True)
         times.append(time.perf_counter() - t0)
         iters.append(r.iters)
         conv.append(bool(r.converged))
@@ -554,10 +558,9 @@ def timed_solves(solver, V0, k, ref, steps, warmup, sym=False):
                       "bound": e["bound"], "achieved": round(e["achieved"], 2), "unit": e["unit"],
                       "frac": round(e["frac"], 5)}
     good = sum(1 for c, r in zip(conv, correct) if c and r)
-    its_med = float(np.median(iters))
     return {"value": k * good / el, "el": el, "ms_per_step": 1e3 * el / steps,
             "median_ms": 1e3 * float(np.median(times)), "iters": iters, "conv": conv,
-            "correct": correct, "us_per_iteration": 1e6 * float(np.median(times)) / max(its_med, 1),
+            "correct": correct, "us_per_iteration": 1e6 * float(np.sum(times)) / max(sum(iters), 1),
             "roof": roof, "dom": dom, "kernels": kernels}
 
 
