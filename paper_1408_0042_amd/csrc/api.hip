@@ -676,23 +676,23 @@ Layout layout(const Grid& g, int k, int kint, bool mgpre, int levels, bool bdiag
 
 // (A - shift B)X and its fused outputs; outb (B X) exists only when B is
 // a stencil (the finite-element mass).
-// The Bloch product on interleaved real column pairs: X staged into the
-// contiguous complex block Xs, the product into Ys, then the outputs (the
-// shifted residual form from Ys as launch_resid_prep writes it).
+// The Bloch product on interleaved real column pairs: read from and
+// written to the strided slots directly (a slot of 2 k_int real columns is
+// k_int complex columns at a 16-byte aligned offset, row stride ld / 2
+// complex entries), then the shifted residual form as launch_resid_prep
+// writes it and the copy output.
 void bloch_stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr,
                    const double* colshift, Blk outc, int ncols, double shift,
                    const DevStatus* st) {
   const size_t n = c->n;
   hipStream_t s = c->stream;
   const plhr_op_desc& A = c->bop;
-  launch_copy(n, X, ldx, c->Xs, ncols, ncols, s, st);
-  launch_bloch_apply(A.nx, A.ny, A.nz, A.h, A.scale, A.theta, c->pot, shift, c->Xs, c->Ys,
-                     ncols / 2, s);
-  launch_copy(n, c->Ys, ncols, out.ptr, out.ld, ncols, s, st);
+  launch_bloch_apply(A.nx, A.ny, A.nz, A.h, A.scale, A.theta, c->pot, shift, X, out.ptr,
+                     ncols / 2, s, ldx / 2, out.ld / 2, st);
   if (outr.ptr)
-    launch_resid_prep(n, X, ldx, c->Ys, ncols, colshift, c->sigma, outr.ptr, outr.ld, ncols,
+    launch_resid_prep(n, X, ldx, out.ptr, out.ld, colshift, c->sigma, outr.ptr, outr.ld, ncols,
                       nullptr, nullptr, 0, c->part, st, s);
-  if (outc.ptr) launch_copy(n, c->Ys, ncols, outc.ptr, outc.ld, ncols, s, st);
+  if (outc.ptr) launch_copy(n, out.ptr, out.ld, outc.ptr, outc.ld, ncols, s, st);
 }
 
 void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const double* colshift,

@@ -161,10 +161,12 @@ void launch_csr_apply(int n, const CsrMat& A, const CsrMat& B, const double* pot
                       double csub, Blk out_c, Blk out_b, int ncols, const DevStatus* st,
                       hipStream_t s);
 // Y = (scale (-Laplacian_theta) + diag(pot) - shift I) X on a Bloch-periodic
-// box, complex128 blocks (interleaved re, im), n x ncols point-major.
+// box, complex128 blocks (interleaved re, im), n x ncols point-major with
+// row strides ldx, ldy in complex entries (<= 0: ncols); nothing when st
+// is halted.
 void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const double* theta,
                         const double* pot, double shift, const double* X, double* Y, int ncols,
-                        hipStream_t s);
+                        hipStream_t s, int ldx = 0, int ldy = 0, const DevStatus* st = nullptr);
 // One V-cycle of a Bloch preconditioner handle on stream s: Y = T X for
 // ncols complex columns (X, Y contiguous n x ncols complex128, no overlap).
 void bloch_prec_cycle(plhr_bloch_prec p, const double* X, double* Y, int ncols, hipStream_t s);

@@ -32,16 +32,18 @@ __global__ __launch_bounds__(256) void k_bloch_apply(int nx, int ny, int nz, dou
                                                      const double* __restrict__ pot,
                                                      double shift, double2 fx, double2 fy,
                                                      double2 fz, const double2* __restrict__ X,
-                                                     double2* __restrict__ Y, int ncols) {
+                                                     int ldx, double2* __restrict__ Y, int ldy,
+                                                     int ncols, const DevStatus* st) {
+  if (halted(st)) return;
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny;
   const int l = row / ny;
   const int nelem = nx * ncols;
   const size_t rowp = (size_t)row * nx;
   // element offsets of the y and z neighbours, and of the wrapped ones
-  const ptrdiff_t sx = ncols;
-  const ptrdiff_t sy = (ptrdiff_t)nx * ncols;
-  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ncols;
+  const ptrdiff_t sx = ldx;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ldx;
+  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ldx;
   const ptrdiff_t ym = (j > 0) ? -sy : (ptrdiff_t)(ny - 1) * sy;
   const ptrdiff_t yp = (j < ny - 1) ? sy : -(ptrdiff_t)(ny - 1) * sy;
   const ptrdiff_t zm = (l > 0) ? -sz : (ptrdiff_t)(nz - 1) * sz;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256) void k_bloch_apply(int nx, int ny, int nz, dou
   const int di = blockDim.x / ncols, dc = blockDim.x - di * ncols;
   for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
     const size_t p = rowp + i;
-    const double2* xp = X + p * ncols + c;
+    const double2* xp = X + p * ldx + c;
     const ptrdiff_t xm = (i > 0) ? -sx : (ptrdiff_t)(nx - 1) * sx;
     const ptrdiff_t xq = (i < nx - 1) ? sx : -(ptrdiff_t)(nx - 1) * sx;
     const double2 x0 = xp[0];
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void k_bloch_apply(int nx, int ny, int nz, dou
     const double sim = ((na.y + nb.y) + (nu.y + nv.y)) + (nw.y + nz2.y);
     double d = 6.0 * cs - shift;
     if (pot) d += pot[p];
-    Y[p * ncols + c] = make_double2(d * x0.x - cs * sre, d * x0.y - cs * sim);
+    Y[p * ldy + c] = make_double2(d * x0.x - cs * sre, d * x0.y - cs * sim);
     c += dc;
     i += di;
     if (c >= ncols) {
@@ -83,14 +85,16 @@ __global__ __launch_bounds__(256) void k_bloch_apply(int nx, int ny, int nz, dou
 
 void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const double* theta,
                         const double* pot, double shift, const double* X, double* Y, int ncols,
-                        hipStream_t s) {
+                        hipStream_t s, int ldx, int ldy, const DevStatus* st) {
+  if (ldx <= 0) ldx = ncols;
+  if (ldy <= 0) ldy = ncols;
   const double cs = scale / (h * h);
   const double2 fx = make_double2(std::cos(theta[0]), std::sin(theta[0]));
   const double2 fy = make_double2(std::cos(theta[1]), std::sin(theta[1]));
   const double2 fz = make_double2(std::cos(theta[2]), std::sin(theta[2]));
   hipLaunchKernelGGL(k_bloch_apply, dim3(ny * nz), dim3(256), 0, s, nx, ny, nz, cs, pot, shift,
-                     fx, fy, fz, reinterpret_cast<const double2*>(X),
-                     reinterpret_cast<double2*>(Y), ncols);
+                     fx, fy, fz, reinterpret_cast<const double2*>(X), ldx,
+                     reinterpret_cast<double2*>(Y), ldy, ncols, st);
 }
 
 // ------------------------------------------------------------- V-cycle
