@@ -716,9 +716,19 @@ void stencil(plhr_ctx_s* c, const double* X, int ldx, Blk out, Blk outr, const d
 // T-harmonic Grams (T(A - sigma B)Z) always use the FP64 V-cycle.
 void precond_raw(plhr_ctx_s* c, const double* Rin, int ldr, Blk o0, Blk o1, int split,
                  int ncols, const DevStatus* st, bool direction) {
-  if (c->bprec) {  // the Bloch V-cycle on the staged complex block
+  if (c->bprec && st != c->gate) {
+    // the Bloch V-cycle reads the strided slot and writes the (split)
+    // outputs directly (its kernels do not read the status: after
+    // convergence they rewrite W, S and T(A - sigma)Z slots that are no
+    // longer used)
+    bloch_prec_cycle(c->bprec, Rin, ldr / 2, o0.ptr, o0.ld / 2, o1.ptr, o1.ld / 2, split / 2,
+                     ncols / 2, c->stream);
+  } else if (c->bprec) {
+    // gated (the recomputation after a second Cholesky-QR pass): through
+    // the staging blocks, whose copies honour the gate
     launch_copy(c->n, Rin, ldr, c->Xs, ncols, ncols, c->stream, st);
-    bloch_prec_cycle(c->bprec, c->Xs, c->Ys, ncols / 2, c->stream);
+    bloch_prec_cycle(c->bprec, c->Xs, ncols / 2, c->Ys, ncols / 2, nullptr, 0, ncols / 2,
+                     ncols / 2, c->stream);
     if (split > 0) launch_copy(c->n, c->Ys, ncols, o0.ptr, o0.ld, split, c->stream, st);
     if (split < ncols)
       launch_copy(c->n, c->Ys + split, ncols, o1.ptr, o1.ld, ncols - split, c->stream, st);

@@ -114,12 +114,26 @@ struct plhr_bloch_prec_s {
   hipStream_t stream = nullptr;
 
   // V-cycle on level lev for right-hand side r; returns the level's result
-  // buffer, or final_out when given (the last post-sweep writes there).
-  double* cycle(size_t lev, const double* r, int ncols, double* final_out) {
+  // buffer, or the final output when `fin` is given (the last post-sweep,
+  // or the coarsest solve of a one-level cycle, writes there).  At level 0
+  // r may be strided (fin->r); the level buffers are contiguous.
+  double* cycle(size_t lev, const double* r, int ncols, double* final_out,
+                const BlochLd* fin = nullptr) {
     BlochLevel& L = lv[lev];
+    BlochLd rin;  // r's stride at this level; everything else contiguous
+    if (lev == 0 && fin) rin.r = fin->r;
+    BlochLd rw = rin;  // w = r in the first fused pre-sweep
+    rw.w = rin.r;
+    BlochLd last = rin;  // the final write
+    if (final_out && fin) {
+      last.o = fin->o;
+      last.out1 = fin->out1;
+      last.o1 = fin->o1;
+      last.split = fin->split;
+    }
     if (lev + 1 == lv.size()) {
       double* out = final_out ? final_out : L.x;
-      launch_bloch_dense(nc, Ainv, r, out, ncols, stream);
+      launch_bloch_dense(nc, Ainv, r, out, ncols, stream, final_out ? last : rin);
       return out;
     }
     const double bj = omega / L.diag;
@@ -130,26 +144,29 @@ struct plhr_bloch_prec_s {
     int it0 = 1;
     if (nu >= 2) {
       launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, r, r, 2.0 * bj - bj * bj, bj * bj, cur,
-                         ncols, stream);
+                         ncols, stream, rw);
       it0 = 2;
     } else {
-      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, nullptr, r, 0.0, bj, cur, ncols, stream);
+      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, nullptr, r, 0.0, bj, cur, ncols, stream,
+                         rin);
     }
     for (int it = it0; it < nu; ++it) {
-      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 1.0, bj, oth, ncols, stream);
+      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 1.0, bj, oth, ncols, stream, rin);
       std::swap(cur, oth);
     }
     // residual, restriction, coarse correction
-    launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 0.0, 1.0, oth, ncols, stream);
+    launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 0.0, 1.0, oth, ncols, stream, rin);
     BlochLevel& C = lv[lev + 1];
     launch_bloch_restrict(C.nx, C.ny, C.nz, theta, oth, C.r, ncols, stream);
     double* ec = cycle(lev + 1, C.r, ncols, nullptr);
     launch_bloch_prolong_add(L.nx, L.ny, L.nz, theta, ec, cur, ncols, stream);
     // post-smoothing
     for (int it = 0; it < nu; ++it) {
-      double* dst = (final_out && it == nu - 1) ? final_out : oth;
-      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 1.0, bj, dst, ncols, stream);
-      if (dst == final_out) return final_out;
+      const bool fl = final_out && it == nu - 1;
+      double* dst = fl ? final_out : oth;
+      launch_bloch_level(L.nx, L.ny, L.nz, L.cs, theta, cur, r, 1.0, bj, dst, ncols, stream,
+                         fl ? last : rin);
+      if (fl) return final_out;
       std::swap(cur, oth);
     }
     return cur;
@@ -316,9 +333,18 @@ namespace plhr {
 
 // One V-cycle of the handle on `s` (the solver context runs it on its own
 // stream, or on the stream a graph is being recorded on).
-void bloch_prec_cycle(plhr_bloch_prec p, const double* X, double* Y, int ncols, hipStream_t s) {
+void bloch_prec_cycle(plhr_bloch_prec p, const double* X, int ldx, double* Y0, int ld0,
+                      double* Y1, int ld1, int split, int ncols, hipStream_t s) {
   p->stream = s;
-  p->cycle(0, X, ncols, Y);
+  BlochLd fin;
+  fin.r = ldx;
+  fin.o = ld0;
+  if (split < ncols) {
+    fin.out1 = Y1;
+    fin.o1 = ld1;
+    fin.split = split;
+  }
+  p->cycle(0, X, ncols, Y0, &fin);
 }
 
 }  // namespace plhr

@@ -168,22 +168,33 @@ void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const do
                         const double* pot, double shift, const double* X, double* Y, int ncols,
                         hipStream_t s, int ldx = 0, int ldy = 0, const DevStatus* st = nullptr);
 // One V-cycle of a Bloch preconditioner handle on stream s: Y = T X for
-// ncols complex columns (X, Y contiguous n x ncols complex128, no overlap).
-void bloch_prec_cycle(plhr_bloch_prec p, const double* X, double* Y, int ncols, hipStream_t s);
+// ncols complex columns, X with row stride ldx, the result's columns
+// c < split to Y0 (stride ld0), the others to Y1 (stride ld1) at column
+// c - split (strides in complex entries; no overlap of X with Y0, Y1).
+void bloch_prec_cycle(plhr_bloch_prec p, const double* X, int ldx, double* Y0, int ld0,
+                      double* Y1, int ld1, int split, int ncols, hipStream_t s);
 // Bloch V-cycle pieces (complex128 blocks, n_l x ncols point-major):
 // out = alpha w + beta (r - A_l w) with A_l the level's Bloch stencil of
 // coefficient cs = scale/h_l^2 (w = NULL: w = 0); rc = P^H res / 8 onto the
 // coarse grid nxc x nyc x nzc; x += P ec on the fine grid nx x ny x nz;
 // x = Ainv r on the coarsest level.
+// Row strides (complex entries; <= 0: ncols) of a level kernel's w, r and
+// out, and a second output: columns c >= split go to out1 (stride o1) at
+// column c - split (out1 = null: every column to out).
+struct BlochLd {
+  int w = 0, r = 0, o = 0;
+  double* out1 = nullptr;
+  int o1 = 0, split = 0;
+};
 void launch_bloch_level(int nx, int ny, int nz, double cs, const double* theta, const double* w,
                         const double* r, double alpha, double beta, double* out, int ncols,
-                        hipStream_t s);
+                        hipStream_t s, const BlochLd& ld = BlochLd{});
 void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const double* res,
                            double* rc, int ncols, hipStream_t s);
 void launch_bloch_prolong_add(int nx, int ny, int nz, const double* theta, const double* ec,
                               double* x, int ncols, hipStream_t s);
 void launch_bloch_dense(int nc, const double* Ainv, const double* r, double* x, int ncols,
-                        hipStream_t s);
+                        hipStream_t s, const BlochLd& ld = BlochLd{});
 
 // Multigrid V-cycle (k_mg.hip).
 struct MGLevel {

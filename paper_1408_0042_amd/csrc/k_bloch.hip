@@ -106,21 +106,25 @@ void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const do
 
 // One level's fused update  out = alpha w + beta (r - A_l w): alpha = 1,
 // beta = omega / diag is a weighted-Jacobi sweep; alpha = 0, beta = 1 the
-// residual.  w = NULL stands for w = 0.  out must not overlap w.
+// residual.  w = NULL stands for w = 0.  out must not overlap w.  Row
+// strides (complex entries): ldw of w, ldr of r; columns c < split go to
+// out (stride ldo), the others to out1 (stride ldo1) at column c - split.
 __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, double cs,
                                                      double2 fx, double2 fy, double2 fz,
-                                                     const double2* __restrict__ w,
-                                                     const double2* __restrict__ r, double alpha,
-                                                     double beta, double2* __restrict__ out,
-                                                     int ncols) {
+                                                     const double2* __restrict__ w, int ldw,
+                                                     const double2* __restrict__ r, int ldr,
+                                                     double alpha, double beta,
+                                                     double2* __restrict__ out, int ldo,
+                                                     double2* __restrict__ out1, int ldo1,
+                                                     int split, int ncols) {
   const int row = xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = row % ny;
   const int l = row / ny;
   const int nelem = nx * ncols;
   const size_t rowp = (size_t)row * nx;
-  const ptrdiff_t sx = ncols;
-  const ptrdiff_t sy = (ptrdiff_t)nx * ncols;
-  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ncols;
+  const ptrdiff_t sx = ldw;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ldw;
+  const ptrdiff_t sz = (ptrdiff_t)nx * ny * ldw;
   const ptrdiff_t ym = (j > 0) ? -sy : (ptrdiff_t)(ny - 1) * sy;
   const ptrdiff_t yp = (j < ny - 1) ? sy : -(ptrdiff_t)(ny - 1) * sy;
   const ptrdiff_t zm = (l > 0) ? -sz : (ptrdiff_t)(nz - 1) * sz;
@@ -135,11 +139,11 @@ __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, dou
   int c = threadIdx.x - i * ncols;
   const int di = blockDim.x / ncols, dc = blockDim.x - di * ncols;
   for (int e = threadIdx.x; e < nelem; e += blockDim.x) {
-    const size_t q = (rowp + i) * ncols + c;
-    const double2 r0 = r[q];
+    const size_t p = rowp + i;
+    const double2 r0 = r[p * ldr + c];
     double2 y;
     if (w) {
-      const double2* xp = w + q;
+      const double2* xp = w + p * ldw + c;
       const ptrdiff_t xm = (i > 0) ? -sx : (ptrdiff_t)(nx - 1) * sx;
       const ptrdiff_t xq = (i < nx - 1) ? sx : -(ptrdiff_t)(nx - 1) * sx;
       const double2 x0 = xp[0];
@@ -155,7 +159,10 @@ __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, dou
     } else {
       y = make_double2(beta * r0.x, beta * r0.y);
     }
-    out[q] = y;
+    if (c < split)
+      out[p * ldo + c] = y;
+    else
+      out1[p * ldo1 + (c - split)] = y;
     c += dc;
     i += di;
     if (c >= ncols) {
@@ -424,8 +431,10 @@ __global__ __launch_bounds__(256) void k_bloch_prolong_add_lds(int nx, int ny, i
 // Workgroup (i, column chunk of 64): its 256 lanes are 64 columns by 4
 // slices of the sum over q (q = slice mod 4), combined through LDS.
 __global__ __launch_bounds__(256) void k_bloch_dense(int nc, const double2* __restrict__ Ainv,
-                                                     const double2* __restrict__ r,
-                                                     double2* __restrict__ x, int ncols) {
+                                                     const double2* __restrict__ r, int ldr,
+                                                     double2* __restrict__ x, int ldx,
+                                                     double2* __restrict__ x1, int ldx1,
+                                                     int split, int ncols) {
   __shared__ double2 part[4][64];
   const int i = blockIdx.x;
   const int cl = threadIdx.x & 63, sl = threadIdx.x >> 6;
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(256) void k_bloch_dense(int nc, const double2* __re
   double2 acc = make_double2(0.0, 0.0);
   if (c < ncols) {
     for (int q = sl; q < nc; q += 4) {
-      const double2 m = a[q], v = r[(size_t)q * ncols + c];
+      const double2 m = a[q], v = r[(size_t)q * ldr + c];
       acc = make_double2(acc.x + (m.x * v.x - m.y * v.y), acc.y + (m.x * v.y + m.y * v.x));
     }
   }
@@ -442,8 +451,12 @@ __global__ __launch_bounds__(256) void k_bloch_dense(int nc, const double2* __re
   __syncthreads();
   if (sl == 0 && c < ncols) {
     const double2 p1 = part[1][cl], p2 = part[2][cl], p3 = part[3][cl];
-    x[(size_t)i * ncols + c] =
+    const double2 v =
         make_double2(((acc.x + p1.x) + p2.x) + p3.x, ((acc.y + p1.y) + p2.y) + p3.y);
+    if (c < split)
+      x[(size_t)i * ldx + c] = v;
+    else
+      x1[(size_t)i * ldx1 + (c - split)] = v;
   }
 }
 
@@ -451,11 +464,15 @@ static double2 phase(double t) { return make_double2(std::cos(t), std::sin(t)); 
 
 void launch_bloch_level(int nx, int ny, int nz, double cs, const double* theta, const double* w,
                         const double* r, double alpha, double beta, double* out, int ncols,
-                        hipStream_t s) {
+                        hipStream_t s, const BlochLd& ld) {
+  const int ldw = ld.w > 0 ? ld.w : ncols, ldr = ld.r > 0 ? ld.r : ncols;
+  const int ldo = ld.o > 0 ? ld.o : ncols;
+  const int split = ld.out1 ? ld.split : ncols;
   hipLaunchKernelGGL(k_bloch_level, dim3(ny * nz), dim3(256), 0, s, nx, ny, nz, cs,
                      phase(theta[0]), phase(theta[1]), phase(theta[2]),
-                     reinterpret_cast<const double2*>(w), reinterpret_cast<const double2*>(r),
-                     alpha, beta, reinterpret_cast<double2*>(out), ncols);
+                     reinterpret_cast<const double2*>(w), ldw, reinterpret_cast<const double2*>(r),
+                     ldr, alpha, beta, reinterpret_cast<double2*>(out), ldo,
+                     reinterpret_cast<double2*>(ld.out1), ld.o1, split, ncols);
 }
 
 void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const double* res,
@@ -489,10 +506,13 @@ void launch_bloch_prolong_add(int nx, int ny, int nz, const double* theta, const
 }
 
 void launch_bloch_dense(int nc, const double* Ainv, const double* r, double* x, int ncols,
-                        hipStream_t s) {
+                        hipStream_t s, const BlochLd& ld) {
+  const int ldr = ld.r > 0 ? ld.r : ncols, ldo = ld.o > 0 ? ld.o : ncols;
+  const int split = ld.out1 ? ld.split : ncols;
   hipLaunchKernelGGL(k_bloch_dense, dim3(nc, (ncols + 63) / 64), dim3(256), 0, s, nc,
                      reinterpret_cast<const double2*>(Ainv), reinterpret_cast<const double2*>(r),
-                     reinterpret_cast<double2*>(x), ncols);
+                     ldr, reinterpret_cast<double2*>(x), ldo,
+                     reinterpret_cast<double2*>(ld.out1), ld.o1, split, ncols);
 }
 
 }  // namespace plhr
