@@ -668,13 +668,29 @@ __global__ __launch_bounds__(256) void k_vstep_small(SmallParams p, size_t n,
     __threadfence_block();
     __syncthreads();
   };
+  // eight rows of a thread in flight at a time, added in row order
   double a0 = 0.0, a1 = 0.0;
-  if (g < per)
-    for (size_t r = g; r < n; r += per) {
+  if (g < per) {
+    size_t r = g;
+    for (; r + 7 * (size_t)per < n; r += 8 * (size_t)per) {
+      double v[8], q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = V[(r + u * per) * ldv + c];
+        q[u] = QV[(r + u * per) * ldq + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 += v[u] * v[u];
+        a1 += v[u] * q[u];
+      }
+    }
+    for (; r < n; r += per) {
       const double v = V[r * ldv + c], q = QV[r * ldq + c];
       a0 += v * v;
       a1 += v * q;
     }
+  }
   column_sums(a0, a1);
   k_rq_small_body(p, part, 1, b, st, 0);
   __threadfence_block();
@@ -682,14 +698,31 @@ __global__ __launch_bounds__(256) void k_vstep_small(SmallParams p, size_t n,
   const double sh = b.lam[c] - p.sigma;
   a0 = 0.0;
   a1 = 0.0;
-  if (g < per)
-    for (size_t r = g; r < n; r += per) {
+  if (g < per) {
+    size_t r = g;
+    for (; r + 7 * (size_t)per < n; r += 8 * (size_t)per) {
+      double v[8], q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = V[(r + u * per) * ldv + c];
+        q[u] = QV[(r + u * per) * ldq + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double rr = q[u] - v[u] * sh;
+        R[(r + u * per) * ldr + c] = rr;
+        a0 += rr * rr;
+        a1 += v[u] * v[u];
+      }
+    }
+    for (; r < n; r += per) {
       const double v = V[r * ldv + c];
       const double rr = QV[r * ldq + c] - v * sh;
       R[r * ldr + c] = rr;
       a0 += rr * rr;
       a1 += v * v;
     }
+  }
   column_sums(a0, a1);
   k_conv_check_body(p, part, 1, b, st);
 }
