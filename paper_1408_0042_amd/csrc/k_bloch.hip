@@ -109,6 +109,9 @@ void launch_bloch_apply(int nx, int ny, int nz, double h, double scale, const do
 // residual.  w = NULL stands for w = 0.  out must not overlap w.  Row
 // strides (complex entries): ldw of w, ldr of r; columns c < split go to
 // out (stride ldo), the others to out1 (stride ldo1) at column c - split.
+// kStrided = false: every stride is ncols and every column goes to out
+// (the contiguous level buffers, with the plain index arithmetic).
+template <bool kStrided>
 __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, double cs,
                                                      double2 fx, double2 fy, double2 fz,
                                                      const double2* __restrict__ w, int ldw,
@@ -122,6 +125,11 @@ __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, dou
   const int l = row / ny;
   const int nelem = nx * ncols;
   const size_t rowp = (size_t)row * nx;
+  if (!kStrided) {
+    ldw = ncols;
+    ldr = ncols;
+    ldo = ncols;
+  }
   const ptrdiff_t sx = ldw;
   const ptrdiff_t sy = (ptrdiff_t)nx * ldw;
   const ptrdiff_t sz = (ptrdiff_t)nx * ny * ldw;
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(256) void k_bloch_level(int nx, int ny, int nz, dou
     } else {
       y = make_double2(beta * r0.x, beta * r0.y);
     }
-    if (c < split)
+    if (!kStrided || c < split)
       out[p * ldo + c] = y;
     else
       out1[p * ldo1 + (c - split)] = y;
@@ -468,11 +476,13 @@ void launch_bloch_level(int nx, int ny, int nz, double cs, const double* theta, 
   const int ldw = ld.w > 0 ? ld.w : ncols, ldr = ld.r > 0 ? ld.r : ncols;
   const int ldo = ld.o > 0 ? ld.o : ncols;
   const int split = ld.out1 ? ld.split : ncols;
-  hipLaunchKernelGGL(k_bloch_level, dim3(ny * nz), dim3(256), 0, s, nx, ny, nz, cs,
-                     phase(theta[0]), phase(theta[1]), phase(theta[2]),
-                     reinterpret_cast<const double2*>(w), ldw, reinterpret_cast<const double2*>(r),
-                     ldr, alpha, beta, reinterpret_cast<double2*>(out), ldo,
-                     reinterpret_cast<double2*>(ld.out1), ld.o1, split, ncols);
+  const bool strided = ldw != ncols || ldr != ncols || ldo != ncols || split != ncols;
+  auto kern = strided ? k_bloch_level<true> : k_bloch_level<false>;
+  hipLaunchKernelGGL(kern, dim3(ny * nz), dim3(256), 0, s, nx, ny, nz, cs, phase(theta[0]),
+                     phase(theta[1]), phase(theta[2]), reinterpret_cast<const double2*>(w), ldw,
+                     reinterpret_cast<const double2*>(r), ldr, alpha, beta,
+                     reinterpret_cast<double2*>(out), ldo, reinterpret_cast<double2*>(ld.out1),
+                     ld.o1, split, ncols);
 }
 
 void launch_bloch_restrict(int nxc, int nyc, int nzc, const double* theta, const double* res,
