@@ -73,8 +73,8 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 24): {"source": "paper_1408_0042_amd/csrc/k_tharm_sym.hip",
-                       "sha256": "5bd7a3f67c50577dd529e986847ecfffa87a20b35b7377a5133c13b36ecc756c",
-                       "fetch_kib": 18.6248, "write_kib": 5.8302},
+                       "sha256": "8e81cd05e95b9d344d86d3181a9feb0770c57b5621f5261642a155c81b9e1d21",
+                       "fetch_kib": 18.4300, "write_kib": 5.3930},
 }
 
 

@@ -23,7 +23,7 @@ namespace plhr {
 
 namespace {
 
-constexpr int kST = 256;
+constexpr int kST = 512;
 
 // 1/d from the hardware estimate and two Newton steps
 __device__ __forceinline__ double sym_rcp(double d) {
