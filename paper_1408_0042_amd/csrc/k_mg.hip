@@ -1219,10 +1219,11 @@ static S* cycle(MG& mg, int lev, const RT* r, int ldr, Blk out0, Blk out1, int s
     bool small = lev > 0 && nl_tot >= 2 && nl_tot <= kCoarseMaxLev;
     for (int q = lev; small && q < (int)mg.lv.size(); ++q)
       small = mg.lv[q].g.n() <= (size_t)kCoarseMaxPts && mg.lv[q].kind != 2;
+    // one column per workgroup: the blocks here have at most 2 k_int
+    // columns, far fewer than the compute units, and each workgroup runs
+    // the coarse cycle's levels one after another (its latency is the cost)
     int cc = 0;
-    for (int w : {2, 1})
-      if (small && cc == 0 && ncols % w == 0 && coarse_lds(mg, lev, w, sizeof(S)) <= kCoarseMaxLds)
-        cc = w;
+    if (small && coarse_lds(mg, lev, 1, sizeof(S)) <= kCoarseMaxLds) cc = 1;
     if (small && cc > 0) {
       CoarseArgs a{};
       a.nlev = nl_tot;
