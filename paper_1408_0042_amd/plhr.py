@@ -80,6 +80,8 @@ class Solver:
     (Algorithm 2); B = I, T the identity or {"levels", "nu", "omega"} for
     its V-cycle; V0 is an (n, k + k_extra) complex128 tensor and the
     vectors come back as (n, k) complex128.
+    workspace: optional device tensor of at least `workspace_bytes` bytes
+    (256-byte aligned) that the context uses instead of allocating.
     """
 
     def __init__(self, kind: str, dims: Sequence[int], h: float, sigma: float, k: int,
@@ -90,7 +92,8 @@ class Solver:
                  drop_tol: float = 1e-10, precision: str = "fp64", ortho_passes: int = 0,
                  extraction: str = "tharmonic", use_graph: bool = False,
                  algorithm: str = "block", stream: Optional[torch.cuda.Stream] = None,
-                 thetas: Sequence[float] = (0.0, 0.0, 0.0)):
+                 thetas: Sequence[float] = (0.0, 0.0, 0.0),
+                 workspace: Optional[torch.Tensor] = None):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
@@ -190,11 +193,24 @@ class Solver:
         self.opts = o
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._a, self._t, self._b = a, t, bdesc
+        sz = C.c_size_t()
+        L.check(self.lib.plhr_workspace_size(C.byref(a),
+                                             C.byref(bdesc) if bdesc is not None else None,
+                                             C.byref(t) if t is not None else None, self.sigma,
+                                             self.k, C.byref(o), C.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+        ws_ptr, ws_len = None, 0
+        if workspace is not None:
+            # a caller workspace: the context allocates no device memory
+            if not workspace.is_cuda or workspace.numel() * workspace.element_size() < sz.value:
+                raise ValueError(f"workspace must be a device tensor of >= {sz.value} bytes")
+            self._ws = workspace
+            ws_ptr, ws_len = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
         ctx = C.c_void_p()
         L.check(self.lib.plhr_create(C.byref(a), C.byref(bdesc) if bdesc is not None else None,
                                      C.byref(t) if t is not None else None,
                                      self.sigma, self.k, C.byref(o),
-                                     C.c_void_p(self.stream.cuda_stream), None, 0,
+                                     C.c_void_p(self.stream.cuda_stream), ws_ptr, ws_len,
                                      C.byref(ctx)))
         self.ctx = ctx
         self.finished = False

@@ -146,3 +146,26 @@ def test_bloch_block_full_size_residuals_by_the_oracle_operator():
     assert rel.max() <= 1.5e-8, rel
     assert np.abs(V.conj().T @ V - np.eye(k)).max() < 1e-10
     assert np.all(lam > sigma) and np.all(lam < 0.0)   # bound states of the wells
+
+
+def test_bloch_block_in_a_caller_workspace_is_bitwise_equal():
+    """plhr_create with a caller workspace (the context and its Bloch
+    V-cycle carve everything from it, no device allocation) gives the same
+    bits as the library-allocated context."""
+    import torch
+    from tests.gpu_util import dev, host
+    dims, n, k, pot, A, ev, sigma, prob, pre = _problem("8x8x4_vcycle")
+    V0 = dev(wl.start_block(n, k + 1, (154, 0), dtype=np.complex128))
+    S1 = _solver(dims, pot, sigma, k, pre, tol=1e-10, max_iters=2000)
+    r1 = S1.solve(V0)
+    nbytes = S1.workspace_bytes
+    S1.close()
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    ws = raw[off:off + nbytes]
+    S2 = _solver(dims, pot, sigma, k, pre, tol=1e-10, max_iters=2000, workspace=ws)
+    r2 = S2.solve(V0)
+    S2.close()
+    assert r1.converged and r2.converged and r1.iters == r2.iters
+    assert np.array_equal(host(r1.eigvals), host(r2.eigvals))
+    assert np.array_equal(host(r1.V), host(r2.V))

@@ -147,3 +147,24 @@ def test_a_smaller_context_does_not_break_a_larger_one():
     assert r.iters == 3 and np.all(np.isfinite(r.rel_res))
     big.close()
     small.close()
+
+
+def test_caller_workspace_is_bitwise_equal():
+    """plhr_create with a caller workspace (no device allocation by the
+    context, multigrid hierarchy included) gives the same bits as the
+    library-allocated context."""
+    import torch
+    args, _ = _small()
+    V0 = dev(wl.start_block(144, 5, (84, 0)))
+    S1 = _solver(**args)
+    r1 = S1.solve(V0)
+    nbytes = S1.workspace_bytes
+    S1.close()
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    S2 = _solver(workspace=raw[off:off + nbytes], **args)
+    r2 = S2.solve(V0)
+    S2.close()
+    assert r1.converged and r2.converged and r1.iters == r2.iters
+    assert np.array_equal(host(r1.eigvals), host(r2.eigvals))
+    assert np.array_equal(host(r1.V), host(r2.V))
