@@ -139,11 +139,14 @@ def test_largest_trial_subspace_m84_matches_closed_form():
     S.close()
 
 
-@pytest.mark.parametrize("no_sym", [False, True])
-def test_first_steps_with_identity_preconditioner_match_oracle(no_sym, monkeypatch):
+@pytest.mark.parametrize("k,kx,no_sym", [(5, 2, False), (5, 2, True), (16, 4, False),
+                                          (16, 5, False)])
+def test_first_steps_with_identity_preconditioner_match_oracle(k, kx, no_sym, monkeypatch):
     """T = I, B = I: the projected problem is Hermitian-definite and runs on
     the Jacobi kernel (no_sym: the general Hessenberg-QR path).  The first
-    iterations' Rayleigh quotients equal the oracle's."""
+    iterations' Rayleigh quotients equal the oracle's.  m = 4 (k + k_extra)
+    = 28, 80 (the widest basis with two copies of the projected matrix in
+    LDS, one barrier per Jacobi round) and 84 (one copy, two barriers)."""
     from tests.gpu_util import dev
     if no_sym:
         monkeypatch.setenv("PLHR_NO_SYM", "1")
@@ -151,7 +154,6 @@ def test_first_steps_with_identity_preconditioner_match_oracle(no_sym, monkeypat
     pot = np.random.default_rng(42).uniform(0, 300, 400)
     A = ops.fd_dirichlet(dims, h, potential=pot)
     sigma = 2500.0
-    k, kx = 5, 2
     V0 = wl.start_block(400, k + kx, (43, 0))
     prob = plhr.Problem(A=A, sigma=sigma)
     o = plhr.BPLHR(prob, V0, k, real=True, lock=False)
