@@ -322,23 +322,17 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     // rows and columns of slots left out at the start are exact zeros and
     // stay zero under the update, and a column dropped at step j' is read
     // by no later step: no per-element test of `valid` is needed
+    // (trip counts from the live sizes: an unrolled loop over the widest
+    // span issues the predicated-off combinations too, which at small m
+    // cost more than the updates)
     const double* gj = Gs + j * m;
     const double* ej = X + j * m;
-#pragma unroll
-    for (int a = 0; a < kOrthoSpan; ++a) {
-      const int i = j + 1 + ty + 16 * a;
-      if (i < m) {
-        const double gji = gj[i] * ip;
-        double* gi = Gs + i * m;
-        double* ei = X + i * m;
-#pragma unroll
-        for (int c = 0; c < kOrthoSpan; ++c) {
-          const int l = i + tx + 16 * c;
-          if (l < m) gi[l] -= gji * gj[l];
-          const int cc = tx + 16 * c;
-          if (cc <= j) ei[cc] -= gji * ej[cc];
-        }
-      }
+    for (int i = j + 1 + ty; i < m; i += 16) {
+      const double gji = gj[i] * ip;
+      double* gi = Gs + i * m;
+      double* ei = X + i * m;
+      for (int l = i + tx; l < m; l += 16) gi[l] -= gji * gj[l];
+      for (int cc = tx; cc <= j; cc += 16) ei[cc] -= gji * ej[cc];
     }
     __syncthreads();
   }
