@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   double* V = C + n * ld;
   double* piv = V + n * ld;  // pivots, later tau
   double* aux = piv + n;     // 1/sqrt(pivot)
-  double* yv = aux + n;      // (unused spare)
+  double* rl = aux + n;      // 1 / L[j][j]
   const int ld2 = 2 * m;
   // symmetric parts of G_L (into V) and G_R (into C) on the kept slots
   for (int e = t; e < n * n; e += kST) {
@@ -159,8 +159,11 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     if (t == 0) piv[j] = pp;
     const double inv = 1.0 / pp;
     const int rem = n - j - 1;
+    // exact quotient e / rem from a float reciprocal (e < 2^13)
+    const float irem = 1.0f / (float)(rem > 0 ? rem : 1);
     for (int e = t; e < rem * rem; e += kST) {
-      const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+      const int q = (int)(((float)e + 0.5f) * irem);
+      const int i = j + 1 + q, c = j + 1 + (e - q * rem);
       if (c <= i) V[i * ld + c] -= V[i * ld + j] * inv * V[c * ld + j];
     }
     __syncthreads();
@@ -179,6 +182,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     else if (c < i)
       v = V[i * ld + c] * aux[c];
     V[i * ld + c] = v;
+    if (c == i) rl[i] = 1.0 / v;  // the triangular solves' divisors, off their chains
     if (dead[i] || dead[c]) C[i * ld + c] = 0.0;
   }
   __syncthreads();
@@ -197,7 +201,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   // C <- C L^-T the same way on columns.  One barrier per step.
   const float inn = 1.0f / (float)n;  // exact float reciprocal: indices < 2^12
   for (int r = 0; r + 1 < n; ++r) {
-    const double ir = 1.0 / V[r * ld + r];
+    const double ir = rl[r];
     const int rem = n - r - 1;
     for (int e = t; e < rem * n; e += kST) {
       const int q = (int)(((float)e + 0.5f) * inn), c = e - q * n;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   }
   __syncthreads();
   for (int r = 0; r + 1 < n; ++r) {
-    const double ir = 1.0 / V[r * ld + r];
+    const double ir = rl[r];
     const int rem = n - r - 1;
     for (int e = t; e < rem * n; e += kST) {
       const int q = (int)(((float)e + 0.5f) * inn), i = e - q * n;
@@ -336,19 +340,26 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
     st->tphase[10] = sweep;
   }
   // tau and the ranks of xi = 1/tau by (|xi|, xi, index); tau = 0 last
-  for (int i = t; i < n; i += kST) piv[i] = C[i * ld + i];
+  // (|xi| once per eigenvalue; xi = 1/tau is |xi| with the sign of tau,
+  // exactly, since a quotient's rounding does not depend on signs)
+  double* xabs = rl + n;
+  for (int i = t; i < n; i += kST) {
+    const double ti = C[i * ld + i];
+    piv[i] = ti;
+    xabs[i] = (ti != 0.0) ? 1.0 / fabs(ti) : INFINITY;
+  }
   __syncthreads();
   int* rank = reinterpret_cast<int*>(aux);  // n ints fit in n doubles
   for (int i = t; i < n; i += kST) {
     const double ti = piv[i];
-    const double xa = (ti != 0.0) ? 1.0 / fabs(ti) : INFINITY;
-    const double xs = (ti != 0.0) ? 1.0 / ti : INFINITY;
+    const double xa = xabs[i];
+    const double xs = (ti != 0.0) ? copysign(xa, ti) : INFINITY;
     int r = 0;
     for (int o = 0; o < n; ++o) {
       if (o == i) continue;
       const double to = piv[o];
-      const double oa = (to != 0.0) ? 1.0 / fabs(to) : INFINITY;
-      const double os = (to != 0.0) ? 1.0 / to : INFINITY;
+      const double oa = xabs[o];
+      const double os = (to != 0.0) ? copysign(oa, to) : INFINITY;
       r += (oa < xa || (oa == xa && (os < xs || (os == xs && o < i)))) ? 1 : 0;
     }
     rank[i] = r;
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   // times row r from the rows q < r; row r is final after step r + 1),
   // then every row scaled by 1 / L[r][r].  One barrier per step.
   for (int r = n - 1; r > 0; --r) {
-    const double ir = 1.0 / C[r * ld + r];
+    const double ir = rl[r];  // C holds L here
     for (int e = t; e < r * n; e += kST) {
       const int q = (int)(((float)e + 0.5f) * inn), c = e - q * n;
       V[q * ld + c] -= (C[r * ld + q] * ir) * V[r * ld + c];
@@ -412,7 +423,6 @@ __global__ __launch_bounds__(kST) void k_tharm_sym(SmallParams p, SmallBufs b, D
   }
   __syncthreads();
   if (t == 0) st->tphase[6] = clock64();
-  (void)yv;
 }
 
 static size_t sym_lds(int m) { return ((size_t)2 * m * (m | 1) + 4 * (size_t)m) * sizeof(double); }
