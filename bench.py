@@ -73,8 +73,8 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     ("tharm_qr", 24): {"source": "paper_1408_0042_amd/csrc/k_tharm_sym.hip",
-                       "sha256": "8e81cd05e95b9d344d86d3181a9feb0770c57b5621f5261642a155c81b9e1d21",
-                       "fetch_kib": 18.4300, "write_kib": 5.3930},
+                       "sha256": "22b097c6473d3c8b30ad8a063d0ac88460037e923ca927e5daf05bfa8c59391f",
+                       "fetch_kib": 18.4300, "write_kib": 5.3925},
 }
 
 
