@@ -257,7 +257,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   __shared__ int valid[256];
   __shared__ int flag;
   const int t = threadIdx.x, nt = blockDim.x;
-  const int tx = t & 15, ty = t >> 4;
+  const int tx = t & 15, ty = t >> 4, nty = nt >> 4;  // 16 columns x nty rows of threads
   const int have_p = st->have_p;
   for (int s = t; s < m; s += nt) {
     int v = slot_valid(s, kint, b.active, have_p);
@@ -270,7 +270,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < kOrthoSpan; ++a) {
-    const int i = ty + 16 * a;
+    const int i = ty + nty * a;
     if (i < m) {
       double g[kOrthoSpan];
 #pragma unroll
@@ -327,7 +327,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     // cost more than the updates)
     const double* gj = Gs + j * m;
     const double* ej = X + j * m;
-    for (int i = j + 1 + ty; i < m; i += 16) {
+    for (int i = j + 1 + ty; i < m; i += nty) {
       const double gji = gj[i] * ip;
       double* gi = Gs + i * m;
       double* ei = X + i * m;
@@ -340,7 +340,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
     if (valid[j]) rsc[j] = 1.0 / sqrt(rsc[j]);
   __syncthreads();
   // M = D R^-1 = D E^T D_piv^-1/2 on the kept slots, zero elsewhere
-  for (int i = ty; i < m; i += 16)
+  for (int i = ty; i < m; i += nty)
     for (int c = tx; c < m; c += 16)
       b.M[(size_t)i * m + c] =
           (valid[i] && valid[c] && c >= i) ? d[i] * X[c * m + i] * rsc[c] : 0.0;
@@ -360,7 +360,7 @@ __device__ void k_ortho_small_body(SmallParams p, SmallBufs b, DevStatus* st) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_ortho_small(SmallParams p, SmallBufs b, DevStatus* st) {
+__global__ __launch_bounds__(1024) void k_ortho_small(SmallParams p, SmallBufs b, DevStatus* st) {
   k_ortho_small_body(p, b, st);
 }
 // batched: workgroup b runs problem b
@@ -746,12 +746,16 @@ void launch_conv_check(const SmallParams& p, const double* part, int nblk, Small
   hipLaunchKernelGGL(k_conv_check, dim3(1), dim3(256), 0, s, p, part, nblk, b, st);
   prof_end(KC_SMALL, s);
 }
+static int ortho_threads(int m) { return (m >= 48) ? 1024 : 256; }
+
 void launch_ortho_small(const SmallParams& p, SmallBufs b, DevStatus* st, hipStream_t s) {
   const size_t lds = ((size_t)2 * p.m * p.m + p.m) * sizeof(double);
   // model count: Cholesky m^3/3, inverse of the factor m^3/3, scaling
   const double m3 = (double)p.m * p.m * p.m;
   prof_begin(KC_ORTHO, 2.0 * p.m * p.m * 8.0, 2.0 * m3 / 3.0, s);
-  hipLaunchKernelGGL(k_ortho_small, dim3(1), dim3(256), lds, s, p, b, st);
+  // wider bases take more rows of threads: the elimination's work per
+  // step grows as m^2, its chain of steps as m
+  hipLaunchKernelGGL(k_ortho_small, dim3(1), dim3(ortho_threads(p.m)), lds, s, p, b, st);
   prof_end(KC_ORTHO, s);
 }
 void launch_rq_small(const SmallParams& p, const double* part, int nblk, SmallBufs b,
