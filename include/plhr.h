@@ -396,8 +396,9 @@ plhr_status plhr_op_apply(const plhr_op_desc* A, double shift, const void* X, vo
  *       of plhr_bloch_prec_create (its rules on levels and the coarsest
  *       grid apply; its levels and coarse inverse live in the context's
  *       workspace); any other kind is PLHR_ERR_UNSUPPORTED
- *   opt algorithm PLHR_ALG_BLOCK, precision PLHR_PREC_FP64; lock is
- *       ignored (no soft locking); 8 (k + k_extra) <= 84, since each of
+ *   opt algorithm PLHR_ALG_BLOCK, precision PLHR_PREC_FP64; lock locks
+ *       a converged complex column (it generates no W, S or P, as in the
+ *       real iteration); 8 (k + k_extra) <= 84, since each of
  *       the k + k_extra complex columns of the four slots counts as two
  *       real columns of the on-chip projected problem.
  * Blocks are complex128, interleaved, point-major: V0 of plhr_start /

@@ -1288,7 +1288,9 @@ plhr_status plhr_create(const plhr_op_desc* A, const plhr_op_desc* B, const plhr
   c->sp.drop_tol = o.drop_tol;
   c->sp.cplx = c->bloch ? 2 : ((o.algorithm == PLHR_ALG_SINGLE) ? 1 : 0);
   c->sp.plmr = (o.algorithm == PLHR_ALG_PLMR) ? 1 : 0;
-  c->sp.lock = (c->sp.cplx || c->sp.plmr) ? 0 : o.lock;
+  // soft locking in the block iterations, real and complex (a complex
+  // column locks both of its real columns); not in the single-vector ones
+  c->sp.lock = (c->sp.cplx == 1 || c->sp.plmr) ? 0 : o.lock;
   // G_R of eq. (3.5) is symmetric when T does not enter the projection
   // (T = I, or the harmonic extraction) and B = I: the projected problem
   // is then Hermitian-definite

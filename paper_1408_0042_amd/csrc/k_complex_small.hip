@@ -261,7 +261,8 @@ __global__ __launch_bounds__(kW) void k_cplx_ortho(SmallParams p, SmallBufs b, D
   const int have_p = st->have_p;
   for (int a = t; a < N; a += kW) {
     const int slot = a / kc, col = a - slot * kc;
-    int v = (slot == 0) ? 1 : (slot == 3 ? have_p : b.active[2 * col]);
+    // a locked column (active 0) generates no W, S or P
+    int v = (slot == 0) ? 1 : (b.active[2 * col] && (slot != 3 || have_p));
     const double g = cgram(b.G, m, a, a).re;
     if (v && !(g > 0.0 && g < INFINITY)) v = 0;
     valid[a] = v;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(kW) void k_cplx_ortho(SmallParams p, SmallBufs b, D
       const int slot = a / kc, col = a - slot * kc;
       nk += valid[a];
       if (slot == 0) anyv |= valid[a];
-      const int wanted = (slot == 0) ? 1 : (slot == 3 ? have_p : b.active[2 * col]);
+      const int wanted = (slot == 0) ? 1 : (b.active[2 * col] && (slot != 3 || have_p));
       if (!valid[a] && wanted) ++nd;
     }
     st->m_kept = 2 * nk;

@@ -67,6 +67,42 @@ def test_bloch_block_steps_match_oracle(name):
     S.close()
 
 
+def test_bloch_block_soft_locking_matches_oracle():
+    """Soft locking in the complex block iteration: a column whose relative
+    residual is at or below tol generates no W, S or P (both of its real
+    columns).  At tol = 1e-6 the 8 x 8 x 4 case locks its first column
+    after 29 steps and stops after 39 (measured on the oracle); every step's
+    Rayleigh quotients and number of active columns equal the oracle's."""
+    from paper_1408_0042_amd.plhr import Solver
+    from tests.gpu_util import dev
+    dims, n, k, pot, A, ev, sigma, prob, pre = _problem("8x8x4_vcycle")
+    tol = 1e-6
+    V0 = wl.start_block(n, k + 1, (151, 0), dtype=np.complex128)
+    o = plhr.BPLHR(prob, V0, k, real=False, lock=True)
+    o.tol = tol
+    S = Solver("bloch7_3d", dims, 1.0, sigma, k, scale=0.5, potential=dev(pot), precond=pre,
+               thetas=THETAS, lock=True, tol=tol, max_iters=200)
+    S.start(dev(V0))
+    locked_steps = 0
+    for it in range(60):
+        act = int(np.sum(o.residuals() > tol))
+        info = S.iterate(1)
+        if info.converged:
+            wanted = plhr.wanted_columns(o.lam, sigma, k)
+            assert np.all(o.residuals()[wanted] <= tol), it
+            break
+        assert info.n_active == 2 * act, (it, info.n_active, act)
+        locked_steps += act < k + 1
+        o.step()
+        lam, _ = S.state()
+        assert np.allclose(np.sort(lam[0::2]), np.sort(o.lam), rtol=1e-9, atol=1e-11), \
+            (it, lam[0::2], o.lam)
+    else:
+        raise AssertionError("no convergence in 60 steps")
+    assert locked_steps >= 5, locked_steps
+    S.close()
+
+
 # (with T = I the 8 x 8 x 8 case stalls near 1e-8 in the oracle as well)
 @pytest.mark.parametrize("name", ["8x8x4_vcycle", "6x6x6_vcycle", "4x4x8_identity"])
 def test_bloch_block_converges_to_the_dense_pairs(name):
