@@ -8,10 +8,10 @@
 //                  M with Zhat = Z M B-orthonormal (Section 4: V, W, S, P
 //                  are orthonormalised in this order, which is what a
 //                  Cholesky factorisation of the Gram matrix in slot order
-//                  computes)
+//                  computes); 256 threads, 1024 from m = 48
 //   (the projected problem eq. (3.5) and the selection of Algorithm 3 are
-//   in k_tharm.hip and k_tharm_sym.hip; the complex single-vector steps of
-//   Algorithm 1 in k_single.hip)
+//   in k_tharm.hip and k_tharm_sym.hip; the complex steps of Algorithms 1
+//   and 2 in k_complex_small.hip, the PLMR refinement in k_single.hip)
 //   k_rq_small     Rayleigh quotients of the new block, eq. (4.1) for pairs
 //   k_final_rr     standard Rayleigh-Ritz on span(V) (the last step of
 //                  Algorithms 2 and 3): Cholesky + cyclic Jacobi
