@@ -21,7 +21,7 @@
 //                  second pass
 //   k_cplx_tharm   eq. (3.5) in complex arithmetic: G_L = L L^H, C = L^-1 G_R
 //                  L^-H, the complex Schur form C = Q T Q^H (Hessenberg by
-//                  Givens rotations, then single-shift QR with Wilkinson
+//                  Householder reflections, then single-shift QR with Wilkinson
 //                  shifts, Golub & Van Loan Sec. 7.5), the k_int eigenvalues
 //                  tau of largest modulus (xi = 1/tau of smallest modulus,
 //                  ties by (Re xi, -Im xi)), their eigenvectors by back
@@ -141,20 +141,63 @@ __device__ bool schur_w(cd* H, cd* Q, int ld, int n, long long* stamp = nullptr)
     Q[i * ld + j] = mk(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  // Hessenberg form by rotations, zeroing column j below the subdiagonal
-  for (int j = 0; j + 2 < n; ++j)
-    for (int i = n - 1; i >= j + 2; --i) {
-      double c;
-      cd s;
-      givens(H[(i - 1) * ld + j], H[i * ld + j], c, s);
-      __syncthreads();
-      rot_rows(H, ld, n, 0, i - 1, i, c, s);
-      __syncthreads();
-      rot_cols(H, Q, ld, n, n, i - 1, i, c, s);
-      __syncthreads();
-      if (threadIdx.x == 0) H[i * ld + j] = mk(0.0, 0.0);
-      __syncthreads();
+  // Hessenberg form by Householder reflections P = I - tau v v^H (Golub &
+  // Van Loan, Sec. 7.4.3, complex): step j maps column j below the
+  // diagonal, x = H[j+1.., j], to alpha e_1 with alpha = -(x_0 / |x_0|)
+  // ||x||, v = x - alpha e_1, tau = 2 / v^H v; then H <- P H P, Q <- Q P.
+  // n - 2 steps of three lane-parallel phases (each lane one column for
+  // P H, one row of H and of Q for H P and Q P) instead of one
+  // rotation per subdiagonal entry.
+  __shared__ cd hv[kMaxN];
+  const int lane = threadIdx.x;
+  for (int j = 0; j + 2 < n; ++j) {
+    const int len = n - j - 1;  // rows j+1 .. n-1
+    cd xl = mk(0.0, 0.0);
+    if (lane < len) xl = H[(j + 1 + lane) * ld + j];
+    double s2 = (lane >= 1 && lane < len) ? xl.re * xl.re + xl.im * xl.im : 0.0;
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+    s2 = __shfl(s2, 0);  // one value for every lane
+    if (s2 == 0.0) continue;  // uniform: the column is already reduced
+    const cd x0 = H[(j + 1) * ld + j];
+    const double a2 = x0.re * x0.re + x0.im * x0.im;
+    const double nrm = sqrt(a2 + s2);
+    const double ia = (a2 > 0.0) ? crsq(a2) : 0.0;
+    const cd alpha = mk((a2 > 0.0) ? -nrm * (ia * x0.re) : -nrm, -nrm * (ia * x0.im));
+    const cd v0 = x0 - alpha;
+    const double tau = 2.0 / (v0.re * v0.re + v0.im * v0.im + s2);
+    if (lane == 0)
+      hv[0] = v0;
+    else if (lane < len)
+      hv[lane] = xl;
+    __syncthreads();
+    // P H on columns j+1 ..; column j becomes alpha e_1
+    for (int c = j + 1 + lane; c < n; c += kW) {
+      cd w = mk(0.0, 0.0);
+      for (int r = 0; r < len; ++r) w = w + cj(hv[r]) * H[(j + 1 + r) * ld + c];
+      const cd tw = tau * w;
+      for (int r = 0; r < len; ++r) H[(j + 1 + r) * ld + c] = H[(j + 1 + r) * ld + c] - hv[r] * tw;
     }
+    if (lane == 0)
+      H[(j + 1) * ld + j] = alpha;
+    else if (lane < len)
+      H[(j + 1 + lane) * ld + j] = mk(0.0, 0.0);
+    __syncthreads();
+    // H P and Q P on rows, columns j+1 ..
+    for (int r = lane; r < n; r += kW) {
+      cd zh = mk(0.0, 0.0), zq = mk(0.0, 0.0);
+      for (int c = 0; c < len; ++c) {
+        zh = zh + H[r * ld + j + 1 + c] * hv[c];
+        zq = zq + Q[r * ld + j + 1 + c] * hv[c];
+      }
+      const cd th = tau * zh, tq = tau * zq;
+      for (int c = 0; c < len; ++c) {
+        const cd vc = cj(hv[c]);
+        H[r * ld + j + 1 + c] = H[r * ld + j + 1 + c] - th * vc;
+        Q[r * ld + j + 1 + c] = Q[r * ld + j + 1 + c] - tq * vc;
+      }
+    }
+    __syncthreads();
+  }
   if (stamp && threadIdx.x == 0) *stamp = clock64();
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, its = 0, total = 0;
