@@ -106,30 +106,6 @@ __device__ void givens(cd a, cd b, double& c, cd& s) {
   s = (ia * ir) * (a * cj(b));
 }
 
-// Rows p, q of the n x n matrix H (stride ld) from column j0 on, by the lanes.
-__device__ void rot_rows(cd* H, int ld, int n, int j0, int p, int q, double c, cd s) {
-  for (int j = j0 + (int)threadIdx.x; j < n; j += kW) {
-    const cd x = H[p * ld + j], y = H[q * ld + j];
-    H[p * ld + j] = c * x + s * y;
-    H[q * ld + j] = c * y - cj(s) * x;
-  }
-}
-
-// Columns p, q of rows 0..r1-1 of H, and of all n rows of Q, by the lanes
-// (the right product with the rotation's conjugate transpose).
-__device__ void rot_cols(cd* H, cd* Q, int ld, int n, int r1, int p, int q, double c, cd s) {
-  for (int r = threadIdx.x; r < r1; r += kW) {
-    const cd x = H[r * ld + p], y = H[r * ld + q];
-    H[r * ld + p] = c * x + cj(s) * y;
-    H[r * ld + q] = c * y - s * x;
-  }
-  for (int r = threadIdx.x; r < n; r += kW) {
-    const cd u = Q[r * ld + p], v = Q[r * ld + q];
-    Q[r * ld + p] = c * u + cj(s) * v;
-    Q[r * ld + q] = c * v - s * u;
-  }
-}
-
 // Complex Schur form H = Q T Q^H of an n x n matrix (stride ld) in place,
 // by the whole wavefront; every lane keeps the same control flow (all its
 // decisions read the matrix after a barrier).  Returns false when the QR
@@ -148,6 +124,7 @@ __device__ bool schur_w(cd* H, cd* Q, int ld, int n, long long* stamp = nullptr)
   // n - 2 steps of three lane-parallel phases (each lane one column for
   // P H, one row of H and of Q for H P and Q P) instead of one
   // rotation per subdiagonal entry.
+  static_assert(kMaxN <= kW, "one lane per row or column");
   __shared__ cd hv[kMaxN];
   const int lane = threadIdx.x;
   for (int j = 0; j + 2 < n; ++j) {
@@ -239,24 +216,51 @@ __device__ bool schur_w(cd* H, cd* Q, int ld, int n, long long* stamp = nullptr)
     // rotations from the left, then RQ + mu I
     for (int k = lo + (int)threadIdx.x; k <= hi; k += kW) H[k * ld + k] = H[k * ld + k] - mu;
     __syncthreads();
-    for (int k = lo; k < hi; ++k) {
-      double c;
-      cd sk;
-      givens(H[k * ld + k], H[(k + 1) * ld + k], c, sk);
-      if (threadIdx.x == 0) {
-        cs[k] = c;
-        sn[k] = sk;
+    // Left sweep: lane j owns column j.  The row being rotated down (row k
+    // after rotation k - 1) stays in a register of each lane; rotation k
+    // comes from its diagonal entry (lane k's register, by shuffle) and
+    // the untouched subdiagonal entry below it, and the rotated upper row
+    // is stored as row k of R.  No lane reads what another lane wrote, so
+    // the sweep needs no barrier; the values are those of applying the
+    // rotations one row pair at a time.
+    {
+      cd cr = mk(0.0, 0.0);
+      if (lane >= lo && lane < n) cr = H[lo * ld + lane];
+      for (int k = lo; k < hi; ++k) {
+        const cd a = mk(__shfl(cr.re, k), __shfl(cr.im, k));
+        double c;
+        cd sk;
+        givens(a, H[(k + 1) * ld + k], c, sk);
+        if (lane == 0) {
+          cs[k] = c;
+          sn[k] = sk;
+        }
+        if (lane >= k && lane < n) {
+          const cd x = cr, y = H[(k + 1) * ld + lane];
+          H[k * ld + lane] = c * x + sk * y;
+          cr = c * y - cj(sk) * x;
+        }
       }
-      __syncthreads();
-      rot_rows(H, ld, n, k, k, k + 1, c, sk);
-      __syncthreads();
-      if (threadIdx.x == 0) H[(k + 1) * ld + k] = mk(0.0, 0.0);
-      __syncthreads();
+      if (lane >= hi && lane < n) H[hi * ld + lane] = cr;
+      if (lane >= lo && lane < hi) H[(lane + 1) * ld + lane] = mk(0.0, 0.0);
     }
-    for (int k = lo; k < hi; ++k) {
-      rot_cols(H, Q, ld, n, hi + 1, k, k + 1, cs[k], sn[k]);
-      __syncthreads();
+    __syncthreads();
+    // Right sweep (R Q^H and the Schur vectors): lane r owns row r of H
+    // (r <= hi) or of Q, and applies every rotation along it in order, the
+    // column between two rotations kept in a register.
+    for (int r = lane; r < hi + 1 + n; r += kW) {
+      cd* row = (r <= hi) ? H + r * ld : Q + (r - hi - 1) * ld;
+      cd x = row[lo];
+      for (int k = lo; k < hi; ++k) {
+        const double c = cs[k];
+        const cd sk = sn[k];
+        const cd y = row[k + 1];
+        row[k] = c * x + cj(sk) * y;
+        x = c * y - sk * x;
+      }
+      row[hi] = x;
     }
+    __syncthreads();
     for (int k = lo + (int)threadIdx.x; k <= hi; k += kW) H[k * ld + k] = H[k * ld + k] + mu;
     __syncthreads();
   }
