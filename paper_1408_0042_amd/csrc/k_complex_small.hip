@@ -488,28 +488,31 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     return;
   }
   if (t == 0) st->tphase[1] = clock64();
-  // C <- L^-1 C (rows, unscaled right-looking), then C <- C L^-H (columns)
-  for (int r = 0; r + 1 < n; ++r) {
-    const double ir = 1.0 / L[r * ld + r].re;
-    for (int e = t; e < (n - r - 1) * n; e += kW) {
-      const int i = r + 1 + e / n, c = e % n;
-      C[i * ld + c] = C[i * ld + c] - (ir * L[i * ld + r]) * C[r * ld + c];
+  // C <- L^-1 C (rows, unscaled right-looking), then C <- C L^-H (columns).
+  // Each lane owns one column (then one row) of C and runs every step on
+  // it in order: the updates of an entry are those of the step-by-step
+  // elimination, with no barrier between steps.
+  for (int c = t; c < n; c += kW)
+    for (int r = 0; r + 1 < n; ++r) {
+      const double ir = 1.0 / L[r * ld + r].re;
+      const cd xr = C[r * ld + c];
+      for (int i = r + 1; i < n; ++i)
+        C[i * ld + c] = C[i * ld + c] - (ir * L[i * ld + r]) * xr;
     }
-    __syncthreads();
-  }
+  __syncthreads();
   for (int e = t; e < n * n; e += kW) {
     const int i = e / n, c = e - i * n;
     C[i * ld + c] = (1.0 / L[i * ld + i].re) * C[i * ld + c];
   }
   __syncthreads();
-  for (int r = 0; r + 1 < n; ++r) {
-    const double ir = 1.0 / L[r * ld + r].re;
-    for (int e = t; e < (n - r - 1) * n; e += kW) {
-      const int c = r + 1 + e / n, i = e % n;
-      C[i * ld + c] = C[i * ld + c] - (ir * cj(L[c * ld + r])) * C[i * ld + r];
+  for (int i = t; i < n; i += kW)
+    for (int r = 0; r + 1 < n; ++r) {
+      const double ir = 1.0 / L[r * ld + r].re;
+      const cd xr = C[i * ld + r];
+      for (int c = r + 1; c < n; ++c)
+        C[i * ld + c] = C[i * ld + c] - (ir * cj(L[c * ld + r])) * xr;
     }
-    __syncthreads();
-  }
+  __syncthreads();
   for (int e = t; e < n * n; e += kW) {
     const int i = e / n, c = e - i * n;
     C[i * ld + c] = (1.0 / L[c * ld + c].re) * C[i * ld + c];
@@ -526,16 +529,21 @@ __global__ __launch_bounds__(kW) void k_cplx_tharm(SmallParams p, SmallBufs b, D
     }
     return;
   }
-  // eigenvalues in xi order (diagnostics) and the selection
+  // eigenvalues in xi order (diagnostics) and the selection: each lane
+  // ranks one eigenvalue by counting those before it (ties by index), the
+  // order of a stable sort by xi_before
+  for (int i = t; i < n; i += kW) {
+    const cd ti = C[i * ld + i];
+    int r = 0;
+    for (int o = 0; o < n; ++o) {
+      if (o == i) continue;
+      const cd to = C[o * ld + o];
+      r += (xi_before(to, ti) || (o < i && !xi_before(ti, to))) ? 1 : 0;
+    }
+    ord[r] = i;
+  }
+  __syncthreads();
   if (t == 0) {
-    for (int i = 0; i < n; ++i) ord[i] = i;
-    for (int i = 1; i < n; ++i)
-      for (int j = i; j > 0 && xi_before(C[ord[j] * ld + ord[j]], C[ord[j - 1] * ld + ord[j - 1]]);
-           --j) {
-        const int tmp = ord[j];
-        ord[j] = ord[j - 1];
-        ord[j - 1] = tmp;
-      }
     ok_s = 1;
     for (int j = 0; j < kc; ++j)
       if (!(ab(C[ord[j] * ld + ord[j]]) > 0.0)) ok_s = 0;
